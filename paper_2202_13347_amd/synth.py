@@ -1,0 +1,174 @@
+"""Seeded synthetic multimodal image pairs and interest-point layouts.
+
+This module only draws inputs: piecewise-constant scenes, intensity remaps,
+noise and shifts.  It holds none of the matching method's arithmetic, so both
+the GPU path and the CPU reference can be fed from it.
+
+The paper's own image pairs (optical / infrared / LiDAR / SAR / map, Section
+4.1, Table 1) are not available; these scenes stand in for them.  Each pair
+is a reference image and a "sensed" image that sees the same layout of
+regions through a different, non-monotonic intensity response per region
+(nonlinear radiometric difference), with contrast reversed in half of the
+regions, additive noise, optional multiplicative gamma speckle (a SAR-like
+look count) and a known translation with a sub-pixel fraction.  After a
+correct match, the sensed point p corresponds to the reference point p + d.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+from scipy import ndimage
+
+
+@dataclass
+class Pair:
+    ref: np.ndarray        # (H, W) float32
+    sen: np.ndarray        # (H, W) float32
+    shift: np.ndarray      # (2,) float64, (dy, dx): sen(p) <-> ref(p + shift)
+    seed: int
+
+
+def _convex_polygon_mask(rng, h, w, cy, cx, rad):
+    """Boolean mask of a random convex polygon (3..7 vertices) of radius ~rad."""
+    nv = int(rng.integers(3, 8))
+    ang = np.sort(rng.uniform(0, 2 * np.pi, nv))
+    rr = rad * rng.uniform(0.6, 1.0, nv)
+    vy = cy + rr * np.sin(ang)
+    vx = cx + rr * np.cos(ang)
+    y0 = int(max(0, np.floor(vy.min()))); y1 = int(min(h, np.ceil(vy.max()) + 1))
+    x0 = int(max(0, np.floor(vx.min()))); x1 = int(min(w, np.ceil(vx.max()) + 1))
+    mask = np.zeros((h, w), dtype=bool)
+    if y1 <= y0 or x1 <= x0:
+        return mask
+    yy, xx = np.mgrid[y0:y1, x0:x1].astype(np.float64)
+    inside = np.ones(yy.shape, dtype=bool)
+    for i in range(nv):
+        j = (i + 1) % nv
+        ex, ey = vx[j] - vx[i], vy[j] - vy[i]
+        inside &= (ex * (yy - vy[i]) - ey * (xx - vx[i])) >= 0
+    mask[y0:y1, x0:x1] = inside
+    return mask
+
+
+def _label_map(rng, h, w, n_shapes, size_lo, size_hi):
+    """Painter's-algorithm region labels: 0 = background, k = k-th shape."""
+    lab = np.zeros((h, w), dtype=np.int32)
+    for k in range(1, n_shapes + 1):
+        sz = rng.uniform(size_lo, size_hi)
+        cy = rng.uniform(0, h); cx = rng.uniform(0, w)
+        if rng.random() < 0.5:
+            hh = sz * rng.uniform(0.4, 1.0); ww = sz * rng.uniform(0.4, 1.0)
+            y0 = int(max(0, cy - hh / 2)); y1 = int(min(h, cy + hh / 2))
+            x0 = int(max(0, cx - ww / 2)); x1 = int(min(w, cx + ww / 2))
+            lab[y0:y1, x0:x1] = k
+        else:
+            lab[_convex_polygon_mask(rng, h, w, cy, cx, sz / 2)] = k
+    return lab
+
+
+def _value_noise(rng, h, w, cell, std):
+    """Smooth noise: a coarse random grid upsampled with cubic splines."""
+    gh = h // cell + 4; gw = w // cell + 4
+    g = rng.standard_normal((gh, gw))
+    up = ndimage.zoom(g, cell, order=3)[:h, :w]
+    s = up.std()
+    return up * (std / s) if s > 0 else up
+
+
+def _cubic_maps(rng, n):
+    """Per-region random non-monotonic cubic intensity responses on [0, 1]."""
+    coef = rng.uniform(-2.0, 2.0, size=(n, 4))
+    v = np.linspace(0, 1, 65)
+    out = []
+    for c in coef:
+        y = c[0] + c[1] * v + c[2] * v ** 2 + c[3] * v ** 3
+        lo, hi = y.min(), y.max()
+        if hi - lo < 1e-3:
+            c = np.array([0.0, 1.0, 0.0, 0.0]); lo, hi = 0.0, 1.0
+        out.append((c, lo, hi))
+    return out
+
+
+def make_pair(seed: int, size: int | tuple[int, int], max_shift: float,
+              speckle_looks: int = 0, n_shapes: int | None = None,
+              noise_std: float = 0.05, integer_shift: bool = False) -> Pair:
+    """One seeded multimodal pair.
+
+    size          : side (or (H, W)) of both images.
+    max_shift     : the true shift is drawn from U[-max_shift, max_shift]^2.
+    speckle_looks : if > 0, the sensed image is multiplied by Gamma(L, 1/L).
+    n_shapes      : regions; default 40 per 256x256 of area.
+    integer_shift : round the drawn shift to whole pixels.
+    """
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    H, W = (size, size) if np.isscalar(size) else size
+    if n_shapes is None:
+        n_shapes = max(8, int(round(40 * H * W / 256.0 ** 2)))
+    shift = rng.uniform(-max_shift, max_shift, size=2)
+    if integer_shift:
+        shift = np.round(shift)
+    pad = int(np.ceil(max_shift)) + 8
+    ch, cw = H + 2 * pad, W + 2 * pad
+    lab = _label_map(rng, ch, cw, n_shapes, 8.0, min(96.0, max(16.0, min(H, W) / 2)))
+    vals = rng.uniform(0, 1, n_shapes + 1)
+    maps = _cubic_maps(rng, n_shapes + 1)
+    flip = rng.random(n_shapes + 1) < 0.5
+    scene_r = vals[lab]
+    resp = np.empty(n_shapes + 1)
+    for k, ((c, lo, hi), f) in enumerate(zip(maps, flip)):
+        v = vals[k]
+        y = (c[0] + c[1] * v + c[2] * v * v + c[3] * v ** 3 - lo) / (hi - lo)
+        resp[k] = 1.0 - y if f else y
+    scene_s = resp[lab]
+    scene_r = scene_r + _value_noise(rng, ch, cw, 16, 0.1)
+    scene_s = scene_s + _value_noise(rng, ch, cw, 24, 0.05)
+    scene_r = ndimage.gaussian_filter(scene_r, 1.0, mode="reflect")
+    scene_s = ndimage.gaussian_filter(scene_s, 1.0, mode="reflect")
+    # sen(y, x) = scene_s(y + dy, x + dx): ndimage.shift moves content by +s,
+    # i.e. out(y) = in(y - s), so shift by -d.
+    if integer_shift:
+        dy, dx = int(shift[0]), int(shift[1])
+        sen_c = np.roll(scene_s, (-dy, -dx), axis=(0, 1))
+    else:
+        sen_c = ndimage.shift(scene_s, -shift, order=3, mode="nearest")
+    ref = scene_r[pad:pad + H, pad:pad + W]
+    sen = sen_c[pad:pad + H, pad:pad + W]
+    if noise_std > 0:
+        sen = sen + rng.normal(0.0, noise_std, sen.shape)
+    if speckle_looks > 0:
+        L = float(speckle_looks)
+        sen = sen * rng.gamma(L, 1.0 / L, sen.shape)
+    return Pair(ref=np.ascontiguousarray(ref, dtype=np.float32),
+                sen=np.ascontiguousarray(sen, dtype=np.float32),
+                shift=shift.astype(np.float64), seed=seed)
+
+
+def grid_ips(H: int, W: int, n_side: int, margin: int) -> np.ndarray:
+    """n_side x n_side interest points evenly spaced in [margin, side-1-margin],
+    as an (n, 2) int32 array of (row, col)."""
+    ys = np.round(np.linspace(margin, H - 1 - margin, n_side)).astype(np.int32)
+    xs = np.round(np.linspace(margin, W - 1 - margin, n_side)).astype(np.int32)
+    yy, xx = np.meshgrid(ys, xs, indexing="ij")
+    return np.stack([yy.ravel(), xx.ravel()], axis=1).astype(np.int32)
+
+
+def random_ips(seed: int, H: int, W: int, n: int, margin: int) -> np.ndarray:
+    """n seeded uniform interest points inside the margin, (n, 2) int32."""
+    rng = np.random.default_rng(np.random.PCG64(seed + 7919))
+    ys = rng.integers(margin, H - margin, n)
+    xs = rng.integers(margin, W - margin, n)
+    return np.stack([ys, xs], axis=1).astype(np.int32)
+
+
+# Workload recipes (image side, IP grid, template m, search radius r, shift bound).
+SMALL = dict(size=256, n_side=4, m=32, r=10, max_shift=8.0, speckle=0)
+SCENE = dict(size=2048, n_side=20, m=64, r=32, max_shift=30.0, speckle=4)
+
+
+def workload(recipe: dict, seed: int):
+    """(pair, ips, m, r) for a recipe; IP margin = ceil(m/2) + r."""
+    p = make_pair(seed, recipe["size"], recipe["max_shift"], speckle_looks=recipe["speckle"])
+    b = (recipe["m"] + 1) // 2 + recipe["r"]
+    ips = grid_ips(recipe["size"], recipe["size"], recipe["n_side"], b)
+    return p, ips, recipe["m"], recipe["r"]
