@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Throughput of the fine-registration hot path on one MI355X.
+
+One step = sfoc_register_cps on the 2048 x 2048 scene pair: dense SFOC of
+both images, float64 integral images of the reference, Fast-NCC_SFOC for the
+400 interest points (20 x 20 grid, template 64, search +-32), peak fit and
+consistency check.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.  --gpus must be 1: this build runs on a single GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VALU = 157.3e12       # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+PEAK_HBM = 8.0e12
+
+
+def sfoc_flops_per_px(p) -> float:
+    """Algorithmic flops per output pixel of SFOC (separable form): per sigma
+    the row pass (g, d, dd) and column pass (5 basis maps), each a (2R+1)-tap
+    FMA; steering 3 flops per first-order and 5 per second-order channel;
+    dilated smoothing separable per rate (2 * (4K+1) flops) plus the sum over
+    rates; normalisation 3 flops per channel plus a root and a divide per order."""
+    sig = {}
+    for s in p.s1[:p.n_s1]:
+        sig[s] = sig.get(s, 0) | 1
+    if p.second_order:
+        for s in p.s2[:p.n_s2]:
+            sig[s] = sig.get(s, 0) | 2
+    conv = 0.0
+    for s, use in sig.items():
+        R = math.ceil(p.trunc * s - 1e-9)
+        rows = 3 if use & 2 else 2
+        cols = (2 if use & 1 else 0) + (3 if use & 2 else 0)
+        conv += 2.0 * (rows + cols) * (2 * R + 1)
+    N = p.n_orient
+    z = N * (2 if p.second_order else 1)
+    steer = 3 * N + (5 * N if p.second_order else 0)
+    smooth = z * (p.n_dil * 2 * (4 * p.K + 1) + (p.n_dil - 1))
+    norm = 3 * z + 2 * (2 if p.second_order else 1)
+    return conv + steer + smooth + norm
+
+
+def fastncc_flops_per_ip(M: int, z: int) -> float:
+    """Algorithmic flops per interest point of Fast-NCC_SFOC with FFT side
+    L = M (Eq. 13): 2z forward real 2-D FFTs and one inverse at
+    2.5 L^2 log2(L^2) flops each, plus the spectrum product summed over
+    channels (8 flops per half-spectrum bin per channel)."""
+    L = M
+    fft = 2.5 * L * L * math.log2(L * L)
+    return (2 * z + 1) * fft + z * L * (L // 2 + 1) * 8
+
+
+def cpu_baseline(pr, ips, m, r, budget_s: float):
+    """The FP64 oracle on a bounded sample: complete CPs (SFOC of the
+    template and search crops + Eq. 9-16 + peak) until the time budget is
+    used, one process, one thread."""
+    from oracle import sfoc_oracle as O
+    p = O.Params()
+    t0 = time.perf_counter()
+    done = 0
+    order = list(range(0, len(ips), 7)) + [i for i in range(len(ips)) if i % 7]
+    for k in order:
+        O.match_one_region(pr.ref, pr.sen, ips[k], m, r, p)
+        done += 1
+        if time.perf_counter() - t0 >= budget_s and done >= 2:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "CPs/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} of the {len(ips)} CPs of the same scene, each computed from its template and "
+                      f"search crops (FP64 SFOC with reflect-101 halo, FFT NCC with integral images, peak), "
+                      f"{dt:.1f} s on one core"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds for the oracle baseline (0: skip)")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2202_13347_amd import sfoc as S
+    from paper_2202_13347_amd import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU", file=sys.stderr)
+        sys.exit(1)
+    S.lib()
+    pr, ips, m, r = synth.workload(synth.SCENE, args.seed)
+    H, W = pr.ref.shape
+    n = len(ips)
+    p = S.preset("baseline")
+    dev = torch.device("cuda:0")
+    ref = torch.from_numpy(pr.ref).to(dev)
+    sen = torch.from_numpy(pr.sen).to(dev)
+    dips = torch.from_numpy(ips).to(dev)
+    R = S.Registrar(H, W, H, W, n, m, r, p, device=dev)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        R(ref, sen, dips)
+    torch.cuda.synchronize()
+    S.trace_enable(True)
+    S.trace_collect()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        R(ref, sen, dips)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = S.trace_collect()
+    S.trace_enable(False)
+    elapsed = t1 - t0
+    ms_step = 1e3 * elapsed / args.steps
+    cps_s = n * args.steps / elapsed
+
+    g = S.cps_to_numpy(R.cps)
+    err = np.hypot(g["dy"] + g["sub_dy"] - pr.shift[0], g["dx"] + g["sub_dx"] - pr.shift[1])
+    valid = (g["flags"] & S.VALID) != 0
+
+    z = p.z
+    avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kt.items()}   # ms per launch
+    d_ms, m_ms = avg["describe"], avg["match"]
+    px = H * W
+    sfoc_mpix = px / (d_ms * 1e-3) / 1e6 if d_ms > 0 else None
+    flops_px = sfoc_flops_per_px(p)
+    flops_ip = fastncc_flops_per_ip(m + 2 * r, z)
+    per_step = {k: kt[k][0] / args.steps for k in kt}
+    if m_ms * kt["match"][1] >= d_ms * kt["describe"][1]:
+        dom, ach = "match", flops_ip * n / (m_ms * 1e-3)
+    else:
+        dom, ach = "describe", flops_px * px / (d_ms * 1e-3)
+    out = {
+        "metric": "matched CPs/s + SFOC Mpixel/s",
+        "value": cps_s,
+        "unit": "CPs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"scene: one {H}x{W} seeded multimodal pair (speckled sensed image), {n} IPs on a "
+                               f"20x20 grid, template {m}, search +-{r}, N=8 orientations, sigma 1/2/3, float32 "
+                               f"descriptors, float64 integral images",
+                   "image": [H, W], "ips": n, "template": m, "radius": r, "z": z, "fft_side": 128},
+        "sfoc_mpixel_per_s": sfoc_mpix,
+        "sfoc_mpixel_per_s_step": 2 * px * args.steps / elapsed / 1e6,
+        "kernel_ms_per_launch": avg,
+        "kernel_ms_per_step": per_step,
+        "roofline": {"kernel": dom, "bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                     "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU, "traffic": None,
+                     "algorithmic": {"sfoc_flop_per_px": flops_px, "fastncc_flop_per_ip": flops_ip}},
+        "accuracy": {"valid": int(valid.sum()), "correct_1p5px": int((err[valid] <= 1.5).sum()),
+                     "rmse_valid_px": float(np.sqrt(np.mean(err[valid] ** 2))) if valid.any() else None},
+    }
+    if args.cpu_budget > 0:
+        out["cpu_baseline"] = cpu_baseline(pr, ips, m, r, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,235 @@
+/*
+ * sfoc.h -- C ABI of the MI355X (gfx950) SFOC / Fast-NCC_SFOC library.
+ *
+ * Method: Ye et al., "A Robust Multimodal Remote Sensing Image Registration
+ * Method and System Using Steerable Filters with First- and Second-order
+ * Gradients" (arXiv 2202.13347).  The library implements the data-parallel
+ * part of the fine-registration stage (Section 3.2): dense SFOC descriptors
+ * (Section 2.1, Eq. 1-7) and CP detection by template matching with
+ * Fast-NCC_SFOC (Section 2.2, Eq. 8-16; Section 3.2.2).
+ *
+ * Conventions shared by every entry point
+ *  - Images are single-band float32, row-major, origin top-left; x is the
+ *    column, y the row (growing downwards).  `ld` is the row pitch in
+ *    elements (ld >= W).
+ *  - Descriptors are channel-planar: desc[c][y][x], row pitch W, channel
+ *    pitch H*W, c in [0, z).  Channels 0..N-1 are the first-order channels at
+ *    directions k*pi/N, channels N..2N-1 the second-order ones (absent when
+ *    second_order == 0).  Element type: float32, bfloat16 or float16
+ *    (sfoc_params.desc_dtype; bf16/f16 are rounded to nearest even).
+ *  - Integral feature images (Eq. 14-16) are float64, (H+1) x (W+1),
+ *    row-major with pitch W+1, zero first row and column:
+ *    integ1[y][x] = sum over rows < y, columns < x, channels of g;
+ *    integ2 the same for g^2.  They are built from the stored (rounded)
+ *    descriptor values.
+ *  - Every pointer argument except `p`, `bytes` and outputs documented as
+ *    host memory is a DEVICE pointer on the current HIP device.  The caller
+ *    owns all buffers, including the workspace.  No entry point allocates
+ *    or frees device memory.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
+ *    null stream).  The caller synchronises before reading results.
+ *  - Return value: SFOC_OK (0) or a negative SFOC_E_* code.  Argument errors
+ *    are detected on the host before anything is enqueued.  Data-dependent
+ *    conditions (flat windows, windows leaving the image, non-finite values)
+ *    are never call failures: they are reported per CP in sfoc_cp.flags.
+ */
+#ifndef SFOC_H
+#define SFOC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define SFOC_OK              0
+#define SFOC_E_INVALID_ARG  (-1)  /* null pointer, bad size, z != channels, ... */
+#define SFOC_E_UNSUPPORTED  (-2)  /* valid but outside what the kernels support */
+#define SFOC_E_WORKSPACE    (-3)  /* workspace smaller than the *_workspace query */
+#define SFOC_E_HIP          (-4)  /* a HIP launch or runtime call failed */
+
+/* ---- descriptor element types ---------------------------------------- */
+#define SFOC_DTYPE_F32   0
+#define SFOC_DTYPE_BF16  1
+#define SFOC_DTYPE_F16   2
+
+/* ---- rectification of the steered responses -------------------------- */
+#define SFOC_RECTIFY_ABS     0   /* |F| (default; contrast-reversal invariant) */
+#define SFOC_RECTIFY_SIGNED  1
+#define SFOC_RECTIFY_RELU    2
+
+/* ---- per-CP flags ------------------------------------------------------ */
+#define SFOC_CP_VALID         1u    /* usable CP: none of the bits below      */
+#define SFOC_CP_OOB           2u    /* template or search window leaves image */
+#define SFOC_CP_FLAT_T        4u    /* template variance <= tau               */
+#define SFOC_CP_FLAT_S        8u    /* search variance <= tau at every offset */
+#define SFOC_CP_EDGE_PEAK    16u    /* argmax on the border of the surface    */
+#define SFOC_CP_INCONSISTENT 32u    /* > 1.5 px from the median displacement  */
+#define SFOC_CP_LEARNED      64u    /* sub-pixel part from the learned head   */
+#define SFOC_CP_NONFINITE   128u    /* a non-finite value reached the surface */
+
+#define SFOC_MAX_SIGMAS   8
+#define SFOC_MAX_DIL      4
+#define SFOC_MAX_ORIENT  16
+
+/*
+ * SFOC parameters (Section 2.1).
+ *  n_orient      N, directions k*pi/N, k = 0..N-1 (the paper uses 6); 1..16.
+ *  s1[n_s1]      standard deviations of the first-order channels; the
+ *                steered responses are summed over them (Table 2).
+ *  s2[n_s2]      the same for the second-order channels.
+ *  trunc         kernel radius = ceil(trunc * sigma), kernels point sampled.
+ *  sd1, sd2      standard deviation of the (2K+1)^2 Gaussian base of the
+ *                dilated smoothing for first- / second-order channels.
+ *  K             half-size of that base (1 -> 3x3).
+ *  dil[n_dil]    dilation rates; the dilated responses are summed ({1,2,3}).
+ *  eps           added under the root of the per-order L2 normalisation.
+ *  rectify       SFOC_RECTIFY_*.
+ *  second_order  1: SFOC (z = 2N); 0: first-order channels only (z = N).
+ *  desc_dtype    SFOC_DTYPE_* of the stored descriptor.
+ * Limits: radius <= 24 (sigma*trunc), K*max(dil) <= 8, n_dil*... see
+ * sfoc_params_check.
+ */
+typedef struct sfoc_params {
+    int32_t n_orient;
+    int32_t n_s1;
+    double  s1[SFOC_MAX_SIGMAS];
+    int32_t n_s2;
+    int32_t n_dil;
+    double  s2[SFOC_MAX_SIGMAS];
+    double  trunc;
+    double  sd1;
+    double  sd2;
+    double  eps;
+    int32_t K;
+    int32_t dil[SFOC_MAX_DIL];
+    int32_t rectify;
+    int32_t second_order;
+    int32_t desc_dtype;
+} sfoc_params;
+
+/*
+ * One control point (32 bytes).  The reference point matched to the sensed
+ * point (sen_row, sen_col) is
+ *   (sen_row + prior_y + dy + sub_dy, sen_col + prior_x + dx + sub_dx),
+ * dy, dx in [-r, r] the integer argmax of the NCC surface (Section 3.2.2),
+ * sub_* in [-0.5, 0.5] its parabola refinement, score the NCC at the
+ * integer peak.  Records with OOB / FLAT_* / NONFINITE have dy = dx = 0,
+ * sub_* = 0 and score = 0.
+ */
+typedef struct sfoc_cp {
+    int32_t  sen_row, sen_col;
+    int32_t  dy, dx;
+    float    sub_dy, sub_dx;
+    float    score;
+    uint32_t flags;
+} sfoc_cp;
+
+/* Human-readable text of a status code (static storage). */
+const char* sfoc_status_string(int status);
+
+/*
+ * Fill *p with a preset: 0 = the paper's (N = 6; first-order sigma 0.6,
+ * 0.8, 1.0 and second-order sigma 1.5, Section 2.1 and Table 2; rates 1,2,3),
+ * 1 = baseline (N = 8; sigma 1, 2, 3 for both orders).  Both use trunc 3,
+ * K = 1, sd1 = 1.0, sd2 = 1.5, eps = 1e-8, |.| rectification, float32.
+ * Host only.  Returns SFOC_E_INVALID_ARG for an unknown preset or p == NULL.
+ */
+int sfoc_params_preset(int32_t which, sfoc_params* p);
+
+/* Validate parameters; writes the channel count z to *z (may be NULL). */
+int sfoc_params_check(const sfoc_params* p, int32_t* z);
+
+/*
+ * Dense SFOC descriptor of one image (Section 2.1): steered first- and
+ * second-order Gaussian-derivative responses summed over scales, rectified,
+ * smoothed by the dilated Gaussians, normalised per order, stacked.  The
+ * image is extended by reflect-101 and every stage is evaluated on the
+ * extended domain.
+ *  img      H x W float32, pitch ld.                        (input)
+ *  desc     z planes of H x W, element type p->desc_dtype.  (output)
+ *  integ1,  (H+1) x (W+1) float64 integral images of sum_c g and sum_c g^2
+ *  integ2   of the stored values, or both NULL to skip them. (output)
+ *  ws       workspace of at least sfoc_describe_workspace() bytes (may be
+ *           NULL if that is 0).
+ * Errors: SFOC_E_INVALID_ARG (null img/desc/p, H or W < 1, ld < W, only one
+ * of integ1/integ2 NULL, bad params), SFOC_E_WORKSPACE, SFOC_E_HIP.
+ */
+int sfoc_describe_workspace(int64_t H, int64_t W, const sfoc_params* p, size_t* bytes);
+int sfoc_describe(const float* img, int64_t H, int64_t W, int64_t ld,
+                  const sfoc_params* p, void* desc, double* integ1, double* integ2,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Fast-NCC_SFOC CP detection for n interest points of one image pair
+ * (Section 2.2, Eq. 9-16; Section 3.2.2).  For IP i at (row, col) in the
+ * sensed image, the template is the m x m x z window with top-left
+ * (row - m/2, col - m/2) of desc_sen; the search window is the M x M x z
+ * window, M = m + 2r, with top-left (row - m/2 - r + prior_y,
+ * col - m/2 - r + prior_x) of desc_ref.  NCC (Eq. 9, one mean over all
+ * m*m*z entries) is evaluated at all (2r+1)^2 offsets; R_ST by FFT
+ * (Eq. 13), R_S and R_SS by four lookups in the float64 integral images of
+ * desc_ref (Eq. 16), the variance subtraction in float64.  Offsets whose
+ * search variance is <= tau = 1e-12*m*m*z score 0.  The CP is the argmax
+ * (ties: smallest row-major offset index) refined per axis by a three-point
+ * parabola; then a median-displacement consistency check at 1.5 px sets
+ * INCONSISTENT / VALID.
+ *  desc_sen, desc_ref  descriptors (layout above), z channels, element type dtype.
+ *  integ1, integ2      integral images of desc_ref ((Hr+1) x (Wr+1) float64).
+ *  ips                 n x 2 int32 (row, col) in the sensed image.
+ *  prior               n x 2 int32 (dy, dx) search-window offsets, or NULL.
+ *  ncc                 n x (2r+1) x (2r+1) float32 surfaces, or NULL.  (output)
+ *  cps                 n records.                                      (output)
+ * Limits: 3 <= m, 1 <= r, m + 2r <= 256 (SFOC_E_UNSUPPORTED beyond).
+ * n == 0 is valid and enqueues nothing.
+ */
+int sfoc_match_workspace(int32_t n, int32_t m, int32_t r, int32_t z, size_t* bytes);
+int sfoc_fastncc_match(const void* desc_sen, int64_t Hs, int64_t Ws,
+                       const void* desc_ref, int64_t Hr, int64_t Wr,
+                       const double* integ1, const double* integ2,
+                       int32_t z, int32_t dtype,
+                       const int32_t* ips, const int32_t* prior, int32_t n,
+                       int32_t m, int32_t r,
+                       float* ncc, sfoc_cp* cps,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Whole fine-registration hot path for one pair: sfoc_describe of both
+ * images into the workspace, integral images of the reference, then
+ * sfoc_fastncc_match.  Arguments as above; the descriptors and integral
+ * images live inside ws (see sfoc_register_workspace).
+ */
+int sfoc_register_workspace(int64_t Hr, int64_t Wr, int64_t Hs, int64_t Ws,
+                            int32_t n, int32_t m, int32_t r,
+                            const sfoc_params* p, size_t* bytes);
+int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr,
+                      const float* sen, int64_t Hs, int64_t Ws, int64_t lds,
+                      const int32_t* ips, const int32_t* prior, int32_t n,
+                      int32_t m, int32_t r, const sfoc_params* p,
+                      float* ncc, sfoc_cp* cps,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Kernel timing (tracing).  While enabled, the library records a pair of
+ * HIP events on the launch stream around every kernel it enqueues.
+ * sfoc_trace_collect waits for those events, writes per-kernel totals into
+ * ms[k] (milliseconds) and counts[k] for k in [0, n) with the kernel ids
+ * below, clears the record, and returns the number of kernel ids written.
+ * At most SFOC_TRACE_MAX launches are recorded between two collections;
+ * later ones are not timed.  Not thread-safe; host only.
+ */
+#define SFOC_K_DESCRIBE     0
+#define SFOC_K_INTEGRAL     1
+#define SFOC_K_MATCH        2
+#define SFOC_K_CONSISTENCY  3
+#define SFOC_K_COUNT        4
+#define SFOC_TRACE_MAX   4096
+int sfoc_trace_enable(int on);
+int sfoc_trace_collect(double* ms, int64_t* counts, int n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFOC_H */

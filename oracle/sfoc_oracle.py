@@ -171,40 +171,43 @@ def dilated_weights(sd: float, K: int) -> np.ndarray:
 
 
 # -------------------------------------------------------------- SFOC -------
-def sfoc_unnormalised(img: np.ndarray, p: Params):
-    """Steered, scale-summed, rectified channels on the domain extended by
-    Q = K * max(dil) around the image.  Returns (A, Q), A: (z, H+2Q, W+2Q)."""
-    img = np.asarray(img, dtype=np.float64)
-    H, W = img.shape
-    rmax = max(p.dil)
-    Q = p.K * rmax
+def halo(p: Params) -> int:
+    """Reach of one output pixel into the input: largest radius + K*max(dil)."""
     sig_all = list(p.s1) + (list(p.s2) if p.second_order else [])
-    P = max(radius(s, p.trunc) for s in sig_all) + Q
-    E = extend(img, P)
+    return max(radius(s, p.trunc) for s in sig_all) + p.K * max(p.dil)
+
+
+def steered_valid(crop: np.ndarray, p: Params):
+    """Steered (Eq. 4/6, 7), scale-summed, rectified channels of `crop`,
+    evaluated where the whole support lies inside it.  For a crop carrying a
+    halo of P = halo(p) around an H x W region, returns (A, Q) with
+    A: (z, H+2Q, W+2Q) on the region grown by Q = K*max(dil)."""
+    crop = np.asarray(crop, dtype=np.float64)
+    P = halo(p)
+    Q = p.K * max(p.dil)
+    H, W = crop.shape[0] - 2 * P, crop.shape[1] - 2 * P
     thetas = orientations(p.n_orient)
-    A = []
 
     def region(R):
         o = P - Q - R
-        return E[o:o + H + 2 * Q + 2 * R, o:o + W + 2 * Q + 2 * R]
+        return crop[o:o + H + 2 * Q + 2 * R, o:o + W + 2 * Q + 2 * R]
 
+    A = []
     F1 = [np.zeros((H + 2 * Q, W + 2 * Q)) for _ in thetas]
-    for s in p.s1:
+    for s in p.s1:                                   # one scale at a time
         k = basis_kernels(s, p.trunc)
         Ereg = region(k["R"])
         bx, by = conv2d_valid(Ereg, k["gx"]), conv2d_valid(Ereg, k["gy"])   # Eq. 6
         for i, th in enumerate(thetas):
             (c, sn), _ = steer_weights(th)
-            F1[i] += c * bx + sn * by
+            F1[i] += c * bx + sn * by                # summed over scales
     A.extend(F1)
     if p.second_order:
         F2 = [np.zeros((H + 2 * Q, W + 2 * Q)) for _ in thetas]
         for s in p.s2:
             k = basis_kernels(s, p.trunc)
             Ereg = region(k["R"])
-            bxx = conv2d_valid(Ereg, k["gxx"])                                # Eq. 7
-            byy = conv2d_valid(Ereg, k["gyy"])
-            bxy = conv2d_valid(Ereg, k["gxy"])
+            bxx, byy, bxy = (conv2d_valid(Ereg, k[n]) for n in ("gxx", "gyy", "gxy"))  # Eq. 7
             for i, th in enumerate(thetas):
                 _, (cc, ss, sc2) = steer_weights(th)
                 F2[i] += cc * bxx + ss * byy + sc2 * bxy
@@ -219,10 +222,15 @@ def sfoc_unnormalised(img: np.ndarray, p: Params):
     return A, Q
 
 
+def sfoc_unnormalised(img: np.ndarray, p: Params):
+    """steered_valid over the reflect-101 extended image: (A, Q)."""
+    return steered_valid(extend(np.asarray(img, dtype=np.float64), halo(p)), p)
+
+
 def dilated_smooth(A: np.ndarray, Q: int, H: int, W: int, sd: float, K: int, dil) -> np.ndarray:
     """Sum over rates r of the (2K+1)^2 Gaussian with holes at r (Section 2.1,
-    Fig. 3), evaluated at the H x W image positions of a map given on the
-    domain extended by Q."""
+    Fig. 3), evaluated at the H x W positions of a map given on the domain
+    extended by Q."""
     w = dilated_weights(sd, K)
     out = np.zeros((H, W))
     for r in dil:
@@ -232,21 +240,40 @@ def dilated_smooth(A: np.ndarray, Q: int, H: int, W: int, sd: float, K: int, dil
     return out
 
 
-def sfoc(img: np.ndarray, p: Params | None = None) -> np.ndarray:
-    """Dense SFOC descriptor, (H, W, z) float64, channels [first-order k=0..N-1,
-    second-order k=0..N-1]."""
-    p = p or Params()
-    img = np.asarray(img, dtype=np.float64)
-    H, W = img.shape
-    A, Q = sfoc_unnormalised(img, p)
+def sfoc_valid(crop: np.ndarray, p: Params) -> np.ndarray:
+    """All SFOC stages on a crop that carries a halo of P = halo(p): the
+    (H, W, z) descriptor of its centre, channels [first-order k = 0..N-1,
+    second-order k = 0..N-1]."""
+    A, Q = steered_valid(crop, p)
+    H, W = A.shape[1] - 2 * Q, A.shape[2] - 2 * Q
     N = p.n_orient
     D = np.stack([dilated_smooth(A[c], Q, H, W, p.sd1 if c < N else p.sd2, p.K, p.dil)
                   for c in range(A.shape[0])])
     out = np.empty_like(D)
     for lo in range(0, D.shape[0], N):
         blk = D[lo:lo + N]
-        out[lo:lo + N] = blk / np.sqrt((blk * blk).sum(axis=0) + p.eps)   # Section 2.1
+        out[lo:lo + N] = blk / np.sqrt((blk * blk).sum(axis=0) + p.eps)   # per order
     return np.ascontiguousarray(out.transpose(1, 2, 0))
+
+
+def sfoc(img: np.ndarray, p: Params | None = None) -> np.ndarray:
+    """Dense SFOC descriptor (H, W, z) float64 of an image: every stage is
+    evaluated on the reflect-101 extended image, then cropped."""
+    p = p or Params()
+    return sfoc_valid(extend(np.asarray(img, dtype=np.float64), halo(p)), p)
+
+
+def sfoc_region(img: np.ndarray, y0: int, x0: int, h: int, w: int, p: Params | None = None) -> np.ndarray:
+    """Rows y0..y0+h-1, columns x0..x0+w-1 of sfoc(img), from a crop of the
+    extended image (each output pixel sees exactly the values the dense
+    evaluation sees).  (h, w, z)."""
+    p = p or Params()
+    P = halo(p)
+    img = np.asarray(img, dtype=np.float64)
+    H, W = img.shape
+    ry = reflect101_index(np.arange(y0 - P, y0 + h + P), H)
+    rx = reflect101_index(np.arange(x0 - P, x0 + w + P), W)
+    return sfoc_valid(img[np.ix_(ry, rx)], p)
 
 
 # -------------------------------------------------------- rounding ---------
@@ -426,6 +453,20 @@ def consistency(cps: np.ndarray, priors=None) -> np.ndarray:
     return cps
 
 
+def decide(ncc: np.ndarray, flatT: bool, nonfinite: bool, r: int):
+    """Per-CP decision from one NCC surface (Section 3.2.2: the most similar
+    position is the CP): (dy, dx, sub_dy, sub_dx, score, flags), before the
+    consistency check."""
+    if nonfinite:
+        return 0, 0, 0.0, 0.0, 0.0, NONFINITE
+    if flatT:
+        return 0, 0, 0.0, 0.0, 0.0, FLAT_T
+    if not np.any(ncc != 0.0):
+        return 0, 0, 0.0, 0.0, 0.0, FLAT_S
+    u, v, sc, su, sv, edge = peak(ncc)
+    return u - r, v - r, su, sv, sc, (EDGE_PEAK if edge else 0)
+
+
 def match(Fs: np.ndarray, Fr: np.ndarray, ips, m: int, r: int, prior=None,
           method: str = "fast", integ=None, want_surfaces: bool = False):
     """CP detection by template matching (Section 3.2.2): template around each
@@ -454,31 +495,32 @@ def match(Fs: np.ndarray, Fr: np.ndarray, ips, m: int, r: int, prior=None,
         T = Fs[ty:ty + m, tx:tx + m, :]
         S = Fr[sy:sy + M, sx:sx + M, :]
         if method == "brute":
-            if not (np.all(np.isfinite(T)) and np.all(np.isfinite(S))):
-                cps["flags"][i] = NONFINITE
-                continue
-            ncc, flatT = ncc_bruteforce(S, T)
-            nonfin = False
+            nonfin = not (np.all(np.isfinite(T)) and np.all(np.isfinite(S)))
+            ncc, flatT = (np.zeros((V, V)), False) if nonfin else ncc_bruteforce(S, T)
         else:
             ncc, flatT, nonfin = ncc_fast(S, T, integ[0], integ[1], (sy, sx))
         surfaces[i] = ncc
-        if nonfin:
-            cps["flags"][i] = NONFINITE
-            continue
-        if flatT:
-            cps["flags"][i] = FLAT_T
-            continue
-        if not np.any(ncc != 0.0):
-            cps["flags"][i] = FLAT_S
-            continue
-        u, v, sc, su, sv, edge = peak(ncc)
-        cps["dy"][i], cps["dx"][i] = u - r, v - r
-        cps["sub_dy"][i], cps["sub_dx"][i] = su, sv
-        cps["score"][i] = sc
-        if edge:
-            cps["flags"][i] = EDGE_PEAK
+        (cps["dy"][i], cps["dx"][i], cps["sub_dy"][i], cps["sub_dx"][i],
+         cps["score"][i], cps["flags"][i]) = decide(ncc, flatT, nonfin, r)
     consistency(cps, prior)
     return (cps, surfaces) if want_surfaces else cps
+
+
+def match_one_region(ref: np.ndarray, sen: np.ndarray, ip, m: int, r: int, p: Params | None = None,
+                     prior=None):
+    """One CP of register_cps (before the consistency check) computed from
+    crops only: SFOC of the template and search windows by sfoc_region, NCC
+    by Eq. 9-16 with integral images built over the search window.  Returns
+    (record, surface) with record = (dy, dx, sub_dy, sub_dx, score, flags)."""
+    p = p or Params()
+    (ty, tx), (sy, sx) = window_origins(ip, prior, m, r)
+    M = m + 2 * r
+    if not (in_bounds(ty, tx, m, m, *sen.shape) and in_bounds(sy, sx, M, M, *ref.shape)):
+        return (0, 0, 0.0, 0.0, 0.0, OOB), np.zeros((2 * r + 1, 2 * r + 1))
+    T = sfoc_region(sen, ty, tx, m, m, p)
+    S = sfoc_region(ref, sy, sx, M, M, p)
+    ncc, flatT, nonfin = ncc_fast(S, T)
+    return decide(ncc, flatT, nonfin, r), ncc
 
 
 def register_cps(ref: np.ndarray, sen: np.ndarray, ips, m: int, r: int,

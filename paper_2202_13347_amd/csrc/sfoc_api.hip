@@ -1,0 +1,212 @@
+// extern "C" entry points: argument checks on the host, then launches on
+// the caller's stream.  Nothing here allocates device memory.
+#include <hip/hip_runtime.h>
+
+#include "sfoc_plan.h"
+
+namespace sfoc {
+hipError_t launch_describe(const float* img, int H, int W, int64_t ld, void* desc, double* i1, double* i2,
+                           const DescribeConsts& c, hipStream_t st);
+hipError_t launch_integral(double* i1, double* i2, int H, int W, double* ws, hipStream_t st);
+hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void* desc_ref, int64_t Hr, int64_t Wr,
+                        const double* i1, const double* i2, int z, int dtype, const int32_t* ips,
+                        const int32_t* prior, int n, int m, int r, float* ncc, sfoc_cp* cps, hipStream_t st);
+
+static thread_local hipError_t g_last_hip = hipSuccess;
+
+static int hip_status(hipError_t e) {
+    if (e == hipSuccess) return SFOC_OK;
+    g_last_hip = e;
+    return SFOC_E_HIP;
+}
+
+// Image sides are limited so that every per-image index fits in int32 and
+// every plane offset in int64.
+constexpr int64_t kMaxSide = 1 << 16;
+
+static int check_image(const void* img, int64_t H, int64_t W, int64_t ld) {
+    if (!img) return SFOC_E_INVALID_ARG;
+    if (H < 1 || W < 1 || ld < W) return SFOC_E_INVALID_ARG;
+    if (H > kMaxSide || W > kMaxSide) return SFOC_E_UNSUPPORTED;
+    return SFOC_OK;
+}
+
+static int check_match_shape(int32_t n, int32_t m, int32_t r) {
+    if (n < 0 || m < 3 || r < 1) return SFOC_E_INVALID_ARG;
+    if (fft_size_for(m + 2 * r) == 0) return SFOC_E_UNSUPPORTED;
+    return SFOC_OK;
+}
+
+struct RegisterLayout {
+    size_t desc_ref, desc_sen, integ1, integ2, scan, total;
+};
+
+static RegisterLayout register_layout(int64_t Hr, int64_t Wr, int64_t Hs, int64_t Ws, int32_t z, size_t es) {
+    RegisterLayout L;
+    size_t off = 0;
+    L.desc_ref = off;
+    off = align_up(off + (size_t)z * Hr * Wr * es, 256);
+    L.desc_sen = off;
+    off = align_up(off + (size_t)z * Hs * Ws * es, 256);
+    L.integ1 = off;
+    off = align_up(off + (size_t)(Hr + 1) * (Wr + 1) * sizeof(double), 256);
+    L.integ2 = off;
+    off = align_up(off + (size_t)(Hr + 1) * (Wr + 1) * sizeof(double), 256);
+    L.scan = off;
+    off = align_up(off + describe_ws_bytes(Hr, Wr), 256);
+    L.total = off;
+    return L;
+}
+
+}  // namespace sfoc
+
+using namespace sfoc;
+
+extern "C" {
+
+const char* sfoc_status_string(int status) {
+    switch (status) {
+        case SFOC_OK: return "SFOC_OK";
+        case SFOC_E_INVALID_ARG: return "SFOC_E_INVALID_ARG: invalid argument";
+        case SFOC_E_UNSUPPORTED: return "SFOC_E_UNSUPPORTED: outside the supported sizes or parameters";
+        case SFOC_E_WORKSPACE: return "SFOC_E_WORKSPACE: workspace too small";
+        case SFOC_E_HIP: return g_last_hip == hipSuccess ? "SFOC_E_HIP" : hipGetErrorString(g_last_hip);
+        default: return "unknown status";
+    }
+}
+
+int sfoc_params_preset(int32_t which, sfoc_params* p) {
+    if (!p || (which != 0 && which != 1)) return SFOC_E_INVALID_ARG;
+    sfoc_params q = {};
+    q.trunc = 3.0;
+    q.K = 1;
+    q.n_dil = 3;
+    q.dil[0] = 1;
+    q.dil[1] = 2;
+    q.dil[2] = 3;
+    q.sd1 = 1.0;
+    q.sd2 = 1.5;
+    q.eps = 1e-8;
+    q.rectify = SFOC_RECTIFY_ABS;
+    q.second_order = 1;
+    q.desc_dtype = SFOC_DTYPE_F32;
+    if (which == 0) {
+        q.n_orient = 6;
+        q.n_s1 = 3;
+        q.s1[0] = 0.6;
+        q.s1[1] = 0.8;
+        q.s1[2] = 1.0;
+        q.n_s2 = 1;
+        q.s2[0] = 1.5;
+    } else {
+        q.n_orient = 8;
+        q.n_s1 = 3;
+        q.n_s2 = 3;
+        for (int i = 0; i < 3; ++i) q.s1[i] = q.s2[i] = (double)(i + 1);
+    }
+    *p = q;
+    return SFOC_OK;
+}
+
+int sfoc_params_check(const sfoc_params* p, int32_t* z) { return check_params(p, z); }
+
+int sfoc_describe_workspace(int64_t H, int64_t W, const sfoc_params* p, size_t* bytes) {
+    if (!bytes || H < 1 || W < 1) return SFOC_E_INVALID_ARG;
+    int rc = check_params(p, nullptr);
+    if (rc) return rc;
+    *bytes = describe_ws_bytes(H, W);
+    return SFOC_OK;
+}
+
+int sfoc_describe(const float* img, int64_t H, int64_t W, int64_t ld, const sfoc_params* p, void* desc,
+                  double* integ1, double* integ2, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_image(img, H, W, ld);
+    if (rc) return rc;
+    if (!desc || ((integ1 == nullptr) != (integ2 == nullptr))) return SFOC_E_INVALID_ARG;
+    rc = check_params(p, nullptr);
+    if (rc) return rc;
+    if (integ1 && (!ws || ws_bytes < describe_ws_bytes(H, W))) return SFOC_E_WORKSPACE;
+    DescribeConsts c;
+    build_describe_consts(p, &c);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = launch_describe(img, (int)H, (int)W, ld, desc, integ1, integ2, c, st);
+    if (e != hipSuccess) return hip_status(e);
+    if (integ1) {
+        e = launch_integral(integ1, integ2, (int)H, (int)W, (double*)ws, st);
+        if (e != hipSuccess) return hip_status(e);
+    }
+    return SFOC_OK;
+}
+
+int sfoc_match_workspace(int32_t n, int32_t m, int32_t r, int32_t z, size_t* bytes) {
+    if (!bytes || z < 1) return SFOC_E_INVALID_ARG;
+    int rc = check_match_shape(n, m, r);
+    if (rc) return rc;
+    *bytes = 0;
+    return SFOC_OK;
+}
+
+int sfoc_fastncc_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void* desc_ref, int64_t Hr, int64_t Wr,
+                       const double* integ1, const double* integ2, int32_t z, int32_t dtype, const int32_t* ips,
+                       const int32_t* prior, int32_t n, int32_t m, int32_t r, float* ncc, sfoc_cp* cps, void* ws,
+                       size_t ws_bytes, void* stream) {
+    (void)ws;
+    (void)ws_bytes;
+    int rc = check_match_shape(n, m, r);
+    if (rc) return rc;
+    if (z < 1 || dtype_size(dtype) == 0) return SFOC_E_INVALID_ARG;
+    if (Hs < 1 || Ws < 1 || Hr < 1 || Wr < 1) return SFOC_E_INVALID_ARG;
+    if (Hs > kMaxSide || Ws > kMaxSide || Hr > kMaxSide || Wr > kMaxSide) return SFOC_E_UNSUPPORTED;
+    if (n == 0) return SFOC_OK;
+    if (!desc_sen || !desc_ref || !integ1 || !integ2 || !ips || !cps) return SFOC_E_INVALID_ARG;
+    hipError_t e = launch_match(desc_sen, Hs, Ws, desc_ref, Hr, Wr, integ1, integ2, z, dtype, ips, prior, n, m, r,
+                                ncc, cps, (hipStream_t)stream);
+    return hip_status(e);
+}
+
+int sfoc_register_workspace(int64_t Hr, int64_t Wr, int64_t Hs, int64_t Ws, int32_t n, int32_t m, int32_t r,
+                            const sfoc_params* p, size_t* bytes) {
+    if (!bytes || Hr < 1 || Wr < 1 || Hs < 1 || Ws < 1) return SFOC_E_INVALID_ARG;
+    int32_t z = 0;
+    int rc = check_params(p, &z);
+    if (rc) return rc;
+    rc = check_match_shape(n, m, r);
+    if (rc) return rc;
+    *bytes = register_layout(Hr, Wr, Hs, Ws, z, dtype_size(p->desc_dtype)).total;
+    return SFOC_OK;
+}
+
+int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr, const float* sen, int64_t Hs,
+                      int64_t Ws, int64_t lds, const int32_t* ips, const int32_t* prior, int32_t n, int32_t m,
+                      int32_t r, const sfoc_params* p, float* ncc, sfoc_cp* cps, void* ws, size_t ws_bytes,
+                      void* stream) {
+    int rc = check_image(ref, Hr, Wr, ldr);
+    if (rc) return rc;
+    rc = check_image(sen, Hs, Ws, lds);
+    if (rc) return rc;
+    int32_t z = 0;
+    rc = check_params(p, &z);
+    if (rc) return rc;
+    rc = check_match_shape(n, m, r);
+    if (rc) return rc;
+    if (n > 0 && (!ips || !cps)) return SFOC_E_INVALID_ARG;
+    const RegisterLayout L = register_layout(Hr, Wr, Hs, Ws, z, dtype_size(p->desc_dtype));
+    if (!ws || ws_bytes < L.total) return SFOC_E_WORKSPACE;
+    char* base = (char*)ws;
+    void* dref = base + L.desc_ref;
+    void* dsen = base + L.desc_sen;
+    double* i1 = (double*)(base + L.integ1);
+    double* i2 = (double*)(base + L.integ2);
+    hipStream_t st = (hipStream_t)stream;
+    DescribeConsts c;
+    build_describe_consts(p, &c);
+    hipError_t e = launch_describe(ref, (int)Hr, (int)Wr, ldr, dref, i1, i2, c, st);
+    if (e == hipSuccess) e = launch_integral(i1, i2, (int)Hr, (int)Wr, (double*)(base + L.scan), st);
+    if (e == hipSuccess) e = launch_describe(sen, (int)Hs, (int)Ws, lds, dsen, nullptr, nullptr, c, st);
+    if (e != hipSuccess) return hip_status(e);
+    if (n == 0) return SFOC_OK;
+    e = launch_match(dsen, Hs, Ws, dref, Hr, Wr, i1, i2, z, p->desc_dtype, ips, prior, n, m, r, ncc, cps, st);
+    return hip_status(e);
+}
+
+}  // extern "C"

@@ -1,0 +1,162 @@
+// Host-side parameter checks, constant synthesis and workspace sizing.
+#include "sfoc_plan.h"
+
+#include <math.h>
+#include <string.h>
+
+namespace sfoc {
+
+static int radius_of(double s, double trunc) { return (int)ceil(trunc * s - 1e-9); }
+
+size_t dtype_size(int32_t dtype) {
+    switch (dtype) {
+        case SFOC_DTYPE_F32: return 4;
+        case SFOC_DTYPE_BF16: return 2;
+        case SFOC_DTYPE_F16: return 2;
+        default: return 0;
+    }
+}
+
+static bool supported_z(int z) {
+    switch (z) {
+        case 2: case 3: case 4: case 6: case 8: case 12: case 16: case 24: case 32: return true;
+        default: return false;
+    }
+}
+
+int check_params(const sfoc_params* p, int32_t* zout) {
+    if (!p) return SFOC_E_INVALID_ARG;
+    if (p->n_orient < 1 || p->n_orient > SFOC_MAX_ORIENT) return SFOC_E_INVALID_ARG;
+    if (p->n_s1 < 1 || p->n_s1 > SFOC_MAX_SIGMAS) return SFOC_E_INVALID_ARG;
+    if (p->second_order != 0 && p->second_order != 1) return SFOC_E_INVALID_ARG;
+    if (p->second_order && (p->n_s2 < 1 || p->n_s2 > SFOC_MAX_SIGMAS)) return SFOC_E_INVALID_ARG;
+    if (!(p->trunc > 0.0) || !isfinite(p->trunc)) return SFOC_E_INVALID_ARG;
+    if (!(p->sd1 > 0.0) || !(p->sd2 > 0.0) || !isfinite(p->sd1) || !isfinite(p->sd2)) return SFOC_E_INVALID_ARG;
+    if (!(p->eps >= 0.0) || !isfinite(p->eps)) return SFOC_E_INVALID_ARG;
+    if (p->K < 0 || p->n_dil < 1 || p->n_dil > SFOC_MAX_DIL) return SFOC_E_INVALID_ARG;
+    if (p->rectify < 0 || p->rectify > 2) return SFOC_E_INVALID_ARG;
+    if (dtype_size(p->desc_dtype) == 0) return SFOC_E_INVALID_ARG;
+    int rmax = 0;
+    for (int i = 0; i < p->n_dil; ++i) {
+        if (p->dil[i] < 1) return SFOC_E_INVALID_ARG;
+        if (p->dil[i] > rmax) rmax = p->dil[i];
+    }
+    const int nl = p->second_order ? 2 : 1;
+    for (int l = 0; l < nl; ++l) {
+        const int n = l ? p->n_s2 : p->n_s1;
+        const double* s = l ? p->s2 : p->s1;
+        for (int i = 0; i < n; ++i) {
+            if (!(s[i] > 0.0) || !isfinite(s[i])) return SFOC_E_INVALID_ARG;
+            if (radius_of(s[i], p->trunc) > kMaxRadius) return SFOC_E_UNSUPPORTED;
+        }
+    }
+    if (p->K > 2 || p->K * rmax > kMaxQ) return SFOC_E_UNSUPPORTED;
+    const int z = p->n_orient * (p->second_order ? 2 : 1);
+    if (!supported_z(z)) return SFOC_E_UNSUPPORTED;
+    // Tap storage.
+    DescribeConsts tmp;
+    int rc = build_describe_consts(p, &tmp);
+    if (rc != SFOC_OK) return rc;
+    if (zout) *zout = z;
+    return SFOC_OK;
+}
+
+int build_describe_consts(const sfoc_params* p, DescribeConsts* c) {
+    memset(c, 0, sizeof(*c));
+    // Distinct sigmas over both order lists (a sigma used by both shares its
+    // row pass).
+    double sig[kMaxSig];
+    int nsig = 0;
+    const int nl = p->second_order ? 2 : 1;
+    for (int l = 0; l < nl; ++l) {
+        const int n = l ? p->n_s2 : p->n_s1;
+        const double* s = l ? p->s2 : p->s1;
+        for (int i = 0; i < n; ++i) {
+            int j = 0;
+            for (; j < nsig; ++j)
+                if (sig[j] == s[i]) break;
+            if (j == nsig) {
+                sig[nsig] = s[i];
+                c->use[nsig] = 0;
+                ++nsig;
+            }
+            c->use[j] |= (1 << l);
+        }
+    }
+    c->nsig = nsig;
+    int off = 0, R = 0;
+    for (int j = 0; j < nsig; ++j) {
+        const double s = sig[j];
+        const int r = radius_of(s, p->trunc);
+        if (off + 3 * (r + 1) > kMaxHalfTaps) return SFOC_E_UNSUPPORTED;
+        c->rad[j] = r;
+        c->off[j] = off;
+        c->cnorm[j] = (float)(1.0 / (2.0 * M_PI * s * s));
+        // 1-D factors of Eq. 2, 3, 5: G = cnorm * e(x) e(y),
+        // dG/dx = cnorm * (-x/s^2) e(x) e(y), d2G/dx2 = cnorm * (x^2/s^4 - 1/s^2) e(x) e(y).
+        for (int k = 0; k <= r; ++k) {
+            const double e = exp(-(double)k * k / (2.0 * s * s));
+            c->taps[off + k] = (float)e;
+            c->taps[off + (r + 1) + k] = (float)(-(double)k / (s * s) * e);
+            c->taps[off + 2 * (r + 1) + k] = (float)(((double)k * k / (s * s * s * s) - 1.0 / (s * s)) * e);
+        }
+        off += 3 * (r + 1);
+        if (r > R) R = r;
+    }
+    c->N = p->n_orient;
+    c->second = p->second_order;
+    c->z = p->n_orient * (p->second_order ? 2 : 1);
+    int rmax = 0;
+    for (int i = 0; i < p->n_dil; ++i) rmax = p->dil[i] > rmax ? p->dil[i] : rmax;
+    c->K = p->K;
+    c->Q = p->K * rmax;
+    c->R = R;
+    c->ndil = p->n_dil;
+    for (int i = 0; i < p->n_dil; ++i) c->dil[i] = p->dil[i];
+    for (int k = 0; k < p->n_orient; ++k) {
+        const double th = k * M_PI / p->n_orient;   // Section 2.1: directions k*pi/N
+        const double cs = cos(th), sn = sin(th);
+        c->c1[k] = (float)cs;
+        c->s1[k] = (float)sn;
+        c->cc[k] = (float)(cs * cs);
+        c->ss[k] = (float)(sn * sn);
+        c->sc2[k] = (float)(2.0 * sn * cs);
+    }
+    for (int l = 0; l < 2; ++l) {
+        const double sd = l ? p->sd2 : p->sd1;
+        double w[5], sum = 0.0;
+        for (int i = -p->K; i <= p->K; ++i) {
+            w[i + p->K] = exp(-(double)i * i / (2.0 * sd * sd));
+            sum += w[i + p->K];
+        }
+        const int B = 2 * p->K + 1;
+        for (int i = 0; i < B; ++i)
+            for (int j = 0; j < B; ++j) {
+                const float v = (float)((w[i] / sum) * (w[j] / sum));
+                (l ? c->w2 : c->w1)[i * B + j] = v;
+            }
+    }
+    c->eps = (float)p->eps;
+    c->rectify = p->rectify;
+    c->dtype = p->desc_dtype;
+    return SFOC_OK;
+}
+
+size_t describe_ws_bytes(int64_t H, int64_t W) {
+    const int64_t nb = (H + kScanRows - 1) / kScanRows;
+    return align_up((size_t)(nb * (W + 1)) * sizeof(double) * 2, 256);
+}
+
+int fft_size_for(int32_t M) {
+    if (M <= 64) return 64;
+    if (M <= 128) return 128;
+    return 0;
+}
+
+size_t match_ws_bytes(int32_t n, int32_t m, int32_t r, int32_t z) {
+    (void)m; (void)r; (void)z;
+    // Displacement keys for the consistency median: 2 floats per CP.
+    return align_up((size_t)n * 2 * sizeof(float), 256) + 256;
+}
+
+}  // namespace sfoc

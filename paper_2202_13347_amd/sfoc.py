@@ -1,0 +1,264 @@
+"""Thin Python binding of libsfoc.so (ctypes).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch supplies device memory and the current HIP stream.
+If the library has not been built, every call raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsfoc.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "sfoc.h")
+
+SFOC_OK, SFOC_E_INVALID_ARG, SFOC_E_UNSUPPORTED, SFOC_E_WORKSPACE, SFOC_E_HIP = 0, -1, -2, -3, -4
+DTYPE_F32, DTYPE_BF16, DTYPE_F16 = 0, 1, 2
+VALID, OOB, FLAT_T, FLAT_S, EDGE_PEAK, INCONSISTENT, LEARNED, NONFINITE = 1, 2, 4, 8, 16, 32, 64, 128
+
+
+class SfocError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n_orient", ctypes.c_int32), ("n_s1", ctypes.c_int32), ("s1", ctypes.c_double * 8),
+                ("n_s2", ctypes.c_int32), ("n_dil", ctypes.c_int32), ("s2", ctypes.c_double * 8),
+                ("trunc", ctypes.c_double), ("sd1", ctypes.c_double), ("sd2", ctypes.c_double),
+                ("eps", ctypes.c_double), ("K", ctypes.c_int32), ("dil", ctypes.c_int32 * 4),
+                ("rectify", ctypes.c_int32), ("second_order", ctypes.c_int32), ("desc_dtype", ctypes.c_int32)]
+
+    @property
+    def z(self) -> int:
+        return self.n_orient * (2 if self.second_order else 1)
+
+    def copy(self) -> "Params":
+        q = Params()
+        ctypes.pointer(q)[0] = self
+        return q
+
+
+CP_DTYPE = np.dtype([("sen_row", np.int32), ("sen_col", np.int32), ("dy", np.int32), ("dx", np.int32),
+                     ("sub_dy", np.float32), ("sub_dx", np.float32), ("score", np.float32),
+                     ("flags", np.uint32)])
+assert CP_DTYPE.itemsize == 32
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2202_13347_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+        P = ctypes.POINTER(Params)
+        L.sfoc_status_string.restype = ctypes.c_char_p
+        L.sfoc_status_string.argtypes = [ctypes.c_int]
+        L.sfoc_params_preset.argtypes = [i32, P]
+        L.sfoc_params_check.argtypes = [P, ctypes.POINTER(i32)]
+        L.sfoc_describe_workspace.argtypes = [i64, i64, P, ctypes.POINTER(sz)]
+        L.sfoc_describe.argtypes = [vp, i64, i64, i64, P, vp, vp, vp, vp, sz, vp]
+        L.sfoc_match_workspace.argtypes = [i32, i32, i32, i32, ctypes.POINTER(sz)]
+        L.sfoc_fastncc_match.argtypes = [vp, i64, i64, vp, i64, i64, vp, vp, i32, i32, vp, vp, i32, i32, i32,
+                                         vp, vp, vp, sz, vp]
+        L.sfoc_register_workspace.argtypes = [i64, i64, i64, i64, i32, i32, i32, P, ctypes.POINTER(sz)]
+        L.sfoc_register_cps.argtypes = [vp, i64, i64, i64, vp, i64, i64, i64, vp, vp, i32, i32, i32, P,
+                                        vp, vp, vp, sz, vp]
+        L.sfoc_trace_enable.argtypes = [ctypes.c_int]
+        L.sfoc_trace_collect.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.c_int]
+        for name in ("sfoc_trace_enable", "sfoc_trace_collect", "sfoc_params_preset", "sfoc_params_check", "sfoc_describe_workspace", "sfoc_describe",
+                     "sfoc_match_workspace", "sfoc_fastncc_match", "sfoc_register_workspace",
+                     "sfoc_register_cps"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list[str]:
+    """Names of the functions include/sfoc.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(sfoc_[a-z0-9_]+)\s*\(", txt)))
+
+
+def status_string(s: int) -> str:
+    return lib().sfoc_status_string(int(s)).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != SFOC_OK:
+        raise SfocError(rc, what)
+
+
+def preset(which: str | int = "baseline", dtype: int = DTYPE_F32) -> Params:
+    """'paper' (N=6; sigma 0.6/0.8/1.0 and 1.5) or 'baseline' (N=8; 1/2/3)."""
+    w = {"paper": 0, "baseline": 1}.get(which, which)
+    p = Params()
+    _check(lib().sfoc_params_preset(int(w), ctypes.byref(p)), "sfoc_params_preset")
+    p.desc_dtype = dtype
+    return p
+
+
+def params(n_orient=8, s1=(1.0, 2.0, 3.0), s2=(1.0, 2.0, 3.0), trunc=3.0, sd1=1.0, sd2=1.5, K=1,
+           dil=(1, 2, 3), eps=1e-8, rectify=0, second_order=True, dtype=DTYPE_F32) -> Params:
+    p = Params()
+    p.n_orient = n_orient
+    p.n_s1 = len(s1)
+    for i, v in enumerate(s1):
+        p.s1[i] = v
+    p.n_s2 = len(s2)
+    for i, v in enumerate(s2):
+        p.s2[i] = v
+    p.trunc, p.sd1, p.sd2, p.eps, p.K = trunc, sd1, sd2, eps, K
+    p.n_dil = len(dil)
+    for i, v in enumerate(dil):
+        p.dil[i] = v
+    p.rectify = {"abs": 0, "signed": 1, "relu": 2}.get(rectify, rectify)
+    p.second_order = int(bool(second_order))
+    p.desc_dtype = dtype
+    return p
+
+
+def check_params(p: Params) -> int:
+    z = ctypes.c_int32(0)
+    _check(lib().sfoc_params_check(ctypes.byref(p), ctypes.byref(z)), "sfoc_params_check")
+    return z.value
+
+
+# ---------------------------------------------------------------- device --
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _desc_torch_dtype(dt: int):
+    torch = _torch()
+    return {DTYPE_F32: torch.float32, DTYPE_BF16: torch.bfloat16, DTYPE_F16: torch.float16}[dt]
+
+
+def describe_workspace(H: int, W: int, p: Params) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().sfoc_describe_workspace(H, W, ctypes.byref(p), ctypes.byref(b)), "sfoc_describe_workspace")
+    return b.value
+
+
+def describe(img, p: Params, integrals: bool = True, stream=None, out=None):
+    """SFOC of one float32 (H, W) CUDA image.  Returns (desc (z, H, W),
+    integ1, integ2) (the integral images are None if not requested)."""
+    torch = _torch()
+    assert img.is_cuda and img.dtype == torch.float32 and img.dim() == 2 and img.stride(1) == 1
+    H, W = img.shape
+    z = check_params(p)
+    desc = out if out is not None else torch.empty((z, H, W), dtype=_desc_torch_dtype(p.desc_dtype),
+                                                   device=img.device)
+    i1 = i2 = ws = None
+    wsb = 0
+    if integrals:
+        i1 = torch.empty((H + 1, W + 1), dtype=torch.float64, device=img.device)
+        i2 = torch.empty_like(i1)
+        wsb = describe_workspace(H, W, p)
+        ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=img.device)
+    rc = lib().sfoc_describe(_ptr(img), H, W, img.stride(0), ctypes.byref(p), _ptr(desc), _ptr(i1), _ptr(i2),
+                             _ptr(ws), wsb, _stream(stream))
+    _check(rc, "sfoc_describe")
+    return desc, i1, i2
+
+
+def fastncc_match(desc_sen, desc_ref, integ1, integ2, ips, m: int, r: int, prior=None, want_ncc=False,
+                  stream=None):
+    """CPs (an (n, 8) int32 CUDA tensor of 32-byte records) and optionally
+    the NCC surfaces (n, 2r+1, 2r+1)."""
+    torch = _torch()
+    z, Hs, Ws = desc_sen.shape
+    _, Hr, Wr = desc_ref.shape
+    dt = {torch.float32: DTYPE_F32, torch.bfloat16: DTYPE_BF16, torch.float16: DTYPE_F16}[desc_sen.dtype]
+    n = ips.shape[0]
+    V = 2 * r + 1
+    cps = torch.empty((n, 8), dtype=torch.int32, device=desc_sen.device)
+    ncc = torch.empty((n, V, V), dtype=torch.float32, device=desc_sen.device) if want_ncc else None
+    rc = lib().sfoc_fastncc_match(_ptr(desc_sen), Hs, Ws, _ptr(desc_ref), Hr, Wr, _ptr(integ1), _ptr(integ2),
+                                  z, dt, _ptr(ips), _ptr(prior), n, m, r, _ptr(ncc), _ptr(cps), None, 0,
+                                  _stream(stream))
+    _check(rc, "sfoc_fastncc_match")
+    return (cps, ncc) if want_ncc else cps
+
+
+def register_workspace(Hr, Wr, Hs, Ws, n, m, r, p: Params) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().sfoc_register_workspace(Hr, Wr, Hs, Ws, n, m, r, ctypes.byref(p), ctypes.byref(b)),
+           "sfoc_register_workspace")
+    return b.value
+
+
+class Registrar:
+    """Holds the workspace of sfoc_register_cps for one shape, so repeated
+    calls allocate nothing."""
+
+    def __init__(self, Hr, Wr, Hs, Ws, n, m, r, p: Params, device="cuda", want_ncc=False):
+        torch = _torch()
+        self.p = p.copy()
+        self.shape = (Hr, Wr, Hs, Ws, n, m, r)
+        self.wsb = register_workspace(Hr, Wr, Hs, Ws, n, m, r, self.p)
+        self.ws = torch.empty(self.wsb, dtype=torch.uint8, device=device)
+        self.cps = torch.empty((n, 8), dtype=torch.int32, device=device)
+        V = 2 * r + 1
+        self.ncc = torch.empty((n, V, V), dtype=torch.float32, device=device) if want_ncc else None
+
+    def __call__(self, ref, sen, ips, prior=None, stream=None):
+        Hr, Wr, Hs, Ws, n, m, r = self.shape
+        assert ref.shape == (Hr, Wr) and sen.shape == (Hs, Ws) and ips.shape[0] == n
+        rc = lib().sfoc_register_cps(_ptr(ref), Hr, Wr, ref.stride(0), _ptr(sen), Hs, Ws, sen.stride(0),
+                                     _ptr(ips), _ptr(prior), n, m, r, ctypes.byref(self.p), _ptr(self.ncc),
+                                     _ptr(self.cps), _ptr(self.ws), self.wsb, _stream(stream))
+        _check(rc, "sfoc_register_cps")
+        return self.cps
+
+
+def register_cps(ref, sen, ips, m: int, r: int, p: Params, prior=None, want_ncc=False, stream=None):
+    R = Registrar(ref.shape[0], ref.shape[1], sen.shape[0], sen.shape[1], ips.shape[0], m, r, p,
+                  device=ref.device, want_ncc=want_ncc)
+    cps = R(ref, sen, ips, prior, stream)
+    return (cps, R.ncc) if want_ncc else cps
+
+
+KERNEL_NAMES = ("describe", "integral", "match", "consistency")
+
+
+def trace_enable(on: bool = True):
+    _check(lib().sfoc_trace_enable(int(on)), "sfoc_trace_enable")
+
+
+def trace_collect() -> dict:
+    """{kernel: (total ms, launches)} since the last collection."""
+    n = len(KERNEL_NAMES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    rc = lib().sfoc_trace_collect(ms, cnt, n)
+    if rc < 0:
+        raise SfocError(rc, "sfoc_trace_collect")
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_NAMES)}
+
+
+def cps_to_numpy(cps) -> np.ndarray:
+    """(n, 8) int32 tensor or array of records -> structured array."""
+    a = cps.detach().cpu().numpy() if hasattr(cps, "detach") else np.asarray(cps)
+    return np.ascontiguousarray(a, dtype=np.int32).view(CP_DTYPE).reshape(-1)

@@ -1,0 +1,252 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Small cases are compared element by element; the 2048 x 2048 scene is run in
+the benchmark's launch configuration and checked on sampled CPs that the
+oracle recomputes from crops, plus properties that hold at any size."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import sfoc_oracle as O
+from paper_2202_13347_amd import sfoc as S
+from paper_2202_13347_amd import synth
+from tests.gpu_util import (DESC_TOL, NCC_TOL, compare_cps, consistency_flip_allowed, to_chw, bf16_ulp,
+                            f16_ulp)
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    S.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def oparams(p: S.Params) -> O.Params:
+    return O.Params(n_orient=p.n_orient, s1=tuple(p.s1[:p.n_s1]), s2=tuple(p.s2[:p.n_s2]), trunc=p.trunc,
+                    sd1=p.sd1, sd2=p.sd2, K=p.K, dil=tuple(p.dil[:p.n_dil]), eps=p.eps,
+                    rectify=["abs", "signed", "relu"][p.rectify], second_order=bool(p.second_order))
+
+
+# ------------------------------------------------------------ describe ----
+DESCRIBE_CASES = [
+    ((37, 53), "baseline", {}),
+    ((64, 64), "baseline", {}),
+    ((100, 70), "paper", {}),
+    ((45, 33), "baseline", {"second_order": 0}),
+    ((40, 48), "baseline", {"rectify": 1}),
+    ((33, 31), "paper", {"rectify": 2}),
+    ((1, 7), "baseline", {}),
+    ((20, 20), "baseline", {"n_orient": 6}),
+]
+
+
+@pytest.mark.parametrize("shape,preset,mods", DESCRIBE_CASES)
+def test_describe_matches_oracle(shape, preset, mods):
+    say("describe", shape, preset, mods)
+    img = synth.make_pair(11, shape, 2.0).ref if min(shape) > 8 else \
+        np.random.default_rng(1).uniform(0, 1, shape).astype(np.float32)
+    p = S.preset(preset)
+    for k, v in mods.items():
+        setattr(p, k, v)
+    desc, i1, i2 = S.describe(dev(img), p)
+    torch.cuda.synchronize()
+    F = O.sfoc(img.astype(np.float64), oparams(p))
+    g = desc.cpu().numpy().astype(np.float64)
+    err = np.abs(g - to_chw(F)).max()
+    say("  max |desc err|", err)
+    assert err <= DESC_TOL
+    G1, G2 = O.integral_feature_images(F)
+    H, W = shape
+    count = (np.arange(H + 1)[:, None] * np.arange(W + 1)[None, :]) * F.shape[2]
+    e1 = np.abs(i1.cpu().numpy() - G1) - DESC_TOL * count
+    e2 = np.abs(i2.cpu().numpy() - G2) - 2 * DESC_TOL * count
+    assert e1.max() <= 1e-9 and e2.max() <= 1e-9
+    assert np.all(i1.cpu().numpy()[0] == 0) and np.all(i1.cpu().numpy()[:, 0] == 0)
+
+
+@pytest.mark.parametrize("dt", [S.DTYPE_BF16, S.DTYPE_F16])
+def test_describe_rounded_storage(dt):
+    say("describe dtype", dt)
+    img = synth.make_pair(5, (70, 90), 2.0).sen
+    p = S.preset("baseline", dtype=dt)
+    desc, i1, i2 = S.describe(dev(img), p)
+    torch.cuda.synchronize()
+    F = to_chw(O.sfoc(img.astype(np.float64), oparams(p)))
+    g = desc.float().cpu().numpy().astype(np.float64)
+    ulp = bf16_ulp(F) if dt == S.DTYPE_BF16 else f16_ulp(F)
+    assert np.all(np.abs(g - F) <= ulp + DESC_TOL)
+    # integral images are built from the stored (rounded) values
+    G1, _ = O.integral_feature_images(g.transpose(1, 2, 0))
+    assert np.abs(i1.cpu().numpy() - G1).max() < 1e-9
+
+
+def test_constant_image_gives_zero_descriptor():
+    img = np.full((40, 40), 0.37, np.float32)
+    desc, i1, i2 = S.describe(dev(img), S.preset("baseline"))
+    torch.cuda.synchronize()
+    F = O.sfoc(img.astype(np.float64))
+    assert np.abs(desc.cpu().numpy() - to_chw(F)).max() <= DESC_TOL
+
+
+# --------------------------------------------------------------- match -----
+def _match_case(seed, recipe, prior=None):
+    pr, ips, m, r = synth.workload(recipe, seed)
+    p = O.Params()
+    Fr = O.sfoc(pr.ref).astype(np.float32).astype(np.float64)
+    Fs = O.sfoc(pr.sen).astype(np.float32).astype(np.float64)
+    return pr, ips, m, r, Fr, Fs
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_match_kernel_on_oracle_descriptors(seed):
+    say("match seed", seed)
+    pr, ips, m, r, Fr, Fs = _match_case(seed, synth.SMALL)
+    G1, G2 = O.integral_feature_images(Fr)
+    o, so = O.match(Fs, Fr, ips, m, r, integ=(G1, G2), want_surfaces=True)
+    cps, ncc = S.fastncc_match(dev(to_chw(Fs), torch.float32), dev(to_chw(Fr), torch.float32), dev(G1), dev(G2),
+                               dev(ips), m, r, want_ncc=True)
+    torch.cuda.synchronize()
+    g = S.cps_to_numpy(cps)
+    st = compare_cps(g, o, so, r, ncc.cpu().numpy())
+    say("  ", st)
+    flips = {i for i in range(len(o)) if o["flags"][i] != g["flags"][i]}
+    assert flips <= consistency_flip_allowed(o)
+
+
+@pytest.mark.parametrize("seed", list(range(10)))
+def test_register_small_pairs(seed):
+    say("register small seed", seed)
+    pr, ips, m, r = synth.workload(synth.SMALL, seed)
+    p = S.preset("baseline")
+    cps, ncc = S.register_cps(dev(pr.ref), dev(pr.sen), dev(ips), m, r, p, want_ncc=True)
+    torch.cuda.synchronize()
+    o, so = O.register_cps(pr.ref, pr.sen, ips, m, r, oparams(p), want_surfaces=True)
+    g = S.cps_to_numpy(cps)
+    st = compare_cps(g, o, so, r, ncc.cpu().numpy())
+    say("  ", st)
+    flips = {i for i in range(len(o)) if o["flags"][i] != g["flags"][i]}
+    assert flips <= consistency_flip_allowed(o)
+
+
+@pytest.mark.parametrize("m,r,size", [(3, 62, 200), (126, 1, 200), (60, 2, 120), (64, 1, 150), (5, 3, 40),
+                                      (31, 16, 150), (17, 9, 90)])
+def test_template_and_radius_extremes(m, r, size):
+    say("extremes", m, r, size)
+    pr = synth.make_pair(21 + m, size, min(3.0, r - 0.5) if r > 1 else 0.4)
+    b = (m + 1) // 2 + r
+    ips = synth.grid_ips(size, size, 3, b) if size - 1 - 2 * b >= 0 else np.array([[size // 2, size // 2]], np.int32)
+    ips = np.concatenate([ips, np.array([[1, 1], [size - 1, size // 2]], np.int32)])   # two OOB
+    p = S.preset("baseline")
+    cps, ncc = S.register_cps(dev(pr.ref), dev(pr.sen), dev(ips), m, r, p, want_ncc=True)
+    torch.cuda.synchronize()
+    o, so = O.register_cps(pr.ref, pr.sen, ips, m, r, oparams(p), want_surfaces=True)
+    g = S.cps_to_numpy(cps)
+    assert g["flags"][-1] == O.OOB and g["flags"][-2] == O.OOB
+    st = compare_cps(g, o, so, r, ncc.cpu().numpy())
+    flips = {i for i in range(len(o)) if o["flags"][i] != g["flags"][i]}
+    assert flips <= consistency_flip_allowed(o)
+
+
+def test_flat_and_nonfinite_windows():
+    pr, ips, m, r = synth.workload(synth.SMALL, 4)
+    p = S.preset("baseline")
+    flat = np.full_like(pr.sen, 0.5)
+    for ref, sen, want in ((pr.ref, flat, O.FLAT_T), (flat, pr.sen, O.FLAT_S),
+                           (pr.ref, np.full_like(pr.sen, np.nan), O.NONFINITE)):
+        cps = S.register_cps(dev(ref), dev(sen), dev(ips), m, r, p)
+        torch.cuda.synchronize()
+        g = S.cps_to_numpy(cps)
+        o = O.register_cps(ref, sen, ips, m, r, oparams(p))
+        assert np.all(g["flags"] == want) and np.all(o["flags"] == want)
+        assert np.all(g["dy"] == 0) and np.all(g["score"] == 0)
+
+
+def test_empty_ip_list_and_prior():
+    pr, ips, m, r = synth.workload(synth.SMALL, 5)
+    p = S.preset("baseline")
+    cps = S.register_cps(dev(pr.ref), dev(pr.sen), dev(ips[:0]), m, r, p)
+    torch.cuda.synchronize()
+    assert cps.shape[0] == 0
+    prior = np.tile(np.round(pr.shift).astype(np.int32), (len(ips), 1))
+    prior[::3] = 0
+    cps, ncc = S.register_cps(dev(pr.ref), dev(pr.sen), dev(ips), m, 6, p, prior=dev(prior), want_ncc=True)
+    torch.cuda.synchronize()
+    o, so = O.register_cps(pr.ref, pr.sen, ips, m, 6, oparams(p), prior=prior, want_surfaces=True)
+    g = S.cps_to_numpy(cps)
+    compare_cps(g, o, so, 6, ncc.cpu().numpy())
+    flips = {i for i in range(len(o)) if o["flags"][i] != g["flags"][i]}
+    assert flips <= consistency_flip_allowed(o, prior)
+
+
+def test_paper_preset_end_to_end():
+    pr, ips, m, r = synth.workload(synth.SMALL, 7)
+    p = S.preset("paper")
+    cps, ncc = S.register_cps(dev(pr.ref), dev(pr.sen), dev(ips), m, r, p, want_ncc=True)
+    torch.cuda.synchronize()
+    o, so = O.register_cps(pr.ref, pr.sen, ips, m, r, oparams(p), want_surfaces=True)
+    compare_cps(S.cps_to_numpy(cps), o, so, r, ncc.cpu().numpy(), check_consistency=False)
+
+
+# ------------------------------------------------- full-size scene ---------
+@pytest.fixture(scope="module")
+def scene():
+    pr, ips, m, r = synth.workload(synth.SCENE, 0)
+    p = S.preset("baseline")
+    R = S.Registrar(2048, 2048, 2048, 2048, len(ips), m, r, p, want_ncc=True)
+    ref, sen, dips = dev(pr.ref), dev(pr.sen), dev(ips)
+    cps = R(ref, sen, dips).clone()
+    ncc = R.ncc.clone()
+    cps2 = R(ref, sen, dips).clone()
+    ncc2 = R.ncc.clone()
+    torch.cuda.synchronize()
+    return pr, ips, m, r, p, cps.cpu(), ncc.cpu(), cps2.cpu(), ncc2.cpu()
+
+
+def test_scene_is_deterministic(scene):
+    pr, ips, m, r, p, cps, ncc, cps2, ncc2 = scene
+    assert torch.equal(cps, cps2) and torch.equal(ncc, ncc2)
+
+
+def test_scene_properties(scene):
+    pr, ips, m, r, p, cps, ncc, cps2, ncc2 = scene
+    g = S.cps_to_numpy(cps)
+    s = ncc.numpy()
+    assert np.all(np.abs(s) <= 1 + 1e-5)
+    ok = (g["flags"] & (O.OOB | O.FLAT_T | O.FLAT_S | O.NONFINITE)) == 0
+    idx = s.reshape(len(g), -1).argmax(axis=1)
+    assert np.all(idx[ok] == ((g["dy"] + r) * (2 * r + 1) + g["dx"] + r)[ok])
+    assert np.all(np.abs(g["sub_dy"]) <= 0.5) and np.all(np.abs(g["sub_dx"]) <= 0.5)
+    valid = (g["flags"] & O.VALID) != 0
+    err = np.hypot(g["dy"] + g["sub_dy"] - pr.shift[0], g["dx"] + g["sub_dx"] - pr.shift[1])
+    say("scene: valid", valid.sum(), "correct@1.5px", int((err <= 1.5).sum()), "of", len(g))
+    assert (err[valid] <= 1.5).mean() > 0.9
+
+
+@pytest.mark.parametrize("k", [0, 19, 210, 380, 399, 57])
+def test_scene_sampled_cps_match_oracle(scene, k):
+    pr, ips, m, r, p, cps, ncc, cps2, ncc2 = scene
+    say("scene sample", k, ips[k])
+    g = S.cps_to_numpy(cps)[k:k + 1]
+    rec, so = O.match_one_region(pr.ref, pr.sen, ips[k], m, r, oparams(p))
+    o = np.zeros(1, dtype=O.CP_DTYPE)
+    o["dy"], o["dx"], o["sub_dy"], o["sub_dx"], o["score"], o["flags"] = rec
+    g = g.copy()
+    g["flags"] &= ~np.uint32(O.VALID | O.INCONSISTENT)
+    st = compare_cps(g, o, so[None], r, ncc.numpy()[k:k + 1], check_consistency=False)
+    say("  ", st)

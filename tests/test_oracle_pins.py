@@ -405,3 +405,26 @@ def test_cost_model_worked_example():
         g = json.load(f)
     got = 100.0 * O.cost_ratio(g["m"], g["M"], g["z"])
     assert round(got, 3) == g["ratio_percent"]
+
+
+def test_region_oracle_equals_dense_crop():
+    # The crop-with-halo evaluation reproduces the dense descriptor exactly,
+    # at borders too (reflect-101 of the whole image).
+    img = _img(41, 37, 9)
+    p = O.Params()
+    F = O.sfoc(img, p)
+    for (y0, x0, h, w) in ((0, 0, 10, 12), (30, 25, 11, 12), (5, 17, 20, 9), (35, 0, 6, 37)):
+        assert np.abs(O.sfoc_region(img, y0, x0, h, w, p) - F[y0:y0 + h, x0:x0 + w]).max() < 1e-13
+
+
+def test_region_match_equals_dense_match():
+    from paper_2202_13347_amd import synth
+    pr = synth.make_pair(3, 96, 4.0)
+    p = O.Params()
+    ips = np.array([[30, 30], [48, 60], [65, 40], [5, 5]])
+    cps, surf = O.register_cps(pr.ref, pr.sen, ips, 16, 6, p, want_surfaces=True)
+    for i, ip in enumerate(ips):
+        rec, s = O.match_one_region(pr.ref, pr.sen, ip, 16, 6, p)
+        assert rec[0] == cps["dy"][i] and rec[1] == cps["dx"][i]
+        assert rec[5] == (int(cps["flags"][i]) & ~(O.VALID | O.INCONSISTENT))
+        assert np.abs(s - surf[i]).max() < 1e-10
