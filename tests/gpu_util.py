@@ -78,3 +78,33 @@ def f16_ulp(x):
     a = np.abs(np.asarray(x, np.float64))
     e = np.floor(np.log2(np.maximum(a, 2.0 ** -14)))
     return 2.0 ** (e - 10)
+
+
+def desc_condition(img, op):
+    """Per-pixel, per-channel amplification of float32 rounding in the
+    descriptor.  The absolute error of the smoothed map D is set by the scale
+    of smooth(|F|) (F the signed steered response); normalisation divides it
+    by the pixel's order norm sqrt(sum D^2 + eps).  Returns
+    max(1, max(median, local) ||smooth(|F|)|| / sqrt(||D||^2 + eps)), which is
+    about 1 for |.| rectification on textured images and large where signed
+    responses cancel or a ReLU leaves an order block near zero."""
+    import dataclasses
+    img = np.asarray(img, np.float64)
+    A, Q = O.sfoc_unnormalised(img, dataclasses.replace(op, rectify="signed"))
+    H, W = img.shape
+    N = op.n_orient
+    if op.rectify == "abs":
+        R = np.abs(A)
+    elif op.rectify == "relu":
+        R = np.maximum(A, 0.0)
+    else:
+        R = A
+    sm = lambda X, c: O.dilated_smooth(X, Q, H, W, op.sd1 if c < N else op.sd2, op.K, op.dil)
+    D = np.stack([sm(R[c], c) for c in range(A.shape[0])])
+    Da = np.stack([sm(np.abs(A[c]), c) for c in range(A.shape[0])])
+    kap = np.empty_like(D)
+    for lo in range(0, D.shape[0], N):
+        mag = np.sqrt((Da[lo:lo + N] ** 2).sum(axis=0))
+        den = np.sqrt((D[lo:lo + N] ** 2).sum(axis=0) + op.eps)
+        kap[lo:lo + N] = np.maximum(1.0, np.maximum(np.median(mag), mag) / den)
+    return kap
