@@ -23,157 +23,343 @@ namespace sfoc {
 
 constexpr int kTS = 32;       // output tile side
 constexpr int kNT = 256;      // threads per tile
-constexpr int kPXT = kTS * kTS / kNT;
+constexpr int kRun = 4;       // outputs per thread along a run
+constexpr int kPXT = kTS * kTS / kNT;   // output pixels per thread (one run of 4)
+static_assert(kPXT == kRun, "one horizontal run of outputs per thread");
 
-struct DescribeLds {
-    int BS, IS, rowN;     // basis side, image-region side, row-buffer rows (max)
-    int off_img, off_row, off_basis, off_chan;
+// LDS geometry of one tile.  Every side is padded to a multiple of kRun so
+// runs never straddle a row; padded rows and columns hold harmless values
+// that no output reads.
+struct DescribeGeom {
+    int BSP;    // basis / channel side incl. the smoothing halo Q, padded
+    int ISX;    // image-region side (BSP + 2R)
+    int nrun;   // runs per basis row (BSP / kRun)
     size_t bytes;
 };
 
-static DescribeLds describe_lds(const DescribeConsts& c, int CG) {
-    DescribeLds L;
-    L.BS = kTS + 2 * c.Q;
-    L.IS = L.BS + 2 * c.R;
-    L.rowN = L.BS + 2 * c.R;
-    L.off_img = 0;
-    L.off_row = L.IS * L.IS;
-    L.off_basis = L.off_row + 3 * L.rowN * L.BS;
-    L.off_chan = 0;   // aliases img + row once the basis is complete
-    int need = L.off_basis + 5 * L.BS * L.BS;
-    L.bytes = (size_t)need * sizeof(float);
-    (void)CG;
-    return L;
+static DescribeGeom describe_geom(const DescribeConsts& c) {
+    DescribeGeom g;
+    g.BSP = (kTS + 2 * c.Q + kRun - 1) / kRun * kRun;
+    g.ISX = g.BSP + 2 * c.R;
+    g.nrun = g.BSP / kRun;
+    const size_t img = (size_t)g.ISX * g.ISX;
+    const size_t row = 3 * (size_t)g.ISX * g.BSP;
+    const size_t bas = 5 * (size_t)g.BSP * g.BSP;
+    g.bytes = (img + row + bas) * sizeof(float);
+    return g;
 }
 
-template <int Z, int CG>
-__global__ __launch_bounds__(kNT) void describe_kernel(const float* __restrict__ img, int H, int W, int64_t ld,
-                                                       void* __restrict__ desc, double* __restrict__ integ1,
-                                                       double* __restrict__ integ2, const DescribeConsts C,
-                                                       int BS, int IS) {
+// Dilated Gaussian smoothing of one channel for a horizontal run of kRun
+// outputs, base 3x3 (K = 1) at rates 1, 2, 3: neighbours shared by the run
+// are read once.  ch points at the run's first output in a map of pitch P.
+SFOC_DEV void smooth_run_k1_123(const float* ch, int P, float wc, float we, float wk, float out[kRun]) {
+    float v[kRun + 6];
+#pragma unroll
+    for (int q = 0; q < kRun + 6; ++q) v[q] = ch[q - 3];
+    float e[kRun], k[kRun];
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) {
+        out[j] = 3.f * wc * v[j + 3];
+        e[j] = (v[j + 2] + v[j + 4]) + (v[j + 1] + v[j + 5]) + (v[j] + v[j + 6]);
+        k[j] = 0.f;
+    }
+#pragma unroll
+    for (int r = 1; r <= 3; ++r) {
+#pragma unroll
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+            const float* row = ch + sgn * r * P;
+            float u[kRun + 6];
+#pragma unroll
+            for (int q = 0; q < kRun + 2 * r; ++q) u[q] = row[q - r];
+#pragma unroll
+            for (int j = 0; j < kRun; ++j) {
+                e[j] += u[j + r];
+                k[j] += u[j] + u[j + 2 * r];
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) out[j] = fmaf(we, e[j], fmaf(wk, k[j], out[j]));
+}
+
+// Row pass for a horizontal run of kRun outputs with radius RHO: g, d, dd
+// taps paired symmetrically, so odd responses of constant input are exactly
+// zero.  p points at the first output's centre.  Correlation form of the
+// convolution: out(x) = sum_k t(-k) I(x + k) -> odd taps act on
+// I(x - k) - I(x + k).
+template <int RHO>
+SFOC_DEV void row_run(const float* p, const float* tg, const float* td, const float* tdd, float og[kRun],
+                      float od[kRun], float odd[kRun]) {
+    float x[2 * RHO + kRun];
+#pragma unroll
+    for (int q = 0; q < 2 * RHO + kRun; ++q) x[q] = p[q - RHO];
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) {
+        const float c = x[j + RHO];
+        float g = tg[0] * c, dd = tdd[0] * c, d = 0.f;
+#pragma unroll
+        for (int k = 1; k <= RHO; ++k) {
+            const float l = x[j + RHO - k], r = x[j + RHO + k];
+            const float sm = l + r, df = l - r;
+            g = fmaf(tg[k], sm, g);
+            dd = fmaf(tdd[k], sm, dd);
+            d = fmaf(td[k], df, d);
+        }
+        og[j] = g;
+        od[j] = d;
+        odd[j] = dd;
+    }
+}
+
+// Even (te) and odd (to) column taps on one map for a vertical run; p points
+// at the first output's centre, pitch P.
+template <int RHO>
+SFOC_DEV void col_run(const float* p, int P, const float* te, const float* to, float ev[kRun], float od[kRun]) {
+    float x[2 * RHO + kRun];
+#pragma unroll
+    for (int q = 0; q < 2 * RHO + kRun; ++q) x[q] = p[(q - RHO) * P];
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) {
+        const float c = x[j + RHO];
+        float e = te ? te[0] * c : 0.f, d = 0.f;
+#pragma unroll
+        for (int k = 1; k <= RHO; ++k) {
+            const float l = x[j + RHO - k], r = x[j + RHO + k];
+            if (te) e = fmaf(te[k], l + r, e);
+            if (to) d = fmaf(to[k], l - r, d);
+        }
+        ev[j] = e;
+        od[j] = d;
+    }
+}
+
+// Any radius: the same sums with taps read pairwise from LDS.
+SFOC_DEV void row_run_any(const float* p, int rho, const float* tg, const float* td, const float* tdd,
+                          float og[kRun], float od[kRun], float odd[kRun]) {
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) {
+        const float c = p[j];
+        float g = tg[0] * c, dd = tdd[0] * c, d = 0.f;
+        for (int k = 1; k <= rho; ++k) {
+            const float l = p[j - k], r = p[j + k];
+            g = fmaf(tg[k], l + r, g);
+            dd = fmaf(tdd[k], l + r, dd);
+            d = fmaf(td[k], l - r, d);
+        }
+        og[j] = g;
+        od[j] = d;
+        odd[j] = dd;
+    }
+}
+SFOC_DEV void col_run_any(const float* p, int P, int rho, const float* te, const float* to, float ev[kRun],
+                          float od[kRun]) {
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) {
+        const float c = p[j * P];
+        float e = te ? te[0] * c : 0.f, d = 0.f;
+        for (int k = 1; k <= rho; ++k) {
+            const float l = p[(j - k) * P], r = p[(j + k) * P];
+            if (te) e = fmaf(te[k], l + r, e);
+            if (to) d = fmaf(to[k], l - r, d);
+        }
+        ev[j] = e;
+        od[j] = d;
+    }
+}
+
+#define SFOC_RADIUS_SWITCH(rho, CALL_T, CALL_ANY) \
+    switch (rho) {                                \
+        case 1: CALL_T(1); break;                 \
+        case 2: CALL_T(2); break;                 \
+        case 3: CALL_T(3); break;                 \
+        case 4: CALL_T(4); break;                 \
+        case 5: CALL_T(5); break;                 \
+        case 6: CALL_T(6); break;                 \
+        case 7: CALL_T(7); break;                 \
+        case 8: CALL_T(8); break;                 \
+        case 9: CALL_T(9); break;                 \
+        case 10: CALL_T(10); break;               \
+        case 11: CALL_T(11); break;               \
+        case 12: CALL_T(12); break;               \
+        default: CALL_ANY; break;                 \
+    }
+
+template <int Z, int CG, bool FAST>
+__global__ __launch_bounds__(kNT, 2) void describe_kernel(const float* __restrict__ img, int H, int W, int64_t ld,
+                                                          void* __restrict__ desc, double* __restrict__ integ1,
+                                                          double* __restrict__ integ2, const DescribeConsts C,
+                                                          int BSP, int ISX) {
     extern __shared__ float lds[];
     const int t = threadIdx.x;
     const int ty0 = blockIdx.y * kTS, tx0 = blockIdx.x * kTS;
     const int Q = C.Q, R = C.R;
-    const int rowN = BS + 2 * R;
+    const int nrun = BSP / kRun;
     float* simg = lds;
-    float* srow = lds + IS * IS;
-    float* sbas = srow + 3 * rowN * BS;
-    const int BB = BS * BS;
+    float* srow = simg + ISX * ISX;
+    float* sbas = srow + 3 * ISX * BSP;
+    const int BB = BSP * BSP;
 
-    // 1. input region with reflect-101 borders.
-    for (int e = t; e < IS * IS; e += kNT) {
-        const int a = e / IS, b = e - a * IS;
-        const int gy = reflect101(ty0 - Q - R + a, H);
-        const int gx = reflect101(tx0 - Q - R + b, W);
-        simg[e] = img[(int64_t)gy * ld + gx];
+    // 1. input region (top-left at tile origin - Q - R), reflect-101 borders.
+    {
+        const int y0 = ty0 - Q - R, x0 = tx0 - Q - R;
+        const bool inside = y0 >= 0 && x0 >= 0 && y0 + ISX <= H && x0 + ISX <= W;
+        for (int e = t; e < ISX * ISX; e += kNT) {
+            const int a = e / ISX, b = e - a * ISX;
+            const int gy = inside ? y0 + a : reflect101(y0 + a, H);
+            const int gx = inside ? x0 + b : reflect101(x0 + b, W);
+            simg[e] = img[(int64_t)gy * ld + gx];
+        }
     }
-    for (int e = t; e < 5 * BB; e += kNT) sbas[e] = 0.f;
     __syncthreads();
 
-    // 2. basis responses summed over sigma.
+    // 2. basis responses Gx, Gy, Gxx, Gyy, Gxy * I summed over sigma, held in
+    //    registers by the thread that owns each vertical run of kRun pixels.
+    constexpr int kMaxOwn = 3;   // runs per thread (BSP <= 48 -> 12 * 48 runs)
+    float bas[kMaxOwn][5][kRun];
+#pragma unroll
+    for (int o = 0; o < kMaxOwn; ++o)
+#pragma unroll
+        for (int m = 0; m < 5; ++m)
+#pragma unroll
+            for (int j = 0; j < kRun; ++j) bas[o][m][j] = 0.f;
+    const int ncolrun = nrun * BSP;   // (row-run, column) pairs
     for (int s = 0; s < C.nsig; ++s) {
         const int rho = C.rad[s];
         const float* tg = C.taps + C.off[s];
         const float* td = tg + (rho + 1);
         const float* tdd = td + (rho + 1);
         const float cn = C.cnorm[s];
-        const int rows = BS + 2 * rho;
-        // row pass: correlation form of the convolution; odd taps flip sign.
-        for (int e = t; e < rows * BS; e += kNT) {
-            const int a = e / BS, b = e - a * BS;
-            const float* p = simg + (a + R - rho) * IS + (b + R);
-            const float x0 = p[0];
-            float ag = tg[0] * x0, add = tdd[0] * x0, ad = 0.f;
-            for (int k = 1; k <= rho; ++k) {
-                const float xp = p[k], xm = p[-k];
-                const float sm = xp + xm, df = xm - xp;
-                ag = fmaf(tg[k], sm, ag);
-                add = fmaf(tdd[k], sm, add);
-                ad = fmaf(td[k], df, ad);
+        const int rows = BSP + 2 * rho;
+        // row pass on rows [0, rows) x cols [0, BSP): horizontal runs.  Row a
+        // of this pass is image-region row a + R - rho.
+        for (int e = t; e < rows * nrun; e += kNT) {
+            const int a = e / nrun, b0 = (e - a * nrun) * kRun;
+            const float* p = simg + (a + R - rho) * ISX + (b0 + R);
+            float og[kRun], od[kRun], odd[kRun];
+#define ROW_T(RR) row_run<RR>(p, tg, td, tdd, og, od, odd)
+            SFOC_RADIUS_SWITCH(rho, ROW_T, row_run_any(p, rho, tg, td, tdd, og, od, odd))
+#undef ROW_T
+            float* w = srow + a * BSP + b0;
+#pragma unroll
+            for (int j = 0; j < kRun; ++j) {
+                w[j] = cn * og[j];
+                w[rows * BSP + j] = cn * od[j];
+                w[2 * rows * BSP + j] = cn * odd[j];
             }
-            srow[e] = cn * ag;
-            srow[rows * BS + e] = cn * ad;
-            srow[2 * rows * BS + e] = cn * add;
         }
         __syncthreads();
+        // column pass on vertical runs; output row a reads pass rows a + rho + k.
         const float* rg = srow;
-        const float* rd = srow + rows * BS;
-        const float* rdd = srow + 2 * rows * BS;
+        const float* rd = srow + rows * BSP;
+        const float* rdd = srow + 2 * rows * BSP;
         const int use = C.use[s];
-        for (int e = t; e < BB; e += kNT) {
-            const int a = e / BS, b = e - a * BS;
-            const int c0 = (a + rho) * BS + b;
-            float bx = tg[0] * rd[c0], by = 0.f;
-            float bxx = tg[0] * rdd[c0], byy = tdd[0] * rg[c0], bxy = 0.f;
-            for (int k = 1; k <= rho; ++k) {
-                const int up = c0 - k * BS, dn = c0 + k * BS;
-                const float gs = rg[up] + rg[dn], gdf = rg[up] - rg[dn];
-                const float ds = rd[up] + rd[dn], ddf = rd[up] - rd[dn];
-                const float dds = rdd[up] + rdd[dn];
-                bx = fmaf(tg[k], ds, bx);
-                by = fmaf(td[k], gdf, by);
-                bxx = fmaf(tg[k], dds, bxx);
-                byy = fmaf(tdd[k], gs, byy);
-                bxy = fmaf(td[k], ddf, bxy);
-            }
-            if (use & 1) {
-                sbas[e] += bx;
-                sbas[BB + e] += by;
-            }
-            if (use & 2) {
-                sbas[2 * BB + e] += bxx;
-                sbas[3 * BB + e] += byy;
-                sbas[4 * BB + e] += bxy;
+#pragma unroll
+        for (int o = 0; o < kMaxOwn; ++o) {
+            const int e = t + o * kNT;
+            if (e < ncolrun) {
+                const int b = e % BSP, a0 = (e / BSP) * kRun;
+                float bx[kRun], by[kRun], bxx[kRun], byy[kRun], bxy[kRun], dummy[kRun];
+                const int c0 = (a0 + rho) * BSP + b;
+                // rg -> By (odd d), Byy (even dd); rd -> Bx (even g), Bxy (odd d);
+                // rdd -> Bxx (even g).
+#define COL_T(RR)                                                \
+    do {                                                         \
+        col_run<RR>(rg + c0, BSP, tdd, td, byy, by);             \
+        col_run<RR>(rd + c0, BSP, tg, td, bx, bxy);              \
+        col_run<RR>(rdd + c0, BSP, tg, nullptr, bxx, dummy);     \
+    } while (0)
+#define COL_ANY                                                  \
+    do {                                                         \
+        col_run_any(rg + c0, BSP, rho, tdd, td, byy, by);        \
+        col_run_any(rd + c0, BSP, rho, tg, td, bx, bxy);         \
+        col_run_any(rdd + c0, BSP, rho, tg, nullptr, bxx, dummy); \
+    } while (0)
+                SFOC_RADIUS_SWITCH(rho, COL_T, COL_ANY)
+#undef COL_T
+#undef COL_ANY
+                (void)dummy;
+#pragma unroll
+                for (int j = 0; j < kRun; ++j) {
+                    if (use & 1) {
+                        bas[o][0][j] += bx[j];
+                        bas[o][1][j] += by[j];
+                    }
+                    if (use & 2) {
+                        bas[o][2][j] += bxx[j];
+                        bas[o][3][j] += byy[j];
+                        bas[o][4][j] += bxy[j];
+                    }
+                }
             }
         }
         __syncthreads();
     }
+#pragma unroll
+    for (int o = 0; o < kMaxOwn; ++o) {
+        const int e = t + o * kNT;
+        if (e < ncolrun) {
+            const int b = e % BSP, a0 = (e / BSP) * kRun;
+#pragma unroll
+            for (int m = 0; m < 5; ++m)
+#pragma unroll
+                for (int j = 0; j < kRun; ++j) sbas[m * BB + (a0 + j) * BSP + b] = bas[o][m][j];
+        }
+    }
+    __syncthreads();
 
-    // 3. steer + rectify per channel group, then dilated smoothing.
-    float acc[Z][kPXT];
-    float* schan = lds;   // img/row regions are free now
+    // 3. steer + rectify per channel group into LDS, then dilated smoothing
+    //    of this thread's horizontal run of kRun outputs.
+    float acc[Z][kRun];
+    float* schan = lds;   // image and row regions are free now
     const int N = C.N;
     const int B = 2 * C.K + 1;
+    const int oy = t / (kTS / kRun), ox0 = (t % (kTS / kRun)) * kRun;
+    const int obase = (oy + Q) * BSP + ox0 + Q;
+    const int BSr = kTS + 2 * Q;   // rows / columns actually read
 #pragma unroll
     for (int c0 = 0; c0 < Z; c0 += CG) {
-        for (int e = t; e < BB; e += kNT) {
+        for (int e = t; e < BSr * BSr; e += kNT) {
+            const int a = e / BSr, b = e - a * BSr;
+            const int idx = a * BSP + b;
 #pragma unroll
             for (int cc = 0; cc < CG; ++cc) {
                 const int c = c0 + cc;
                 if (c < Z) {
                     float v;
                     if (c < N) {
-                        v = C.c1[c] * sbas[e] + C.s1[c] * sbas[BB + e];
+                        v = C.c1[c] * sbas[idx] + C.s1[c] * sbas[BB + idx];
                     } else {
                         const int k = c - N;
-                        v = C.cc[k] * sbas[2 * BB + e] + C.ss[k] * sbas[3 * BB + e] + C.sc2[k] * sbas[4 * BB + e];
+                        v = C.cc[k] * sbas[2 * BB + idx] + C.ss[k] * sbas[3 * BB + idx] +
+                            C.sc2[k] * sbas[4 * BB + idx];
                     }
                     if (C.rectify == SFOC_RECTIFY_ABS) v = fabsf(v);
                     else if (C.rectify == SFOC_RECTIFY_RELU) v = fmaxf(v, 0.f);
-                    schan[cc * BB + e] = v;
+                    schan[cc * BB + idx] = v;
                 }
             }
         }
         __syncthreads();
 #pragma unroll
-        for (int px = 0; px < kPXT; ++px) {
-            const int oy = t / kTS + px * (kNT / kTS), ox = t % kTS;
-            const int base = (oy + Q) * BS + ox + Q;
+        for (int cc = 0; cc < CG; ++cc) {
+            const int c = c0 + cc;
+            if (c < Z) {
+                const float* w = (c < N) ? C.w1 : C.w2;
+                const float* ch = schan + cc * BB + obase;
+                if (FAST) {
+                    smooth_run_k1_123(ch, BSP, w[4], w[1], w[0], acc[c]);
+                } else {
 #pragma unroll
-            for (int cc = 0; cc < CG; ++cc) {
-                const int c = c0 + cc;
-                if (c < Z) {
-                    const float* w = (c < N) ? C.w1 : C.w2;
-                    const float* ch = schan + cc * BB + base;
-                    float a = 0.f;
-                    for (int di = 0; di < C.ndil; ++di) {
-                        const int r = C.dil[di];
-                        for (int i = 0; i < B; ++i)
-                            for (int j = 0; j < B; ++j)
-                                a = fmaf(w[i * B + j], ch[(i - C.K) * r * BS + (j - C.K) * r], a);
+                    for (int j = 0; j < kRun; ++j) {
+                        float a = 0.f;
+                        for (int di = 0; di < C.ndil; ++di) {
+                            const int r = C.dil[di];
+                            for (int i = 0; i < B; ++i)
+                                for (int jj = 0; jj < B; ++jj)
+                                    a = fmaf(w[i * B + jj], ch[(i - C.K) * r * BSP + (jj - C.K) * r + j], a);
+                        }
+                        acc[c][j] = a;
                     }
-                    acc[c][px] = a;
                 }
             }
         }
@@ -182,35 +368,34 @@ __global__ __launch_bounds__(kNT) void describe_kernel(const float* __restrict__
 
     // 4. per-order normalisation, rounding, store, channel sums.
     const int64_t plane = (int64_t)H * W;
-    const int nord = C.second ? 2 : 1;
+    const int gy = ty0 + oy;
 #pragma unroll
-    for (int px = 0; px < kPXT; ++px) {
-        const int oy = t / kTS + px * (kNT / kTS), ox = t % kTS;
-        const int gy = ty0 + oy, gx = tx0 + ox;
+    for (int j = 0; j < kRun; ++j) {
+        const int gx = tx0 + ox0 + j;
         float inv[2];
+#pragma unroll
         for (int o = 0; o < 2; ++o) {
             float s2 = 0.f;
 #pragma unroll
             for (int c = 0; c < Z; ++c)
-                if ((c < N) == (o == 0)) s2 = fmaf(acc[c][px], acc[c][px], s2);
+                if ((c < N) == (o == 0)) s2 = fmaf(acc[c][j], acc[c][j], s2);
             inv[o] = 1.0f / sqrtf(s2 + C.eps);
         }
-        (void)nord;
         if (gy < H && gx < W) {
-            const int64_t o = (int64_t)gy * W + gx;
+            const int64_t off = (int64_t)gy * W + gx;
             double d1 = 0.0, d2 = 0.0;
 #pragma unroll
             for (int c = 0; c < Z; ++c) {
-                float v = acc[c][px] * inv[c < N ? 0 : 1];
+                float v = acc[c][j] * inv[c < N ? 0 : 1];
                 if (C.dtype == SFOC_DTYPE_F32) {
-                    ((float*)desc)[c * plane + o] = v;
+                    ((float*)desc)[c * plane + off] = v;
                 } else if (C.dtype == SFOC_DTYPE_BF16) {
                     const uint16_t b = f32_to_bf16_bits(v);
-                    ((uint16_t*)desc)[c * plane + o] = b;
+                    ((uint16_t*)desc)[c * plane + off] = b;
                     v = bf16_bits_to_f32(b);
                 } else {
                     const uint16_t b = f32_to_f16_bits(v);
-                    ((uint16_t*)desc)[c * plane + o] = b;
+                    ((uint16_t*)desc)[c * plane + off] = b;
                     v = f16_bits_to_f32(b);
                 }
                 const double dv = (double)v;
@@ -346,19 +531,27 @@ __global__ __launch_bounds__(kScanNT) void integral_col_apply(double* __restrict
 }
 
 // ---- launch -------------------------------------------------------------
+template <int Z, bool FAST>
+static hipError_t launch_describe_zf(const float* img, int H, int W, int64_t ld, void* desc, double* i1, double* i2,
+                                     const DescribeConsts& c, hipStream_t st) {
+    constexpr int CG = Z >= 4 ? 4 : Z;
+    const DescribeGeom g = describe_geom(c);
+    dim3 grid((W + kTS - 1) / kTS, (H + kTS - 1) / kTS);
+    auto kern = describe_kernel<Z, CG, FAST>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.bytes);
+    if (e != hipSuccess) return e;
+    trace_begin(st, SFOC_K_DESCRIBE);
+    hipLaunchKernelGGL(kern, grid, dim3(kNT), g.bytes, st, img, H, W, ld, desc, i1, i2, c, g.BSP, g.ISX);
+    trace_end(st, SFOC_K_DESCRIBE);
+    return hipGetLastError();
+}
+
 template <int Z>
 static hipError_t launch_describe_z(const float* img, int H, int W, int64_t ld, void* desc, double* i1, double* i2,
                                     const DescribeConsts& c, hipStream_t st) {
-    constexpr int CG = Z >= 4 ? 4 : Z;
-    const DescribeLds L = describe_lds(c, CG);
-    dim3 grid((W + kTS - 1) / kTS, (H + kTS - 1) / kTS);
-    auto kern = describe_kernel<Z, CG>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.bytes);
-    if (e != hipSuccess) return e;
-    trace_begin(st, SFOC_K_DESCRIBE);
-    hipLaunchKernelGGL(kern, grid, dim3(kNT), L.bytes, st, img, H, W, ld, desc, i1, i2, c, L.BS, L.IS);
-    trace_end(st, SFOC_K_DESCRIBE);
-    return hipGetLastError();
+    const bool fast = c.K == 1 && c.ndil == 3 && c.dil[0] == 1 && c.dil[1] == 2 && c.dil[2] == 3;
+    return fast ? launch_describe_zf<Z, true>(img, H, W, ld, desc, i1, i2, c, st)
+                : launch_describe_zf<Z, false>(img, H, W, ld, desc, i1, i2, c, st);
 }
 
 hipError_t launch_describe(const float* img, int H, int W, int64_t ld, void* desc, double* i1, double* i2,

@@ -72,13 +72,19 @@ def test_describe_matches_oracle(shape, preset, mods):
     err = np.abs(g - to_chw(F))
     say("  max |desc err|", err.max(), "max err/condition", (err / kap).max())
     assert np.all(err <= DESC_TOL * kap)
+    # integral images: within the prefix sum of the per-element descriptor
+    # tolerance of the oracle's, and (a property) exactly the 2-D prefix sums
+    # of the stored channel sums.
     G1, G2 = O.integral_feature_images(F)
-    H, W = shape
-    count = (np.arange(H + 1)[:, None] * np.arange(W + 1)[None, :]) * F.shape[2]
-    e1 = np.abs(i1.cpu().numpy() - G1) - DESC_TOL * count
-    e2 = np.abs(i2.cpu().numpy() - G2) - 2 * DESC_TOL * count
-    assert e1.max() <= 1e-9 and e2.max() <= 1e-9
-    assert np.all(i1.cpu().numpy()[0] == 0) and np.all(i1.cpu().numpy()[:, 0] == 0)
+    tol = DESC_TOL * kap
+    T1 = O.integral_image(tol.sum(axis=0))
+    T2 = O.integral_image((2.0 * tol * (np.abs(to_chw(F)) + tol)).sum(axis=0))
+    g1, g2 = i1.cpu().numpy(), i2.cpu().numpy()
+    assert np.all(np.abs(g1 - G1) <= T1 + 1e-9) and np.all(np.abs(g2 - G2) <= T2 + 1e-9)
+    own1, own2 = O.integral_feature_images(g.transpose(1, 2, 0))
+    assert np.abs(g1 - own1).max() <= 1e-9 * max(1.0, np.abs(own1).max())
+    assert np.abs(g2 - own2).max() <= 1e-9 * max(1.0, np.abs(own2).max())
+    assert np.all(g1[0] == 0) and np.all(g1[:, 0] == 0)
 
 
 @pytest.mark.parametrize("dt", [S.DTYPE_BF16, S.DTYPE_F16])
