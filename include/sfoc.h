@@ -182,7 +182,8 @@ int sfoc_describe(const float* img, int64_t H, int64_t W, int64_t ld,
  *  prior               n x 2 int32 (dy, dx) search-window offsets, or NULL.
  *  ncc                 n x (2r+1) x (2r+1) float32 surfaces, or NULL.  (output)
  *  cps                 n records.                                      (output)
- * Limits: 3 <= m, 1 <= r, m + 2r <= 256 (SFOC_E_UNSUPPORTED beyond).
+ * Limits: 3 <= m, 1 <= r, m + 2r <= 128, each image below 2^30 pixels
+ * (SFOC_E_UNSUPPORTED beyond).
  * n == 0 is valid and enqueues nothing.
  */
 int sfoc_match_workspace(int32_t n, int32_t m, int32_t r, int32_t z, size_t* bytes);

@@ -21,8 +21,10 @@ static int hip_status(hipError_t e) {
 }
 
 // Image sides are limited so that every per-image index fits in int32 and
-// every plane offset in int64.
+// every plane offset in int64; the match kernel addresses a descriptor
+// plane with 32-bit element offsets, so a plane holds fewer than 2^30 pixels.
 constexpr int64_t kMaxSide = 1 << 16;
+constexpr int64_t kMaxPlane = (int64_t)1 << 30;
 
 static int check_image(const void* img, int64_t H, int64_t W, int64_t ld) {
     if (!img) return SFOC_E_INVALID_ARG;
@@ -157,6 +159,7 @@ int sfoc_fastncc_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void*
     if (z < 1 || dtype_size(dtype) == 0) return SFOC_E_INVALID_ARG;
     if (Hs < 1 || Ws < 1 || Hr < 1 || Wr < 1) return SFOC_E_INVALID_ARG;
     if (Hs > kMaxSide || Ws > kMaxSide || Hr > kMaxSide || Wr > kMaxSide) return SFOC_E_UNSUPPORTED;
+    if (Hs * Ws >= kMaxPlane || Hr * Wr >= kMaxPlane) return SFOC_E_UNSUPPORTED;
     if (n == 0) return SFOC_OK;
     if (!desc_sen || !desc_ref || !integ1 || !integ2 || !ips || !cps) return SFOC_E_INVALID_ARG;
     hipError_t e = launch_match(desc_sen, Hs, Ws, desc_ref, Hr, Wr, integ1, integ2, z, dtype, ips, prior, n, m, r,
@@ -189,6 +192,7 @@ int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr, con
     if (rc) return rc;
     rc = check_match_shape(n, m, r);
     if (rc) return rc;
+    if (Hs * Ws >= kMaxPlane || Hr * Wr >= kMaxPlane) return SFOC_E_UNSUPPORTED;
     if (n > 0 && (!ips || !cps)) return SFOC_E_INVALID_ARG;
     const RegisterLayout L = register_layout(Hr, Wr, Hs, Ws, z, dtype_size(p->desc_dtype));
     if (!ws || ws_bytes < L.total) return SFOC_E_WORKSPACE;

@@ -2,22 +2,28 @@
 //
 // One workgroup per interest point.  For each descriptor channel h the
 // template T_h (m x m, zero padded) and the search window S_h (M x M) get a
-// real 2-D FFT of side L >= M in LDS:
-//   rows    : two real rows packed as one complex row, in-place radix-2^2
-//             decimation-in-time FFT over bit-reversed input;
-//   unpack  : the two row spectra separated with the conjugate-symmetry
-//             identity into the half spectrum k2 = 0..L/2, transposed so
-//             that columns are contiguous;
-//   columns : the same FFT along the rows' axis.
-// The template spectrum is kept in registers and the product
-// F(S_h) conj(F(T_h)) is accumulated over channels in registers (summing in
-// the spectrum is exact by linearity, so only one inverse is needed, Eq. 13).
-// The inverse runs columns first, then rows packed in pairs, giving R_ST on
-// the (2r+1)^2 valid offsets.  R_S and R_SS come from four lookups in the
-// float64 integral images of the reference descriptor (Eq. 16); R_T and R_TT
-// are accumulated in float64 while the template is read.  The NCC of Eq. 9
-// is assembled with the variance subtraction in float64, then the argmax,
-// the parabola refinement and the per-CP flags are written.
+// real 2-D FFT of side L >= M, with the spectrum product F(S_h) conj(F(T_h))
+// summed over channels in registers; summing in the spectrum is exact by
+// linearity, so one inverse transform gives R_ST (Eq. 10, 13).
+//
+// Each length-L transform is a two-pass Cooley-Tukey with L = NA * NB:
+//   pass A: a thread holds x[n1 + NB*n2], n2 = 0..NA-1, does an NA-point
+//           DFT in registers and applies the twiddle W_L^(n1*k2);
+//   pass B: a thread holds those results for two mirrored columns k2 and
+//           NA - k2 and does NB-point DFTs, so it ends with the bins k and
+//           L - k together.
+// Rows of the window are real: two rows form one complex row, and the two
+// half spectra are separated in the thread that holds k and L - k.  Of the
+// column transforms, the DC and Nyquist columns (both real) are packed into
+// one complex column and separated the same way.  The spectrum of T_h and
+// the running sum over channels stay in registers; one LDS buffer of
+// L x (L/2 + 1) complex values (padded) carries each 2-D transform.
+//
+// R_S and R_SS come from four lookups in the float64 integral images of the
+// reference descriptor (Eq. 16); R_T and R_TT are accumulated in float64
+// while the template is read.  NCC (Eq. 9) is assembled with the variance
+// subtraction in float64, then the argmax, the parabola refinement and the
+// per-CP flags are written.
 #include "sfoc_dev.h"
 #include "sfoc_plan.h"
 #include "sfoc_trace.h"
@@ -37,136 +43,344 @@ struct MatchArgs {
     int32_t z, dtype, n, m, r;
 };
 
+// Keeps the scheduler from moving work across stage boundaries (it would
+// otherwise hoist the next stage's global loads and raise register pressure).
+SFOC_DEV void stage_fence() { __builtin_amdgcn_sched_barrier(0); }
+// The thread index laundered through an empty asm: index arithmetic derived
+// from it is recomputed inside each stage instead of being hoisted out of
+// the channel loop and kept live (which costs registers, then spills).
+SFOC_DEV int tid_local() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 SFOC_DEV float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 SFOC_DEV float2 cmulc(float2 a, float2 b) {  // a * conj(b)
     return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
+SFOC_DEV float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 SFOC_DEV float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 SFOC_DEV float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+SFOC_DEV float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+SFOC_DEV float2 mul_mi(float2 a) { return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x); }
 
-template <int LOG>
-SFOC_DEV int bitrev(int i) {
-    return (int)(__brev((unsigned)i) >> (32 - LOG));
+// Descriptor element of type DT (0 f32, 1 bf16, 2 f16) at p[i].
+template <int DT>
+SFOC_DEV float ldd(const void* p, int i) {
+    if constexpr (DT == 0) return ((const float*)p)[i];
+    else if constexpr (DT == 1) return bf16_bits_to_f32(((const uint16_t*)p)[i]);
+    else return f16_bits_to_f32(((const uint16_t*)p)[i]);
+}
+template <int DT>
+SFOC_DEV const void* elem_ptr(const void* base, int64_t idx) {
+    return (const char*)base + idx * (DT == 0 ? 4 : 2);
 }
 
-// In-place DIT FFT of nb transforms of length L (input bit-reversed, output
-// natural order), transform b at buf + b * pitch.  tw[k] = exp(-2 pi i k / L);
-// inverse uses conj(tw) (no 1/L scaling).  Two radix-2 stages per LDS pass.
-template <int L, int NT>
-SFOC_DEV void fft_inplace(float2* buf, int nb, int pitch, const float2* tw, bool inverse) {
-    constexpr int LOG = __builtin_ctz(L);
-    const float sg = inverse ? -1.f : 1.f;
-    int s = 0;
-    for (; s + 1 < LOG; s += 2) {
-        const int h = 1 << s;
-        const int tot = nb * (L / 4);
-        for (int e = threadIdx.x; e < tot; e += NT) {
-            const int b = e / (L / 4), q = e - b * (L / 4);
-            const int blk = q >> s, j = q & (h - 1);
-            float2* p = buf + b * pitch + blk * 4 * h + j;
-            float2 x0 = p[0], x1 = p[h], x2 = p[2 * h], x3 = p[3 * h];
-            float2 w = tw[j * (L / (2 * h))];
-            w.y *= sg;
-            float2 t = cmul(w, x1);
-            float2 a0 = cadd(x0, t), a1 = csub(x0, t);
-            t = cmul(w, x3);
-            float2 a2 = cadd(x2, t), a3 = csub(x2, t);
-            float2 w2 = tw[j * (L / (4 * h))];
-            w2.y *= sg;
-            float2 w3 = tw[(j + h) * (L / (4 * h))];
-            w3.y *= sg;
-            t = cmul(w2, a2);
-            p[0] = cadd(a0, t);
-            p[2 * h] = csub(a0, t);
-            t = cmul(w3, a3);
-            p[h] = cadd(a1, t);
-            p[3 * h] = csub(a1, t);
-        }
-        __syncthreads();
+// ---- small DFTs in registers -------------------------------------------
+template <bool INV>
+SFOC_DEV void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+    const float2 t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = mul_mi<INV>(csub(a1, a3));
+    a0 = cadd(t0, t2);
+    a2 = csub(t0, t2);
+    a1 = cadd(t1, t3);
+    a3 = csub(t1, t3);
+}
+
+// x[k] <- sum_n x[n] W_8^(nk), W_8 = exp(-+2 pi i / 8); 2 x 4 split.
+template <bool INV>
+SFOC_DEV void dft8(float2 (&x)[8]) {
+    float2 a0 = x[0], a1 = x[2], a2 = x[4], a3 = x[6];
+    float2 b0 = x[1], b1 = x[3], b2 = x[5], b3 = x[7];
+    dft4<INV>(a0, a1, a2, a3);
+    dft4<INV>(b0, b1, b2, b3);
+    const float h = 0.70710678118654752f;
+    const float sg = INV ? 1.f : -1.f;
+    b1 = cmul(b1, make_float2(h, sg * h));
+    b2 = mul_mi<INV>(b2);
+    b3 = cmul(b3, make_float2(-h, sg * h));
+    x[0] = cadd(a0, b0);
+    x[4] = csub(a0, b0);
+    x[1] = cadd(a1, b1);
+    x[5] = csub(a1, b1);
+    x[2] = cadd(a2, b2);
+    x[6] = csub(a2, b2);
+    x[3] = cadd(a3, b3);
+    x[7] = csub(a3, b3);
+}
+
+// 16-point DFT, 4 x 4 split: n = n1 + 4 n2, k = 4 k1 + k2.
+template <bool INV>
+SFOC_DEV void dft16(float2 (&x)[16]) {
+    const float sg = INV ? 1.f : -1.f;
+    const float c1 = 0.92387953251128676f, s1 = 0.38268343236508977f, h = 0.70710678118654752f;
+    // twiddles W_16^e for e = 0..9
+    const float2 w[10] = {make_float2(1.f, 0.f),  make_float2(c1, sg * s1), make_float2(h, sg * h),
+                          make_float2(s1, sg * c1), make_float2(0.f, sg * 1.f), make_float2(-s1, sg * c1),
+                          make_float2(-h, sg * h), make_float2(-c1, sg * s1), make_float2(-1.f, 0.f),
+                          make_float2(-c1, -sg * s1)};
+    float2 y[4][4];
+#pragma unroll
+    for (int n1 = 0; n1 < 4; ++n1) {
+        float2 a0 = x[n1], a1 = x[n1 + 4], a2 = x[n1 + 8], a3 = x[n1 + 12];
+        dft4<INV>(a0, a1, a2, a3);
+        y[n1][0] = a0;
+        y[n1][1] = a1;
+        y[n1][2] = a2;
+        y[n1][3] = a3;
     }
-    if (s < LOG) {
-        const int h = 1 << s;
-        const int tot = nb * (L / 2);
-        for (int e = threadIdx.x; e < tot; e += NT) {
-            const int b = e / (L / 2), q = e - b * (L / 2);
-            const int blk = q >> s, j = q & (h - 1);
-            float2* p = buf + b * pitch + blk * 2 * h + j;
-            float2 x0 = p[0], x1 = p[h];
-            float2 w = tw[j * (L / (2 * h))];
-            w.y *= sg;
-            const float2 t = cmul(w, x1);
-            p[0] = cadd(x0, t);
-            p[h] = csub(x0, t);
-        }
-        __syncthreads();
+#pragma unroll
+    for (int n1 = 1; n1 < 4; ++n1)
+#pragma unroll
+        for (int k2 = 1; k2 < 4; ++k2) y[n1][k2] = cmul(y[n1][k2], w[n1 * k2]);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+        float2 a0 = y[0][k2], a1 = y[1][k2], a2 = y[2][k2], a3 = y[3][k2];
+        dft4<INV>(a0, a1, a2, a3);
+        x[k2] = a0;
+        x[4 + k2] = a1;
+        x[8 + k2] = a2;
+        x[12 + k2] = a3;
     }
 }
 
-template <int L, int NT>
-struct MatchCfg {
-    static constexpr int LOG = __builtin_ctz(L);
-    static constexpr int H2 = L / 2 + 1;          // half-spectrum columns
-    static constexpr int CP = L + 1;              // column-buffer pitch (float2)
-    static constexpr int NBIN = H2 * L;           // spectrum bins kept
-    static constexpr int NB = (NBIN + NT - 1) / NT;
-    static constexpr size_t lds_bytes = sizeof(float2) * ((size_t)L + (size_t)(L / 2) * L + (size_t)H2 * CP) + 1024;
+template <int N, bool INV>
+SFOC_DEV void dftn(float2 (&x)[N]) {
+    if constexpr (N == 8) dft8<INV>(x);
+    else dft16<INV>(x);
+}
+
+// ---- geometry ----------------------------------------------------------
+template <int L>
+struct Fft;
+template <>
+struct Fft<128> {
+    static constexpr int NA = 16, NB = 8, NT = 512, PITCH = 68;
+};
+template <>
+struct Fft<64> {
+    static constexpr int NA = 8, NB = 8, NT = 128, PITCH = 36;
 };
 
-// Real 2-D FFT of rows [0, nrows) x cols [0, ncols) of one descriptor
-// channel, zero padded to L x L, into colbuf (layout [k2][k1], pitch CP).
-template <int L, int NT>
-SFOC_DEV void real_fft2(const void* desc, int dt, int64_t plane_off, int64_t pitch, int y0, int x0, int nrows,
-                        int ncols, float2* rowbuf, float2* colbuf, const float2* tw, double* s1, double* s2) {
-    using C = MatchCfg<L, NT>;
+template <int L>
+struct MatchCfg {
+    using F = Fft<L>;
+    static constexpr int NA = F::NA, NB = F::NB, NT = F::NT, P = F::PITCH;
+    static constexpr int HA = NA / 2;
+    static constexpr int COLS = L / 2;                     // column transforms (DC+Nyquist packed)
+    static constexpr int RB = COLS * HA / NT;              // pass-B tasks per thread
+    static constexpr int BINS = 2 * NB;                    // bins per pass-B task
+    static_assert(COLS * HA % NT == 0 && COLS * NB % NT == 0, "balanced column passes");
+    static constexpr size_t buf_elems = (size_t)L * P;     // complex
+    static constexpr size_t lds_bytes = sizeof(float2) * (buf_elems + L) + 1024;
+};
+
+// Bin index (within the transform) of value q of a pass-B task with j.
+template <int L>
+SFOC_DEV int bin_of(int j, int q) {
+    using C = MatchCfg<L>;
+    const int k1 = q % C::NB;
+    const int kk = q < C::NB ? j : (j == 0 ? C::HA : C::NA - j);
+    return C::NA * k1 + kk;
+}
+// Packed DC / Nyquist column (C = F_dc + i F_nyq, both Hermitian): replace
+// each mirrored pair of slots (k, L-k) by (F_dc[k], F_nyq[k]).  Self-mirrored
+// slots (k = 0, L/2) already hold (F_dc, F_nyq) as (re, im).
+SFOC_DEV void sep_pair(float2& x, float2& y) {
+    const float2 a = x, b = cconj(y);
+    x = cscale(cadd(a, b), 0.5f);
+    y = cscale(mul_mi<false>(csub(a, b)), 0.5f);
+}
+template <int NB>
+SFOC_DEV void separate_packed(float2 (&u)[NB], float2 (&v)[NB], int j) {
+    if (j == 0) {
+#pragma unroll
+        for (int k1 = 1; k1 < NB / 2; ++k1) sep_pair(u[k1], u[NB - k1]);
+#pragma unroll
+        for (int k1 = 0; k1 < NB / 2; ++k1) sep_pair(v[k1], v[NB - 1 - k1]);
+    } else {
+#pragma unroll
+        for (int k1 = 0; k1 < NB; ++k1) sep_pair(u[k1], v[NB - 1 - k1]);
+    }
+}
+// Inverse of the above on the accumulated products (Q_dc, Q_nyq) -> the
+// packed spectrum P = Q_dc + i Q_nyq at both bins of each pair.
+SFOC_DEV void join_pair(float2& x, float2& y) {
+    const float2 q0 = x, qn = y;
+    x = make_float2(q0.x - qn.y, q0.y + qn.x);
+    y = make_float2(q0.x + qn.y, -q0.y + qn.x);
+}
+template <int NB>
+SFOC_DEV void join_packed(float2 (&u)[NB], float2 (&v)[NB], int j) {
+    if (j == 0) {
+#pragma unroll
+        for (int k1 = 1; k1 < NB / 2; ++k1) join_pair(u[k1], u[NB - k1]);
+#pragma unroll
+        for (int k1 = 0; k1 < NB / 2; ++k1) join_pair(v[k1], v[NB - 1 - k1]);
+    } else {
+#pragma unroll
+        for (int k1 = 0; k1 < NB; ++k1) join_pair(u[k1], v[NB - 1 - k1]);
+    }
+}
+
+// ---- row stage: real rows -> half spectra -------------------------------
+// Rows [0, nrows) x columns [0, ncols) of one descriptor plane, zero padded
+// to L; result: buf row a holds the half spectrum (bins 0..L/2) of row a.
+// s1 / s2 (if given) accumulate the sum and sum of squares of the values.
+template <int L, int DT>
+SFOC_DEV void row_stage(const void* plane, int pitch, int y0, int x0, int nrows, int ncols, float2* buf,
+                        const float2* tw, double* s1, double* s2) {
+    using C = MatchCfg<L>;
+    const int tid = tid_local();
     const int npair = (nrows + 1) / 2;
-    // rows: load (coalesced along x), pack two rows per complex row, bit reverse.
-    for (int e = threadIdx.x; e < npair * L; e += NT) {
-        const int p = e / L, b = e - p * L;
-        float re = 0.f, im = 0.f;
-        if (b < ncols) {
-            const int64_t base = plane_off + (int64_t)(y0 + 2 * p) * pitch + x0 + b;
-            re = load_desc(desc, base, dt);
-            if (2 * p + 1 < nrows) im = load_desc(desc, base + pitch, dt);
-            if (s1) {
-                const double dr = re, di = im;
-                *s1 += dr + di;
-                *s2 += dr * dr + di * di;
+    const int tasksA = npair * C::NB;
+#pragma unroll 1
+    for (int task = tid; task < tasksA; task += C::NT) {
+        const int p = task / C::NB, n1 = task - p * C::NB;
+        float2 x[C::NA];
+        // Branch-free loads with 32-bit offsets from the plane base (a plane
+        // holds < 2^30 elements): the window lies inside the image, so
+        // columns past ncols are clamped to the last one and zeroed after
+        // the load, and a missing second row re-reads the first.
+        const bool two = 2 * p + 1 < nrows;
+        const int oa = (y0 + 2 * p) * pitch + x0;
+        const int ob = oa + (two ? pitch : 0);
+#pragma unroll
+        for (int n2 = 0; n2 < C::NA; ++n2) {
+            const int b = n1 + C::NB * n2;
+            const int bc = b < ncols ? b : ncols - 1;
+            const float re = ldd<DT>(plane, oa + bc), im = ldd<DT>(plane, ob + bc);
+            x[n2] = make_float2(b < ncols ? re : 0.f, (b < ncols && two) ? im : 0.f);
+        }
+        if (s1) {
+            double a = 0.0, q = 0.0;
+#pragma unroll
+            for (int n2 = 0; n2 < C::NA; ++n2) {
+                const double dr = x[n2].x, di = x[n2].y;
+                a += dr + di;
+                q += dr * dr + di * di;
+            }
+            *s1 += a;
+            *s2 += q;
+        }
+        dftn<C::NA, false>(x);
+        float2* reg = buf + 2 * p * C::P;
+#pragma unroll
+        for (int k2 = 0; k2 < C::NA; ++k2)
+            reg[k2 * C::NB + (n1 ^ (k2 & (C::NB - 1)))] = k2 == 0 ? x[0] : cmul(x[k2], tw[n1 * k2]);
+    }
+    __syncthreads();
+    const int tasksB = npair * C::HA;
+    const int rounds = (tasksB + C::NT - 1) / C::NT;
+#pragma unroll 1
+    for (int rd = 0; rd < rounds; ++rd) {
+        const int task = rd * C::NT + tid;
+        const bool act = task < tasksB;
+        const int p = task / C::HA, j = task - p * C::HA;
+        float2 u[C::NB], v[C::NB];
+        float2* reg = buf + 2 * p * C::P;
+        if (act) {
+            const int ka = j, kb = j == 0 ? C::HA : C::NA - j;
+#pragma unroll
+            for (int n1 = 0; n1 < C::NB; ++n1) {
+                u[n1] = reg[ka * C::NB + (n1 ^ (ka & (C::NB - 1)))];
+                v[n1] = reg[kb * C::NB + (n1 ^ (kb & (C::NB - 1)))];
+            }
+            dftn<C::NB, false>(u);
+            dftn<C::NB, false>(v);
+        }
+        __syncthreads();
+        if (act) {
+            // half spectra of the two real rows: A = (X + conj X~)/2, B = -i (X - conj X~)/2
+            float2* ra = buf + (2 * p) * C::P;
+            float2* rb = ra + C::P;
+            const int ka = j, kb = j == 0 ? C::HA : C::NA - j;
+#pragma unroll
+            for (int k1 = 0; k1 <= C::NB / 2; ++k1) {
+                if (k1 < C::NB / 2 || j == 0) {
+                    const float2 za = u[k1];
+                    const float2 zb = cconj(j == 0 ? u[(C::NB - k1) % C::NB] : v[C::NB - 1 - k1]);
+                    const int k = C::NA * k1 + ka;
+                    ra[k] = cscale(cadd(za, zb), 0.5f);
+                    rb[k] = cscale(mul_mi<false>(csub(za, zb)), 0.5f);
+                }
+            }
+#pragma unroll
+            for (int k1 = 0; k1 < C::NB / 2; ++k1) {
+                const float2 za = v[k1];
+                const float2 zb = cconj(j == 0 ? v[C::NB - 1 - k1] : u[C::NB - 1 - k1]);
+                const int k = C::NA * k1 + kb;
+                ra[k] = cscale(cadd(za, zb), 0.5f);
+                rb[k] = cscale(mul_mi<false>(csub(za, zb)), 0.5f);
             }
         }
-        rowbuf[p * L + bitrev<C::LOG>(b)] = make_float2(re, im);
     }
     __syncthreads();
-    fft_inplace<L, NT>(rowbuf, npair, L, tw, false);
-    // unpack the two real-row spectra, transpose to columns, bit reverse rows.
-    for (int e = threadIdx.x; e < C::H2 * L; e += NT) {
-        const int row = e / C::H2, k2 = e - row * C::H2;
-        float2 v = make_float2(0.f, 0.f);
-        if (row < 2 * npair) {
-            const int p = row >> 1;
-            const float2 za = rowbuf[p * L + k2];
-            float2 zb = rowbuf[p * L + ((L - k2) & (L - 1))];
-            zb.y = -zb.y;
-            if ((row & 1) == 0) v = make_float2(0.5f * (za.x + zb.x), 0.5f * (za.y + zb.y));
-            else v = make_float2(0.5f * (za.y - zb.y), -0.5f * (za.x - zb.x));   // -i (za - zb) / 2
+}
+
+// ---- column stage: buf columns -> spectrum bins in registers --------------
+// Column transforms over rows 0..L-1 of columns 1..L/2-1 and of the packed
+// column 0 (forward: DC + i Nyquist taken from columns 0 and L/2; inverse:
+// column 0 as stored).  Rows >= nvalid read as zero.  out[rd][q] receives
+// bin bin_of(j, q) of task rd (column cc = task / HA, j = task % HA):
+// sink(rd, cc, j, u, v) gets values q < NB in u and q >= NB in v (writable).
+template <int L, bool INV, typename Sink>
+SFOC_DEV void col_stage(float2* buf, const float2* tw, int nvalid, Sink&& sink) {
+    using C = MatchCfg<L>;
+    const int tid = tid_local();
+#pragma unroll 1
+    for (int task = tid; task < C::COLS * C::NB; task += C::NT) {
+        const int cc = task / C::NB, n1 = task - cc * C::NB;
+        float2 x[C::NA];
+#pragma unroll
+        for (int n2 = 0; n2 < C::NA; ++n2) {
+            const int row = n1 + C::NB * n2;
+            float2 v = make_float2(0.f, 0.f);
+            if (row < nvalid) {
+                if (cc == 0 && !INV) v = make_float2(buf[row * C::P].x, buf[row * C::P + L / 2].x);
+                else v = buf[row * C::P + cc];
+            }
+            x[n2] = v;
         }
-        colbuf[k2 * C::CP + bitrev<C::LOG>(row)] = v;
+        dftn<C::NA, INV>(x);
+#pragma unroll
+        for (int k2 = 0; k2 < C::NA; ++k2) {
+            float2 w = tw[n1 * k2];
+            if (INV) w.y = -w.y;
+            buf[(n1 + C::NB * k2) * C::P + cc] = k2 == 0 ? x[0] : cmul(x[k2], w);
+        }
     }
     __syncthreads();
-    fft_inplace<L, NT>(colbuf, C::H2, C::CP, tw, false);
+#pragma unroll
+    for (int rd = 0; rd < C::RB; ++rd) {
+        const int task = rd * C::NT + tid;
+        const int cc = task / C::HA, j = task - cc * C::HA;
+        const int ka = j, kb = j == 0 ? C::HA : C::NA - j;
+        float2 u[C::NB], v[C::NB];
+#pragma unroll
+        for (int n1 = 0; n1 < C::NB; ++n1) {
+            u[n1] = buf[(n1 + C::NB * ka) * C::P + cc];
+            v[n1] = buf[(n1 + C::NB * kb) * C::P + cc];
+        }
+        dftn<C::NB, INV>(u);
+        dftn<C::NB, INV>(v);
+        sink(rd, cc, j, u, v);
+    }
 }
 
 SFOC_DEV bool in_image(int64_t y, int64_t x, int h, int w, int64_t H, int64_t W) {
     return y >= 0 && x >= 0 && y + h <= H && x + w <= W;
 }
 
-template <int L, int NT>
-__global__ __launch_bounds__(NT) void match_kernel(const MatchArgs A) {
-    using C = MatchCfg<L, NT>;
+template <int L, int DT>
+__global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchArgs A) {
+    using C = MatchCfg<L>;
     extern __shared__ float4 lds_raw[];
     float2* tw = reinterpret_cast<float2*>(lds_raw);
-    float2* rowbuf = tw + L;
-    float2* colbuf = rowbuf + (L / 2) * L;
-    double* red = reinterpret_cast<double*>(colbuf + C::H2 * C::CP);   // 1 KB scratch
+    float2* buf = tw + L;
+    double* red = reinterpret_cast<double*>(buf + C::buf_elems);   // 1 KB scratch
 
     const int i = blockIdx.x;
     const int t = threadIdx.x;
@@ -188,45 +402,55 @@ __global__ __launch_bounds__(NT) void match_kernel(const MatchArgs A) {
             A.cps[i] = out;
         }
         if (A.ncc)
-            for (int e = t; e < V * V; e += NT) A.ncc[(int64_t)i * V * V + e] = 0.f;
+            for (int e = t; e < V * V; e += C::NT) A.ncc[(int64_t)i * V * V + e] = 0.f;
         return;
     }
-    for (int k = t; k < L; k += NT) {
+    for (int k = t; k < L; k += C::NT) {
         float sn, cs;
         sincospif(-2.0f * (float)k / (float)L, &sn, &cs);
         tw[k] = make_float2(cs, sn);
     }
     __syncthreads();
 
-    float2 ysp[C::NB];   // template spectrum of the current channel
-    float2 acc[C::NB];   // sum over channels of F(S_h) conj(F(T_h))
+    float2 ysp[C::RB][C::BINS];   // template spectrum of the current channel
+    float2 acc[C::RB][C::BINS];   // sum over channels of F(S_h) conj(F(T_h))
 #pragma unroll
-    for (int j = 0; j < C::NB; ++j) acc[j] = make_float2(0.f, 0.f);
+    for (int rd = 0; rd < C::RB; ++rd)
+#pragma unroll
+        for (int q = 0; q < C::BINS; ++q) acc[rd][q] = make_float2(0.f, 0.f);
     double s1 = 0.0, s2 = 0.0;
     const int64_t plane_s = A.Hs * A.Ws, plane_r = A.Hr * A.Wr;
+    const int mpair2 = 2 * ((m + 1) / 2), Mpair2 = 2 * ((M + 1) / 2);
     for (int h = 0; h < A.z; ++h) {
-        real_fft2<L, NT>(A.desc_sen, A.dtype, h * plane_s, A.Ws, (int)ty, (int)tx, m, m, rowbuf, colbuf, tw, &s1, &s2);
+        stage_fence();
+        row_stage<L, DT>(elem_ptr<DT>(A.desc_sen, h * plane_s), (int)A.Ws, (int)ty, (int)tx, m, m, buf, tw, &s1, &s2);
+        stage_fence();
+        col_stage<L, false>(buf, tw, mpair2, [&](int rd, int cc, int j, float2(&u)[C::NB], float2(&v)[C::NB]) {
+            if (cc == 0) separate_packed<C::NB>(u, v, j);
 #pragma unroll
-        for (int j = 0; j < C::NB; ++j) {
-            const int e = t + j * NT;
-            if (e < C::NBIN) {
-                const int k2 = e / L, k1 = e - k2 * L;
-                ysp[j] = colbuf[k2 * C::CP + k1];
+            for (int q = 0; q < C::NB; ++q) {
+                ysp[rd][q] = u[q];
+                ysp[rd][C::NB + q] = v[q];
             }
-        }
+        });
         __syncthreads();
-        real_fft2<L, NT>(A.desc_ref, A.dtype, h * plane_r, A.Wr, (int)sy, (int)sx, M, M, rowbuf, colbuf, tw, nullptr,
+        stage_fence();
+        row_stage<L, DT>(elem_ptr<DT>(A.desc_ref, h * plane_r), (int)A.Wr, (int)sy, (int)sx, M, M, buf, tw, nullptr,
                          nullptr);
+        stage_fence();
+        col_stage<L, false>(buf, tw, Mpair2, [&](int rd, int cc, int j, float2(&u)[C::NB], float2(&v)[C::NB]) {
+            if (cc == 0) separate_packed<C::NB>(u, v, j);
+            const bool self = cc == 0 && j == 0;   // slots 0 and NB/2 hold (F_dc, F_nyq) as reals
 #pragma unroll
-        for (int j = 0; j < C::NB; ++j) {
-            const int e = t + j * NT;
-            if (e < C::NBIN) {
-                const int k2 = e / L, k1 = e - k2 * L;
-                const float2 xs = colbuf[k2 * C::CP + k1];
-                const float2 pr = cmulc(xs, ysp[j]);
-                acc[j] = cadd(acc[j], pr);
+            for (int q = 0; q < C::BINS; ++q) {
+                const float2 xs = q < C::NB ? u[q] : v[q - C::NB];
+                const float2 yt = ysp[rd][q];
+                if ((q == 0 || q == C::NB / 2) && self)
+                    acc[rd][q] = make_float2(fmaf(xs.x, yt.x, acc[rd][q].x), fmaf(xs.y, yt.y, acc[rd][q].y));
+                else
+                    acc[rd][q] = cadd(acc[rd][q], cmulc(xs, yt));
             }
-        }
+        });
         __syncthreads();
     }
 
@@ -244,7 +468,7 @@ __global__ __launch_bounds__(NT) void match_kernel(const MatchArgs A) {
         __syncthreads();
         if (t == 0) {
             double a = 0.0, b = 0.0;
-            for (int w = 0; w < NT / 64; ++w) {
+            for (int w = 0; w < C::NT / 64; ++w) {
                 a += red[2 * w];
                 b += red[2 * w + 1];
             }
@@ -258,62 +482,165 @@ __global__ __launch_bounds__(NT) void match_kernel(const MatchArgs A) {
     const double tau = 1e-12 * mnz;
     const double varT = RTT - RT * RT / mnz;
 
-    // inverse: columns (k1 -> u) for k2 = 0..L/2, then rows (k2 -> v) in pairs.
+    // inverse, columns first: spectrum bins back to LDS (natural order), then
+    // column transforms k1 -> u.
 #pragma unroll
-    for (int j = 0; j < C::NB; ++j) {
-        const int e = t + j * NT;
-        if (e < C::NBIN) {
-            const int k2 = e / L, k1 = e - k2 * L;
-            colbuf[k2 * C::CP + bitrev<C::LOG>(k1)] = acc[j];
+    for (int rd = 0; rd < C::RB; ++rd) {
+        const int task = rd * C::NT + t;
+        const int cc = task / C::HA, j = task - cc * C::HA;
+        if (cc == 0) {
+            float2 u[C::NB], v[C::NB];
+#pragma unroll
+            for (int q = 0; q < C::NB; ++q) {
+                u[q] = acc[rd][q];
+                v[q] = acc[rd][C::NB + q];
+            }
+            join_packed<C::NB>(u, v, j);
+#pragma unroll
+            for (int q = 0; q < C::NB; ++q) {
+                acc[rd][q] = u[q];
+                acc[rd][C::NB + q] = v[q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < C::BINS; ++q) buf[bin_of<L>(j, q) * C::P + cc] = acc[rd][q];
+    }
+    __syncthreads();
+    {
+        float2 zc[C::RB][C::BINS];
+        col_stage<L, true>(buf, tw, L, [&](int rd, int, int, float2(&u)[C::NB], float2(&v)[C::NB]) {
+#pragma unroll
+            for (int q = 0; q < C::NB; ++q) {
+                zc[rd][q] = u[q];
+                zc[rd][C::NB + q] = v[q];
+            }
+        });
+        __syncthreads();
+#pragma unroll
+        for (int rd = 0; rd < C::RB; ++rd) {
+            const int task = rd * C::NT + t;
+            const int cc = task / C::HA, j = task - cc * C::HA;
+#pragma unroll
+            for (int q = 0; q < C::BINS; ++q) {
+                const int u = bin_of<L>(j, q);
+                if (u < V) buf[u * C::P + cc] = zc[rd][q];
+            }
         }
     }
     __syncthreads();
-    fft_inplace<L, NT>(colbuf, C::H2, C::CP, tw, true);
+    // rows: pairs (u, u+1) of Hermitian half spectra -> one complex inverse;
+    // real part row u, imaginary part row u+1.
     const int vpair = (V + 1) / 2;
-    for (int e = t; e < vpair * L; e += NT) {
-        const int p = e / L, k2 = e - p * L;
-        const int u0 = 2 * p, u1 = 2 * p + 1;
-        float2 ha, hb;
-        if (k2 <= L / 2) {
-            ha = colbuf[k2 * C::CP + u0];
-            hb = colbuf[k2 * C::CP + u1];
-        } else {
-            ha = colbuf[(L - k2) * C::CP + u0];
-            hb = colbuf[(L - k2) * C::CP + u1];
-            ha.y = -ha.y;
-            hb.y = -hb.y;
+    {
+        const int tasksA = vpair * C::NB;
+        const int rounds = (tasksA + C::NT - 1) / C::NT;
+        for (int rd = 0; rd < rounds; ++rd) {
+            const int task = rd * C::NT + t;
+            const bool act = task < tasksA;
+            const int p = task / C::NB, n1 = task - p * C::NB;
+            float2 x[C::NA];
+            if (act) {
+                const float2* ra = buf + (2 * p) * C::P;
+                const float2* rb = ra + C::P;
+#pragma unroll
+                for (int n2 = 0; n2 < C::NA; ++n2) {
+                    const int k2 = n1 + C::NB * n2;
+                    float2 ha, hb;
+                    if (k2 == 0) {
+                        ha = make_float2(ra[0].x, 0.f);
+                        hb = make_float2(rb[0].x, 0.f);
+                    } else if (k2 == L / 2) {
+                        ha = make_float2(ra[0].y, 0.f);
+                        hb = make_float2(rb[0].y, 0.f);
+                    } else if (k2 < L / 2) {
+                        ha = ra[k2];
+                        hb = rb[k2];
+                    } else {
+                        ha = cconj(ra[L - k2]);
+                        hb = cconj(rb[L - k2]);
+                    }
+                    x[n2] = make_float2(ha.x - hb.y, ha.y + hb.x);
+                }
+                dftn<C::NA, true>(x);
+            }
+            __syncthreads();
+            if (act) {
+                float2* reg = buf + 2 * p * C::P;
+#pragma unroll
+                for (int k2 = 0; k2 < C::NA; ++k2)
+                    reg[k2 * C::NB + (n1 ^ (k2 & (C::NB - 1)))] = k2 == 0 ? x[0] : cmul(x[k2], cconj(tw[n1 * k2]));
+            }
         }
-        rowbuf[p * L + bitrev<C::LOG>(k2)] = make_float2(ha.x - hb.y, ha.y + hb.x);
+        __syncthreads();
+        const float inv = 1.0f / ((float)L * (float)L);
+        const int tasksB = vpair * C::HA;
+        const int roundsB = (tasksB + C::NT - 1) / C::NT;
+        for (int rd = 0; rd < roundsB; ++rd) {
+            const int task = rd * C::NT + t;
+            const bool act = task < tasksB;
+            const int p = task / C::HA, j = task - p * C::HA;
+            float2 u[C::NB], v[C::NB];
+            float2* reg = buf + 2 * p * C::P;
+            const int ka = j, kb = j == 0 ? C::HA : C::NA - j;
+            if (act) {
+#pragma unroll
+                for (int n1 = 0; n1 < C::NB; ++n1) {
+                    u[n1] = reg[ka * C::NB + (n1 ^ (ka & (C::NB - 1)))];
+                    v[n1] = reg[kb * C::NB + (n1 ^ (kb & (C::NB - 1)))];
+                }
+                dftn<C::NB, true>(u);
+                dftn<C::NB, true>(v);
+            }
+            __syncthreads();
+            if (act) {
+                float* rr = reinterpret_cast<float*>(reg);   // R[2p][v] at rr[v], R[2p+1][v] at rr[L + v]
+#pragma unroll
+                for (int k1 = 0; k1 < C::NB; ++k1) {
+                    const int va = C::NA * k1 + ka, vb = C::NA * k1 + kb;
+                    rr[va] = u[k1].x * inv;
+                    rr[L + va] = u[k1].y * inv;
+                    rr[vb] = v[k1].x * inv;
+                    rr[L + vb] = v[k1].y * inv;
+                }
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    fft_inplace<L, NT>(rowbuf, vpair, L, tw, true);
 
     // NCC (Eq. 9) with integral-image box sums (Eq. 16), float64 variance.
-    float* surf = reinterpret_cast<float*>(colbuf);
-    const float inv = 1.0f / ((float)L * (float)L);
     const int64_t IW = A.Wr + 1;
-    int nonflat = 0, nonfin = 0;
-    float best = -INFINITY;
-    int bidx = 0x7fffffff;
     const bool flatT = !(varT > tau);
     const bool badT = !isfinite(RT) || !isfinite(RTT);
-    for (int e = t; e < V * V; e += NT) {
-        const int u = e / V, v = e - u * V;
-        const float2 rr = rowbuf[(u >> 1) * L + v];
-        const float rst = ((u & 1) ? rr.y : rr.x) * inv;
+    // NCC at offset (u, v); flags: bit 0 non-flat search window, bit 1 non-finite.
+    auto ncc_at = [&](int u, int v, int& fl) -> float {
+        const float* rr = reinterpret_cast<const float*>(buf + (u >> 1) * 2 * C::P);
+        const float rst = rr[(u & 1) * L + v];
         const int64_t y = sy + u, x = sx + v;
         const int64_t a00 = y * IW + x, a01 = a00 + m, a10 = a00 + (int64_t)m * IW, a11 = a10 + m;
         const double RS = A.integ1[a11] - A.integ1[a10] - A.integ1[a01] + A.integ1[a00];
         const double RSS = A.integ2[a11] - A.integ2[a10] - A.integ2[a01] + A.integ2[a00];
         const double varS = RSS - RS * RS / mnz;
         float val = 0.f;
-        if (!isfinite(rst) || !isfinite(RS) || !isfinite(varS)) nonfin = 1;
+        fl = 0;
+        if (!isfinite(rst) || !isfinite(RS) || !isfinite(varS)) fl |= 2;
         if (varS > tau && !flatT) {
-            nonflat = 1;
+            fl |= 1;
             const double num = (double)rst - RS * RT / mnz;
             val = (float)(num / sqrt(varS * varT));
         }
-        surf[e] = val;
+        return val;
+    };
+    int nonflat = 0, nonfin = 0;
+    float best = -INFINITY;
+    int bidx = 0x7fffffff;
+    float* nout = A.ncc ? A.ncc + (int64_t)i * V * V : nullptr;
+    for (int e = t; e < V * V; e += C::NT) {
+        const int u = e / V, v = e - u * V;
+        int fl;
+        const float val = ncc_at(u, v, fl);
+        nonflat |= fl & 1;
+        nonfin |= fl >> 1;
+        if (nout) nout[e] = val;
         if (val > best) {   // strictly greater: the first index wins ties
             best = val;
             bidx = e;
@@ -343,7 +670,7 @@ __global__ __launch_bounds__(NT) void match_kernel(const MatchArgs A) {
         }
         __syncthreads();
         if (t == 0) {
-            for (int w = 1; w < NT / 64; ++w) {
+            for (int w = 1; w < C::NT / 64; ++w) {
                 if (rf[w] > rf[0] || (rf[w] == rf[0] && ri[w] < ri[0])) {
                     rf[0] = rf[w];
                     ri[0] = ri[w];
@@ -358,8 +685,6 @@ __global__ __launch_bounds__(NT) void match_kernel(const MatchArgs A) {
         nonflat = ri[16];
         nonfin = ri[32];
     }
-    if (A.ncc)
-        for (int e = t; e < V * V; e += NT) A.ncc[(int64_t)i * V * V + e] = surf[e];
     if (t == 0) {
         if (badT || (nonfin && !flatT)) {
             out.flags = SFOC_CP_NONFINITE;
@@ -375,9 +700,10 @@ __global__ __launch_bounds__(NT) void match_kernel(const MatchArgs A) {
             if (u == 0 || v == 0 || u == V - 1 || v == V - 1) {
                 out.flags = SFOC_CP_EDGE_PEAK;
             } else {
-                const float c0 = surf[bidx];
-                const float cu = surf[bidx - V], cd = surf[bidx + V];
-                const float cl = surf[bidx - 1], cr = surf[bidx + 1];
+                int fl;
+                const float c0 = best;
+                const float cu = ncc_at(u - 1, v, fl), cd = ncc_at(u + 1, v, fl);
+                const float cl = ncc_at(u, v - 1, fl), cr = ncc_at(u, v + 1, fl);
                 float den = cu - 2.f * c0 + cd;
                 float d = 0.f;
                 if (den < 0.f) d = fminf(0.5f, fmaxf(-0.5f, (cu - cd) / (2.f * den)));
@@ -479,15 +805,15 @@ __global__ __launch_bounds__(kConsNT) void consistency_kernel(sfoc_cp* cps, cons
 }
 
 // ---- launch -------------------------------------------------------------
-template <int L, int NT>
+template <int L, int DT>
 static hipError_t launch_match_L(const MatchArgs& a, hipStream_t st) {
-    using C = MatchCfg<L, NT>;
-    auto kern = match_kernel<L, NT>;
+    using C = MatchCfg<L>;
+    auto kern = match_kernel<L, DT>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)C::lds_bytes);
     if (e != hipSuccess) return e;
     trace_begin(st, SFOC_K_MATCH);
-    hipLaunchKernelGGL(kern, dim3(a.n), dim3(NT), C::lds_bytes, st, a);
+    hipLaunchKernelGGL(kern, dim3(a.n), dim3(C::NT), C::lds_bytes, st, a);
     trace_end(st, SFOC_K_MATCH);
     return hipGetLastError();
 }
@@ -515,8 +841,10 @@ hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void
     a.r = r;
     const int L = fft_size_for(m + 2 * r);
     hipError_t e;
-    if (L == 64) e = launch_match_L<64, 256>(a, st);
-    else if (L == 128) e = launch_match_L<128, 512>(a, st);
+    if (L == 64) e = dtype == 0 ? launch_match_L<64, 0>(a, st)
+                   : dtype == 1 ? launch_match_L<64, 1>(a, st) : launch_match_L<64, 2>(a, st);
+    else if (L == 128) e = dtype == 0 ? launch_match_L<128, 0>(a, st)
+                        : dtype == 1 ? launch_match_L<128, 1>(a, st) : launch_match_L<128, 2>(a, st);
     else return hipErrorInvalidValue;
     if (e != hipSuccess) return e;
     trace_begin(st, SFOC_K_CONSISTENCY);
