@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds for the oracle baseline (0: skip)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (use --gpus 1)", file=sys.stderr)
@@ -114,6 +116,12 @@ def main():
     R = S.Registrar(H, W, H, W, n, m, r, p, device=dev)
     stream = torch.cuda.current_stream()
 
+    if args.copy_mb > 0:
+        src = torch.empty(args.copy_mb << 18, dtype=torch.float32, device=dev).uniform_()
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         R(ref, sen, dips)
     torch.cuda.synchronize()

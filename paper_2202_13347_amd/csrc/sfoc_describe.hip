@@ -34,6 +34,8 @@ struct DescribeGeom {
     int BSP;    // basis / channel side incl. the smoothing halo Q, padded
     int ISX;    // image-region side (BSP + 2R)
     int nrun;   // runs per basis row (BSP / kRun)
+    int BPP;    // LDS row pitch of the basis / channel / row-pass maps (odd)
+    int IPP;    // LDS row pitch of the image region (odd)
     size_t bytes;
 };
 
@@ -42,9 +44,12 @@ static DescribeGeom describe_geom(const DescribeConsts& c) {
     g.BSP = (kTS + 2 * c.Q + kRun - 1) / kRun * kRun;
     g.ISX = g.BSP + 2 * c.R;
     g.nrun = g.BSP / kRun;
-    const size_t img = (size_t)g.ISX * g.ISX;
-    const size_t row = 3 * (size_t)g.ISX * g.BSP;
-    const size_t bas = 5 * (size_t)g.BSP * g.BSP;
+    // Odd pitches spread the rows of a wave's accesses over all LDS banks.
+    g.BPP = g.BSP | 1;
+    g.IPP = g.ISX | 1;
+    const size_t img = (size_t)g.ISX * g.IPP;
+    const size_t row = 3 * (size_t)g.ISX * g.BPP;
+    const size_t bas = 5 * (size_t)g.BSP * g.BPP;
     g.bytes = (img + row + bas) * sizeof(float);
     return g;
 }
@@ -67,6 +72,9 @@ SFOC_DEV void smooth_run_k1_123(const float* ch, int P, float wc, float we, floa
     for (int r = 1; r <= 3; ++r) {
 #pragma unroll
         for (int sgn = -1; sgn <= 1; sgn += 2) {
+            // one tap row's reads in flight at a time keeps registers for the
+            // 4 x z accumulators the caller holds
+            __builtin_amdgcn_sched_barrier(0);
             const float* row = ch + sgn * r * P;
             float u[kRun + 6];
 #pragma unroll
@@ -188,16 +196,16 @@ template <int Z, int CG, bool FAST>
 __global__ __launch_bounds__(kNT, 2) void describe_kernel(const float* __restrict__ img, int H, int W, int64_t ld,
                                                           void* __restrict__ desc, double* __restrict__ integ1,
                                                           double* __restrict__ integ2, const DescribeConsts C,
-                                                          int BSP, int ISX) {
+                                                          int BSP, int ISX, int BPP, int IPP) {
     extern __shared__ float lds[];
     const int t = threadIdx.x;
     const int ty0 = blockIdx.y * kTS, tx0 = blockIdx.x * kTS;
     const int Q = C.Q, R = C.R;
     const int nrun = BSP / kRun;
     float* simg = lds;
-    float* srow = simg + ISX * ISX;
-    float* sbas = srow + 3 * ISX * BSP;
-    const int BB = BSP * BSP;
+    float* srow = simg + ISX * IPP;
+    float* sbas = srow + 3 * ISX * BPP;
+    const int BB = BSP * BPP;   // one basis / channel map
 
     // 1. input region (top-left at tile origin - Q - R), reflect-101 borders.
     {
@@ -207,14 +215,16 @@ __global__ __launch_bounds__(kNT, 2) void describe_kernel(const float* __restric
             const int a = e / ISX, b = e - a * ISX;
             const int gy = inside ? y0 + a : reflect101(y0 + a, H);
             const int gx = inside ? x0 + b : reflect101(x0 + b, W);
-            simg[e] = img[(int64_t)gy * ld + gx];
+            simg[a * IPP + b] = img[(int64_t)gy * ld + gx];
         }
     }
     __syncthreads();
 
     // 2. basis responses Gx, Gy, Gxx, Gyy, Gxy * I summed over sigma, held in
     //    registers by the thread that owns each vertical run of kRun pixels.
-    constexpr int kMaxOwn = 3;   // runs per thread (BSP <= 48 -> 12 * 48 runs)
+    // runs per thread: (BSP / kRun) * BSP runs; BSP = 40 when Q = 3 (the
+    // K = 1, rates 1-3 path), at most 48 otherwise.
+    constexpr int kMaxOwn = FAST ? 2 : 3;
     float bas[kMaxOwn][5][kRun];
 #pragma unroll
     for (int o = 0; o < kMaxOwn; ++o)
@@ -234,24 +244,24 @@ __global__ __launch_bounds__(kNT, 2) void describe_kernel(const float* __restric
         // of this pass is image-region row a + R - rho.
         for (int e = t; e < rows * nrun; e += kNT) {
             const int a = e / nrun, b0 = (e - a * nrun) * kRun;
-            const float* p = simg + (a + R - rho) * ISX + (b0 + R);
+            const float* p = simg + (a + R - rho) * IPP + (b0 + R);
             float og[kRun], od[kRun], odd[kRun];
 #define ROW_T(RR) row_run<RR>(p, tg, td, tdd, og, od, odd)
             SFOC_RADIUS_SWITCH(rho, ROW_T, row_run_any(p, rho, tg, td, tdd, og, od, odd))
 #undef ROW_T
-            float* w = srow + a * BSP + b0;
+            float* w = srow + a * BPP + b0;
 #pragma unroll
             for (int j = 0; j < kRun; ++j) {
                 w[j] = cn * og[j];
-                w[rows * BSP + j] = cn * od[j];
-                w[2 * rows * BSP + j] = cn * odd[j];
+                w[rows * BPP + j] = cn * od[j];
+                w[2 * rows * BPP + j] = cn * odd[j];
             }
         }
         __syncthreads();
         // column pass on vertical runs; output row a reads pass rows a + rho + k.
         const float* rg = srow;
-        const float* rd = srow + rows * BSP;
-        const float* rdd = srow + 2 * rows * BSP;
+        const float* rd = srow + rows * BPP;
+        const float* rdd = srow + 2 * rows * BPP;
         const int use = C.use[s];
 #pragma unroll
         for (int o = 0; o < kMaxOwn; ++o) {
@@ -259,20 +269,20 @@ __global__ __launch_bounds__(kNT, 2) void describe_kernel(const float* __restric
             if (e < ncolrun) {
                 const int b = e % BSP, a0 = (e / BSP) * kRun;
                 float bx[kRun], by[kRun], bxx[kRun], byy[kRun], bxy[kRun], dummy[kRun];
-                const int c0 = (a0 + rho) * BSP + b;
+                const int c0 = (a0 + rho) * BPP + b;
                 // rg -> By (odd d), Byy (even dd); rd -> Bx (even g), Bxy (odd d);
                 // rdd -> Bxx (even g).
 #define COL_T(RR)                                                \
     do {                                                         \
-        col_run<RR>(rg + c0, BSP, tdd, td, byy, by);             \
-        col_run<RR>(rd + c0, BSP, tg, td, bx, bxy);              \
-        col_run<RR>(rdd + c0, BSP, tg, nullptr, bxx, dummy);     \
+        col_run<RR>(rg + c0, BPP, tdd, td, byy, by);             \
+        col_run<RR>(rd + c0, BPP, tg, td, bx, bxy);              \
+        col_run<RR>(rdd + c0, BPP, tg, nullptr, bxx, dummy);     \
     } while (0)
 #define COL_ANY                                                  \
     do {                                                         \
-        col_run_any(rg + c0, BSP, rho, tdd, td, byy, by);        \
-        col_run_any(rd + c0, BSP, rho, tg, td, bx, bxy);         \
-        col_run_any(rdd + c0, BSP, rho, tg, nullptr, bxx, dummy); \
+        col_run_any(rg + c0, BPP, rho, tdd, td, byy, by);        \
+        col_run_any(rd + c0, BPP, rho, tg, td, bx, bxy);         \
+        col_run_any(rdd + c0, BPP, rho, tg, nullptr, bxx, dummy); \
     } while (0)
                 SFOC_RADIUS_SWITCH(rho, COL_T, COL_ANY)
 #undef COL_T
@@ -302,7 +312,7 @@ __global__ __launch_bounds__(kNT, 2) void describe_kernel(const float* __restric
 #pragma unroll
             for (int m = 0; m < 5; ++m)
 #pragma unroll
-                for (int j = 0; j < kRun; ++j) sbas[m * BB + (a0 + j) * BSP + b] = bas[o][m][j];
+                for (int j = 0; j < kRun; ++j) sbas[m * BB + (a0 + j) * BPP + b] = bas[o][m][j];
         }
     }
     __syncthreads();
@@ -314,13 +324,17 @@ __global__ __launch_bounds__(kNT, 2) void describe_kernel(const float* __restric
     const int N = C.N;
     const int B = 2 * C.K + 1;
     const int oy = t / (kTS / kRun), ox0 = (t % (kTS / kRun)) * kRun;
-    const int obase = (oy + Q) * BSP + ox0 + Q;
     const int BSr = kTS + 2 * Q;   // rows / columns actually read
 #pragma unroll
     for (int c0 = 0; c0 < Z; c0 += CG) {
-        for (int e = t; e < BSr * BSr; e += kNT) {
+        // thread index laundered per group: keeps the group's LDS addresses
+        // from being hoisted (and kept live) across the whole channel loop.
+        int tl = t;
+        asm volatile("" : "+v"(tl));
+        const int obase = (tl / (kTS / kRun) + Q) * BPP + (tl % (kTS / kRun)) * kRun + Q;
+        for (int e = tl; e < BSr * BSr; e += kNT) {
             const int a = e / BSr, b = e - a * BSr;
-            const int idx = a * BSP + b;
+            const int idx = a * BPP + b;
 #pragma unroll
             for (int cc = 0; cc < CG; ++cc) {
                 const int c = c0 + cc;
@@ -347,7 +361,10 @@ __global__ __launch_bounds__(kNT, 2) void describe_kernel(const float* __restric
                 const float* w = (c < N) ? C.w1 : C.w2;
                 const float* ch = schan + cc * BB + obase;
                 if (FAST) {
-                    smooth_run_k1_123(ch, BSP, w[4], w[1], w[0], acc[c]);
+                    smooth_run_k1_123(ch, BPP, w[4], w[1], w[0], acc[c]);
+                    // one channel's reads in flight at a time (the scheduler
+                    // would otherwise hoist all of a group's LDS reads)
+                    __builtin_amdgcn_sched_barrier(0);
                 } else {
 #pragma unroll
                     for (int j = 0; j < kRun; ++j) {
@@ -356,7 +373,7 @@ __global__ __launch_bounds__(kNT, 2) void describe_kernel(const float* __restric
                             const int r = C.dil[di];
                             for (int i = 0; i < B; ++i)
                                 for (int jj = 0; jj < B; ++jj)
-                                    a = fmaf(w[i * B + jj], ch[(i - C.K) * r * BSP + (jj - C.K) * r + j], a);
+                                    a = fmaf(w[i * B + jj], ch[(i - C.K) * r * BPP + (jj - C.K) * r + j], a);
                         }
                         acc[c][j] = a;
                     }
@@ -541,7 +558,8 @@ static hipError_t launch_describe_zf(const float* img, int H, int W, int64_t ld,
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.bytes);
     if (e != hipSuccess) return e;
     trace_begin(st, SFOC_K_DESCRIBE);
-    hipLaunchKernelGGL(kern, grid, dim3(kNT), g.bytes, st, img, H, W, ld, desc, i1, i2, c, g.BSP, g.ISX);
+    hipLaunchKernelGGL(kern, grid, dim3(kNT), g.bytes, st, img, H, W, ld, desc, i1, i2, c, g.BSP, g.ISX, g.BPP,
+                       g.IPP);
     trace_end(st, SFOC_K_DESCRIBE);
     return hipGetLastError();
 }
