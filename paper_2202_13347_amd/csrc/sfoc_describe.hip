@@ -196,11 +196,17 @@ template <int Z, int CG, bool FAST>
 __global__ __launch_bounds__(kNT, 2) void describe_kernel(const float* __restrict__ img, int H, int W, int64_t ld,
                                                           void* __restrict__ desc, double* __restrict__ integ1,
                                                           double* __restrict__ integ2, const DescribeConsts C,
-                                                          int BSP, int ISX, int BPP, int IPP) {
+                                                          int BSP_, int ISX, int BPP_, int IPP) {
     extern __shared__ float lds[];
     const int t = threadIdx.x;
     const int ty0 = blockIdx.y * kTS, tx0 = blockIdx.x * kTS;
-    const int Q = C.Q, R = C.R;
+    // The K = 1, rates 1..3 path has Q = 3: its tile geometry is compile-time,
+    // so the index arithmetic below divides by constants.
+    constexpr int kFastQ = 3, kFastBSP = (kTS + 2 * kFastQ + kRun - 1) / kRun * kRun;
+    const int Q = FAST ? kFastQ : C.Q;
+    const int BSP = FAST ? kFastBSP : BSP_;
+    const int BPP = FAST ? (kFastBSP | 1) : BPP_;
+    const int R = C.R;
     const int nrun = BSP / kRun;
     float* simg = lds;
     float* srow = simg + ISX * IPP;
@@ -211,11 +217,13 @@ __global__ __launch_bounds__(kNT, 2) void describe_kernel(const float* __restric
     {
         const int y0 = ty0 - Q - R, x0 = tx0 - Q - R;
         const bool inside = y0 >= 0 && x0 >= 0 && y0 + ISX <= H && x0 + ISX <= W;
-        for (int e = t; e < ISX * ISX; e += kNT) {
-            const int a = e / ISX, b = e - a * ISX;
+        for (int a = t / 64; a < ISX; a += kNT / 64) {
             const int gy = inside ? y0 + a : reflect101(y0 + a, H);
-            const int gx = inside ? x0 + b : reflect101(x0 + b, W);
-            simg[a * IPP + b] = img[(int64_t)gy * ld + gx];
+            const float* row = img + (int64_t)gy * ld;
+            for (int b = t % 64; b < ISX; b += 64) {
+                const int gx = inside ? x0 + b : reflect101(x0 + b, W);
+                simg[a * IPP + b] = row[gx];
+            }
         }
     }
     __syncthreads();

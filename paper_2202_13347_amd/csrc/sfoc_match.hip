@@ -157,7 +157,7 @@ template <int L>
 struct Fft;
 template <>
 struct Fft<128> {
-    static constexpr int NA = 16, NB = 8, NT = 512, PITCH = 68;
+    static constexpr int NA = 16, NB = 8, NT = 256, PITCH = 68;
 };
 template <>
 struct Fft<64> {
@@ -412,7 +412,6 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
     }
     __syncthreads();
 
-    float2 ysp[C::RB][C::BINS];   // template spectrum of the current channel
     float2 acc[C::RB][C::BINS];   // sum over channels of F(S_h) conj(F(T_h))
 #pragma unroll
     for (int rd = 0; rd < C::RB; ++rd)
@@ -421,30 +420,34 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
     double s1 = 0.0, s2 = 0.0;
     const int64_t plane_s = A.Hs * A.Ws, plane_r = A.Hr * A.Wr;
     const int mpair2 = 2 * ((m + 1) / 2), Mpair2 = 2 * ((M + 1) / 2);
+    // Per channel: the search window first (only the running sum is live
+    // during its larger row stage), its spectrum kept in registers, then the
+    // template, whose column stage accumulates F(S_h) conj(F(T_h)).
+    float2 xsp[C::RB][C::BINS];   // search-window spectrum of the current channel
     for (int h = 0; h < A.z; ++h) {
-        stage_fence();
-        row_stage<L, DT>(elem_ptr<DT>(A.desc_sen, h * plane_s), (int)A.Ws, (int)ty, (int)tx, m, m, buf, tw, &s1, &s2);
-        stage_fence();
-        col_stage<L, false>(buf, tw, mpair2, [&](int rd, int cc, int j, float2(&u)[C::NB], float2(&v)[C::NB]) {
-            if (cc == 0) separate_packed<C::NB>(u, v, j);
-#pragma unroll
-            for (int q = 0; q < C::NB; ++q) {
-                ysp[rd][q] = u[q];
-                ysp[rd][C::NB + q] = v[q];
-            }
-        });
-        __syncthreads();
         stage_fence();
         row_stage<L, DT>(elem_ptr<DT>(A.desc_ref, h * plane_r), (int)A.Wr, (int)sy, (int)sx, M, M, buf, tw, nullptr,
                          nullptr);
         stage_fence();
         col_stage<L, false>(buf, tw, Mpair2, [&](int rd, int cc, int j, float2(&u)[C::NB], float2(&v)[C::NB]) {
             if (cc == 0) separate_packed<C::NB>(u, v, j);
+#pragma unroll
+            for (int q = 0; q < C::NB; ++q) {
+                xsp[rd][q] = u[q];
+                xsp[rd][C::NB + q] = v[q];
+            }
+        });
+        __syncthreads();
+        stage_fence();
+        row_stage<L, DT>(elem_ptr<DT>(A.desc_sen, h * plane_s), (int)A.Ws, (int)ty, (int)tx, m, m, buf, tw, &s1, &s2);
+        stage_fence();
+        col_stage<L, false>(buf, tw, mpair2, [&](int rd, int cc, int j, float2(&u)[C::NB], float2(&v)[C::NB]) {
+            if (cc == 0) separate_packed<C::NB>(u, v, j);
             const bool self = cc == 0 && j == 0;   // slots 0 and NB/2 hold (F_dc, F_nyq) as reals
 #pragma unroll
             for (int q = 0; q < C::BINS; ++q) {
-                const float2 xs = q < C::NB ? u[q] : v[q - C::NB];
-                const float2 yt = ysp[rd][q];
+                const float2 xs = xsp[rd][q];
+                const float2 yt = q < C::NB ? u[q] : v[q - C::NB];
                 if ((q == 0 || q == C::NB / 2) && self)
                     acc[rd][q] = make_float2(fmaf(xs.x, yt.x, acc[rd][q].x), fmaf(xs.y, yt.y, acc[rd][q].y));
                 else

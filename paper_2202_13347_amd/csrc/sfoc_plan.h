@@ -5,7 +5,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
-#include "../../include/sfoc.h"
+#include "sfoc.h"
 
 namespace sfoc {
 

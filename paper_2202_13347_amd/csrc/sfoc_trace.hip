@@ -3,7 +3,7 @@
 
 #include <vector>
 
-#include "../../include/sfoc.h"
+#include "sfoc.h"
 
 namespace sfoc {
 
