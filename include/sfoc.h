@@ -182,8 +182,12 @@ int sfoc_describe(const float* img, int64_t H, int64_t W, int64_t ld,
  *  prior               n x 2 int32 (dy, dx) search-window offsets, or NULL.
  *  ncc                 n x (2r+1) x (2r+1) float32 surfaces, or NULL.  (output)
  *  cps                 n records.                                      (output)
- * Limits: 3 <= m, 1 <= r, m + 2r <= 128, each image below 2^30 pixels
- * (SFOC_E_UNSUPPORTED beyond).
+ * Search windows up to 128 x 128 (m + 2r <= 128) are one transform; larger
+ * ones split the offsets into blocks whose windows fit 128 x 128 and need
+ * the workspace sfoc_match_workspace reports (per-CP surfaces and block
+ * records; 0 bytes otherwise).
+ * Limits: 3 <= m, 1 <= r <= 511, m <= 126 when m + 2r > 128, each image
+ * below 2^30 pixels (SFOC_E_UNSUPPORTED beyond).
  * n == 0 is valid and enqueues nothing.
  */
 int sfoc_match_workspace(int32_t n, int32_t m, int32_t r, int32_t z, size_t* bytes);
@@ -225,7 +229,8 @@ int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr,
 #define SFOC_K_INTEGRAL     1
 #define SFOC_K_MATCH        2
 #define SFOC_K_CONSISTENCY  3
-#define SFOC_K_COUNT        4
+#define SFOC_K_PEAK         4
+#define SFOC_K_COUNT        5
 #define SFOC_TRACE_MAX   4096
 int sfoc_trace_enable(int on);
 int sfoc_trace_collect(double* ms, int64_t* counts, int n);

@@ -10,7 +10,8 @@ hipError_t launch_describe(const float* img, int H, int W, int64_t ld, void* des
 hipError_t launch_integral(double* i1, double* i2, int H, int W, double* ws, hipStream_t st);
 hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void* desc_ref, int64_t Hr, int64_t Wr,
                         const double* i1, const double* i2, int z, int dtype, const int32_t* ips,
-                        const int32_t* prior, int n, int m, int r, float* ncc, sfoc_cp* cps, hipStream_t st);
+                        const int32_t* prior, int n, int m, int r, float* ncc, sfoc_cp* cps, void* ws,
+                        hipStream_t st);
 
 static thread_local hipError_t g_last_hip = hipSuccess;
 
@@ -35,15 +36,16 @@ static int check_image(const void* img, int64_t H, int64_t W, int64_t ld) {
 
 static int check_match_shape(int32_t n, int32_t m, int32_t r) {
     if (n < 0 || m < 3 || r < 1) return SFOC_E_INVALID_ARG;
-    if (fft_size_for(m + 2 * r) == 0) return SFOC_E_UNSUPPORTED;
+    if (match_plan(n, m, r).L == 0) return SFOC_E_UNSUPPORTED;
     return SFOC_OK;
 }
 
 struct RegisterLayout {
-    size_t desc_ref, desc_sen, integ1, integ2, scan, total;
+    size_t desc_ref, desc_sen, integ1, integ2, scan, match, total;
 };
 
-static RegisterLayout register_layout(int64_t Hr, int64_t Wr, int64_t Hs, int64_t Ws, int32_t z, size_t es) {
+static RegisterLayout register_layout(int64_t Hr, int64_t Wr, int64_t Hs, int64_t Ws, int32_t z, size_t es,
+                                      size_t match_ws) {
     RegisterLayout L;
     size_t off = 0;
     L.desc_ref = off;
@@ -56,6 +58,8 @@ static RegisterLayout register_layout(int64_t Hr, int64_t Wr, int64_t Hs, int64_
     off = align_up(off + (size_t)(Hr + 1) * (Wr + 1) * sizeof(double), 256);
     L.scan = off;
     off = align_up(off + describe_ws_bytes(Hr, Wr), 256);
+    L.match = off;
+    off = align_up(off + match_ws, 256);
     L.total = off;
     return L;
 }
@@ -144,7 +148,7 @@ int sfoc_match_workspace(int32_t n, int32_t m, int32_t r, int32_t z, size_t* byt
     if (!bytes || z < 1) return SFOC_E_INVALID_ARG;
     int rc = check_match_shape(n, m, r);
     if (rc) return rc;
-    *bytes = 0;
+    *bytes = match_plan(n, m, r).ws_bytes;
     return SFOC_OK;
 }
 
@@ -152,8 +156,6 @@ int sfoc_fastncc_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void*
                        const double* integ1, const double* integ2, int32_t z, int32_t dtype, const int32_t* ips,
                        const int32_t* prior, int32_t n, int32_t m, int32_t r, float* ncc, sfoc_cp* cps, void* ws,
                        size_t ws_bytes, void* stream) {
-    (void)ws;
-    (void)ws_bytes;
     int rc = check_match_shape(n, m, r);
     if (rc) return rc;
     if (z < 1 || dtype_size(dtype) == 0) return SFOC_E_INVALID_ARG;
@@ -162,8 +164,10 @@ int sfoc_fastncc_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void*
     if (Hs * Ws >= kMaxPlane || Hr * Wr >= kMaxPlane) return SFOC_E_UNSUPPORTED;
     if (n == 0) return SFOC_OK;
     if (!desc_sen || !desc_ref || !integ1 || !integ2 || !ips || !cps) return SFOC_E_INVALID_ARG;
+    const size_t need = match_plan(n, m, r).ws_bytes;
+    if (need > 0 && (!ws || ws_bytes < need)) return SFOC_E_WORKSPACE;
     hipError_t e = launch_match(desc_sen, Hs, Ws, desc_ref, Hr, Wr, integ1, integ2, z, dtype, ips, prior, n, m, r,
-                                ncc, cps, (hipStream_t)stream);
+                                ncc, cps, ws, (hipStream_t)stream);
     return hip_status(e);
 }
 
@@ -175,7 +179,7 @@ int sfoc_register_workspace(int64_t Hr, int64_t Wr, int64_t Hs, int64_t Ws, int3
     if (rc) return rc;
     rc = check_match_shape(n, m, r);
     if (rc) return rc;
-    *bytes = register_layout(Hr, Wr, Hs, Ws, z, dtype_size(p->desc_dtype)).total;
+    *bytes = register_layout(Hr, Wr, Hs, Ws, z, dtype_size(p->desc_dtype), match_plan(n, m, r).ws_bytes).total;
     return SFOC_OK;
 }
 
@@ -194,7 +198,7 @@ int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr, con
     if (rc) return rc;
     if (Hs * Ws >= kMaxPlane || Hr * Wr >= kMaxPlane) return SFOC_E_UNSUPPORTED;
     if (n > 0 && (!ips || !cps)) return SFOC_E_INVALID_ARG;
-    const RegisterLayout L = register_layout(Hr, Wr, Hs, Ws, z, dtype_size(p->desc_dtype));
+    const RegisterLayout L = register_layout(Hr, Wr, Hs, Ws, z, dtype_size(p->desc_dtype), match_plan(n, m, r).ws_bytes);
     if (!ws || ws_bytes < L.total) return SFOC_E_WORKSPACE;
     char* base = (char*)ws;
     void* dref = base + L.desc_ref;
@@ -209,7 +213,8 @@ int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr, con
     if (e == hipSuccess) e = launch_describe(sen, (int)Hs, (int)Ws, lds, dsen, nullptr, nullptr, c, st);
     if (e != hipSuccess) return hip_status(e);
     if (n == 0) return SFOC_OK;
-    e = launch_match(dsen, Hs, Ws, dref, Hr, Wr, i1, i2, z, p->desc_dtype, ips, prior, n, m, r, ncc, cps, st);
+    e = launch_match(dsen, Hs, Ws, dref, Hr, Wr, i1, i2, z, p->desc_dtype, ips, prior, n, m, r, ncc, cps,
+                     base + L.match, st);
     return hip_status(e);
 }
 

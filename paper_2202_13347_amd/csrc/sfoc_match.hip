@@ -39,9 +39,15 @@ struct MatchArgs {
     const int32_t* prior;
     float* ncc;
     sfoc_cp* cps;
+    float* surf;      // n x V x V scratch surfaces when the offsets are split and ncc == NULL
+    float4* blk;      // per (IP, offset block): best score, its index, flags
     int64_t Hs, Ws, Hr, Wr;
     int32_t z, dtype, n, m, r;
+    int32_t nbu, nbv, Vb;   // offset blocks per axis and offsets per block
 };
+
+// Per-block flags of a split surface.
+constexpr int kBlkNonflat = 1, kBlkNonfin = 2, kBlkFlatT = 4, kBlkBadT = 8, kBlkOOB = 16;
 
 // Keeps the scheduler from moving work across stage boundaries (it would
 // otherwise hoist the next stage's global loads and raise register pressure).
@@ -382,13 +388,24 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
     float2* buf = tw + L;
     double* red = reinterpret_cast<double*>(buf + C::buf_elems);   // 1 KB scratch
 
-    const int i = blockIdx.x;
+    // Work item: interest point i, offset block (bu, bv).  With M <= L there
+    // is one block and this workgroup finishes the CP; otherwise each block
+    // covers offsets [u0, u0 + Vu) x [v0, v0 + Vv) with a search window of
+    // (m + Vu - 1) x (m + Vv - 1) <= L x L, writes its part of the surface and
+    // its best score, and peak_kernel combines the blocks.
+    const int nblk = A.nbu * A.nbv;
+    const int i = blockIdx.x / nblk, bq = blockIdx.x - i * nblk;
+    const int bu = bq / A.nbv, bv = bq - bu * A.nbv;
     const int t = threadIdx.x;
     const int m = A.m, r = A.r, M = m + 2 * r, V = 2 * r + 1;
+    const int u0 = bu * A.Vb, v0 = bv * A.Vb;
+    const int Vu = min(A.Vb, V - u0), Vv = min(A.Vb, V - v0);
+    const int Mu = m + Vu - 1, Mv = m + Vv - 1;
     const int py = A.ips[2 * i], px = A.ips[2 * i + 1];
     const int pry = A.prior ? A.prior[2 * i] : 0, prx = A.prior ? A.prior[2 * i + 1] : 0;
     const int64_t ty = (int64_t)py - m / 2, tx = (int64_t)px - m / 2;
     const int64_t sy = ty - r + pry, sx = tx - r + prx;
+    float* nout = A.ncc ? A.ncc + (int64_t)i * V * V : (nblk > 1 ? A.surf + (int64_t)i * V * V : nullptr);
     sfoc_cp out;
     out.sen_row = py;
     out.sen_col = px;
@@ -398,11 +415,18 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
     out.flags = 0;
     if (!in_image(ty, tx, m, m, A.Hs, A.Ws) || !in_image(sy, sx, M, M, A.Hr, A.Wr)) {
         if (t == 0) {
-            out.flags = SFOC_CP_OOB;
-            A.cps[i] = out;
+            if (nblk == 1) {
+                out.flags = SFOC_CP_OOB;
+                A.cps[i] = out;
+            } else {
+                A.blk[blockIdx.x] = make_float4(0.f, __int_as_float(0), __int_as_float(kBlkOOB), 0.f);
+            }
         }
-        if (A.ncc)
-            for (int e = t; e < V * V; e += C::NT) A.ncc[(int64_t)i * V * V + e] = 0.f;
+        if (nout)
+            for (int e = t; e < Vu * Vv; e += C::NT) {
+                const int u = e / Vv, v = e - u * Vv;
+                nout[(u0 + u) * V + v0 + v] = 0.f;
+            }
         return;
     }
     for (int k = t; k < L; k += C::NT) {
@@ -419,15 +443,15 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
         for (int q = 0; q < C::BINS; ++q) acc[rd][q] = make_float2(0.f, 0.f);
     double s1 = 0.0, s2 = 0.0;
     const int64_t plane_s = A.Hs * A.Ws, plane_r = A.Hr * A.Wr;
-    const int mpair2 = 2 * ((m + 1) / 2), Mpair2 = 2 * ((M + 1) / 2);
+    const int mpair2 = 2 * ((m + 1) / 2), Mpair2 = 2 * ((Mu + 1) / 2);
     // Per channel: the search window first (only the running sum is live
     // during its larger row stage), its spectrum kept in registers, then the
     // template, whose column stage accumulates F(S_h) conj(F(T_h)).
     float2 xsp[C::RB][C::BINS];   // search-window spectrum of the current channel
     for (int h = 0; h < A.z; ++h) {
         stage_fence();
-        row_stage<L, DT>(elem_ptr<DT>(A.desc_ref, h * plane_r), (int)A.Wr, (int)sy, (int)sx, M, M, buf, tw, nullptr,
-                         nullptr);
+        row_stage<L, DT>(elem_ptr<DT>(A.desc_ref, h * plane_r), (int)A.Wr, (int)(sy + u0), (int)(sx + v0), Mu, Mv,
+                         buf, tw, nullptr, nullptr);
         stage_fence();
         col_stage<L, false>(buf, tw, Mpair2, [&](int rd, int cc, int j, float2(&u)[C::NB], float2(&v)[C::NB]) {
             if (cc == 0) separate_packed<C::NB>(u, v, j);
@@ -526,14 +550,14 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
 #pragma unroll
             for (int q = 0; q < C::BINS; ++q) {
                 const int u = bin_of<L>(j, q);
-                if (u < V) buf[u * C::P + cc] = zc[rd][q];
+                if (u < Vu) buf[u * C::P + cc] = zc[rd][q];
             }
         }
     }
     __syncthreads();
     // rows: pairs (u, u+1) of Hermitian half spectra -> one complex inverse;
     // real part row u, imaginary part row u+1.
-    const int vpair = (V + 1) / 2;
+    const int vpair = (Vu + 1) / 2;
     {
         const int tasksA = vpair * C::NB;
         const int rounds = (tasksA + C::NT - 1) / C::NT;
@@ -615,10 +639,11 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
     const bool flatT = !(varT > tau);
     const bool badT = !isfinite(RT) || !isfinite(RTT);
     // NCC at offset (u, v); flags: bit 0 non-flat search window, bit 1 non-finite.
+    // (u, v) are offsets within this block; the surface offset is (u0 + u, v0 + v).
     auto ncc_at = [&](int u, int v, int& fl) -> float {
         const float* rr = reinterpret_cast<const float*>(buf + (u >> 1) * 2 * C::P);
         const float rst = rr[(u & 1) * L + v];
-        const int64_t y = sy + u, x = sx + v;
+        const int64_t y = sy + u0 + u, x = sx + v0 + v;
         const int64_t a00 = y * IW + x, a01 = a00 + m, a10 = a00 + (int64_t)m * IW, a11 = a10 + m;
         const double RS = A.integ1[a11] - A.integ1[a10] - A.integ1[a01] + A.integ1[a00];
         const double RSS = A.integ2[a11] - A.integ2[a10] - A.integ2[a01] + A.integ2[a00];
@@ -636,17 +661,17 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
     int nonflat = 0, nonfin = 0;
     float best = -INFINITY;
     int bidx = 0x7fffffff;
-    float* nout = A.ncc ? A.ncc + (int64_t)i * V * V : nullptr;
-    for (int e = t; e < V * V; e += C::NT) {
-        const int u = e / V, v = e - u * V;
+    for (int e = t; e < Vu * Vv; e += C::NT) {
+        const int u = e / Vv, v = e - u * Vv;
         int fl;
         const float val = ncc_at(u, v, fl);
         nonflat |= fl & 1;
         nonfin |= fl >> 1;
-        if (nout) nout[e] = val;
+        const int eg = (u0 + u) * V + v0 + v;   // row-major index on the whole surface
+        if (nout) nout[eg] = val;
         if (val > best) {   // strictly greater: the first index wins ties
             best = val;
-            bidx = e;
+            bidx = eg;
         }
     }
     // block reduce (max value, min index), and the flags.
@@ -688,6 +713,14 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
         nonflat = ri[16];
         nonfin = ri[32];
     }
+    if (nblk > 1) {
+        if (t == 0) {
+            const int fl = (nonflat ? kBlkNonflat : 0) | (nonfin ? kBlkNonfin : 0) | (flatT ? kBlkFlatT : 0) |
+                           (badT ? kBlkBadT : 0);
+            A.blk[blockIdx.x] = make_float4(best, __int_as_float(bidx), __int_as_float(fl), 0.f);
+        }
+        return;
+    }
     if (t == 0) {
         if (badT || (nonfin && !flatT)) {
             out.flags = SFOC_CP_NONFINITE;
@@ -719,6 +752,65 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
         }
         A.cps[i] = out;
     }
+}
+
+// ---- combining offset blocks --------------------------------------------
+// One thread per interest point: the best score over its blocks (ties: the
+// smallest row-major surface index), the flags, and the parabola from the
+// surface the blocks wrote.  Same decisions as the single-block path.
+__global__ __launch_bounds__(256) void peak_kernel(const MatchArgs A) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    const int nblk = A.nbu * A.nbv;
+    const int r = A.r, V = 2 * r + 1;
+    sfoc_cp out;
+    out.sen_row = A.ips[2 * i];
+    out.sen_col = A.ips[2 * i + 1];
+    out.dy = out.dx = 0;
+    out.sub_dy = out.sub_dx = 0.f;
+    out.score = 0.f;
+    out.flags = 0;
+    float best = -INFINITY;
+    int bidx = 0x7fffffff, fl = 0;
+    for (int b = 0; b < nblk; ++b) {
+        const float4 q = A.blk[(int64_t)i * nblk + b];
+        const int qi = __float_as_int(q.y);
+        fl |= __float_as_int(q.z);
+        if (q.x > best || (q.x == best && qi < bidx)) {
+            best = q.x;
+            bidx = qi;
+        }
+    }
+    const float* surf = (A.ncc ? A.ncc : A.surf) + (int64_t)i * V * V;
+    if (fl & kBlkOOB) {
+        out.flags = SFOC_CP_OOB;
+    } else if ((fl & kBlkBadT) || ((fl & kBlkNonfin) && !(fl & kBlkFlatT))) {
+        out.flags = SFOC_CP_NONFINITE;
+    } else if (fl & kBlkFlatT) {
+        out.flags = SFOC_CP_FLAT_T;
+    } else if (!(fl & kBlkNonflat) || bidx >= V * V) {
+        out.flags = SFOC_CP_FLAT_S;
+    } else {
+        const int u = bidx / V, v = bidx - u * V;
+        out.dy = u - r;
+        out.dx = v - r;
+        out.score = best;
+        if (u == 0 || v == 0 || u == V - 1 || v == V - 1) {
+            out.flags = SFOC_CP_EDGE_PEAK;
+        } else {
+            const float c0 = best;
+            const float cu = surf[bidx - V], cd = surf[bidx + V], cl = surf[bidx - 1], cr = surf[bidx + 1];
+            float den = cu - 2.f * c0 + cd;
+            float d = 0.f;
+            if (den < 0.f) d = fminf(0.5f, fmaxf(-0.5f, (cu - cd) / (2.f * den)));
+            out.sub_dy = d;
+            den = cl - 2.f * c0 + cr;
+            d = 0.f;
+            if (den < 0.f) d = fminf(0.5f, fmaxf(-0.5f, (cl - cr) / (2.f * den)));
+            out.sub_dx = d;
+        }
+    }
+    A.cps[i] = out;
 }
 
 // ---- consistency: median displacement, 1.5 px (Section 4.1) ------------
@@ -816,14 +908,15 @@ static hipError_t launch_match_L(const MatchArgs& a, hipStream_t st) {
                                        (int)C::lds_bytes);
     if (e != hipSuccess) return e;
     trace_begin(st, SFOC_K_MATCH);
-    hipLaunchKernelGGL(kern, dim3(a.n), dim3(C::NT), C::lds_bytes, st, a);
+    hipLaunchKernelGGL(kern, dim3(a.n * a.nbu * a.nbv), dim3(C::NT), C::lds_bytes, st, a);
     trace_end(st, SFOC_K_MATCH);
     return hipGetLastError();
 }
 
 hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void* desc_ref, int64_t Hr, int64_t Wr,
                         const double* i1, const double* i2, int z, int dtype, const int32_t* ips,
-                        const int32_t* prior, int n, int m, int r, float* ncc, sfoc_cp* cps, hipStream_t st) {
+                        const int32_t* prior, int n, int m, int r, float* ncc, sfoc_cp* cps, void* ws,
+                        hipStream_t st) {
     MatchArgs a;
     a.desc_sen = desc_sen;
     a.desc_ref = desc_ref;
@@ -842,7 +935,17 @@ hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void
     a.n = n;
     a.m = m;
     a.r = r;
-    const int L = fft_size_for(m + 2 * r);
+    const MatchPlan mp = match_plan(n, m, r);
+    const int L = mp.L;
+    a.nbu = a.nbv = mp.nb;
+    a.Vb = mp.Vb;
+    a.surf = nullptr;
+    a.blk = nullptr;
+    if (mp.nb > 1) {
+        const int V = 2 * r + 1;
+        a.surf = (float*)ws;
+        a.blk = (float4*)((char*)ws + align_up((size_t)n * V * V * sizeof(float), 256));
+    }
     hipError_t e;
     if (L == 64) e = dtype == 0 ? launch_match_L<64, 0>(a, st)
                    : dtype == 1 ? launch_match_L<64, 1>(a, st) : launch_match_L<64, 2>(a, st);
@@ -850,6 +953,11 @@ hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void
                         : dtype == 1 ? launch_match_L<128, 1>(a, st) : launch_match_L<128, 2>(a, st);
     else return hipErrorInvalidValue;
     if (e != hipSuccess) return e;
+    if (mp.nb > 1) {
+        trace_begin(st, SFOC_K_PEAK);
+        hipLaunchKernelGGL(peak_kernel, dim3((n + 255) / 256), dim3(256), 0, st, a);
+        trace_end(st, SFOC_K_PEAK);
+    }
     trace_begin(st, SFOC_K_CONSISTENCY);
     hipLaunchKernelGGL(consistency_kernel, dim3(1), dim3(kConsNT), 0, st, cps, prior, n);
     trace_end(st, SFOC_K_CONSISTENCY);

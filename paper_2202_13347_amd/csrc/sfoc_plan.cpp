@@ -147,16 +147,25 @@ size_t describe_ws_bytes(int64_t H, int64_t W) {
     return align_up((size_t)(nb * (W + 1)) * sizeof(double) * 2, 256);
 }
 
-int fft_size_for(int32_t M) {
-    if (M <= 64) return 64;
-    if (M <= 128) return 128;
-    return 0;
-}
-
-size_t match_ws_bytes(int32_t n, int32_t m, int32_t r, int32_t z) {
-    (void)m; (void)r; (void)z;
-    // Displacement keys for the consistency median: 2 floats per CP.
-    return align_up((size_t)n * 2 * sizeof(float), 256) + 256;
+MatchPlan match_plan(int32_t n, int32_t m, int32_t r) {
+    MatchPlan p{0, 1, 0, 0};
+    if (m < 3 || r < 1 || r > kMaxRadiusMatch || n < 0) return p;
+    const int M = m + 2 * r, V = 2 * r + 1;
+    if (M <= 64) {
+        p.L = 64;
+        p.Vb = V;
+    } else if (M <= 128) {
+        p.L = 128;
+        p.Vb = V;
+    } else if (m <= 126) {
+        // offsets split so that each block's search window fits L = 128
+        p.L = 128;
+        p.Vb = 128 - m + 1;
+        p.nb = (V + p.Vb - 1) / p.Vb;
+        p.ws_bytes = align_up((size_t)n * V * V * sizeof(float), 256) +
+                     align_up((size_t)n * p.nb * p.nb * 4 * sizeof(float), 256);
+    }
+    return p;
 }
 
 }  // namespace sfoc

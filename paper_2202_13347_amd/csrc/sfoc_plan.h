@@ -45,9 +45,15 @@ size_t dtype_size(int32_t dtype);
 constexpr int kScanRows = 64;
 size_t describe_ws_bytes(int64_t H, int64_t W);
 
-// FFT side of a match: smallest supported L >= M, or 0.
-int fft_size_for(int32_t M);
-size_t match_ws_bytes(int32_t n, int32_t m, int32_t r, int32_t z);
+// How a match is laid out: FFT side L and the split of the (2r+1)^2 offsets
+// into nb x nb blocks of at most Vb offsets per axis, each with a search
+// window of at most L x L.  L = 0 means unsupported.
+struct MatchPlan {
+    int L, nb, Vb;
+    size_t ws_bytes;   // surfaces + per-block records when nb > 1
+};
+MatchPlan match_plan(int32_t n, int32_t m, int32_t r);
+constexpr int kMaxRadiusMatch = 511;
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 

@@ -195,8 +195,11 @@ def fastncc_match(desc_sen, desc_ref, integ1, integ2, ips, m: int, r: int, prior
     V = 2 * r + 1
     cps = torch.empty((n, 8), dtype=torch.int32, device=desc_sen.device)
     ncc = torch.empty((n, V, V), dtype=torch.float32, device=desc_sen.device) if want_ncc else None
+    b = ctypes.c_size_t(0)
+    _check(lib().sfoc_match_workspace(n, m, r, z, ctypes.byref(b)), "sfoc_match_workspace")
+    ws = torch.empty(b.value, dtype=torch.uint8, device=desc_sen.device) if b.value else None
     rc = lib().sfoc_fastncc_match(_ptr(desc_sen), Hs, Ws, _ptr(desc_ref), Hr, Wr, _ptr(integ1), _ptr(integ2),
-                                  z, dt, _ptr(ips), _ptr(prior), n, m, r, _ptr(ncc), _ptr(cps), None, 0,
+                                  z, dt, _ptr(ips), _ptr(prior), n, m, r, _ptr(ncc), _ptr(cps), _ptr(ws), b.value,
                                   _stream(stream))
     _check(rc, "sfoc_fastncc_match")
     return (cps, ncc) if want_ncc else cps
@@ -240,7 +243,7 @@ def register_cps(ref, sen, ips, m: int, r: int, p: Params, prior=None, want_ncc=
     return (cps, R.ncc) if want_ncc else cps
 
 
-KERNEL_NAMES = ("describe", "integral", "match", "consistency")
+KERNEL_NAMES = ("describe", "integral", "match", "consistency", "peak")
 
 
 def trace_enable(on: bool = True):

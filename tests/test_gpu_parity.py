@@ -152,7 +152,10 @@ def test_register_small_pairs(seed):
 
 
 @pytest.mark.parametrize("m,r,size", [(3, 62, 200), (126, 1, 200), (60, 2, 120), (64, 1, 150), (5, 3, 40),
-                                      (31, 16, 150), (17, 9, 90)])
+                                      (31, 16, 150), (17, 9, 90),
+                                      # search windows beyond 128: offsets split into blocks
+                                      (64, 48, 300), (32, 60, 300), (100, 20, 260), (16, 100, 330),
+                                      (126, 2, 200)])
 def test_template_and_radius_extremes(m, r, size):
     say("extremes", m, r, size)
     pr = synth.make_pair(21 + m, size, min(3.0, r - 0.5) if r > 1 else 0.4)
