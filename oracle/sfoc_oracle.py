@@ -506,19 +506,30 @@ def match(Fs: np.ndarray, Fr: np.ndarray, ips, m: int, r: int, prior=None,
     return (cps, surfaces) if want_surfaces else cps
 
 
+def quantiser(kind):
+    """None, "bf16" or "f16": the rounding of the stored descriptor (float64
+    -> float32 -> storage type), as a function on arrays."""
+    if kind is None:
+        return lambda a: a
+    q = round_to_bf16 if kind == "bf16" else round_to_f16
+    return lambda a: q(np.asarray(a, np.float32)).astype(np.float64)
+
+
 def match_one_region(ref: np.ndarray, sen: np.ndarray, ip, m: int, r: int, p: Params | None = None,
-                     prior=None):
+                     prior=None, quantise=None):
     """One CP of register_cps (before the consistency check) computed from
-    crops only: SFOC of the template and search windows by sfoc_region, NCC
-    by Eq. 9-16 with integral images built over the search window.  Returns
-    (record, surface) with record = (dy, dx, sub_dy, sub_dx, score, flags)."""
+    crops only: SFOC of the template and search windows by sfoc_region
+    (optionally rounded to the storage type), NCC by Eq. 9-16 with integral
+    images built over the search window.  Returns (record, surface) with
+    record = (dy, dx, sub_dy, sub_dx, score, flags)."""
     p = p or Params()
     (ty, tx), (sy, sx) = window_origins(ip, prior, m, r)
     M = m + 2 * r
     if not (in_bounds(ty, tx, m, m, *sen.shape) and in_bounds(sy, sx, M, M, *ref.shape)):
         return (0, 0, 0.0, 0.0, 0.0, OOB), np.zeros((2 * r + 1, 2 * r + 1))
-    T = sfoc_region(sen, ty, tx, m, m, p)
-    S = sfoc_region(ref, sy, sx, M, M, p)
+    q = quantiser(quantise)
+    T = q(sfoc_region(sen, ty, tx, m, m, p))
+    S = q(sfoc_region(ref, sy, sx, M, M, p))
     ncc, flatT, nonfin = ncc_fast(S, T)
     return decide(ncc, flatT, nonfin, r), ncc
 
@@ -531,11 +542,8 @@ def register_cps(ref: np.ndarray, sen: np.ndarray, ips, m: int, r: int,
     p = p or Params()
     Fr = sfoc(ref, p)
     Fs = sfoc(sen, p)
-    if quantise is not None:
-        q = round_to_bf16 if quantise == "bf16" else round_to_f16
-        Fr = q(Fr.astype(np.float32)).astype(np.float64)
-        Fs = q(Fs.astype(np.float32)).astype(np.float64)
-    return match(Fs, Fr, ips, m, r, prior, method, want_surfaces=want_surfaces)
+    q = quantiser(quantise)
+    return match(q(Fs), q(Fr), ips, m, r, prior, method, want_surfaces=want_surfaces)
 
 
 # ------------------------------------------------------ cost model ---------

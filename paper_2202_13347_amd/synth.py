@@ -18,6 +18,7 @@ from __future__ import annotations
 from dataclasses import dataclass
 
 import numpy as np
+from scipy import fft as sfft
 from scipy import ndimage
 
 
@@ -29,8 +30,9 @@ class Pair:
     seed: int
 
 
-def _convex_polygon_mask(rng, h, w, cy, cx, rad):
-    """Boolean mask of a random convex polygon (3..7 vertices) of radius ~rad."""
+def _convex_polygon(rng, h, w, cy, cx, rad):
+    """Random convex polygon (3..7 vertices) of radius ~rad: its clipped
+    bounding box (y0, y1, x0, x1) and the inside mask over that box."""
     nv = int(rng.integers(3, 8))
     ang = np.sort(rng.uniform(0, 2 * np.pi, nv))
     rr = rad * rng.uniform(0.6, 1.0, nv)
@@ -38,17 +40,15 @@ def _convex_polygon_mask(rng, h, w, cy, cx, rad):
     vx = cx + rr * np.cos(ang)
     y0 = int(max(0, np.floor(vy.min()))); y1 = int(min(h, np.ceil(vy.max()) + 1))
     x0 = int(max(0, np.floor(vx.min()))); x1 = int(min(w, np.ceil(vx.max()) + 1))
-    mask = np.zeros((h, w), dtype=bool)
     if y1 <= y0 or x1 <= x0:
-        return mask
+        return y0, y0, x0, x0, None
     yy, xx = np.mgrid[y0:y1, x0:x1].astype(np.float64)
     inside = np.ones(yy.shape, dtype=bool)
     for i in range(nv):
         j = (i + 1) % nv
         ex, ey = vx[j] - vx[i], vy[j] - vy[i]
         inside &= (ex * (yy - vy[i]) - ey * (xx - vx[i])) >= 0
-    mask[y0:y1, x0:x1] = inside
-    return mask
+    return y0, y1, x0, x1, inside
 
 
 def _label_map(rng, h, w, n_shapes, size_lo, size_hi):
@@ -63,17 +63,32 @@ def _label_map(rng, h, w, n_shapes, size_lo, size_hi):
             x0 = int(max(0, cx - ww / 2)); x1 = int(min(w, cx + ww / 2))
             lab[y0:y1, x0:x1] = k
         else:
-            lab[_convex_polygon_mask(rng, h, w, cy, cx, sz / 2)] = k
+            y0, y1, x0, x1, inside = _convex_polygon(rng, h, w, cy, cx, sz / 2)
+            if inside is not None:
+                lab[y0:y1, x0:x1][inside] = k
     return lab
 
 
 def _value_noise(rng, h, w, cell, std):
-    """Smooth noise: a coarse random grid upsampled with cubic splines."""
+    """Smooth noise: a coarse random grid upsampled bilinearly."""
     gh = h // cell + 4; gw = w // cell + 4
-    g = rng.standard_normal((gh, gw))
-    up = ndimage.zoom(g, cell, order=3)[:h, :w]
+    g = rng.standard_normal((gh, gw)).astype(np.float32)
+    up = ndimage.zoom(g, cell, order=1)[:h, :w]
     s = up.std()
     return up * (std / s) if s > 0 else up
+
+
+def _blur_shift(img, sigma, shift):
+    """Gaussian blur (standard deviation sigma) and a translation by shift =
+    (dy, dx), out(y, x) = blurred(y - dy, x - dx) on a periodic canvas, in one
+    Fourier-domain product."""
+    H, W = img.shape
+    F = sfft.rfft2(img, workers=-1)
+    ky = sfft.fftfreq(H)[:, None]
+    kx = sfft.rfftfreq(W)[None, :]
+    g = np.exp(-2.0 * (np.pi * sigma) ** 2 * (ky * ky + kx * kx))
+    ph = np.exp(-2j * np.pi * (ky * shift[0] + kx * shift[1]))
+    return sfft.irfft2(F * (g * ph), s=(H, W), workers=-1)
 
 
 def _cubic_maps(rng, n):
@@ -123,15 +138,14 @@ def make_pair(seed: int, size: int | tuple[int, int], max_shift: float,
     scene_s = resp[lab]
     scene_r = scene_r + _value_noise(rng, ch, cw, 16, 0.1)
     scene_s = scene_s + _value_noise(rng, ch, cw, 24, 0.05)
-    scene_r = ndimage.gaussian_filter(scene_r, 1.0, mode="reflect")
-    scene_s = ndimage.gaussian_filter(scene_s, 1.0, mode="reflect")
-    # sen(y, x) = scene_s(y + dy, x + dx): ndimage.shift moves content by +s,
-    # i.e. out(y) = in(y - s), so shift by -d.
+    # sen(y, x) = blurred scene_s(y + dy, x + dx): translate by -d.  The
+    # canvas margin exceeds the shift, so the periodic wrap stays outside.
+    scene_r = _blur_shift(scene_r, 1.0, (0.0, 0.0))
     if integer_shift:
         dy, dx = int(shift[0]), int(shift[1])
-        sen_c = np.roll(scene_s, (-dy, -dx), axis=(0, 1))
+        sen_c = np.roll(_blur_shift(scene_s, 1.0, (0.0, 0.0)), (-dy, -dx), axis=(0, 1))
     else:
-        sen_c = ndimage.shift(scene_s, -shift, order=3, mode="nearest")
+        sen_c = _blur_shift(scene_s, 1.0, (-shift[0], -shift[1]))
     ref = scene_r[pad:pad + H, pad:pad + W]
     sen = sen_c[pad:pad + H, pad:pad + W]
     if noise_std > 0:
@@ -164,6 +178,7 @@ def random_ips(seed: int, H: int, W: int, n: int, margin: int) -> np.ndarray:
 # Workload recipes (image side, IP grid, template m, search radius r, shift bound).
 SMALL = dict(size=256, n_side=4, m=32, r=10, max_shift=8.0, speckle=0)
 SCENE = dict(size=2048, n_side=20, m=64, r=32, max_shift=30.0, speckle=4)
+LARGE = dict(size=10000, n_side=71, m=64, r=48, max_shift=44.0, speckle=4, n_ips=5000)
 
 
 def workload(recipe: dict, seed: int):
@@ -171,4 +186,6 @@ def workload(recipe: dict, seed: int):
     p = make_pair(seed, recipe["size"], recipe["max_shift"], speckle_looks=recipe["speckle"])
     b = (recipe["m"] + 1) // 2 + recipe["r"]
     ips = grid_ips(recipe["size"], recipe["size"], recipe["n_side"], b)
+    if "n_ips" in recipe:
+        ips = ips[:recipe["n_ips"]]
     return p, ips, recipe["m"], recipe["r"]
