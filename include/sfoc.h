@@ -217,6 +217,101 @@ int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr,
                       void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Batched registration of many image pairs (uneven sizes, templates and
+ * radii) as one plan.  Each pair is what sfoc_register_cps takes for one
+ * pair; every pair is computed exactly as sfoc_register_cps computes it
+ * with the same transform side (Section 2.2, Eq. 9-16 and the peak and
+ * consistency decisions per pair), so with the default sides the results
+ * are bit-identical to per-pair calls.
+ *
+ * sfoc_plan_create validates every pair, allocates the plan's device memory
+ * (descriptors, integral images, scratch and the launch tables; it is the
+ * only call of this library that allocates) and builds the work lists:
+ *  - describe: one launch over (image, 32 x 32 tile) entries of all images;
+ *    the sensed images get only the tiles that their templates read unless
+ *    SFOC_PLAN_DENSE_SEN is set (then they are described whole);
+ *  - integral images: three launches over all reference images;
+ *  - match: one launch per transform side over (pair, IP, offset block)
+ *    items, the two sides on two graph branches; a peak launch over pairs
+ *    whose offsets are split; one consistency launch, a workgroup per pair.
+ * The transform side of a pair is pair.fft_side when that is 64 or 128
+ * (SFOC_E_UNSUPPORTED if the template does not fit it), else the default of
+ * sfoc_match_workspace, or with SFOC_PLAN_AUTOTUNE the faster of the
+ * candidates sfoc_match_candidates lists, timed on the plan's own work at
+ * creation (the images should hold data by then) and remembered per
+ * (device, z, dtype, m, r) in the text file tune_cache when that is not
+ * NULL (read at creation, rewritten when a new entry was timed).
+ * With SFOC_PLAN_GRAPH the first sfoc_register_cps_batched captures the
+ * whole sequence on its stream into a hipGraph and every call replays it.
+ *
+ * Ownership and lifetime: the caller owns every pair buffer (device
+ * pointers) and keeps them allocated for the plan's lifetime; the plan
+ * reads the image contents at each execution.  The IP and prior values are
+ * read once at creation (host copies) when the sensed images are described
+ * sparsely or the plan is autotuned; they must not change afterwards unless
+ * SFOC_PLAN_DENSE_SEN is set and autotuning is off.  create synchronises
+ * `stream`; execute is asynchronous on `stream`.  A plan is used by one
+ * host thread at a time and on the device that was current at creation.
+ * Errors: SFOC_E_INVALID_ARG (null plan or pairs, n_pairs < 1, a pair
+ * failing the sfoc_register_cps checks), SFOC_E_UNSUPPORTED, SFOC_E_HIP
+ * (including out of device memory).
+ */
+typedef struct sfoc_pair {
+    const float* ref;           /* Hr x Wr float32, pitch ldr (elements) */
+    int64_t Hr, Wr, ldr;
+    const float* sen;           /* Hs x Ws float32, pitch lds */
+    int64_t Hs, Ws, lds;
+    const int32_t* ips;         /* n x 2 (row, col) in the sensed image */
+    const int32_t* prior;       /* n x 2 (dy, dx) or NULL */
+    int32_t n, m, r;
+    int32_t fft_side;           /* 0: default / autotuned; 64 or 128: forced */
+    float* ncc;                 /* n x (2r+1)^2 float32 surfaces or NULL (output) */
+    sfoc_cp* cps;               /* n records (output) */
+} sfoc_pair;
+
+typedef struct sfoc_plan sfoc_plan;
+
+#define SFOC_PLAN_GRAPH      1
+#define SFOC_PLAN_AUTOTUNE   2
+#define SFOC_PLAN_DENSE_SEN  4
+
+int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params* p, int32_t flags,
+                     const char* tune_cache, void* stream, sfoc_plan** plan);
+int sfoc_register_cps_batched(sfoc_plan* plan, void* stream);
+int sfoc_plan_destroy(sfoc_plan* plan);
+
+/*
+ * What a plan chose and holds.  fft_side[i] / blocks[i] (per axis) for the
+ * first min(n_pairs, cap) pairs; the totals of work items and device bytes.
+ */
+typedef struct sfoc_plan_info {
+    int32_t n_pairs;
+    int32_t describe_tiles;     /* entries of the describe launch */
+    int32_t match_items[2];     /* items of the L = 64 and L = 128 launches */
+    int32_t peak_items;
+    int32_t tuned_classes;      /* (m, r) classes timed at creation */
+    int32_t cached_classes;     /* (m, r) classes taken from tune_cache */
+    int32_t graph;              /* 1 once a graph is captured */
+    int64_t device_bytes;
+} sfoc_plan_info;
+int sfoc_plan_get_info(const sfoc_plan* plan, sfoc_plan_info* info, int32_t* fft_side, int32_t* blocks,
+                       int32_t cap);
+
+/*
+ * Planning queries (host only, no device work).
+ * sfoc_match_candidates: the transform sides (64 / 128) usable for template
+ * m and radius r with at most 8 offset blocks per axis, the default first,
+ * and the offset blocks per axis of each; returns the count (0: none).
+ * sfoc_sensed_tiles: the 32 x 32 sensed-image tiles that the templates of
+ * in-bounds IPs read (host arrays; mask has ceil(Hs/32) * ceil(Ws/32) bytes,
+ * row-major over tiles); returns the number of marked tiles, or a negative
+ * status.
+ */
+int sfoc_match_candidates(int32_t m, int32_t r, int32_t* fft_side, int32_t* blocks, int32_t cap);
+int64_t sfoc_sensed_tiles(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m, int32_t r,
+                          int64_t Hs, int64_t Ws, int64_t Hr, int64_t Wr, uint8_t* mask);
+
+/*
  * Kernel timing (tracing).  While enabled, the library records a pair of
  * HIP events on the launch stream around every kernel it enqueues.
  * sfoc_trace_collect waits for those events, writes per-kernel totals into

@@ -2,42 +2,34 @@
 // the caller's stream.  Nothing here allocates device memory.
 #include <hip/hip_runtime.h>
 
-#include "sfoc_plan.h"
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "sfoc_launch.h"
 
 namespace sfoc {
-hipError_t launch_describe(const float* img, int H, int W, int64_t ld, void* desc, double* i1, double* i2,
-                           const DescribeConsts& c, hipStream_t st);
-hipError_t launch_integral(double* i1, double* i2, int H, int W, double* ws, hipStream_t st);
-hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void* desc_ref, int64_t Hr, int64_t Wr,
-                        const double* i1, const double* i2, int z, int dtype, const int32_t* ips,
-                        const int32_t* prior, int n, int m, int r, float* ncc, sfoc_cp* cps, void* ws,
-                        hipStream_t st);
 
 static thread_local hipError_t g_last_hip = hipSuccess;
 
-static int hip_status(hipError_t e) {
+int hip_status(hipError_t e) {
     if (e == hipSuccess) return SFOC_OK;
     g_last_hip = e;
     return SFOC_E_HIP;
 }
 
-// Image sides are limited so that every per-image index fits in int32 and
-// every plane offset in int64; the match kernel addresses a descriptor
-// plane with 32-bit element offsets, so a plane holds fewer than 2^30 pixels.
-constexpr int64_t kMaxSide = 1 << 16;
-constexpr int64_t kMaxPlane = (int64_t)1 << 30;
-
-static int check_image(const void* img, int64_t H, int64_t W, int64_t ld) {
-    if (!img) return SFOC_E_INVALID_ARG;
-    if (H < 1 || W < 1 || ld < W) return SFOC_E_INVALID_ARG;
-    if (H > kMaxSide || W > kMaxSide) return SFOC_E_UNSUPPORTED;
-    return SFOC_OK;
-}
-
-static int check_match_shape(int32_t n, int32_t m, int32_t r) {
-    if (n < 0 || m < 3 || r < 1) return SFOC_E_INVALID_ARG;
-    if (match_plan(n, m, r).L == 0) return SFOC_E_UNSUPPORTED;
-    return SFOC_OK;
+hipError_t ensure_dynamic_lds(const void* kern, int bytes) {
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, int> done;   // (kernel, device) -> bytes allowed
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = done.find({kern, dev});
+    if (it != done.end() && it->second >= bytes) return hipSuccess;
+    e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess) done[{kern, dev}] = bytes;
+    return e;
 }
 
 struct RegisterLayout {
@@ -216,6 +208,29 @@ int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr, con
     e = launch_match(dsen, Hs, Ws, dref, Hr, Wr, i1, i2, z, p->desc_dtype, ips, prior, n, m, r, ncc, cps,
                      base + L.match, st);
     return hip_status(e);
+}
+
+int sfoc_match_candidates(int32_t m, int32_t r, int32_t* fft_side, int32_t* blocks, int32_t cap) {
+    if (cap < 0 || (cap > 0 && !fft_side)) return SFOC_E_INVALID_ARG;
+    int Ls[2];
+    const int n = match_candidates(m, r, Ls);
+    for (int k = 0; k < n && k < cap; ++k) {
+        fft_side[k] = Ls[k];
+        if (blocks) blocks[k] = match_plan_L(1, m, r, Ls[k]).nb;
+    }
+    return n;
+}
+
+int64_t sfoc_sensed_tiles(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m, int32_t r, int64_t Hs,
+                          int64_t Ws, int64_t Hr, int64_t Wr, uint8_t* mask) {
+    if (n < 0 || m < 3 || r < 1 || Hs < 1 || Ws < 1 || Hr < 1 || Wr < 1 || !mask || (n > 0 && !ips))
+        return SFOC_E_INVALID_ARG;
+    if (Hs > kMaxSide || Ws > kMaxSide) return SFOC_E_UNSUPPORTED;
+    sensed_tile_mask(ips, prior, n, m, r, Hs, Ws, Hr, Wr, kDescribeTile, mask);
+    const int64_t nt = ((Hs + kDescribeTile - 1) / kDescribeTile) * ((Ws + kDescribeTile - 1) / kDescribeTile);
+    int64_t c = 0;
+    for (int64_t k = 0; k < nt; ++k) c += mask[k];
+    return c;
 }
 
 }  // extern "C"

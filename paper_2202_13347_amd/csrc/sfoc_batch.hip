@@ -1,0 +1,554 @@
+// Batched plans: many image pairs of uneven sizes, templates and radii run
+// as one describe launch, one set of integral-image scans, one match launch
+// per transform side, one peak and one consistency launch, optionally
+// captured into a hipGraph.  Each pair's arithmetic is exactly the per-pair
+// path's (the kernels are shared; only where their arguments come from
+// differs).  A timing autotuner picks the transform side per (m, r) class.
+#include <hip/hip_runtime.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "sfoc_launch.h"
+
+using namespace sfoc;
+
+struct sfoc_plan {
+    int device = 0;
+    sfoc_params p{};
+    DescribeConsts c{};
+    int32_t z = 0, dtype = 0, flags = 0;
+    std::vector<sfoc_pair> pairs;
+    std::vector<int> side;          // chosen transform side per pair
+    std::vector<MatchPlan> mp;      // its layout
+    char* mem = nullptr;            // one device allocation
+    size_t bytes = 0;
+    DescribeJob* djobs = nullptr;
+    int4* dtiles = nullptr;
+    int ndt = 0;
+    IntegJob* ijobs = nullptr;
+    int4* irows = nullptr;
+    int4* icols = nullptr;
+    int nir = 0, nic = 0;
+    MatchArgs* margs = nullptr;
+    int4* items[2] = {nullptr, nullptr};   // L = 64, L = 128
+    int nitems[2] = {0, 0};
+    int4* peak = nullptr;
+    int npeak = 0;
+    hipStream_t side_stream = nullptr;   // second graph branch
+    hipStream_t cap_stream = nullptr;    // capture happens here (the caller's may be the null stream)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int tuned = 0, cached = 0;
+};
+
+namespace {
+
+// Device memory of one pair inside the plan's allocation.
+struct PairMem {
+    size_t dref, dsen, i1, i2, scan, ws;
+};
+
+struct Cursor {
+    size_t off = 0;
+    size_t take(size_t n) {
+        const size_t o = off;
+        off = align_up(off + n, 256);
+        return o;
+    }
+};
+
+int bucket_of(int L) { return L == 64 ? 0 : 1; }
+
+MatchArgs make_args(const sfoc_pair& q, const char* mem, const PairMem& pm, int32_t z, int32_t dtype,
+                    const MatchPlan& mp) {
+    MatchArgs a{};
+    a.desc_sen = mem + pm.dsen;
+    a.desc_ref = mem + pm.dref;
+    a.integ1 = (const double*)(mem + pm.i1);
+    a.integ2 = (const double*)(mem + pm.i2);
+    a.ips = q.ips;
+    a.prior = q.prior;
+    a.ncc = q.ncc;
+    a.cps = q.cps;
+    a.Hs = q.Hs;
+    a.Ws = q.Ws;
+    a.Hr = q.Hr;
+    a.Wr = q.Wr;
+    a.z = z;
+    a.dtype = dtype;
+    a.n = q.n;
+    a.m = q.m;
+    a.r = q.r;
+    match_args_layout(a, mp, (void*)(mem + pm.ws));
+    return a;
+}
+
+// Match items of one pair: (pair, IP, block) for every IP and block.
+void append_items(std::vector<int4>& out, int pair, int n, int nb) {
+    const int nblk = nb * nb;
+    for (int i = 0; i < n; ++i)
+        for (int b = 0; b < nblk; ++b) out.push_back(make_int4(pair, i, b, 0));
+}
+
+// Tune cache: one line per (device, z, dtype, m, r) -> L.
+using TuneKey = std::tuple<std::string, int, int, int, int>;
+
+std::string device_key(int dev) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s/%dcu", prop.gcnArchName, prop.multiProcessorCount);
+    for (char* c = buf; *c; ++c)
+        if (*c == ' ') *c = '_';
+    return buf;
+}
+
+std::map<TuneKey, int> read_cache(const char* path) {
+    std::map<TuneKey, int> m;
+    if (!path) return m;
+    FILE* f = fopen(path, "r");
+    if (!f) return m;
+    char dev[160];
+    int z, dt, mm, r, L;
+    while (fscanf(f, "%159s %d %d %d %d %d", dev, &z, &dt, &mm, &r, &L) == 6)
+        if (L == 64 || L == 128) m[TuneKey(dev, z, dt, mm, r)] = L;
+    fclose(f);
+    return m;
+}
+
+void write_cache(const char* path, const std::map<TuneKey, int>& m) {
+    if (!path) return;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    for (const auto& kv : m)
+        fprintf(f, "%s %d %d %d %d %d\n", std::get<0>(kv.first).c_str(), std::get<1>(kv.first),
+                std::get<2>(kv.first), std::get<3>(kv.first), std::get<4>(kv.first), kv.second);
+    fclose(f);
+    rename(tmp.c_str(), path);
+}
+
+// Everything after the describe / integral stage for the plan's current
+// tables.  The two transform sides run on two streams (two graph branches).
+hipError_t enqueue_match(sfoc_plan* P, hipStream_t st) {
+    hipError_t e = hipSuccess;
+    const bool both = P->nitems[0] > 0 && P->nitems[1] > 0;
+    if (both) {
+        if ((e = hipEventRecord(P->ev_fork, st)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(P->side_stream, P->ev_fork, 0)) != hipSuccess) return e;
+        e = launch_match_items(64, P->dtype, P->margs, P->items[0], P->nitems[0], P->side_stream);
+        if (e != hipSuccess) return e;
+        if ((e = hipEventRecord(P->ev_join, P->side_stream)) != hipSuccess) return e;
+        e = launch_match_items(128, P->dtype, P->margs, P->items[1], P->nitems[1], st);
+        if (e != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(st, P->ev_join, 0)) != hipSuccess) return e;
+    } else {
+        for (int b = 0; b < 2; ++b) {
+            e = launch_match_items(b ? 128 : 64, P->dtype, P->margs, P->items[b], P->nitems[b], st);
+            if (e != hipSuccess) return e;
+        }
+    }
+    if ((e = launch_peak_batched(P->margs, P->peak, P->npeak, st)) != hipSuccess) return e;
+    return launch_consistency_batched(P->margs, (int)P->pairs.size(), st);
+}
+
+hipError_t enqueue_all(sfoc_plan* P, hipStream_t st) {
+    hipError_t e = launch_describe_batched(P->djobs, P->dtiles, P->ndt, P->c, st);
+    if (e == hipSuccess) e = launch_integral_batched(P->ijobs, P->irows, P->nir, P->icols, P->nic, st);
+    if (e == hipSuccess) e = enqueue_match(P, st);
+    return e;
+}
+
+void free_plan(sfoc_plan* P) {
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+    if (P->ev_join) (void)hipEventDestroy(P->ev_join);
+    if (P->side_stream) (void)hipStreamDestroy(P->side_stream);
+    if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+    if (P->mem) (void)hipFree(P->mem);
+    delete P;
+}
+
+// Median time of `reps` launches of one candidate side over `items`.
+float time_items(int L, int dtype, const MatchArgs* margs, const int4* items, int nitems, hipStream_t st, int reps,
+                 hipError_t* err) {
+    hipEvent_t a, b;
+    *err = hipEventCreate(&a);
+    if (*err != hipSuccess) return 0.f;
+    *err = hipEventCreate(&b);
+    if (*err != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return 0.f;
+    }
+    std::vector<float> t;
+    *err = launch_match_items(L, dtype, margs, items, nitems, st);   // warm-up
+    for (int k = 0; k < reps && *err == hipSuccess; ++k) {
+        *err = hipEventRecord(a, st);
+        if (*err == hipSuccess) *err = launch_match_items(L, dtype, margs, items, nitems, st);
+        if (*err == hipSuccess) *err = hipEventRecord(b, st);
+        if (*err == hipSuccess) *err = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (*err == hipSuccess) *err = hipEventElapsedTime(&ms, a, b);
+        t.push_back(ms);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (t.empty()) return 0.f;
+    std::sort(t.begin(), t.end());
+    return t[t.size() / 2];
+}
+
+}  // namespace
+
+extern "C" {
+
+int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params* p, int32_t flags,
+                     const char* tune_cache, void* stream, sfoc_plan** plan) {
+    if (!plan || !pairs || n_pairs < 1) return SFOC_E_INVALID_ARG;
+    *plan = nullptr;
+    if (flags & ~(SFOC_PLAN_GRAPH | SFOC_PLAN_AUTOTUNE | SFOC_PLAN_DENSE_SEN)) return SFOC_E_INVALID_ARG;
+    int32_t z = 0;
+    int rc = check_params(p, &z);
+    if (rc) return rc;
+    const size_t es = dtype_size(p->desc_dtype);
+    const bool tune = (flags & SFOC_PLAN_AUTOTUNE) != 0;
+    const bool sparse = !(flags & SFOC_PLAN_DENSE_SEN);
+    // ---- validation (the checks of sfoc_register_cps, per pair) ----
+    for (int k = 0; k < n_pairs; ++k) {
+        const sfoc_pair& q = pairs[k];
+        if ((rc = check_image(q.ref, q.Hr, q.Wr, q.ldr))) return rc;
+        if ((rc = check_image(q.sen, q.Hs, q.Ws, q.lds))) return rc;
+        if ((rc = check_match_shape(q.n, q.m, q.r))) return rc;
+        if (q.Hs * q.Ws >= kMaxPlane || q.Hr * q.Wr >= kMaxPlane) return SFOC_E_UNSUPPORTED;
+        if (q.n > 0 && (!q.ips || !q.cps)) return SFOC_E_INVALID_ARG;
+        if (q.fft_side != 0 && q.fft_side != 64 && q.fft_side != 128) return SFOC_E_INVALID_ARG;
+        if (q.fft_side != 0 && match_plan_L(q.n, q.m, q.r, q.fft_side).L == 0) return SFOC_E_UNSUPPORTED;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    sfoc_plan* P = new sfoc_plan;
+    P->p = *p;
+    build_describe_consts(p, &P->c);
+    P->z = z;
+    P->dtype = p->desc_dtype;
+    P->flags = flags;
+    P->pairs.assign(pairs, pairs + n_pairs);
+    hipError_t e = hipGetDevice(&P->device);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        free_plan(P);
+        return hip_status(e);
+    }
+
+    // ---- host copies of the IPs (sparse describe tiles, autotuning) ----
+    std::vector<std::vector<int32_t>> hips(n_pairs), hprior(n_pairs);
+    if (sparse || tune) {
+        for (int k = 0; k < n_pairs && e == hipSuccess; ++k) {
+            const sfoc_pair& q = pairs[k];
+            if (q.n == 0) continue;
+            hips[k].resize(2 * (size_t)q.n);
+            e = hipMemcpy(hips[k].data(), q.ips, hips[k].size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+            if (e == hipSuccess && q.prior) {
+                hprior[k].resize(2 * (size_t)q.n);
+                e = hipMemcpy(hprior[k].data(), q.prior, hprior[k].size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+            }
+        }
+        if (e != hipSuccess) {
+            free_plan(P);
+            return hip_status(e);
+        }
+    }
+
+    // ---- describe tiles ----
+    const int T = kDescribeTile;
+    std::vector<DescribeJob> djobs(2 * (size_t)n_pairs);
+    std::vector<int4> dtiles;
+    std::vector<uint8_t> mask;
+    for (int k = 0; k < n_pairs; ++k) {
+        const sfoc_pair& q = pairs[k];
+        const int ntyr = (int)((q.Hr + T - 1) / T), ntxr = (int)((q.Wr + T - 1) / T);
+        for (int a = 0; a < ntyr; ++a)
+            for (int b = 0; b < ntxr; ++b) dtiles.push_back(make_int4(2 * k, a * T, b * T, 0));
+        const int ntys = (int)((q.Hs + T - 1) / T), ntxs = (int)((q.Ws + T - 1) / T);
+        if (sparse) {
+            mask.assign((size_t)ntys * ntxs, 0);
+            if (q.n > 0)
+                sensed_tile_mask(hips[k].data(), q.prior ? hprior[k].data() : nullptr, q.n, q.m, q.r, q.Hs, q.Ws,
+                                 q.Hr, q.Wr, T, mask.data());
+        }
+        for (int a = 0; a < ntys; ++a)
+            for (int b = 0; b < ntxs; ++b)
+                if (!sparse || mask[(size_t)a * ntxs + b]) dtiles.push_back(make_int4(2 * k + 1, a * T, b * T, 0));
+    }
+
+    // ---- memory: per pair descriptors, integrals, scan scratch, match scratch ----
+    std::vector<PairMem> pm(n_pairs);
+    Cursor cur;
+    std::vector<std::vector<int>> cands(n_pairs);
+    for (int k = 0; k < n_pairs; ++k) {
+        const sfoc_pair& q = pairs[k];
+        int Ls[2];
+        int nc = 0;
+        if (q.fft_side) {
+            Ls[nc++] = q.fft_side;
+        } else if (tune) {
+            nc = match_candidates(q.m, q.r, Ls);
+        } else {
+            Ls[nc++] = match_plan(q.n, q.m, q.r).L;
+        }
+        cands[k].assign(Ls, Ls + nc);
+        size_t ws = 0;
+        for (int L : cands[k]) ws = std::max(ws, match_plan_L(q.n, q.m, q.r, L).ws_bytes);
+        pm[k].dref = cur.take((size_t)z * q.Hr * q.Wr * es);
+        pm[k].dsen = cur.take((size_t)z * q.Hs * q.Ws * es);
+        pm[k].i1 = cur.take((size_t)(q.Hr + 1) * (q.Wr + 1) * sizeof(double));
+        pm[k].i2 = cur.take((size_t)(q.Hr + 1) * (q.Wr + 1) * sizeof(double));
+        pm[k].scan = cur.take(describe_ws_bytes(q.Hr, q.Wr));
+        pm[k].ws = cur.take(ws);
+    }
+    // integral-scan work lists
+    std::vector<IntegJob> ijobs(n_pairs);
+    std::vector<int4> irows, icols;
+    size_t max_items[2] = {0, 0}, max_peak = 0;
+    for (int k = 0; k < n_pairs; ++k) {
+        const sfoc_pair& q = pairs[k];
+        for (int y = 0; y <= q.Hr; ++y) irows.push_back(make_int4(k, y, 0, 0));
+        const int nbr = (int)((q.Hr + kScanRows - 1) / kScanRows);
+        const int ncb = (int)((q.Wr + 1 + 255) / 256);
+        for (int b = 0; b < nbr; ++b)
+            for (int x = 0; x < ncb; ++x) icols.push_back(make_int4(k, x, b, 0));
+        for (int L : cands[k]) {
+            const MatchPlan m = match_plan_L(q.n, q.m, q.r, L);
+            max_items[bucket_of(L)] += (size_t)q.n * m.nb * m.nb;
+        }
+        max_peak += ((size_t)q.n + 255) / 256;
+    }
+    const size_t o_djobs = cur.take(djobs.size() * sizeof(DescribeJob));
+    const size_t o_dtiles = cur.take(dtiles.size() * sizeof(int4));
+    const size_t o_ijobs = cur.take(ijobs.size() * sizeof(IntegJob));
+    const size_t o_irows = cur.take(irows.size() * sizeof(int4));
+    const size_t o_icols = cur.take(icols.size() * sizeof(int4));
+    const size_t o_margs = cur.take((size_t)n_pairs * sizeof(MatchArgs));
+    const size_t o_items0 = cur.take(max_items[0] * sizeof(int4));
+    const size_t o_items1 = cur.take(max_items[1] * sizeof(int4));
+    const size_t o_peak = cur.take(max_peak * sizeof(int4));
+    P->bytes = cur.off;
+    e = hipMalloc((void**)&P->mem, P->bytes);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->side_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        free_plan(P);
+        return hip_status(e);
+    }
+    char* mem = P->mem;
+    for (int k = 0; k < n_pairs; ++k) {
+        const sfoc_pair& q = pairs[k];
+        djobs[2 * k] = DescribeJob{q.ref, mem + pm[k].dref, (double*)(mem + pm[k].i1), (double*)(mem + pm[k].i2),
+                                   q.ldr, (int)q.Hr, (int)q.Wr};
+        djobs[2 * k + 1] = DescribeJob{q.sen, mem + pm[k].dsen, nullptr, nullptr, q.lds, (int)q.Hs, (int)q.Ws};
+        const int nbr = (int)((q.Hr + kScanRows - 1) / kScanRows);
+        double* bs = (double*)(mem + pm[k].scan);
+        ijobs[k] = IntegJob{(double*)(mem + pm[k].i1), (double*)(mem + pm[k].i2), bs, bs + (size_t)nbr * (q.Wr + 1),
+                            (int)q.Hr, (int)q.Wr};
+    }
+    P->djobs = (DescribeJob*)(mem + o_djobs);
+    P->dtiles = (int4*)(mem + o_dtiles);
+    P->ndt = (int)dtiles.size();
+    P->ijobs = (IntegJob*)(mem + o_ijobs);
+    P->irows = (int4*)(mem + o_irows);
+    P->icols = (int4*)(mem + o_icols);
+    P->nir = (int)irows.size();
+    P->nic = (int)icols.size();
+    P->margs = (MatchArgs*)(mem + o_margs);
+    P->items[0] = (int4*)(mem + o_items0);
+    P->items[1] = (int4*)(mem + o_items1);
+    P->peak = (int4*)(mem + o_peak);
+    auto up = [&](void* dst, const void* src, size_t n) {
+        if (e == hipSuccess && n) e = hipMemcpy(dst, src, n, hipMemcpyHostToDevice);
+    };
+    up(P->djobs, djobs.data(), djobs.size() * sizeof(DescribeJob));
+    up(P->dtiles, dtiles.data(), dtiles.size() * sizeof(int4));
+    up(P->ijobs, ijobs.data(), ijobs.size() * sizeof(IntegJob));
+    up(P->irows, irows.data(), irows.size() * sizeof(int4));
+    up(P->icols, icols.data(), icols.size() * sizeof(int4));
+    if (e != hipSuccess) {
+        free_plan(P);
+        return hip_status(e);
+    }
+
+    // ---- transform side per pair ----
+    P->side.assign(n_pairs, 0);
+    std::map<std::pair<int, int>, std::vector<int>> classes;   // (m, r) -> pairs still open
+    for (int k = 0; k < n_pairs; ++k) {
+        if (cands[k].size() == 1) P->side[k] = cands[k][0];
+        else classes[{pairs[k].m, pairs[k].r}].push_back(k);
+    }
+    if (!classes.empty()) {
+        const std::string dev = device_key(P->device);
+        std::map<TuneKey, int> cache = read_cache(tune_cache);
+        bool wrote = false;
+        bool described = false;
+        for (auto& cl : classes) {
+            const int m = cl.first.first, r = cl.first.second;
+            const TuneKey key(dev, z, P->dtype, m, r);
+            auto hit = cache.find(key);
+            int best = 0;
+            if (hit != cache.end()) {
+                best = hit->second;
+                ++P->cached;
+            } else {
+                if (!described) {   // the candidates are timed on this plan's own descriptors
+                    e = launch_describe_batched(P->djobs, P->dtiles, P->ndt, P->c, st);
+                    if (e == hipSuccess)
+                        e = launch_integral_batched(P->ijobs, P->irows, P->nir, P->icols, P->nic, st);
+                    described = true;
+                }
+                // at most ~2048 IPs of the class are timed
+                float tbest = 0.f;
+                int Ls[2];
+                const int nc = match_candidates(m, r, Ls);
+                for (int c = 0; c < nc && e == hipSuccess; ++c) {
+                    const int L = Ls[c];
+                    std::vector<MatchArgs> margs(n_pairs);
+                    std::vector<int4> items;
+                    int budget = 2048;
+                    for (int k : cl.second) {
+                        if (budget <= 0) break;
+                        const MatchPlan mpl = match_plan_L(pairs[k].n, m, r, L);
+                        margs[k] = make_args(pairs[k], mem, pm[k], z, P->dtype, mpl);
+                        append_items(items, k, std::min(pairs[k].n, budget), mpl.nb);
+                        budget -= pairs[k].n;
+                    }
+                    if (items.empty()) break;
+                    up(P->margs, margs.data(), margs.size() * sizeof(MatchArgs));
+                    int4* dit = P->items[bucket_of(L)];
+                    up(dit, items.data(), items.size() * sizeof(int4));
+                    if (e != hipSuccess) break;
+                    const float t = time_items(L, P->dtype, P->margs, dit, (int)items.size(), st, 3, &e);
+                    if (c == 0 || t < tbest) {
+                        tbest = t;
+                        best = L;
+                    }
+                }
+                if (e != hipSuccess) break;
+                if (best == 0) {
+                    best = Ls[0];   // nothing to time (no IPs): the default, not remembered
+                } else {
+                    cache[key] = best;
+                    wrote = true;
+                    ++P->tuned;
+                }
+            }
+            for (int k : cl.second) P->side[k] = best;
+        }
+        if (e != hipSuccess) {
+            free_plan(P);
+            return hip_status(e);
+        }
+        if (wrote) write_cache(tune_cache, cache);
+    }
+
+    // ---- match work lists; costlier items first ----
+    P->mp.resize(n_pairs);
+    std::vector<MatchArgs> margs(n_pairs);
+    for (int k = 0; k < n_pairs; ++k) {
+        P->mp[k] = match_plan_L(pairs[k].n, pairs[k].m, pairs[k].r, P->side[k]);
+        margs[k] = make_args(pairs[k], mem, pm[k], z, P->dtype, P->mp[k]);
+    }
+    std::vector<int> order(n_pairs);
+    for (int k = 0; k < n_pairs; ++k) order[k] = k;
+    auto cost = [&](int k) {   // rows transformed per item: search block + template
+        const MatchPlan& m = P->mp[k];
+        return pairs[k].m + std::min(m.Vb, 2 * pairs[k].r + 1) - 1 + pairs[k].m;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    std::vector<int4> items[2], peak;
+    for (int k : order) {
+        append_items(items[bucket_of(P->side[k])], k, pairs[k].n, P->mp[k].nb);
+        if (P->mp[k].nb > 1)
+            for (int i = 0; i < pairs[k].n; i += 256) peak.push_back(make_int4(k, i, 0, 0));
+    }
+    up(P->margs, margs.data(), margs.size() * sizeof(MatchArgs));
+    for (int b = 0; b < 2; ++b) {
+        up(P->items[b], items[b].data(), items[b].size() * sizeof(int4));
+        P->nitems[b] = (int)items[b].size();
+    }
+    up(P->peak, peak.data(), peak.size() * sizeof(int4));
+    P->npeak = (int)peak.size();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        free_plan(P);
+        return hip_status(e);
+    }
+    *plan = P;
+    return SFOC_OK;
+}
+
+int sfoc_register_cps_batched(sfoc_plan* P, void* stream) {
+    if (!P) return SFOC_E_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    if (!(P->flags & SFOC_PLAN_GRAPH)) return hip_status(enqueue_all(P, st));
+    hipError_t e = hipSuccess;
+    if (!P->exec) {
+        // One eager pass first, so that kernel attributes are set outside the
+        // capture; then the sequence is captured on the plan's own stream
+        // and the graph is launched on the caller's.
+        e = enqueue_all(P, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess) e = hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_status(e);
+        const hipError_t ee = enqueue_all(P, P->cap_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(P->cap_stream, &g);
+        if (ee != hipSuccess || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_status(ee != hipSuccess ? ee : e);
+        }
+        e = hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            P->exec = nullptr;
+            return hip_status(e);
+        }
+        P->graph = g;
+    }
+    return hip_status(hipGraphLaunch(P->exec, st));
+}
+
+int sfoc_plan_destroy(sfoc_plan* P) {
+    if (!P) return SFOC_E_INVALID_ARG;
+    // the plan's memory may still be in use by work enqueued on any stream
+    (void)hipDeviceSynchronize();
+    free_plan(P);
+    return SFOC_OK;
+}
+
+int sfoc_plan_get_info(const sfoc_plan* P, sfoc_plan_info* info, int32_t* fft_side, int32_t* blocks, int32_t cap) {
+    if (!P || !info || cap < 0) return SFOC_E_INVALID_ARG;
+    info->n_pairs = (int32_t)P->pairs.size();
+    info->describe_tiles = P->ndt;
+    info->match_items[0] = P->nitems[0];
+    info->match_items[1] = P->nitems[1];
+    info->peak_items = P->npeak;
+    info->tuned_classes = P->tuned;
+    info->cached_classes = P->cached;
+    info->graph = P->exec != nullptr;
+    info->device_bytes = (int64_t)P->bytes;
+    const int n = std::min<int>(cap, (int)P->pairs.size());
+    for (int k = 0; k < n; ++k) {
+        if (fft_side) fft_side[k] = P->side[k];
+        if (blocks) blocks[k] = P->mp[k].nb;
+    }
+    return SFOC_OK;
+}
+
+}  // extern "C"

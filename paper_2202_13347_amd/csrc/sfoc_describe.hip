@@ -16,12 +16,12 @@
 //      sum_c g and sum_c g^2 (float64, from the stored values) for the
 //      integral images.
 #include "sfoc_dev.h"
-#include "sfoc_plan.h"
+#include "sfoc_launch.h"
 #include "sfoc_trace.h"
 
 namespace sfoc {
 
-constexpr int kTS = 32;       // output tile side
+constexpr int kTS = kDescribeTile;   // output tile side
 constexpr int kNT = 256;      // threads per tile
 constexpr int kRun = 4;       // outputs per thread along a run
 constexpr int kPXT = kTS * kTS / kNT;   // output pixels per thread (one run of 4)
@@ -193,13 +193,30 @@ SFOC_DEV void col_run_any(const float* p, int P, int rho, const float* te, const
     }
 
 template <int Z, int CG, bool FAST>
-__global__ __launch_bounds__(kNT, 2) void describe_kernel(const float* __restrict__ img, int H, int W, int64_t ld,
-                                                          void* __restrict__ desc, double* __restrict__ integ1,
-                                                          double* __restrict__ integ2, const DescribeConsts C,
+__global__ __launch_bounds__(kNT, 2) void describe_kernel(const DescribeJob single,
+                                                          const DescribeJob* __restrict__ jobs,
+                                                          const int4* __restrict__ tiles, const DescribeConsts C,
                                                           int BSP_, int ISX, int BPP_, int IPP) {
     extern __shared__ float lds[];
     const int t = threadIdx.x;
-    const int ty0 = blockIdx.y * kTS, tx0 = blockIdx.x * kTS;
+    DescribeJob J;
+    int ty0, tx0;
+    if (tiles) {
+        const int4 e = tiles[blockIdx.x];
+        J = load_table(jobs, e.x);
+        ty0 = e.y;
+        tx0 = e.z;
+    } else {
+        J = single;
+        ty0 = blockIdx.y * kTS;
+        tx0 = blockIdx.x * kTS;
+    }
+    const float* __restrict__ img = J.img;
+    void* __restrict__ desc = J.desc;
+    double* __restrict__ integ1 = J.integ1;
+    double* __restrict__ integ2 = J.integ2;
+    const int H = J.H, W = J.W;
+    const int64_t ld = J.ld;
     // The K = 1, rates 1..3 path has Q = 3: its tile geometry is compile-time,
     // so the index arithmetic below divides by constants.
     constexpr int kFastQ = 3, kFastBSP = (kTS + 2 * kFastQ + kRun - 1) / kRun * kRun;
@@ -442,11 +459,16 @@ __global__ __launch_bounds__(kNT, 2) void describe_kernel(const float* __restric
 constexpr int kScanNT = 256;
 constexpr int kScanPer = 8;
 
-__global__ __launch_bounds__(kScanNT) void integral_row_scan(double* __restrict__ g1, double* __restrict__ g2,
-                                                              int H, int W) {
+template <bool BATCH>
+__global__ __launch_bounds__(kScanNT) void integral_row_scan(const IntegJob single, const IntegJob* __restrict__ jobs,
+                                                              const int4* __restrict__ rows) {
     __shared__ double sh[2][kScanNT * kScanPer];
     __shared__ double wsum[2][kScanNT / 64];
-    const int y = blockIdx.x;  // 0..H
+    const IntegJob J = BATCH ? load_table(jobs, rows[blockIdx.x].x) : single;
+    const int y = BATCH ? rows[blockIdx.x].y : (int)blockIdx.x;   // 0..H
+    double* __restrict__ g1 = J.g1;
+    double* __restrict__ g2 = J.g2;
+    const int W = J.W;
     const int t = threadIdx.x;
     const int64_t rowoff = (int64_t)y * (W + 1);
     if (y == 0) {
@@ -517,11 +539,19 @@ __global__ __launch_bounds__(kScanNT) void integral_row_scan(double* __restrict_
 }
 
 // Column pass, phase 1: per block of kScanRows rows, the column totals.
-__global__ __launch_bounds__(kScanNT) void integral_col_blocksum(const double* __restrict__ g1,
-                                                                  const double* __restrict__ g2, int H, int W,
-                                                                  double* __restrict__ bs1, double* __restrict__ bs2) {
-    const int x = blockIdx.x * kScanNT + threadIdx.x;
-    const int b = blockIdx.y;
+template <bool BATCH>
+__global__ __launch_bounds__(kScanNT) void integral_col_blocksum(const IntegJob single,
+                                                                  const IntegJob* __restrict__ jobs,
+                                                                  const int4* __restrict__ cols) {
+    const IntegJob J = BATCH ? load_table(jobs, cols[blockIdx.x].x) : single;
+    const int bx = BATCH ? cols[blockIdx.x].y : (int)blockIdx.x;
+    const int b = BATCH ? cols[blockIdx.x].z : (int)blockIdx.y;
+    const int H = J.H, W = J.W;
+    const double* __restrict__ g1 = J.g1;
+    const double* __restrict__ g2 = J.g2;
+    double* __restrict__ bs1 = J.bs1;
+    double* __restrict__ bs2 = J.bs2;
+    const int x = bx * kScanNT + threadIdx.x;
     if (x > W) return;
     const int y0 = 1 + b * kScanRows, y1 = min(H, y0 + kScanRows - 1);
     double s1 = 0.0, s2 = 0.0;
@@ -534,11 +564,18 @@ __global__ __launch_bounds__(kScanNT) void integral_col_blocksum(const double* _
 }
 
 // Column pass, phase 2: carry from the blocks above, then the in-block scan.
-__global__ __launch_bounds__(kScanNT) void integral_col_apply(double* __restrict__ g1, double* __restrict__ g2,
-                                                               int H, int W, const double* __restrict__ bs1,
-                                                               const double* __restrict__ bs2) {
-    const int x = blockIdx.x * kScanNT + threadIdx.x;
-    const int b = blockIdx.y;
+template <bool BATCH>
+__global__ __launch_bounds__(kScanNT) void integral_col_apply(const IntegJob single, const IntegJob* __restrict__ jobs,
+                                                               const int4* __restrict__ cols) {
+    const IntegJob J = BATCH ? load_table(jobs, cols[blockIdx.x].x) : single;
+    const int bx = BATCH ? cols[blockIdx.x].y : (int)blockIdx.x;
+    const int b = BATCH ? cols[blockIdx.x].z : (int)blockIdx.y;
+    const int H = J.H, W = J.W;
+    double* __restrict__ g1 = J.g1;
+    double* __restrict__ g2 = J.g2;
+    const double* __restrict__ bs1 = J.bs1;
+    const double* __restrict__ bs2 = J.bs2;
+    const int x = bx * kScanNT + threadIdx.x;
     if (x > W) return;
     double c1 = 0.0, c2 = 0.0;
     for (int q = 0; q < b; ++q) {
@@ -557,54 +594,80 @@ __global__ __launch_bounds__(kScanNT) void integral_col_apply(double* __restrict
 
 // ---- launch -------------------------------------------------------------
 template <int Z, bool FAST>
-static hipError_t launch_describe_zf(const float* img, int H, int W, int64_t ld, void* desc, double* i1, double* i2,
+static hipError_t launch_describe_zf(const DescribeJob& job, const DescribeJob* jobs, const int4* tiles, int ntiles,
                                      const DescribeConsts& c, hipStream_t st) {
     constexpr int CG = Z >= 4 ? 4 : Z;
     const DescribeGeom g = describe_geom(c);
-    dim3 grid((W + kTS - 1) / kTS, (H + kTS - 1) / kTS);
+    dim3 grid = tiles ? dim3(ntiles) : dim3((job.W + kTS - 1) / kTS, (job.H + kTS - 1) / kTS);
+    if (grid.x == 0) return hipSuccess;
     auto kern = describe_kernel<Z, CG, FAST>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.bytes);
+    hipError_t e = ensure_dynamic_lds((const void*)kern, (int)g.bytes);
     if (e != hipSuccess) return e;
     trace_begin(st, SFOC_K_DESCRIBE);
-    hipLaunchKernelGGL(kern, grid, dim3(kNT), g.bytes, st, img, H, W, ld, desc, i1, i2, c, g.BSP, g.ISX, g.BPP,
-                       g.IPP);
+    hipLaunchKernelGGL(kern, grid, dim3(kNT), g.bytes, st, job, jobs, tiles, c, g.BSP, g.ISX, g.BPP, g.IPP);
     trace_end(st, SFOC_K_DESCRIBE);
     return hipGetLastError();
 }
 
 template <int Z>
-static hipError_t launch_describe_z(const float* img, int H, int W, int64_t ld, void* desc, double* i1, double* i2,
+static hipError_t launch_describe_z(const DescribeJob& job, const DescribeJob* jobs, const int4* tiles, int ntiles,
                                     const DescribeConsts& c, hipStream_t st) {
     const bool fast = c.K == 1 && c.ndil == 3 && c.dil[0] == 1 && c.dil[1] == 2 && c.dil[2] == 3;
-    return fast ? launch_describe_zf<Z, true>(img, H, W, ld, desc, i1, i2, c, st)
-                : launch_describe_zf<Z, false>(img, H, W, ld, desc, i1, i2, c, st);
+    return fast ? launch_describe_zf<Z, true>(job, jobs, tiles, ntiles, c, st)
+                : launch_describe_zf<Z, false>(job, jobs, tiles, ntiles, c, st);
 }
 
-hipError_t launch_describe(const float* img, int H, int W, int64_t ld, void* desc, double* i1, double* i2,
-                           const DescribeConsts& c, hipStream_t st) {
+static hipError_t launch_describe_any(const DescribeJob& job, const DescribeJob* jobs, const int4* tiles, int ntiles,
+                                      const DescribeConsts& c, hipStream_t st) {
     switch (c.z) {
-        case 2: return launch_describe_z<2>(img, H, W, ld, desc, i1, i2, c, st);
-        case 3: return launch_describe_z<3>(img, H, W, ld, desc, i1, i2, c, st);
-        case 4: return launch_describe_z<4>(img, H, W, ld, desc, i1, i2, c, st);
-        case 6: return launch_describe_z<6>(img, H, W, ld, desc, i1, i2, c, st);
-        case 8: return launch_describe_z<8>(img, H, W, ld, desc, i1, i2, c, st);
-        case 12: return launch_describe_z<12>(img, H, W, ld, desc, i1, i2, c, st);
-        case 16: return launch_describe_z<16>(img, H, W, ld, desc, i1, i2, c, st);
-        case 24: return launch_describe_z<24>(img, H, W, ld, desc, i1, i2, c, st);
-        case 32: return launch_describe_z<32>(img, H, W, ld, desc, i1, i2, c, st);
+        case 2: return launch_describe_z<2>(job, jobs, tiles, ntiles, c, st);
+        case 3: return launch_describe_z<3>(job, jobs, tiles, ntiles, c, st);
+        case 4: return launch_describe_z<4>(job, jobs, tiles, ntiles, c, st);
+        case 6: return launch_describe_z<6>(job, jobs, tiles, ntiles, c, st);
+        case 8: return launch_describe_z<8>(job, jobs, tiles, ntiles, c, st);
+        case 12: return launch_describe_z<12>(job, jobs, tiles, ntiles, c, st);
+        case 16: return launch_describe_z<16>(job, jobs, tiles, ntiles, c, st);
+        case 24: return launch_describe_z<24>(job, jobs, tiles, ntiles, c, st);
+        case 32: return launch_describe_z<32>(job, jobs, tiles, ntiles, c, st);
         default: return hipErrorInvalidValue;
     }
 }
 
+// Several images in one launch: jobs and tiles are device tables.
+hipError_t launch_describe_batched(const DescribeJob* jobs, const int4* tiles, int ntiles, const DescribeConsts& c,
+                                   hipStream_t st) {
+    DescribeJob none{};
+    return launch_describe_any(none, jobs, tiles, ntiles, c, st);
+}
+
+hipError_t launch_describe(const float* img, int H, int W, int64_t ld, void* desc, double* i1, double* i2,
+                           const DescribeConsts& c, hipStream_t st) {
+    DescribeJob job{img, desc, i1, i2, ld, H, W};
+    return launch_describe_any(job, nullptr, nullptr, 0, c, st);
+}
+
 hipError_t launch_integral(double* i1, double* i2, int H, int W, double* ws, hipStream_t st) {
-    trace_begin(st, SFOC_K_INTEGRAL);
-    hipLaunchKernelGGL(integral_row_scan, dim3(H + 1), dim3(kScanNT), 0, st, i1, i2, H, W);
     const int nb = (H + kScanRows - 1) / kScanRows;
-    double* bs1 = ws;
-    double* bs2 = ws + (size_t)nb * (W + 1);
+    const IntegJob J{i1, i2, ws, ws + (size_t)nb * (W + 1), H, W};
+    const IntegJob* none = nullptr;
+    const int4* nit = nullptr;
+    trace_begin(st, SFOC_K_INTEGRAL);
+    hipLaunchKernelGGL(integral_row_scan<false>, dim3(H + 1), dim3(kScanNT), 0, st, J, none, nit);
     dim3 grid((W + 1 + kScanNT - 1) / kScanNT, nb);
-    hipLaunchKernelGGL(integral_col_blocksum, grid, dim3(kScanNT), 0, st, i1, i2, H, W, bs1, bs2);
-    hipLaunchKernelGGL(integral_col_apply, grid, dim3(kScanNT), 0, st, i1, i2, H, W, bs1, bs2);
+    hipLaunchKernelGGL(integral_col_blocksum<false>, grid, dim3(kScanNT), 0, st, J, none, nit);
+    hipLaunchKernelGGL(integral_col_apply<false>, grid, dim3(kScanNT), 0, st, J, none, nit);
+    trace_end(st, SFOC_K_INTEGRAL);
+    return hipGetLastError();
+}
+
+hipError_t launch_integral_batched(const IntegJob* jobs, const int4* rows, int nrows, const int4* cols, int ncols,
+                                   hipStream_t st) {
+    if (nrows == 0) return hipSuccess;
+    const IntegJob none{};
+    trace_begin(st, SFOC_K_INTEGRAL);
+    hipLaunchKernelGGL(integral_row_scan<true>, dim3(nrows), dim3(kScanNT), 0, st, none, jobs, rows);
+    hipLaunchKernelGGL(integral_col_blocksum<true>, dim3(ncols), dim3(kScanNT), 0, st, none, jobs, cols);
+    hipLaunchKernelGGL(integral_col_apply<true>, dim3(ncols), dim3(kScanNT), 0, st, none, jobs, cols);
     trace_end(st, SFOC_K_INTEGRAL);
     return hipGetLastError();
 }

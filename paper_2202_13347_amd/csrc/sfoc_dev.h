@@ -5,6 +5,19 @@
 
 #define SFOC_DEV __device__ __forceinline__
 
+// Load a launch-table entry (read-only for the whole launch) through the
+// constant address space.  Pointers loaded that way are known to address
+// global memory, so accesses through them stay global loads and stores with
+// scalar bases instead of flat ones.  The host pass never runs this.
+template <class T>
+SFOC_DEV T load_table(const T* p, int i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return ((const __attribute__((address_space(4))) T*)p)[i];
+#else
+    return p[i];
+#endif
+}
+
 // Reflect-101 index (mirror without repeating the edge), periodic for any i.
 SFOC_DEV int reflect101(int i, int n) {
     if (n == 1) return 0;

@@ -1,0 +1,90 @@
+// Kernel argument records and the launch functions behind the C-ABI.  A
+// launch either takes one record by value (one image or one pair) or a
+// device table of records plus a table of work items (batched plans).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sfoc_plan.h"
+
+namespace sfoc {
+
+// One image to describe.  A launch covers either the whole tile grid of one
+// image or a table of (job, tile row origin, tile column origin) entries
+// over several images.
+struct DescribeJob {
+    const float* img;
+    void* desc;
+    double* integ1;   // (H+1) x (W+1) per-pixel sum / sum of squares, or null
+    double* integ2;
+    int64_t ld;
+    int H, W;
+};
+
+// The float64 integral images of one reference image and the scratch of
+// the column pass (ceil(H / kScanRows) x (W + 1) doubles per image).
+struct IntegJob {
+    double* g1;
+    double* g2;
+    double* bs1;
+    double* bs2;
+    int H, W;
+};
+
+// One pair of a match launch.
+struct MatchArgs {
+    const void* desc_sen;
+    const void* desc_ref;
+    const double* integ1;
+    const double* integ2;
+    const int32_t* ips;
+    const int32_t* prior;
+    float* ncc;
+    sfoc_cp* cps;
+    float* surf;      // n x V x V scratch surfaces when the offsets are split and ncc == NULL
+    float4* blk;      // per (IP, offset block): best score, its index, flags
+    int64_t Hs, Ws, Hr, Wr;
+    int32_t z, dtype, n, m, r;
+    int32_t nbu, nbv, Vb;   // offset blocks per axis and offsets per block
+};
+
+// Side of the square describe tile.
+constexpr int kDescribeTile = 32;
+
+// SFOC_OK for hipSuccess, else SFOC_E_HIP (the HIP error is kept for
+// sfoc_status_string).
+int hip_status(hipError_t e);
+
+// Raises a kernel's dynamic-LDS limit on the current device to at least
+// `bytes`, once per (kernel, device, size): later launches, including those
+// recorded under stream capture, make no attribute call.
+hipError_t ensure_dynamic_lds(const void* kern, int bytes);
+
+// ---- one image / one pair ------------------------------------------------
+hipError_t launch_describe(const float* img, int H, int W, int64_t ld, void* desc, double* i1, double* i2,
+                           const DescribeConsts& c, hipStream_t st);
+hipError_t launch_integral(double* i1, double* i2, int H, int W, double* ws, hipStream_t st);
+hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void* desc_ref, int64_t Hr, int64_t Wr,
+                        const double* i1, const double* i2, int z, int dtype, const int32_t* ips,
+                        const int32_t* prior, int n, int m, int r, float* ncc, sfoc_cp* cps, void* ws,
+                        hipStream_t st);
+// Fills the offset-block fields and scratch pointers of `a` for transform
+// side L (a.surf / a.blk point into ws, whose size is match_plan_L().ws_bytes).
+void match_args_layout(MatchArgs& a, const MatchPlan& mp, void* ws);
+
+// ---- tables (device pointers) --------------------------------------------
+// tiles[k] = {job, tile row origin, tile column origin, 0}
+hipError_t launch_describe_batched(const DescribeJob* jobs, const int4* tiles, int ntiles, const DescribeConsts& c,
+                                   hipStream_t st);
+// rows[k] = {job, row 0..H, 0, 0};  cols[k] = {job, column block, row block, 0}
+hipError_t launch_integral_batched(const IntegJob* jobs, const int4* rows, int nrows, const int4* cols, int ncols,
+                                   hipStream_t st);
+// items[k] = {pair, IP, offset block, 0}, all with transform side L
+hipError_t launch_match_items(int L, int dtype, const MatchArgs* pairs, const int4* items, int nitems,
+                              hipStream_t st);
+// items[k] = {pair, first IP of a run of 256, 0, 0} over pairs with split offsets
+hipError_t launch_peak_batched(const MatchArgs* pairs, const int4* items, int nitems, hipStream_t st);
+// one workgroup per pair
+hipError_t launch_consistency_batched(const MatchArgs* pairs, int npairs, hipStream_t st);
+
+}  // namespace sfoc

@@ -25,26 +25,10 @@
 // subtraction in float64, then the argmax, the parabola refinement and the
 // per-CP flags are written.
 #include "sfoc_dev.h"
-#include "sfoc_plan.h"
+#include "sfoc_launch.h"
 #include "sfoc_trace.h"
 
 namespace sfoc {
-
-struct MatchArgs {
-    const void* desc_sen;
-    const void* desc_ref;
-    const double* integ1;
-    const double* integ2;
-    const int32_t* ips;
-    const int32_t* prior;
-    float* ncc;
-    sfoc_cp* cps;
-    float* surf;      // n x V x V scratch surfaces when the offsets are split and ncc == NULL
-    float4* blk;      // per (IP, offset block): best score, its index, flags
-    int64_t Hs, Ws, Hr, Wr;
-    int32_t z, dtype, n, m, r;
-    int32_t nbu, nbv, Vb;   // offset blocks per axis and offsets per block
-};
 
 // Per-block flags of a split surface.
 constexpr int kBlkNonflat = 1, kBlkNonfin = 2, kBlkFlatT = 4, kBlkBadT = 8, kBlkOOB = 16;
@@ -380,8 +364,10 @@ SFOC_DEV bool in_image(int64_t y, int64_t x, int h, int w, int64_t H, int64_t W)
     return y >= 0 && x >= 0 && y + h <= H && x + w <= W;
 }
 
-template <int L, int DT>
-__global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchArgs A) {
+template <int L, int DT, bool BATCH>
+__global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchArgs single,
+                                                                   const MatchArgs* __restrict__ pairs,
+                                                                   const int4* __restrict__ items) {
     using C = MatchCfg<L>;
     extern __shared__ float4 lds_raw[];
     float2* tw = reinterpret_cast<float2*>(lds_raw);
@@ -393,8 +379,21 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
     // covers offsets [u0, u0 + Vu) x [v0, v0 + Vv) with a search window of
     // (m + Vu - 1) x (m + Vv - 1) <= L x L, writes its part of the surface and
     // its best score, and peak_kernel combines the blocks.
+    // One pair per launch (blockIdx.x -> IP, block), or (BATCH) a table of
+    // (pair, IP, block) items over several pairs.
+    int i, bq, slot;
+    const MatchArgs A = BATCH ? load_table(pairs, items[blockIdx.x].x) : single;
     const int nblk = A.nbu * A.nbv;
-    const int i = blockIdx.x / nblk, bq = blockIdx.x - i * nblk;
+    if (BATCH) {
+        const int4 it = items[blockIdx.x];
+        i = it.y;
+        bq = it.z;
+        slot = i * nblk + bq;
+    } else {
+        i = blockIdx.x / nblk;
+        bq = blockIdx.x - i * nblk;
+        slot = blockIdx.x;
+    }
     const int bu = bq / A.nbv, bv = bq - bu * A.nbv;
     const int t = threadIdx.x;
     const int m = A.m, r = A.r, M = m + 2 * r, V = 2 * r + 1;
@@ -419,7 +418,7 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
                 out.flags = SFOC_CP_OOB;
                 A.cps[i] = out;
             } else {
-                A.blk[blockIdx.x] = make_float4(0.f, __int_as_float(0), __int_as_float(kBlkOOB), 0.f);
+                A.blk[slot] = make_float4(0.f, __int_as_float(0), __int_as_float(kBlkOOB), 0.f);
             }
         }
         if (nout)
@@ -717,7 +716,7 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
         if (t == 0) {
             const int fl = (nonflat ? kBlkNonflat : 0) | (nonfin ? kBlkNonfin : 0) | (flatT ? kBlkFlatT : 0) |
                            (badT ? kBlkBadT : 0);
-            A.blk[blockIdx.x] = make_float4(best, __int_as_float(bidx), __int_as_float(fl), 0.f);
+            A.blk[slot] = make_float4(best, __int_as_float(bidx), __int_as_float(fl), 0.f);
         }
         return;
     }
@@ -758,8 +757,11 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
 // One thread per interest point: the best score over its blocks (ties: the
 // smallest row-major surface index), the flags, and the parabola from the
 // surface the blocks wrote.  Same decisions as the single-block path.
-__global__ __launch_bounds__(256) void peak_kernel(const MatchArgs A) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+template <bool BATCH>
+__global__ __launch_bounds__(256) void peak_kernel(const MatchArgs single, const MatchArgs* __restrict__ pairs,
+                                                   const int4* __restrict__ items) {
+    const MatchArgs A = BATCH ? load_table(pairs, items[blockIdx.x].x) : single;
+    const int i = (BATCH ? items[blockIdx.x].y : (int)(blockIdx.x * blockDim.x)) + (int)threadIdx.x;
     if (i >= A.n) return;
     const int nblk = A.nbu * A.nbv;
     const int r = A.r, V = 2 * r + 1;
@@ -865,7 +867,14 @@ SFOC_DEV float select_kth(const sfoc_cp* cps, const int32_t* prior, int n, int a
     return fkey_inv(prefix);
 }
 
-__global__ __launch_bounds__(kConsNT) void consistency_kernel(sfoc_cp* cps, const int32_t* prior, int n) {
+__global__ __launch_bounds__(kConsNT) void consistency_kernel(sfoc_cp* cps, const int32_t* prior, int n,
+                                                              const MatchArgs* __restrict__ pairs) {
+    if (pairs) {   // one workgroup per pair of a batched plan
+        const MatchArgs P = load_table(pairs, (int)blockIdx.x);
+        cps = P.cps;
+        prior = P.prior;
+        n = P.n;
+    }
     __shared__ uint32_t hist[256];
     __shared__ uint32_t sel[2];
     __shared__ int cnt;
@@ -900,15 +909,27 @@ __global__ __launch_bounds__(kConsNT) void consistency_kernel(sfoc_cp* cps, cons
 }
 
 // ---- launch -------------------------------------------------------------
+void match_args_layout(MatchArgs& a, const MatchPlan& mp, void* ws) {
+    a.nbu = a.nbv = mp.nb;
+    a.Vb = mp.Vb;
+    a.surf = nullptr;
+    a.blk = nullptr;
+    if (mp.nb > 1) {
+        const int V = 2 * a.r + 1;
+        a.surf = (float*)ws;
+        a.blk = (float4*)((char*)ws + align_up((size_t)a.n * V * V * sizeof(float), 256));
+    }
+}
+
 template <int L, int DT>
 static hipError_t launch_match_L(const MatchArgs& a, hipStream_t st) {
     using C = MatchCfg<L>;
-    auto kern = match_kernel<L, DT>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)C::lds_bytes);
+    auto kern = match_kernel<L, DT, false>;
+    hipError_t e = ensure_dynamic_lds((const void*)kern, (int)C::lds_bytes);
     if (e != hipSuccess) return e;
     trace_begin(st, SFOC_K_MATCH);
-    hipLaunchKernelGGL(kern, dim3(a.n * a.nbu * a.nbv), dim3(C::NT), C::lds_bytes, st, a);
+    hipLaunchKernelGGL(kern, dim3(a.n * a.nbu * a.nbv), dim3(C::NT), C::lds_bytes, st, a, (const MatchArgs*)nullptr,
+                       (const int4*)nullptr);
     trace_end(st, SFOC_K_MATCH);
     return hipGetLastError();
 }
@@ -937,15 +958,7 @@ hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void
     a.r = r;
     const MatchPlan mp = match_plan(n, m, r);
     const int L = mp.L;
-    a.nbu = a.nbv = mp.nb;
-    a.Vb = mp.Vb;
-    a.surf = nullptr;
-    a.blk = nullptr;
-    if (mp.nb > 1) {
-        const int V = 2 * r + 1;
-        a.surf = (float*)ws;
-        a.blk = (float4*)((char*)ws + align_up((size_t)n * V * V * sizeof(float), 256));
-    }
+    match_args_layout(a, mp, ws);
     hipError_t e;
     if (L == 64) e = dtype == 0 ? launch_match_L<64, 0>(a, st)
                    : dtype == 1 ? launch_match_L<64, 1>(a, st) : launch_match_L<64, 2>(a, st);
@@ -955,11 +968,61 @@ hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void
     if (e != hipSuccess) return e;
     if (mp.nb > 1) {
         trace_begin(st, SFOC_K_PEAK);
-        hipLaunchKernelGGL(peak_kernel, dim3((n + 255) / 256), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(peak_kernel<false>, dim3((n + 255) / 256), dim3(256), 0, st, a, (const MatchArgs*)nullptr,
+                           (const int4*)nullptr);
         trace_end(st, SFOC_K_PEAK);
     }
     trace_begin(st, SFOC_K_CONSISTENCY);
-    hipLaunchKernelGGL(consistency_kernel, dim3(1), dim3(kConsNT), 0, st, cps, prior, n);
+    hipLaunchKernelGGL(consistency_kernel, dim3(1), dim3(kConsNT), 0, st, cps, prior, n, (const MatchArgs*)nullptr);
+    trace_end(st, SFOC_K_CONSISTENCY);
+    return hipGetLastError();
+}
+
+// ---- batched launches ---------------------------------------------------
+template <int L, int DT>
+static hipError_t launch_match_items_L(const MatchArgs* pairs, const int4* items, int nitems, hipStream_t st) {
+    using C = MatchCfg<L>;
+    auto kern = match_kernel<L, DT, true>;
+    hipError_t e = ensure_dynamic_lds((const void*)kern, (int)C::lds_bytes);
+    if (e != hipSuccess) return e;
+    MatchArgs none{};
+    trace_begin(st, SFOC_K_MATCH);
+    hipLaunchKernelGGL(kern, dim3(nitems), dim3(C::NT), C::lds_bytes, st, none, pairs, items);
+    trace_end(st, SFOC_K_MATCH);
+    return hipGetLastError();
+}
+
+// One launch over (pair, IP, block) items that share the transform side L.
+hipError_t launch_match_items(int L, int dtype, const MatchArgs* pairs, const int4* items, int nitems,
+                              hipStream_t st) {
+    if (nitems == 0) return hipSuccess;
+    if (L == 64)
+        return dtype == 0 ? launch_match_items_L<64, 0>(pairs, items, nitems, st)
+             : dtype == 1 ? launch_match_items_L<64, 1>(pairs, items, nitems, st)
+                          : launch_match_items_L<64, 2>(pairs, items, nitems, st);
+    if (L == 128)
+        return dtype == 0 ? launch_match_items_L<128, 0>(pairs, items, nitems, st)
+             : dtype == 1 ? launch_match_items_L<128, 1>(pairs, items, nitems, st)
+                          : launch_match_items_L<128, 2>(pairs, items, nitems, st);
+    return hipErrorInvalidValue;
+}
+
+// Peak of split pairs: items {pair, first IP of a run of 256}.
+hipError_t launch_peak_batched(const MatchArgs* pairs, const int4* items, int nitems, hipStream_t st) {
+    if (nitems == 0) return hipSuccess;
+    MatchArgs none{};
+    trace_begin(st, SFOC_K_PEAK);
+    hipLaunchKernelGGL(peak_kernel<true>, dim3(nitems), dim3(256), 0, st, none, pairs, items);
+    trace_end(st, SFOC_K_PEAK);
+    return hipGetLastError();
+}
+
+// Consistency of every pair of a plan: one workgroup per pair.
+hipError_t launch_consistency_batched(const MatchArgs* pairs, int npairs, hipStream_t st) {
+    if (npairs == 0) return hipSuccess;
+    trace_begin(st, SFOC_K_CONSISTENCY);
+    hipLaunchKernelGGL(consistency_kernel, dim3(npairs), dim3(kConsNT), 0, st, (sfoc_cp*)nullptr,
+                       (const int32_t*)nullptr, 0, pairs);
     trace_end(st, SFOC_K_CONSISTENCY);
     return hipGetLastError();
 }

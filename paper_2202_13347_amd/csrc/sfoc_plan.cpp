@@ -147,25 +147,56 @@ size_t describe_ws_bytes(int64_t H, int64_t W) {
     return align_up((size_t)(nb * (W + 1)) * sizeof(double) * 2, 256);
 }
 
-MatchPlan match_plan(int32_t n, int32_t m, int32_t r) {
+MatchPlan match_plan_L(int32_t n, int32_t m, int32_t r, int L) {
     MatchPlan p{0, 1, 0, 0};
-    if (m < 3 || r < 1 || r > kMaxRadiusMatch || n < 0) return p;
+    if (m < 3 || r < 1 || r > kMaxRadiusMatch || n < 0 || (L != 64 && L != 128)) return p;
     const int M = m + 2 * r, V = 2 * r + 1;
-    if (M <= 64) {
-        p.L = 64;
+    if (M <= L) {
+        p.L = L;
         p.Vb = V;
-    } else if (M <= 128) {
-        p.L = 128;
-        p.Vb = V;
-    } else if (m <= 126) {
-        // offsets split so that each block's search window fits L = 128
-        p.L = 128;
-        p.Vb = 128 - m + 1;
+    } else if (m <= L - 1) {
+        // offsets split so that each block's search window fits L x L
+        p.L = L;
+        p.Vb = L - m + 1;
         p.nb = (V + p.Vb - 1) / p.Vb;
         p.ws_bytes = align_up((size_t)n * V * V * sizeof(float), 256) +
                      align_up((size_t)n * p.nb * p.nb * 4 * sizeof(float), 256);
     }
     return p;
+}
+
+MatchPlan match_plan(int32_t n, int32_t m, int32_t r) {
+    if (m < 3 || r < 1) return MatchPlan{0, 1, 0, 0};
+    const int M = m + 2 * r;
+    if (M <= 64) return match_plan_L(n, m, r, 64);
+    if (m > 126) return MatchPlan{0, 1, 0, 0};
+    return match_plan_L(n, m, r, 128);
+}
+
+int match_candidates(int32_t m, int32_t r, int* Ls) {
+    const MatchPlan d = match_plan(1, m, r);
+    if (d.L == 0) return 0;
+    int k = 0;
+    Ls[k++] = d.L;
+    const int other = d.L == 64 ? 128 : 64;
+    const MatchPlan o = match_plan_L(1, m, r, other);
+    if (o.L != 0 && o.nb <= kMaxTuneBlocks && o.Vb >= 2) Ls[k++] = other;
+    return k;
+}
+
+void sensed_tile_mask(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m, int32_t r, int64_t Hs,
+                      int64_t Ws, int64_t Hr, int64_t Wr, int kTile, uint8_t* mask) {
+    const int64_t ntx = (Ws + kTile - 1) / kTile, nty = (Hs + kTile - 1) / kTile;
+    memset(mask, 0, (size_t)(ntx * nty));
+    const int64_t M = (int64_t)m + 2 * r;
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t ty = (int64_t)ips[2 * i] - m / 2, tx = (int64_t)ips[2 * i + 1] - m / 2;
+        const int64_t sy = ty - r + (prior ? prior[2 * i] : 0), sx = tx - r + (prior ? prior[2 * i + 1] : 0);
+        if (ty < 0 || tx < 0 || ty + m > Hs || tx + m > Ws) continue;
+        if (sy < 0 || sx < 0 || sy + M > Hr || sx + M > Wr) continue;
+        for (int64_t a = ty / kTile; a <= (ty + m - 1) / kTile; ++a)
+            for (int64_t b = tx / kTile; b <= (tx + m - 1) / kTile; ++b) mask[a * ntx + b] = 1;
+    }
 }
 
 }  // namespace sfoc

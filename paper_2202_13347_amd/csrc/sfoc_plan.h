@@ -53,8 +53,43 @@ struct MatchPlan {
     size_t ws_bytes;   // surfaces + per-block records when nb > 1
 };
 MatchPlan match_plan(int32_t n, int32_t m, int32_t r);
+// The same for a given transform side L (64 or 128); L = 0 in the result if
+// the template does not fit (a block needs m + Vb - 1 <= L with Vb >= 2).
+MatchPlan match_plan_L(int32_t n, int32_t m, int32_t r, int L);
 constexpr int kMaxRadiusMatch = 511;
 
+// Transform sides an autotuner may time for (m, r): every L in {64, 128}
+// whose plan exists with at most kMaxTuneBlocks offset blocks per axis, the
+// default first.  Returns the count written to Ls (at most 2).
+constexpr int kMaxTuneBlocks = 8;
+int match_candidates(int32_t m, int32_t r, int* Ls);
+
+// Sensed-image describe tiles (side kTile) that the templates of in-bounds
+// interest points read: mask[ty * ceil(Ws / kTile) + tx] = 1.  An IP whose
+// template or search window leaves its image reads nothing (it is flagged
+// out of bounds).  ips / prior are host arrays (prior may be null).
+void sensed_tile_mask(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m, int32_t r, int64_t Hs,
+                      int64_t Ws, int64_t Hr, int64_t Wr, int kTile, uint8_t* mask);
+
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Image sides are limited so that every per-image index fits in int32 and
+// every plane offset in int64; the match kernel addresses a descriptor
+// plane with 32-bit element offsets, so a plane holds fewer than 2^30 pixels.
+constexpr int64_t kMaxSide = 1 << 16;
+constexpr int64_t kMaxPlane = (int64_t)1 << 30;
+
+inline int check_image(const void* img, int64_t H, int64_t W, int64_t ld) {
+    if (!img) return SFOC_E_INVALID_ARG;
+    if (H < 1 || W < 1 || ld < W) return SFOC_E_INVALID_ARG;
+    if (H > kMaxSide || W > kMaxSide) return SFOC_E_UNSUPPORTED;
+    return SFOC_OK;
+}
+
+inline int check_match_shape(int32_t n, int32_t m, int32_t r) {
+    if (n < 0 || m < 3 || r < 1) return SFOC_E_INVALID_ARG;
+    if (match_plan(n, m, r).L == 0) return SFOC_E_UNSUPPORTED;
+    return SFOC_OK;
+}
 
 }  // namespace sfoc

@@ -27,8 +27,14 @@ static hipEvent_t take_event() {
     return e;
 }
 
+// Launches recorded into a graph under stream capture are not timed.
+static bool capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
 void trace_begin(hipStream_t st, int kid) {
-    if (!g_on || g_recs.size() >= SFOC_TRACE_MAX) return;
+    if (!g_on || g_recs.size() >= SFOC_TRACE_MAX || capturing(st)) return;
     hipEvent_t a = take_event(), b = take_event();
     if (!a || !b) return;
     hipEventRecord(a, st);
@@ -37,7 +43,7 @@ void trace_begin(hipStream_t st, int kid) {
 }
 
 void trace_end(hipStream_t st, int kid) {
-    if (!g_on || g_open < 0 || g_recs[g_open].kid != kid) return;
+    if (!g_on || g_open < 0 || g_recs[g_open].kid != kid || capturing(st)) return;
     hipEventRecord(g_recs[g_open].b, st);
     g_open = -1;
 }

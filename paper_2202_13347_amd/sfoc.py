@@ -49,6 +49,25 @@ CP_DTYPE = np.dtype([("sen_row", np.int32), ("sen_col", np.int32), ("dy", np.int
                      ("flags", np.uint32)])
 assert CP_DTYPE.itemsize == 32
 
+
+class Pair(ctypes.Structure):
+    """One image pair of a batched plan (device pointers)."""
+    _fields_ = [("ref", ctypes.c_void_p), ("Hr", ctypes.c_int64), ("Wr", ctypes.c_int64), ("ldr", ctypes.c_int64),
+                ("sen", ctypes.c_void_p), ("Hs", ctypes.c_int64), ("Ws", ctypes.c_int64), ("lds", ctypes.c_int64),
+                ("ips", ctypes.c_void_p), ("prior", ctypes.c_void_p), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("r", ctypes.c_int32), ("fft_side", ctypes.c_int32), ("ncc", ctypes.c_void_p),
+                ("cps", ctypes.c_void_p)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_int32), ("describe_tiles", ctypes.c_int32),
+                ("match_items", ctypes.c_int32 * 2), ("peak_items", ctypes.c_int32),
+                ("tuned_classes", ctypes.c_int32), ("cached_classes", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("device_bytes", ctypes.c_int64)]
+
+
+PLAN_GRAPH, PLAN_AUTOTUNE, PLAN_DENSE_SEN = 1, 2, 4
+
 _lib = None
 
 
@@ -72,12 +91,22 @@ def lib() -> ctypes.CDLL:
         L.sfoc_register_workspace.argtypes = [i64, i64, i64, i64, i32, i32, i32, P, ctypes.POINTER(sz)]
         L.sfoc_register_cps.argtypes = [vp, i64, i64, i64, vp, i64, i64, i64, vp, vp, i32, i32, i32, P,
                                         vp, vp, vp, sz, vp]
+        L.sfoc_plan_create.argtypes = [ctypes.POINTER(Pair), i32, P, i32, ctypes.c_char_p, vp,
+                                       ctypes.POINTER(vp)]
+        L.sfoc_register_cps_batched.argtypes = [vp, vp]
+        L.sfoc_plan_destroy.argtypes = [vp]
+        L.sfoc_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                         i32]
+        L.sfoc_match_candidates.argtypes = [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), i32]
+        L.sfoc_sensed_tiles.argtypes = [vp, vp, i32, i32, i32, i64, i64, i64, i64, vp]
+        L.sfoc_sensed_tiles.restype = i64
         L.sfoc_trace_enable.argtypes = [ctypes.c_int]
         L.sfoc_trace_collect.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.c_int]
         for name in ("sfoc_trace_enable", "sfoc_trace_collect", "sfoc_params_preset", "sfoc_params_check", "sfoc_describe_workspace", "sfoc_describe",
                      "sfoc_match_workspace", "sfoc_fastncc_match", "sfoc_register_workspace",
-                     "sfoc_register_cps"):
+                     "sfoc_register_cps", "sfoc_plan_create", "sfoc_register_cps_batched", "sfoc_plan_destroy",
+                     "sfoc_plan_get_info", "sfoc_match_candidates"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -241,6 +270,101 @@ def register_cps(ref, sen, ips, m: int, r: int, p: Params, prior=None, want_ncc=
                   device=ref.device, want_ncc=want_ncc)
     cps = R(ref, sen, ips, prior, stream)
     return (cps, R.ncc) if want_ncc else cps
+
+
+class Plan:
+    """A batched plan over image pairs (sfoc_plan_create).
+
+    pairs: sequence of dicts with CUDA tensors ref (Hr, Wr) float32, sen
+    (Hs, Ws) float32, ips (n, 2) int32, optional prior (n, 2) int32, and ints
+    m, r, optional fft_side (0 / 64 / 128).  The plan owns per-pair outputs
+    cps (n, 8) int32 and, with want_ncc, ncc (n, 2r+1, 2r+1); it keeps
+    references to every input tensor for its lifetime.  Calling the plan
+    runs sfoc_register_cps_batched on the current stream."""
+
+    def __init__(self, pairs, p: Params, flags: int = 0, tune_cache: str | None = None, want_ncc=False,
+                 stream=None):
+        torch = _torch()
+        self.p = p.copy()
+        self.inputs = []
+        self.cps, self.ncc = [], []
+        arr = (Pair * len(pairs))()
+        for k, q in enumerate(pairs):
+            ref, sen, ips = q["ref"], q["sen"], q["ips"]
+            prior = q.get("prior")
+            for t in (ref, sen):
+                assert t.is_cuda and t.dtype == torch.float32 and t.dim() == 2 and t.stride(1) == 1
+            assert ips.dtype == torch.int32 and ips.is_contiguous()
+            n, m, r = ips.shape[0], int(q["m"]), int(q["r"])
+            cps = torch.empty((n, 8), dtype=torch.int32, device=ref.device)
+            V = 2 * r + 1
+            ncc = torch.empty((n, V, V), dtype=torch.float32, device=ref.device) if want_ncc else None
+            self.inputs.append((ref, sen, ips, prior))
+            self.cps.append(cps)
+            self.ncc.append(ncc)
+            a = arr[k]
+            a.ref, a.Hr, a.Wr, a.ldr = ref.data_ptr(), ref.shape[0], ref.shape[1], ref.stride(0)
+            a.sen, a.Hs, a.Ws, a.lds = sen.data_ptr(), sen.shape[0], sen.shape[1], sen.stride(0)
+            a.ips = ips.data_ptr()
+            a.prior = prior.data_ptr() if prior is not None else None
+            a.n, a.m, a.r, a.fft_side = n, m, r, int(q.get("fft_side", 0))
+            a.ncc = ncc.data_ptr() if ncc is not None else None
+            a.cps = cps.data_ptr()
+        self._pairs = arr
+        h = ctypes.c_void_p(0)
+        tc = tune_cache.encode() if tune_cache else None
+        _check(lib().sfoc_plan_create(arr, len(pairs), ctypes.byref(self.p), flags, tc, _stream(stream),
+                                      ctypes.byref(h)), "sfoc_plan_create")
+        self.handle = h
+
+    def __call__(self, stream=None):
+        _check(lib().sfoc_register_cps_batched(self.handle, _stream(stream)), "sfoc_register_cps_batched")
+        return self.cps
+
+    def info(self) -> dict:
+        n = len(self.cps)
+        inf = PlanInfo()
+        L = (ctypes.c_int32 * n)()
+        nb = (ctypes.c_int32 * n)()
+        _check(lib().sfoc_plan_get_info(self.handle, ctypes.byref(inf), L, nb, n), "sfoc_plan_get_info")
+        return {"n_pairs": inf.n_pairs, "describe_tiles": inf.describe_tiles,
+                "match_items": (inf.match_items[0], inf.match_items[1]), "peak_items": inf.peak_items,
+                "tuned_classes": inf.tuned_classes, "cached_classes": inf.cached_classes, "graph": inf.graph,
+                "device_bytes": inf.device_bytes, "fft_side": list(L), "blocks": list(nb)}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _check(lib().sfoc_plan_destroy(self.handle), "sfoc_plan_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def match_candidates(m: int, r: int) -> list[tuple[int, int]]:
+    """[(transform side, offset blocks per axis)] an autotuner may time."""
+    L = (ctypes.c_int32 * 2)()
+    nb = (ctypes.c_int32 * 2)()
+    k = lib().sfoc_match_candidates(m, r, L, nb, 2)
+    if k < 0:
+        raise SfocError(k, "sfoc_match_candidates")
+    return [(L[i], nb[i]) for i in range(k)]
+
+
+def sensed_tiles(ips: np.ndarray, m: int, r: int, Hs: int, Ws: int, Hr: int, Wr: int, prior=None) -> np.ndarray:
+    """(ceil(Hs/32), ceil(Ws/32)) uint8 mask of the describe tiles that
+    in-bounds templates read (host arrays, no device work)."""
+    ips = np.ascontiguousarray(ips, dtype=np.int32)
+    pr = None if prior is None else np.ascontiguousarray(prior, dtype=np.int32)
+    mask = np.zeros(((Hs + 31) // 32, (Ws + 31) // 32), dtype=np.uint8)
+    c = lib().sfoc_sensed_tiles(ips.ctypes.data, None if pr is None else pr.ctypes.data, len(ips), m, r, Hs, Ws,
+                                Hr, Wr, mask.ctypes.data)
+    if c < 0:
+        raise SfocError(int(c), "sfoc_sensed_tiles")
+    return mask
 
 
 KERNEL_NAMES = ("describe", "integral", "match", "consistency", "peak")

@@ -1,0 +1,154 @@
+"""Host-side logic of batched plans (no GPU): struct layouts, transform-side
+candidates, the sensed-tile cover and argument rejection in
+sfoc_plan_create."""
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2202_13347_amd import sfoc as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = 0x1000   # never dereferenced: every call below fails validation first
+
+
+def test_pair_and_info_layout_match_header(tmp_path):
+    src = tmp_path / "lay.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "sfoc.h"
+#define P(f) printf("pair.%s %zu\n", #f, offsetof(sfoc_pair, f));
+#define I(f) printf("info.%s %zu\n", #f, offsetof(sfoc_plan_info, f));
+int main(void) {
+  P(ref) P(Hr) P(Wr) P(ldr) P(sen) P(Hs) P(Ws) P(lds) P(ips) P(prior) P(n) P(m) P(r) P(fft_side) P(ncc) P(cps)
+  I(n_pairs) I(describe_tiles) I(match_items) I(peak_items) I(tuned_classes) I(cached_classes) I(graph)
+  I(device_bytes)
+  printf("pair.size %zu\ninfo.size %zu\n", sizeof(sfoc_pair), sizeof(sfoc_plan_info));
+  return 0;
+}''')
+    exe = tmp_path / "lay"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True).stdout.splitlines())
+    for name, _ in S.Pair._fields_:
+        assert int(got["pair." + name]) == getattr(S.Pair, name).offset, name
+    for name, _ in S.PlanInfo._fields_:
+        assert int(got["info." + name]) == getattr(S.PlanInfo, name).offset, name
+    assert int(got["pair.size"]) == ctypes.sizeof(S.Pair)
+    assert int(got["info.size"]) == ctypes.sizeof(S.PlanInfo)
+
+
+def _split(m, r, L):
+    """Offset blocks per axis for transform side L, written from the
+    condition that a block of Vb offsets needs a search window of
+    m + Vb - 1 <= L rows (None if no block of >= 2 offsets fits)."""
+    V = 2 * r + 1
+    best = None
+    for Vb in range(V, 1, -1):
+        if m + Vb - 1 <= L:
+            best = Vb
+            break
+    if best is None:
+        return None
+    return math.ceil(V / best)
+
+
+@pytest.mark.parametrize("m,r", [(32, 10), (48, 16), (64, 32), (96, 64), (48, 64), (30, 100), (64, 16),
+                                 (96, 16), (3, 1), (126, 200), (60, 2), (62, 40)])
+def test_match_candidates(m, r):
+    got = S.match_candidates(m, r)
+    M = m + 2 * r
+    default = 64 if M <= 64 else 128
+    assert got[0][0] == default
+    assert got[0][1] == _split(m, r, default)
+    other = 128 if default == 64 else 64
+    nb = _split(m, r, other)
+    want_other = nb is not None and nb <= 8
+    assert (len(got) == 2) == want_other, got
+    if want_other:
+        assert got[1] == (other, nb)
+
+
+def test_match_candidates_unsupported():
+    assert S.match_candidates(2, 4) == []      # m < 3
+    assert S.match_candidates(127, 10) == []   # m > 126 with M > 128
+
+
+def _brute_tiles(ips, prior, m, r, Hs, Ws, Hr, Wr):
+    mask = np.zeros(((Hs + 31) // 32, (Ws + 31) // 32), dtype=np.uint8)
+    M = m + 2 * r
+    for i, (y, x) in enumerate(ips):
+        ty, tx = y - m // 2, x - m // 2
+        py, px = (prior[i] if prior is not None else (0, 0))
+        sy, sx = ty - r + py, tx - r + px
+        if ty < 0 or tx < 0 or ty + m > Hs or tx + m > Ws:
+            continue
+        if sy < 0 or sx < 0 or sy + M > Hr or sx + M > Wr:
+            continue
+        for yy in range(ty, ty + m):
+            for xx in range(tx, tx + m):
+                mask[yy // 32, xx // 32] = 1
+    return mask
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_sensed_tiles_match_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    Hs, Ws = int(rng.integers(100, 300)), int(rng.integers(100, 300))
+    Hr, Wr = int(rng.integers(100, 300)), int(rng.integers(100, 300))
+    m, r = int(rng.integers(3, 40)), int(rng.integers(1, 20))
+    n = 40
+    ips = np.stack([rng.integers(-10, Hs + 10, n), rng.integers(-10, Ws + 10, n)], 1).astype(np.int32)
+    prior = rng.integers(-15, 16, (n, 2)).astype(np.int32) if seed else None
+    got = S.sensed_tiles(ips, m, r, Hs, Ws, Hr, Wr, prior)
+    want = _brute_tiles(ips, prior, m, r, Hs, Ws, Hr, Wr)
+    np.testing.assert_array_equal(got, want)
+
+
+def _pair(**kw):
+    q = S.Pair()
+    q.ref, q.Hr, q.Wr, q.ldr = FAKE, 64, 64, 64
+    q.sen, q.Hs, q.Ws, q.lds = FAKE, 64, 64, 64
+    q.ips, q.prior, q.n, q.m, q.r, q.fft_side = FAKE, None, 4, 16, 4, 0
+    q.ncc, q.cps = None, FAKE
+    for k, v in kw.items():
+        setattr(q, k, v)
+    return q
+
+
+@pytest.mark.parametrize("kw,flags,code", [
+    ({}, 8, S.SFOC_E_INVALID_ARG),                                 # unknown flag
+    ({"ref": None}, 0, S.SFOC_E_INVALID_ARG),
+    ({"ldr": 10}, 0, S.SFOC_E_INVALID_ARG),
+    ({"m": 2}, 0, S.SFOC_E_INVALID_ARG),
+    ({"fft_side": 96}, 0, S.SFOC_E_INVALID_ARG),
+    ({"m": 70, "r": 4, "fft_side": 64}, 0, S.SFOC_E_UNSUPPORTED),   # template wider than the transform
+    ({"m": 127, "r": 10}, 0, S.SFOC_E_UNSUPPORTED),
+    ({"cps": None}, 0, S.SFOC_E_INVALID_ARG),
+    ({"Hs": 1 << 17}, 0, S.SFOC_E_UNSUPPORTED),
+])
+def test_plan_create_rejects_bad_pairs(kw, flags, code):
+    arr = (S.Pair * 2)(_pair(), _pair(**kw))
+    p = S.preset("baseline")
+    h = ctypes.c_void_p(0)
+    rc = S.lib().sfoc_plan_create(arr, 2, ctypes.byref(p), flags, None, None, ctypes.byref(h))
+    assert rc == code
+    assert not h.value
+
+
+def test_plan_create_rejects_empty_and_null():
+    p = S.preset("baseline")
+    h = ctypes.c_void_p(0)
+    arr = (S.Pair * 1)(_pair())
+    assert S.lib().sfoc_plan_create(arr, 0, ctypes.byref(p), 0, None, None, ctypes.byref(h)) == S.SFOC_E_INVALID_ARG
+    assert S.lib().sfoc_plan_create(None, 1, ctypes.byref(p), 0, None, None, ctypes.byref(h)) == S.SFOC_E_INVALID_ARG
+    assert S.lib().sfoc_plan_create(arr, 1, ctypes.byref(p), 0, None, None, None) == S.SFOC_E_INVALID_ARG
+    bad = S.preset("baseline")
+    bad.n_orient = 0
+    assert S.lib().sfoc_plan_create(arr, 1, ctypes.byref(bad), 0, None, None, ctypes.byref(h)) == \
+        S.SFOC_E_INVALID_ARG
+    assert S.lib().sfoc_register_cps_batched(None, None) == S.SFOC_E_INVALID_ARG
+    assert S.lib().sfoc_plan_destroy(None) == S.SFOC_E_INVALID_ARG

@@ -1,0 +1,211 @@
+"""Batched plans on the GPU (through the C ABI): many uneven pairs in one
+plan give the per-pair results bit for bit with the default transform
+sides, graph replays read fresh image contents, forced and autotuned sides
+stay within the oracle tolerances."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import sfoc_oracle as O
+from paper_2202_13347_amd import sfoc as S
+from paper_2202_13347_amd import synth
+from tests.gpu_util import compare_cps, consistency_flip_allowed
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    S.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+# seed, (H, W) of the pair, sensed crop (H, W) or None, m, r, n IPs, prior, pitched ref
+SPECS = [
+    (0, (200, 240), (180, 240), 24, 6, 9, False, False),
+    (1, (256, 256), None, 32, 10, 16, True, True),
+    (2, (300, 220), (300, 200), 48, 48, 6, False, False),   # 144-px window: offsets split (L = 128)
+    (3, (160, 160), None, 16, 4, 0, False, False),          # no IPs
+    (4, (240, 260), None, 32, 20, 12, False, False),
+    (5, (220, 220), None, 20, 60, 5, False, True),          # 140-px window, split
+]
+
+
+def build_pairs(specs, seed_shift=0):
+    out = []
+    for seed, hw, crop, m, r, n, use_prior, pitched in specs:
+        pr = synth.make_pair(seed + 100 + seed_shift, hw, max_shift=min(8.0, r - 2.0))
+        sen = pr.sen if crop is None else np.ascontiguousarray(pr.sen[:crop[0], :crop[1]])
+        Hs, Ws = sen.shape
+        b = (m + 1) // 2 + r
+        rng = np.random.default_rng(seed)
+        if n:
+            ips = synth.random_ips(seed, Hs, Ws, n, b) if min(Hs, Ws) > 2 * b + 1 else np.zeros((0, 2), np.int32)
+            ips = np.concatenate([ips, np.array([[2, 3], [Hs - 3, Ws // 2]], np.int32)])   # two out of bounds
+        else:
+            ips = np.zeros((0, 2), np.int32)
+        prior = rng.integers(-3, 4, (len(ips), 2)).astype(np.int32) if use_prior else None
+        out.append(dict(ref=pr.ref, sen=sen, ips=ips, prior=prior, m=m, r=r, pitched=pitched, shift=pr.shift))
+    return out
+
+
+def to_device(pairs):
+    dp = []
+    for q in pairs:
+        ref = torch.from_numpy(q["ref"]).cuda()
+        if q["pitched"]:
+            H, W = ref.shape
+            big = torch.full((H, W + 13), float("nan"), device="cuda")
+            big[:, :W] = ref
+            ref = big[:, :W]
+        dp.append(dict(ref=ref, sen=torch.from_numpy(q["sen"]).cuda(), ips=torch.from_numpy(q["ips"]).cuda(),
+                       prior=None if q["prior"] is None else torch.from_numpy(q["prior"]).cuda(),
+                       m=q["m"], r=q["r"]))
+    return dp
+
+
+def per_pair(dp, p):
+    res = []
+    for q in dp:
+        cps, ncc = S.register_cps(q["ref"], q["sen"], q["ips"], q["m"], q["r"], p, prior=q["prior"],
+                                  want_ncc=True)
+        res.append((cps.cpu().numpy(), ncc.cpu().numpy()))
+    return res
+
+
+def assert_same(plan, ref_res):
+    for k, (c, n) in enumerate(ref_res):
+        np.testing.assert_array_equal(plan.cps[k].cpu().numpy(), c, err_msg=f"pair {k}")
+        np.testing.assert_array_equal(plan.ncc[k].cpu().numpy(), n, err_msg=f"pair {k}")
+
+
+@pytest.mark.parametrize("flags", [0, S.PLAN_GRAPH, S.PLAN_DENSE_SEN])
+def test_batched_equals_per_pair(flags):
+    say(f"batched vs per-pair, flags {flags}")
+    p = S.preset("baseline")
+    dp = to_device(build_pairs(SPECS))
+    want = per_pair(dp, p)
+    plan = S.Plan(dp, p, flags=flags, want_ncc=True)
+    info = plan.info()
+    assert info["fft_side"] == [64 if q["m"] + 2 * q["r"] <= 64 else 128 for q in dp]
+    assert info["blocks"][2] == 2 and info["blocks"][5] == 2
+    for rep in range(2):
+        plan()
+        torch.cuda.synchronize()
+        assert_same(plan, want)
+    if flags & S.PLAN_GRAPH:
+        assert plan.info()["graph"] == 1
+    plan.close()
+
+
+def test_sparse_tiles_count():
+    p = S.preset("baseline")
+    pairs = build_pairs(SPECS)
+    dp = to_device(pairs)
+    plan = S.Plan(dp, p)
+    want = 0
+    for q in pairs:
+        Hr, Wr = q["ref"].shape
+        Hs, Ws = q["sen"].shape
+        want += ((Hr + 31) // 32) * ((Wr + 31) // 32)
+        want += int(S.sensed_tiles(q["ips"], q["m"], q["r"], Hs, Ws, Hr, Wr, q["prior"]).sum())
+    assert plan.info()["describe_tiles"] == want
+    plan.close()
+
+
+def test_graph_replay_reads_new_images():
+    say("graph replay with new image contents")
+    p = S.preset("baseline")
+    dp = to_device(build_pairs(SPECS))
+    plan = S.Plan(dp, p, flags=S.PLAN_GRAPH | S.PLAN_DENSE_SEN, want_ncc=True)
+    plan()
+    torch.cuda.synchronize()
+    assert_same(plan, per_pair(dp, p))
+    # new contents in the same buffers (and new IP values: dense sensed images)
+    new = build_pairs(SPECS, seed_shift=17)
+    for q, d in zip(new, dp):
+        d["ref"].copy_(torch.from_numpy(q["ref"]))
+        d["sen"].copy_(torch.from_numpy(q["sen"]))
+        if len(q["ips"]):
+            d["ips"].copy_(torch.flip(d["ips"], [0]))
+    torch.cuda.synchronize()
+    want = per_pair(dp, p)
+    for rep in range(3):
+        plan()
+        torch.cuda.synchronize()
+        assert_same(plan, want)
+    plan.close()
+
+
+def oracle_check(q, cps, ncc, p):
+    op = O.Params(n_orient=p.n_orient, s1=tuple(p.s1[:p.n_s1]), s2=tuple(p.s2[:p.n_s2]), trunc=p.trunc,
+                  sd1=p.sd1, sd2=p.sd2, K=p.K, dil=tuple(p.dil[:p.n_dil]), eps=p.eps)
+    o, so = O.register_cps(q["ref"], q["sen"], q["ips"], q["m"], q["r"], op, prior=q["prior"],
+                           want_surfaces=True)
+    g = S.cps_to_numpy(cps)
+    st = compare_cps(g, o, so, q["r"], surf_g=ncc.cpu().numpy(), check_consistency=False)
+    allowed = consistency_flip_allowed(o, q["prior"])
+    for i in range(len(o)):
+        if int(o["flags"][i]) != int(g["flags"][i]):
+            assert allowed[i], (i, o[i], g[i])
+    return st
+
+
+@pytest.mark.parametrize("sides", [(64, 128), (128, 64)])
+def test_forced_sides_match_oracle(sides):
+    # pair 0: 36-px window (default 64); pair 4: 72-px window (default 128, or 64 in two blocks per axis)
+    say(f"forced transform sides {sides}")
+    specs = [SPECS[0], SPECS[4]]
+    pairs = build_pairs(specs)
+    dp = to_device(pairs)
+    for d, L in zip(dp, sides):
+        d["fft_side"] = L
+    p = S.preset("baseline")
+    plan = S.Plan(dp, p, want_ncc=True)
+    info = plan.info()
+    assert info["fft_side"] == list(sides)
+    plan()
+    torch.cuda.synchronize()
+    for k, q in enumerate(pairs):
+        st = oracle_check(q, plan.cps[k], plan.ncc[k], p)
+        say(k, sides[k], st)
+    plan.close()
+
+
+def test_autotune_and_cache(tmp_path):
+    say("autotune")
+    cache = str(tmp_path / "tune.txt")
+    p = S.preset("baseline")
+    pairs = build_pairs(SPECS)
+    dp = to_device(pairs)
+    want = per_pair(dp, p)
+    plan = S.Plan(dp, p, flags=S.PLAN_AUTOTUNE | S.PLAN_GRAPH, tune_cache=cache, want_ncc=True)
+    info = plan.info()
+    # every class with IPs and two candidate sides is timed once
+    timed = sum(len(S.match_candidates(q["m"], q["r"])) > 1 and len(q["ips"]) > 0 for q in pairs)
+    assert timed == 5
+    assert info["tuned_classes"] == timed
+    for q, L in zip(pairs, info["fft_side"]):
+        assert L in [c[0] for c in S.match_candidates(q["m"], q["r"])]
+    plan()
+    torch.cuda.synchronize()
+    for k, q in enumerate(pairs):
+        g = plan.cps[k].cpu().numpy()
+        if info["fft_side"][k] == (64 if q["m"] + 2 * q["r"] <= 64 else 128):
+            np.testing.assert_array_equal(g, want[k][0])
+        elif len(q["ips"]):
+            oracle_check(q, plan.cps[k], plan.ncc[k], p)
+    plan.close()
+    plan2 = S.Plan(dp, p, flags=S.PLAN_AUTOTUNE, tune_cache=cache)
+    i2 = plan2.info()
+    assert i2["tuned_classes"] == 0 and i2["cached_classes"] == timed
+    assert i2["fft_side"] == info["fft_side"]
+    plan2.close()
