@@ -181,6 +181,46 @@ SCENE = dict(size=2048, n_side=20, m=64, r=32, max_shift=30.0, speckle=4)
 LARGE = dict(size=10000, n_side=71, m=64, r=48, max_shift=44.0, speckle=4, n_ips=5000)
 
 
+# Batching workload: 64 pairs of uneven square sides U{512..4096}, 50..500
+# seeded uniform IPs each, template sides from {48, 64, 96} and radii from
+# {16, 32, 64} per pair, shift bound r - 2, every second pair speckled.
+BATCH = dict(n_pairs=64, side=(512, 4096), n_ips=(50, 500), m=(48, 64, 96), r=(16, 32, 64), speckle=4)
+
+
+def batch_specs(seed: int, recipe: dict = BATCH) -> list[dict]:
+    """Per-pair draws of the batching workload (no images): seed, side, m,
+    r, shift bound, speckle looks and IP count."""
+    rng = np.random.default_rng(np.random.PCG64(seed + 424242))
+    out = []
+    for k in range(recipe["n_pairs"]):
+        side = int(rng.integers(recipe["side"][0], recipe["side"][1] + 1))
+        m = int(rng.choice(recipe["m"]))
+        r = int(rng.choice(recipe["r"]))
+        n = int(rng.integers(recipe["n_ips"][0], recipe["n_ips"][1] + 1))
+        out.append(dict(seed=seed * 1000 + k, side=side, m=m, r=r, max_shift=float(r - 2),
+                        speckle=recipe["speckle"] if k % 2 else 0, n=n))
+    return out
+
+
+def batch_pair(spec: dict):
+    """(pair, ips) of one batching spec; IPs uniform within the margin."""
+    p = make_pair(spec["seed"], spec["side"], spec["max_shift"], speckle_looks=spec["speckle"])
+    b = (spec["m"] + 1) // 2 + spec["r"]
+    ips = random_ips(spec["seed"], spec["side"], spec["side"], spec["n"], b)
+    return p, ips
+
+
+def batch_workload(seed: int, recipe: dict = BATCH, workers: int = 8):
+    """[(spec, pair, ips)] for the batching workload, generated in a
+    process pool."""
+    from concurrent.futures import ProcessPoolExecutor
+    specs = batch_specs(seed, recipe)
+    order = sorted(range(len(specs)), key=lambda k: -specs[k]["side"])   # big ones first
+    with ProcessPoolExecutor(max_workers=max(1, workers)) as ex:
+        res = dict(zip(order, ex.map(batch_pair, [specs[k] for k in order])))
+    return [(specs[k], res[k][0], res[k][1]) for k in range(len(specs))]
+
+
 def workload(recipe: dict, seed: int):
     """(pair, ips, m, r) for a recipe; IP margin = ceil(m/2) + r."""
     p = make_pair(seed, recipe["size"], recipe["max_shift"], speckle_looks=recipe["speckle"])
