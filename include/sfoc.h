@@ -312,6 +312,75 @@ int64_t sfoc_sensed_tiles(const int32_t* ips, const int32_t* prior, int32_t n, i
                           int64_t Hs, int64_t Ws, int64_t Hr, int64_t Wr, uint8_t* mask);
 
 /*
+ * Learned CP-validity and sub-pixel head (not part of the paper).  It reads
+ * what the paper's matching produces, the NCC surface of Eq. 9 around the
+ * argmax CP (Section 3.2.2), and is trained against the 1.5 px correctness
+ * threshold of Section 4.1; the plain peak fit and consistency check stay the
+ * fallback for every CP it does not take.
+ *
+ * Features (sfoc_head_features), per CP with an interior peak (flags VALID
+ * or INCONSISTENT; every other CP gets zeros):
+ *   crops  n x 33 x 33 float32: the surface around the integer peak
+ *          (u*, v*) = (dy + r, dx + r), crop[a][b] = S[u*-16+a][v*-16+b],
+ *          -1 outside the (2r+1)^2 surface;
+ *   stats  n x 8 float32: peak; the largest value outside the 3 x 3 block
+ *          around the peak (-1 if none); surface mean; surface standard
+ *          deviation; template standard deviation sqrt(max(varT,0)/mnz)
+ *          (Eq. 11-12, mnz = m*m*z); search-window standard deviation at the
+ *          peak from the integral images (Eq. 16); template mean R_T/mnz;
+ *          the mean of the two second differences at the peak.
+ *   Arguments as for sfoc_fastncc_match, plus ncc (n x (2r+1)^2 surfaces it
+ *   wrote) and cps (its records).
+ *
+ * Network (parameters: SFOC_HEAD_PARAMS float32 in this order): conv1 3x3
+ * 1->32 stride 1; conv2..conv4 3x3 32->32 stride 2 (33 -> 33 -> 17 -> 9 ->
+ * 5, zero padding 1, ReLU after each); fc1 (800 channel-major values + the 8
+ * stats) -> 32, ReLU; fc2 32 -> 3 = (validity logit, oy, ox).  Conv
+ * weights are [out][in][3][3] then the bias [out]; fc weights [out][in]
+ * then the bias.  Weights (not biases) enter every product rounded to
+ * bfloat16 (round to nearest even); all sums are float32.
+ *
+ * sfoc_head_forward: out (n x 3) for n samples.
+ * sfoc_head_train_step: one step on a batch of n samples: forward, the
+ *   loss mean_b[ BCE(logit, label) + 4 label (SmoothL1(oy - ty) +
+ *   SmoothL1(ox - tx)) ] with SmoothL1 of width 0.1, its gradient w.r.t. the
+ *   rounded weights applied to the float32 master params (straight
+ *   through), written to grad (SFOC_HEAD_PARAMS floats, may be NULL) and
+ *   loss (one float, may be NULL), then an Adam update (beta1 0.9, beta2
+ *   0.999, eps 1e-8, bias-corrected with step t >= 1, learning rate lr; lr =
+ *   0 leaves params unchanged) of params, adam_m and adam_v in place.
+ *   label: n floats in {0, 1}; target: n x 2 (ty, tx).
+ * sfoc_head_infer: forward, then on every CP with an interior peak:
+ *   sigmoid(logit) >= threshold sets VALID (else INCONSISTENT), LEARNED is
+ *   set, sub_dy / sub_dx become oy / ox clipped to [-1.5, 1.5]; other CPs
+ *   are left as they are.  out (n x 3) may be NULL.
+ * All device pointers; ws of sfoc_head_workspace(n, train) bytes.
+ * Every reduction runs in a fixed order: results are bit-reproducible.
+ * Limits: 1 <= n <= 65536 per call (SFOC_E_UNSUPPORTED beyond).
+ * Errors: SFOC_E_INVALID_ARG (null pointers, n < 0, t < 1), SFOC_E_WORKSPACE,
+ * SFOC_E_HIP.  n == 0 is valid and enqueues nothing.
+ */
+#define SFOC_HEAD_PARAMS  54051
+#define SFOC_HEAD_CROP    33
+#define SFOC_HEAD_NSTAT   8
+int sfoc_head_features(const void* desc_sen, int64_t Hs, int64_t Ws,
+                       const double* integ1, const double* integ2, int64_t Hr, int64_t Wr,
+                       int32_t z, int32_t dtype,
+                       const int32_t* ips, const int32_t* prior, int32_t n, int32_t m, int32_t r,
+                       const float* ncc, const sfoc_cp* cps,
+                       float* crops, float* stats, void* stream);
+int sfoc_head_workspace(int32_t n, int32_t train, size_t* bytes);
+int sfoc_head_forward(const float* params, const float* crops, const float* stats, int32_t n,
+                      float* out, void* ws, size_t ws_bytes, void* stream);
+int sfoc_head_train_step(float* params, float* adam_m, float* adam_v, int32_t t, float lr,
+                         const float* crops, const float* stats, const float* label,
+                         const float* target, int32_t n, float* grad, float* loss,
+                         void* ws, size_t ws_bytes, void* stream);
+int sfoc_head_infer(const float* params, const float* crops, const float* stats, int32_t n,
+                    float threshold, sfoc_cp* cps, float* out, void* ws, size_t ws_bytes,
+                    void* stream);
+
+/*
  * Kernel timing (tracing).  While enabled, the library records a pair of
  * HIP events on the launch stream around every kernel it enqueues.
  * sfoc_trace_collect waits for those events, writes per-kernel totals into
@@ -325,7 +394,11 @@ int64_t sfoc_sensed_tiles(const int32_t* ips, const int32_t* prior, int32_t n, i
 #define SFOC_K_MATCH        2
 #define SFOC_K_CONSISTENCY  3
 #define SFOC_K_PEAK         4
-#define SFOC_K_COUNT        5
+#define SFOC_K_HEAD_FEAT    5
+#define SFOC_K_HEAD_FWD     6
+#define SFOC_K_HEAD_BWD     7
+#define SFOC_K_HEAD_ADAM    8
+#define SFOC_K_COUNT        9
 #define SFOC_TRACE_MAX   4096
 int sfoc_trace_enable(int on);
 int sfoc_trace_collect(double* ms, int64_t* counts, int n);

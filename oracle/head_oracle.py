@@ -100,19 +100,6 @@ def pack(d: dict) -> np.ndarray:
     return np.concatenate([np.asarray(d[name], dtype=np.float64).ravel() for name, _ in layout()])
 
 
-def init_params(seed: int) -> np.ndarray:
-    """He-uniform weights (bound sqrt(6 / fan_in)), zero biases."""
-    rng = np.random.default_rng(np.random.PCG64(seed))
-    d = {}
-    for name, shape in layout():
-        if name.endswith(".b"):
-            d[name] = np.zeros(shape)
-        else:
-            fan_in = int(np.prod(shape[1:]))
-            d[name] = rng.uniform(-1.0, 1.0, shape) * np.sqrt(6.0 / fan_in)
-    return pack(d).astype(np.float32)
-
-
 # ------------------------------------------------------------ features -----
 def crop_and_stats(S: np.ndarray, u: int, v: int, varT: float, varS: float, RT: float, mnz: float):
     """33 x 33 crop and the 8 statistics of one surface (see the module text)."""

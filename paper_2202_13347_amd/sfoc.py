@@ -100,13 +100,22 @@ def lib() -> ctypes.CDLL:
         L.sfoc_match_candidates.argtypes = [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), i32]
         L.sfoc_sensed_tiles.argtypes = [vp, vp, i32, i32, i32, i64, i64, i64, i64, vp]
         L.sfoc_sensed_tiles.restype = i64
+        f32p = ctypes.c_void_p
+        L.sfoc_head_features.argtypes = [vp, i64, i64, vp, vp, i64, i64, i32, i32, vp, vp, i32, i32, i32, vp, vp,
+                                         vp, vp, vp]
+        L.sfoc_head_workspace.argtypes = [i32, i32, ctypes.POINTER(sz)]
+        L.sfoc_head_forward.argtypes = [vp, vp, vp, i32, vp, vp, sz, vp]
+        L.sfoc_head_train_step.argtypes = [vp, vp, vp, i32, ctypes.c_float, vp, vp, vp, vp, i32, vp, vp, vp, sz,
+                                           vp]
+        L.sfoc_head_infer.argtypes = [vp, vp, vp, i32, ctypes.c_float, vp, vp, vp, sz, vp]
         L.sfoc_trace_enable.argtypes = [ctypes.c_int]
         L.sfoc_trace_collect.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.c_int]
         for name in ("sfoc_trace_enable", "sfoc_trace_collect", "sfoc_params_preset", "sfoc_params_check", "sfoc_describe_workspace", "sfoc_describe",
                      "sfoc_match_workspace", "sfoc_fastncc_match", "sfoc_register_workspace",
                      "sfoc_register_cps", "sfoc_plan_create", "sfoc_register_cps_batched", "sfoc_plan_destroy",
-                     "sfoc_plan_get_info", "sfoc_match_candidates"):
+                     "sfoc_plan_get_info", "sfoc_match_candidates", "sfoc_head_features", "sfoc_head_workspace",
+                     "sfoc_head_forward", "sfoc_head_train_step", "sfoc_head_infer"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -367,7 +376,92 @@ def sensed_tiles(ips: np.ndarray, m: int, r: int, Hs: int, Ws: int, Hr: int, Wr:
     return mask
 
 
-KERNEL_NAMES = ("describe", "integral", "match", "consistency", "peak")
+HEAD_PARAMS, HEAD_CROP, HEAD_NSTAT = 54051, 33, 8
+
+
+def head_features(desc_sen, desc_ref, integ1, integ2, ips, m: int, r: int, ncc, cps, prior=None, stream=None):
+    """(crops (n, 33, 33), stats (n, 8)) float32 CUDA tensors for the head."""
+    torch = _torch()
+    z, Hs, Ws = desc_sen.shape
+    _, Hr, Wr = desc_ref.shape
+    dt = {torch.float32: DTYPE_F32, torch.bfloat16: DTYPE_BF16, torch.float16: DTYPE_F16}[desc_sen.dtype]
+    n = ips.shape[0]
+    crops = torch.empty((n, HEAD_CROP, HEAD_CROP), dtype=torch.float32, device=desc_sen.device)
+    stats = torch.empty((n, HEAD_NSTAT), dtype=torch.float32, device=desc_sen.device)
+    rc = lib().sfoc_head_features(_ptr(desc_sen), Hs, Ws, _ptr(integ1), _ptr(integ2), Hr, Wr, z, dt, _ptr(ips),
+                                  _ptr(prior), n, m, r, _ptr(ncc), _ptr(cps), _ptr(crops), _ptr(stats),
+                                  _stream(stream))
+    _check(rc, "sfoc_head_features")
+    return crops, stats
+
+
+def head_workspace(n: int, train: bool) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().sfoc_head_workspace(n, int(train), ctypes.byref(b)), "sfoc_head_workspace")
+    return b.value
+
+
+class Head:
+    """Parameters (float32 master copy), Adam moments and workspaces of the
+    learned head on one device.  Every computation runs in the library."""
+
+    def __init__(self, params, device="cuda"):
+        torch = _torch()
+        p = torch.as_tensor(params, dtype=torch.float32).reshape(-1)
+        assert p.numel() == HEAD_PARAMS
+        self.params = p.to(device).contiguous().clone()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.t = 0
+        self.device = device
+        self._ws = {}
+
+    def _workspace(self, n, train):
+        torch = _torch()
+        key = (n, bool(train))
+        if key not in self._ws:
+            self._ws = {k: w for k, w in self._ws.items() if k[1] != bool(train)}   # one per mode
+            self._ws[key] = torch.empty(max(1, head_workspace(n, train)), dtype=torch.uint8, device=self.device)
+        return self._ws[key]
+
+    def forward(self, crops, stats, stream=None):
+        torch = _torch()
+        n = crops.shape[0]
+        out = torch.empty((n, 3), dtype=torch.float32, device=self.device)
+        if n:
+            ws = self._workspace(n, False)
+            _check(lib().sfoc_head_forward(_ptr(self.params), _ptr(crops), _ptr(stats), n, _ptr(out), _ptr(ws),
+                                           ws.numel(), _stream(stream)), "sfoc_head_forward")
+        return out
+
+    def train_step(self, crops, stats, label, target, lr: float, want_grad=False, stream=None):
+        """One Adam step; returns (loss tensor (1,), gradient or None)."""
+        torch = _torch()
+        n = crops.shape[0]
+        ws = self._workspace(n, True)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        grad = torch.empty(HEAD_PARAMS, dtype=torch.float32, device=self.device) if want_grad else None
+        self.t += 1
+        _check(lib().sfoc_head_train_step(_ptr(self.params), _ptr(self.m), _ptr(self.v), self.t, float(lr),
+                                          _ptr(crops), _ptr(stats), _ptr(label), _ptr(target), n, _ptr(grad),
+                                          _ptr(loss), _ptr(ws), ws.numel(), _stream(stream)),
+               "sfoc_head_train_step")
+        return loss, grad
+
+    def infer(self, crops, stats, cps, threshold: float = 0.5, want_out=False, stream=None):
+        """Applies the head to CP records in place (eligible CPs only)."""
+        torch = _torch()
+        n = crops.shape[0]
+        out = torch.empty((n, 3), dtype=torch.float32, device=self.device) if want_out else None
+        if n:
+            ws = self._workspace(n, False)
+            _check(lib().sfoc_head_infer(_ptr(self.params), _ptr(crops), _ptr(stats), n, float(threshold), _ptr(cps),
+                                         _ptr(out), _ptr(ws), ws.numel(), _stream(stream)), "sfoc_head_infer")
+        return out
+
+
+KERNEL_NAMES = ("describe", "integral", "match", "consistency", "peak", "head_features", "head_forward",
+                "head_backward", "head_adam")
 
 
 def trace_enable(on: bool = True):

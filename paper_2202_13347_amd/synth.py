@@ -6,11 +6,11 @@ the GPU path and the CPU reference can be fed from it.
 
 The paper's own image pairs (optical / infrared / LiDAR / SAR / map, Section
 4.1, Table 1) are not available; these scenes stand in for them.  Each pair
-is a reference image and a "sensed" image that sees the same layout of
-regions through a different, non-monotonic intensity response per region
-(nonlinear radiometric difference), with contrast reversed in half of the
-regions, additive noise, optional multiplicative gamma speckle (a SAR-like
-look count) and a known translation with a sub-pixel fraction.  After a
+is a reference image and a "sensed" image that sees the same scene through
+a different, non-monotonic intensity response per region (nonlinear
+radiometric difference), with contrast reversed in half of the regions,
+additive noise, optional multiplicative gamma speckle (a SAR-like look
+count) and a known translation with a sub-pixel fraction.  After a
 correct match, the sensed point p corresponds to the reference point p + d.
 """
 from __future__ import annotations
@@ -105,10 +105,35 @@ def _cubic_maps(rng, n):
     return out
 
 
+def _apply_maps(scene, lab, maps, flip, rows=512):
+    """Per-region response: the region's cubic applied to the reference
+    intensity, normalised by its range on [0, 1], reversed where flipped.
+    Evaluated in row bands to bound memory."""
+    coef = np.array([c for c, _, _ in maps])                      # (k, 4)
+    lo = np.array([l for _, l, _ in maps])
+    span = np.array([h - l for _, l, h in maps])
+    out = np.empty_like(scene)
+    for y0 in range(0, scene.shape[0], rows):
+        v = scene[y0:y0 + rows]
+        k = lab[y0:y0 + rows]
+        c = coef[k]
+        y = (c[..., 0] + v * (c[..., 1] + v * (c[..., 2] + v * c[..., 3])) - lo[k]) / span[k]
+        out[y0:y0 + rows] = np.where(flip[k], 1.0 - y, y)
+    return out
+
+
 def make_pair(seed: int, size: int | tuple[int, int], max_shift: float,
               speckle_looks: int = 0, n_shapes: int | None = None,
               noise_std: float = 0.05, integer_shift: bool = False) -> Pair:
     """One seeded multimodal pair.
+
+    The reference is a painter's-algorithm layout of rectangles and convex
+    polygons with U[0, 1] intensities plus smooth value noise (standard
+    deviation 0.1), blurred with a Gaussian of standard deviation 1.  The
+    sensed image applies to the same (unblurred) reference intensities a
+    per-region random non-monotonic cubic response, reversed in half of the
+    regions, is blurred the same way and translated, then gets additive
+    N(0, noise_std^2) noise and optional Gamma(L, 1/L) speckle.
 
     size          : side (or (H, W)) of both images.
     max_shift     : the true shift is drawn from U[-max_shift, max_shift]^2.
@@ -129,15 +154,8 @@ def make_pair(seed: int, size: int | tuple[int, int], max_shift: float,
     vals = rng.uniform(0, 1, n_shapes + 1)
     maps = _cubic_maps(rng, n_shapes + 1)
     flip = rng.random(n_shapes + 1) < 0.5
-    scene_r = vals[lab]
-    resp = np.empty(n_shapes + 1)
-    for k, ((c, lo, hi), f) in enumerate(zip(maps, flip)):
-        v = vals[k]
-        y = (c[0] + c[1] * v + c[2] * v * v + c[3] * v ** 3 - lo) / (hi - lo)
-        resp[k] = 1.0 - y if f else y
-    scene_s = resp[lab]
-    scene_r = scene_r + _value_noise(rng, ch, cw, 16, 0.1)
-    scene_s = scene_s + _value_noise(rng, ch, cw, 24, 0.05)
+    scene_r = vals[lab] + _value_noise(rng, ch, cw, 16, 0.1)
+    scene_s = _apply_maps(scene_r, lab, maps, flip)
     # sen(y, x) = blurred scene_s(y + dy, x + dx): translate by -d.  The
     # canvas margin exceeds the shift, so the periodic wrap stays outside.
     scene_r = _blur_shift(scene_r, 1.0, (0.0, 0.0))
@@ -187,6 +205,14 @@ LARGE = dict(size=10000, n_side=71, m=64, r=48, max_shift=44.0, speckle=4, n_ips
 BATCH = dict(n_pairs=64, side=(512, 4096), n_ips=(50, 500), m=(48, 64, 96), r=(16, 32, 64), speckle=4)
 
 
+def _pool(workers: int):
+    """Process pool of forked workers (NumPy only; they never exec, so a
+    parent that already uses the GPU can fan out input generation)."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+    return ProcessPoolExecutor(max_workers=max(1, workers), mp_context=multiprocessing.get_context("fork"))
+
+
 def batch_specs(seed: int, recipe: dict = BATCH) -> list[dict]:
     """Per-pair draws of the batching workload (no images): seed, side, m,
     r, shift bound, speckle looks and IP count."""
@@ -213,12 +239,74 @@ def batch_pair(spec: dict):
 def batch_workload(seed: int, recipe: dict = BATCH, workers: int = 8):
     """[(spec, pair, ips)] for the batching workload, generated in a
     process pool."""
-    from concurrent.futures import ProcessPoolExecutor
     specs = batch_specs(seed, recipe)
     order = sorted(range(len(specs)), key=lambda k: -specs[k]["side"])   # big ones first
-    with ProcessPoolExecutor(max_workers=max(1, workers)) as ex:
+    with _pool(workers) as ex:
         res = dict(zip(order, ex.map(batch_pair, [specs[k] for k in order])))
     return [(specs[k], res[k][0], res[k][1]) for k in range(len(specs))]
+
+
+# Learned-head training pairs: 512 x 512, ~100 uniform IPs, m 64, r 32,
+# 30% of the pairs with occlusion patches pasted on the sensed image.
+HEAD = dict(size=512, n_ips=100, m=64, r=32, occluded=0.3, speckle=4)
+
+
+def occlude(sen: np.ndarray, seed: int, n_patches=(2, 5), side=(48, 128)):
+    """Paste 2..4 rectangles of unrelated texture (smooth noise at a random
+    level) onto a copy of the sensed image.  Returns (image, mask of the
+    pasted pixels)."""
+    rng = np.random.default_rng(np.random.PCG64(seed + 99991))
+    H, W = sen.shape
+    out = sen.copy()
+    mask = np.zeros((H, W), dtype=bool)
+    for _ in range(int(rng.integers(*n_patches))):
+        h = int(rng.integers(side[0], side[1] + 1))
+        w = int(rng.integers(side[0], side[1] + 1))
+        y0 = int(rng.integers(0, max(1, H - h)))
+        x0 = int(rng.integers(0, max(1, W - w)))
+        tex = _value_noise(rng, h, w, 8, 0.3) + rng.uniform(0.0, 1.0)
+        out[y0:y0 + h, x0:x0 + w] = tex
+        mask[y0:y0 + h, x0:x0 + w] = True
+    return out.astype(np.float32), mask
+
+
+def head_pair(seed: int, recipe: dict = HEAD):
+    """(pair, ips, occlusion mask or None) of one head-training seed."""
+    rng = np.random.default_rng(np.random.PCG64(seed + 31337))
+    occluded = rng.random() < recipe["occluded"]
+    p = make_pair(seed, recipe["size"], float(recipe["r"] - 2),
+                  speckle_looks=recipe["speckle"] if rng.random() < 0.5 else 0)
+    b = (recipe["m"] + 1) // 2 + recipe["r"]
+    ips = random_ips(seed, recipe["size"], recipe["size"], recipe["n_ips"], b)
+    mask = None
+    if occluded:
+        sen, mask = occlude(p.sen, seed)
+        p = Pair(ref=p.ref, sen=sen, shift=p.shift, seed=p.seed)
+    return p, ips, mask
+
+
+def head_pairs(seeds, recipe: dict = HEAD, workers: int = 8):
+    seeds = list(seeds)
+    if workers <= 1 or len(seeds) < 4:
+        return [head_pair(s, recipe) for s in seeds]
+    with _pool(workers) as ex:
+        return list(ex.map(head_pair, seeds, [recipe] * len(seeds), chunksize=8))
+
+
+def head_init_params(seed: int) -> np.ndarray:
+    """Seeded initial parameters of the learned head (float32, the order of
+    the header): He-uniform weights with bound sqrt(6 / fan_in), zero
+    biases."""
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    parts = []
+    for shape in [(32, 1, 3, 3), (32,), (32, 32, 3, 3), (32,), (32, 32, 3, 3), (32,), (32, 32, 3, 3), (32,),
+                  (32, 808), (32,), (3, 32), (3,)]:
+        if len(shape) == 1:
+            parts.append(np.zeros(shape))
+        else:
+            fan_in = int(np.prod(shape[1:]))
+            parts.append(rng.uniform(-1.0, 1.0, shape) * np.sqrt(6.0 / fan_in))
+    return np.concatenate([q.ravel() for q in parts]).astype(np.float32)
 
 
 def workload(recipe: dict, seed: int):

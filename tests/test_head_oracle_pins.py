@@ -6,15 +6,17 @@ from scipy.signal import correlate2d
 
 from oracle import head_oracle as H
 from oracle import sfoc_oracle as O
+from paper_2202_13347_amd import synth
 
 
 def test_parameter_count():
     # conv1 32*9 + 32; conv2..4 3 * (32*32*9 + 32); fc1 32*(800 + 8) + 32; fc2 3*32 + 3
     assert H.N_PARAMS == 288 + 32 + 3 * (9216 + 32) + 32 * 808 + 32 + 96 + 3 == 54051
-    th = H.init_params(0)
+    th = synth.head_init_params(0)
     assert th.shape == (H.N_PARAMS,) and th.dtype == np.float32
     P = H.unpack(th)
     assert np.all(P["conv1.b"] == 0) and np.abs(P["conv2.w"]).max() <= np.sqrt(6 / 288)
+    assert np.abs(P["fc1.w"]).max() <= np.sqrt(6 / 808) and np.abs(P["fc1.w"]).max() > 0.9 * np.sqrt(6 / 808)
 
 
 @pytest.mark.parametrize("stride", [1, 2])
@@ -66,7 +68,7 @@ def _batch(seed, B=3):
 
 
 def test_network_gradient_finite_differences():
-    th = H.init_params(3).astype(np.float64)
+    th = synth.head_init_params(3).astype(np.float64)
     th += np.random.default_rng(4).normal(0, 0.01, th.shape)   # non-zero biases
     crops, stats, y, ty, tx = _batch(5)
     L, g = H.backward(th, crops, stats, y, ty, tx, quantise=False)
@@ -93,7 +95,7 @@ def test_network_gradient_finite_differences():
 
 
 def test_quantised_gradient_is_straight_through():
-    th = H.init_params(7).astype(np.float64)
+    th = synth.head_init_params(7).astype(np.float64)
     crops, stats, y, ty, tx = _batch(8)
     L1, g1 = H.backward(th, crops, stats, y, ty, tx, quantise=True)
     P = H.unpack(th.copy())
