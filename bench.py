@@ -144,6 +144,46 @@ def run_batched(args, S, synth, torch, p, dev):
             "device_gb": info["device_bytes"] / 2 ** 30}
 
 
+def run_learned(args, S, synth, torch, p, dev, ref, sen, dips, m, r):
+    """The learned head on the scene workload: describe + match (with NCC
+    surfaces) + head features + head inference per step, against the plain
+    step; and its accuracy against the plain peak fit and consistency check
+    on held-out seeded pairs."""
+    from paper_2202_13347_amd import head as HD
+    head = S.Head(HD.load_params(), device=dev)
+    H, W = ref.shape
+    n = dips.shape[0]
+
+    def step():
+        d_ref, i1, i2 = S.describe(ref, p)
+        d_sen, _, _ = S.describe(sen, p, integrals=False)
+        cps, ncc = S.fastncc_match(d_sen, d_ref, i1, i2, dips, m, r, want_ncc=True)
+        crops, stats = S.head_features(d_sen, d_ref, i1, i2, dips, m, r, ncc, cps)
+        head.infer(crops, stats, cps)
+        return cps
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    S.trace_enable(True)
+    S.trace_collect()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    kt = S.trace_collect()
+    S.trace_enable(False)
+    res = HD.evaluate(head, range(HD.TEST_SEED0, HD.TEST_SEED0 + args.learned_pairs),
+                      workers=min(16, os.cpu_count() or 1))
+    return {"workload": f"the scene step with NCC surfaces kept, then head features and inference for its {n} "
+                        f"CPs; accuracy on {args.learned_pairs} held-out 512x512 pairs (m 64, r 32, 30% with "
+                        f"occlusion patches)",
+            "value": n / dt, "unit": "CPs/s", "ms_per_step": 1e3 * dt,
+            "head_ms_per_step": (kt["head_features"][0] + kt["head_forward"][0]) / args.steps,
+            "accuracy": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +193,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--batched-steps", type=int, default=5, help="timed steps of the batching workload (0: skip)")
     ap.add_argument("--batched-warmup", type=int, default=2)
+    ap.add_argument("--learned-pairs", type=int, default=100, help="held-out pairs for the head (0: skip)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -247,6 +288,8 @@ def main():
         "accuracy": {"valid": int(valid.sum()), "correct_1p5px": int((err[valid] <= 1.5).sum()),
                      "rmse_valid_px": float(np.sqrt(np.mean(err[valid] ** 2))) if valid.any() else None},
     }
+    if args.learned_pairs > 0:
+        out["learned"] = run_learned(args, S, synth, torch, p, dev, ref, sen, dips, m, r)
     if args.batched_steps > 0:
         del R
         torch.cuda.empty_cache()

@@ -39,7 +39,7 @@ struct DescribeGeom {
     size_t bytes;
 };
 
-static DescribeGeom describe_geom(const DescribeConsts& c) {
+static DescribeGeom describe_geom(const DescribeConsts& c, int CG) {
     DescribeGeom g;
     g.BSP = (kTS + 2 * c.Q + kRun - 1) / kRun * kRun;
     g.ISX = g.BSP + 2 * c.R;
@@ -47,10 +47,13 @@ static DescribeGeom describe_geom(const DescribeConsts& c) {
     // Odd pitches spread the rows of a wave's accesses over all LDS banks.
     g.BPP = g.BSP | 1;
     g.IPP = g.ISX | 1;
+    // Phase 2 holds the image region and the row-pass maps; phase 3 the five
+    // basis maps (over the same memory) and CG steered channels.
     const size_t img = (size_t)g.ISX * g.IPP;
     const size_t row = 3 * (size_t)g.ISX * g.BPP;
-    const size_t bas = 5 * (size_t)g.BSP * g.BPP;
-    g.bytes = (img + row + bas) * sizeof(float);
+    const size_t bb = (size_t)g.BSP * g.BPP;
+    const size_t p2 = img + row, p3 = (5 + (size_t)CG) * bb;
+    g.bytes = (p2 > p3 ? p2 : p3) * sizeof(float);
     return g;
 }
 
@@ -193,7 +196,7 @@ SFOC_DEV void col_run_any(const float* p, int P, int rho, const float* te, const
     }
 
 template <int Z, int CG, bool FAST>
-__global__ __launch_bounds__(kNT, 2) void describe_kernel(const DescribeJob single,
+__global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const DescribeJob single,
                                                           const DescribeJob* __restrict__ jobs,
                                                           const int4* __restrict__ tiles, const DescribeConsts C,
                                                           int BSP_, int ISX, int BPP_, int IPP) {
@@ -227,7 +230,7 @@ __global__ __launch_bounds__(kNT, 2) void describe_kernel(const DescribeJob sing
     const int nrun = BSP / kRun;
     float* simg = lds;
     float* srow = simg + ISX * IPP;
-    float* sbas = srow + 3 * ISX * BPP;
+    float* sbas = lds;   // written once the image and row-pass maps are dead
     const int BB = BSP * BPP;   // one basis / channel map
 
     // 1. input region (top-left at tile origin - Q - R), reflect-101 borders.
@@ -345,11 +348,79 @@ __global__ __launch_bounds__(kNT, 2) void describe_kernel(const DescribeJob sing
     // 3. steer + rectify per channel group into LDS, then dilated smoothing
     //    of this thread's horizontal run of kRun outputs.
     float acc[Z][kRun];
-    float* schan = lds;   // image and row regions are free now
-    const int N = C.N;
+    float* schan = sbas + 5 * BB;
+    // The fast path has both orders (N = Z / 2 at compile time).
+    const int N = FAST ? Z / 2 : C.N;
     const int B = 2 * C.K + 1;
     const int oy = t / (kTS / kRun), ox0 = (t % (kTS / kRun)) * kRun;
     const int BSr = kTS + 2 * Q;   // rows / columns actually read
+
+    // 4. (per order block) normalisation, rounding, store, channel sums.
+    //    Each thread stores its run of kRun pixels of a channel as one
+    //    vector (8 threads cover a 128-byte row segment), so every store
+    //    instruction writes whole cache lines; unaligned widths and the
+    //    right edge fall back to scalar stores.  The channel sums for the
+    //    integral images accumulate in channel order.
+    const int64_t plane = (int64_t)H * W;
+    const int gy = ty0 + oy, gx0 = tx0 + ox0;
+    const size_t align = C.dtype == SFOC_DTYPE_F32 ? 15 : 7;
+    const bool full = (W & (kRun - 1)) == 0 && ((uintptr_t)desc & align) == 0 && gx0 + kRun <= W;
+    const int64_t off0 = (int64_t)gy * W + gx0;
+    double d1[kRun], d2[kRun];
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) d1[j] = d2[j] = 0.0;
+    auto emit = [&](int lo, int hi) {   // channels [lo, hi): one order block
+        float inv[kRun];
+#pragma unroll
+        for (int j = 0; j < kRun; ++j) {
+            float s2 = 0.f;
+#pragma unroll
+            for (int c = 0; c < Z; ++c)
+                if (c >= lo && c < hi) s2 = fmaf(acc[c][j], acc[c][j], s2);
+            inv[j] = 1.0f / sqrtf(s2 + C.eps);
+        }
+        if (gy >= H) return;
+#pragma unroll
+        for (int c = 0; c < Z; ++c) {
+            if (c < lo || c >= hi) continue;
+            float v[kRun];
+#pragma unroll
+            for (int j = 0; j < kRun; ++j) v[j] = acc[c][j] * inv[j];
+            if (C.dtype == SFOC_DTYPE_F32) {
+                float* dst = (float*)desc + c * plane + off0;
+                if (full) {
+                    *(float4*)dst = make_float4(v[0], v[1], v[2], v[3]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < kRun; ++j)
+                        if (gx0 + j < W) dst[j] = v[j];
+                }
+            } else {
+                uint16_t q[kRun];
+#pragma unroll
+                for (int j = 0; j < kRun; ++j) {
+                    q[j] = C.dtype == SFOC_DTYPE_BF16 ? f32_to_bf16_bits(v[j]) : f32_to_f16_bits(v[j]);
+                    v[j] = C.dtype == SFOC_DTYPE_BF16 ? bf16_bits_to_f32(q[j]) : f16_bits_to_f32(q[j]);
+                }
+                uint16_t* dst = (uint16_t*)desc + c * plane + off0;
+                if (full) {
+                    *(ushort4*)dst = make_ushort4(q[0], q[1], q[2], q[3]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < kRun; ++j)
+                        if (gx0 + j < W) dst[j] = q[j];
+                }
+            }
+            if (integ1) {
+#pragma unroll
+                for (int j = 0; j < kRun; ++j) {
+                    const double dv = (double)v[j];
+                    d1[j] += dv;
+                    d2[j] = fma(dv, dv, d2[j]);
+                }
+            }
+        }
+    };
 #pragma unroll
     for (int c0 = 0; c0 < Z; c0 += CG) {
         // thread index laundered per group: keeps the group's LDS addresses
@@ -407,51 +478,24 @@ __global__ __launch_bounds__(kNT, 2) void describe_kernel(const DescribeJob sing
         }
         __syncthreads();
     }
-
-    // 4. per-order normalisation, rounding, store, channel sums.
-    const int64_t plane = (int64_t)H * W;
-    const int gy = ty0 + oy;
+    if (FAST) {
+        emit(0, Z / 2);
+        emit(Z / 2, Z);
+    } else {
+        emit(0, N);
+        emit(N, Z);
+    }
+    if (integ1 && gy < H) {
+        const int64_t io = (int64_t)(gy + 1) * (W + 1) + gx0 + 1;
 #pragma unroll
-    for (int j = 0; j < kRun; ++j) {
-        const int gx = tx0 + ox0 + j;
-        float inv[2];
-#pragma unroll
-        for (int o = 0; o < 2; ++o) {
-            float s2 = 0.f;
-#pragma unroll
-            for (int c = 0; c < Z; ++c)
-                if ((c < N) == (o == 0)) s2 = fmaf(acc[c][j], acc[c][j], s2);
-            inv[o] = 1.0f / sqrtf(s2 + C.eps);
-        }
-        if (gy < H && gx < W) {
-            const int64_t off = (int64_t)gy * W + gx;
-            double d1 = 0.0, d2 = 0.0;
-#pragma unroll
-            for (int c = 0; c < Z; ++c) {
-                float v = acc[c][j] * inv[c < N ? 0 : 1];
-                if (C.dtype == SFOC_DTYPE_F32) {
-                    ((float*)desc)[c * plane + off] = v;
-                } else if (C.dtype == SFOC_DTYPE_BF16) {
-                    const uint16_t b = f32_to_bf16_bits(v);
-                    ((uint16_t*)desc)[c * plane + off] = b;
-                    v = bf16_bits_to_f32(b);
-                } else {
-                    const uint16_t b = f32_to_f16_bits(v);
-                    ((uint16_t*)desc)[c * plane + off] = b;
-                    v = f16_bits_to_f32(b);
-                }
-                const double dv = (double)v;
-                d1 += dv;
-                d2 = fma(dv, dv, d2);
+        for (int j = 0; j < kRun; ++j)
+            if (gx0 + j < W) {
+                integ1[io + j] = d1[j];
+                integ2[io + j] = d2[j];
             }
-            if (integ1) {
-                const int64_t io = (int64_t)(gy + 1) * (W + 1) + gx + 1;
-                integ1[io] = d1;
-                integ2[io] = d2;
-            }
-        }
     }
 }
+
 
 // ---- integral images (Eq. 15 as two scans) -----------------------------
 // Row pass: in place, inclusive prefix along each row 1..H of the
@@ -596,8 +640,8 @@ __global__ __launch_bounds__(kScanNT) void integral_col_apply(const IntegJob sin
 template <int Z, bool FAST>
 static hipError_t launch_describe_zf(const DescribeJob& job, const DescribeJob* jobs, const int4* tiles, int ntiles,
                                      const DescribeConsts& c, hipStream_t st) {
-    constexpr int CG = Z >= 4 ? 4 : Z;
-    const DescribeGeom g = describe_geom(c);
+    constexpr int CG = FAST ? 2 : (Z >= 4 ? 4 : Z);
+    const DescribeGeom g = describe_geom(c, CG);
     dim3 grid = tiles ? dim3(ntiles) : dim3((job.W + kTS - 1) / kTS, (job.H + kTS - 1) / kTS);
     if (grid.x == 0) return hipSuccess;
     auto kern = describe_kernel<Z, CG, FAST>;
@@ -612,7 +656,8 @@ static hipError_t launch_describe_zf(const DescribeJob& job, const DescribeJob* 
 template <int Z>
 static hipError_t launch_describe_z(const DescribeJob& job, const DescribeJob* jobs, const int4* tiles, int ntiles,
                                     const DescribeConsts& c, hipStream_t st) {
-    const bool fast = c.K == 1 && c.ndil == 3 && c.dil[0] == 1 && c.dil[1] == 2 && c.dil[2] == 3;
+    const bool fast = c.K == 1 && c.ndil == 3 && c.dil[0] == 1 && c.dil[1] == 2 && c.dil[2] == 3 && c.second &&
+                      c.N * 2 == Z;
     return fast ? launch_describe_zf<Z, true>(job, jobs, tiles, ntiles, c, st)
                 : launch_describe_zf<Z, false>(job, jobs, tiles, ntiles, c, st);
 }
