@@ -26,6 +26,32 @@ PEAK_FP32_VALU = 157.3e12       # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (pack
 PEAK_HBM = 8.0e12
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_scene2048.md")
+KERNEL_SOURCES = {"describe": "sfoc_describe.hip", "match": "sfoc_match.hip"}
+
+
+def stored_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary:
+    (FETCH_SIZE * fetch_scale + WRITE_SIZE * write_scale) KiB, the scales
+    measured on a plain device copy of known size.  None when the summary
+    has no line for the kernel or was taken on a different kernel source."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2202_13347_amd", "csrc", KERNEL_SOURCES[kernel])
+    if not os.path.exists(TRAFFIC_FILE) or not os.path.exists(src):
+        return None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for line in open(TRAFFIC_FILE):
+        f = line.strip().strip("`").split()
+        if len(f) < 3 or f[0] != "traffic" or f[1] != kernel:
+            continue
+        kv = dict(x.split("=", 1) for x in f[2:] if "=" in x)
+        if kv.get("sha256") != digest:
+            return None
+        return 1024.0 * (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) +
+                         float(kv["write_kib"]) * float(kv["write_scale"]))
+    return None
+
+
 def sfoc_flops_per_px(p) -> float:
     """Algorithmic flops per output pixel of SFOC (separable form): per sigma
     the row pass (g, d, dd) and column pass (5 basis maps), each a (2R+1)-tap
@@ -283,7 +309,7 @@ def main():
         "kernel_ms_per_launch": avg,
         "kernel_ms_per_step": per_step,
         "roofline": {"kernel": dom, "bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-                     "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU, "traffic": None,
+                     "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU, "traffic": stored_traffic(dom),
                      "algorithmic": {"sfoc_flop_per_px": flops_px, "fastncc_flop_per_ip": flops_ip}},
         "accuracy": {"valid": int(valid.sum()), "correct_1p5px": int((err[valid] <= 1.5).sum()),
                      "rmse_valid_px": float(np.sqrt(np.mean(err[valid] ** 2))) if valid.any() else None},
