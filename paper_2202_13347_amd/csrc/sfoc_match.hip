@@ -833,29 +833,55 @@ SFOC_DEV float cp_disp(const sfoc_cp& c, const int32_t* prior, int i, int axis) 
     return axis == 0 ? (float)(pr + c.dy) + c.sub_dy : (float)(pr + c.dx) + c.sub_dx;
 }
 
-// k-th smallest (0-based) displacement along axis over eligible CPs.
-SFOC_DEV float select_kth(const sfoc_cp* cps, const int32_t* prior, int n, int axis, int k, uint32_t* hist,
-                          uint32_t* shared_sel) {
+// Keys of the eligible CPs' displacements are cached in LDS up to this many
+// CPs (both axes); larger pairs read them from the records on every pass.
+constexpr int kConsCache = 4096;
+
+// k-th smallest (0-based) key among the eligible CPs along one axis: four
+// 8-bit radix passes; each histogram is scanned by the first wave (four
+// bins per lane) to find the bin holding rank k.
+SFOC_DEV uint32_t select_kth(const sfoc_cp* cps, const int32_t* prior, int n, int axis, int k,
+                             const uint32_t* cache, int ncache, uint32_t* hist, uint32_t* shared_sel) {
     uint32_t prefix = 0, mask = 0;
     for (int shift = 24; shift >= 0; shift -= 8) {
         for (int b = threadIdx.x; b < 256; b += kConsNT) hist[b] = 0;
         __syncthreads();
-        for (int i = threadIdx.x; i < n; i += kConsNT) {
-            const sfoc_cp c = cps[i];
-            if (c.flags & kBad) continue;
-            const uint32_t key = fkey(cp_disp(c, prior, i, axis));
-            if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+        if (cache) {
+            for (int i = threadIdx.x; i < ncache; i += kConsNT) {
+                const uint32_t key = cache[i];
+                if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+            }
+        } else {
+            for (int i = threadIdx.x; i < n; i += kConsNT) {
+                const sfoc_cp c = cps[i];
+                if (c.flags & kBad) continue;
+                const uint32_t key = fkey(cp_disp(c, prior, i, axis));
+                if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+            }
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t cum = 0;
-            int b = 0;
-            for (; b < 256; ++b) {
-                if (cum + hist[b] > (uint32_t)k) break;
-                cum += hist[b];
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
+            const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2],
+                           h3 = hist[4 * lane + 3];
+            const uint32_t own = h0 + h1 + h2 + h3;
+            uint32_t incl = own;   // inclusive prefix over lanes
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t u = __shfl_up(incl, d, 64);
+                if (lane >= d) incl += u;
             }
-            shared_sel[0] = (uint32_t)b;
-            shared_sel[1] = cum;
+            const uint32_t before = incl - own;   // keys in bins below this lane's four
+            if (before <= (uint32_t)k && (uint32_t)k < incl) {   // exactly one lane
+                uint32_t cum = before;
+                int b = 4 * lane;
+                const uint32_t hs[4] = {h0, h1, h2, h3};
+                for (int q = 0; q < 4; ++q, ++b) {
+                    if (cum + hs[q] > (uint32_t)k) break;
+                    cum += hs[q];
+                }
+                shared_sel[0] = (uint32_t)b;
+                shared_sel[1] = cum;
+            }
         }
         __syncthreads();
         const uint32_t b = shared_sel[0];
@@ -864,7 +890,7 @@ SFOC_DEV float select_kth(const sfoc_cp* cps, const int32_t* prior, int n, int a
         mask |= 255u << shift;
         __syncthreads();
     }
-    return fkey_inv(prefix);
+    return prefix;
 }
 
 __global__ __launch_bounds__(kConsNT) void consistency_kernel(sfoc_cp* cps, const int32_t* prior, int n,
@@ -878,22 +904,32 @@ __global__ __launch_bounds__(kConsNT) void consistency_kernel(sfoc_cp* cps, cons
     __shared__ uint32_t hist[256];
     __shared__ uint32_t sel[2];
     __shared__ int cnt;
+    __shared__ uint32_t keys[2][kConsCache];
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
-    int local = 0;
-    for (int i = threadIdx.x; i < n; i += kConsNT)
-        if (!(cps[i].flags & kBad)) ++local;
-    atomicAdd(&cnt, local);
+    // eligible CPs: count, and (for small pairs) their keys, compacted in
+    // any order (the selection does not depend on it)
+    const bool cached = n <= kConsCache;
+    for (int i = threadIdx.x; i < n; i += kConsNT) {
+        const sfoc_cp c = cps[i];
+        if (c.flags & kBad) continue;
+        const int slot = atomicAdd(&cnt, 1);
+        if (cached) {
+            keys[0][slot] = fkey(cp_disp(c, prior, i, 0));
+            keys[1][slot] = fkey(cp_disp(c, prior, i, 1));
+        }
+    }
     __syncthreads();
     const int ne = cnt;
     if (ne == 0) return;
     float med[2];
     for (int axis = 0; axis < 2; ++axis) {
+        const uint32_t* cache = cached ? keys[axis] : nullptr;
         if (ne & 1) {
-            med[axis] = select_kth(cps, prior, n, axis, ne / 2, hist, sel);
+            med[axis] = fkey_inv(select_kth(cps, prior, n, axis, ne / 2, cache, ne, hist, sel));
         } else {
-            const float a = select_kth(cps, prior, n, axis, ne / 2 - 1, hist, sel);
-            const float b = select_kth(cps, prior, n, axis, ne / 2, hist, sel);
+            const float a = fkey_inv(select_kth(cps, prior, n, axis, ne / 2 - 1, cache, ne, hist, sel));
+            const float b = fkey_inv(select_kth(cps, prior, n, axis, ne / 2, cache, ne, hist, sel));
             med[axis] = 0.5f * (a + b);
         }
     }
