@@ -32,6 +32,32 @@ hipError_t ensure_dynamic_lds(const void* kern, int bytes) {
     return e;
 }
 
+// A second stream (and a fork / join event pair) per device and host
+// thread, for work that overlaps the caller's stream inside one call.  Kept
+// for the life of the process; default priority, non-blocking.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
+static hipError_t side_stream(SideStream** out) {
+    thread_local std::map<int, SideStream> per_device;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    SideStream& ss = per_device[dev];
+    if (!ss.s) {
+        SideStream t;
+        e = hipStreamCreateWithFlags(&t.s, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&t.fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&t.join, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+        ss = t;
+    }
+    *out = &ss;
+    return hipSuccess;
+}
+
 struct RegisterLayout {
     size_t desc_ref, desc_sen, integ1, integ2, scan, match, total;
 };
@@ -200,9 +226,17 @@ int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr, con
     hipStream_t st = (hipStream_t)stream;
     DescribeConsts c;
     build_describe_consts(p, &c);
-    hipError_t e = launch_describe(ref, (int)Hr, (int)Wr, ldr, dref, i1, i2, c, st);
-    if (e == hipSuccess) e = launch_integral(i1, i2, (int)Hr, (int)Wr, (double*)(base + L.scan), st);
+    // The reference's integral scans (memory-bound) run on a second stream
+    // while the sensed image is described; the match waits for both.
+    SideStream* side = nullptr;
+    hipError_t e = side_stream(&side);
+    if (e == hipSuccess) e = launch_describe(ref, (int)Hr, (int)Wr, ldr, dref, i1, i2, c, st);
+    if (e == hipSuccess) e = hipEventRecord(side->fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->fork, 0);
+    if (e == hipSuccess) e = launch_integral(i1, i2, (int)Hr, (int)Wr, (double*)(base + L.scan), side->s);
+    if (e == hipSuccess) e = hipEventRecord(side->join, side->s);
     if (e == hipSuccess) e = launch_describe(sen, (int)Hs, (int)Ws, lds, dsen, nullptr, nullptr, c, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, side->join, 0);
     if (e != hipSuccess) return hip_status(e);
     if (n == 0) return SFOC_OK;
     e = launch_match(dsen, Hs, Ws, dref, Hr, Wr, i1, i2, z, p->desc_dtype, ips, prior, n, m, r, ncc, cps,

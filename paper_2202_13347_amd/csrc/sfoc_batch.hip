@@ -30,7 +30,7 @@ struct sfoc_plan {
     size_t bytes = 0;
     DescribeJob* djobs = nullptr;
     int4* dtiles = nullptr;
-    int ndt = 0;
+    int ndt = 0, ndt_ref = 0;   // all tiles; reference tiles (first)
     IntegJob* ijobs = nullptr;
     int4* irows = nullptr;
     int4* icols = nullptr;
@@ -42,7 +42,8 @@ struct sfoc_plan {
     int npeak = 0;
     hipStream_t side_stream = nullptr;   // second graph branch
     hipStream_t cap_stream = nullptr;    // capture happens here (the caller's may be the null stream)
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;     // match sides
+    hipEvent_t ev_fork2 = nullptr, ev_join2 = nullptr;   // integral scans beside the sensed describe
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int tuned = 0, cached = 0;
@@ -159,9 +160,18 @@ hipError_t enqueue_match(sfoc_plan* P, hipStream_t st) {
     return launch_consistency_batched(P->margs, (int)P->pairs.size(), st);
 }
 
+// Reference descriptors, then the integral scans on the second branch while
+// the sensed tiles are described, then the match.
 hipError_t enqueue_all(sfoc_plan* P, hipStream_t st) {
-    hipError_t e = launch_describe_batched(P->djobs, P->dtiles, P->ndt, P->c, st);
-    if (e == hipSuccess) e = launch_integral_batched(P->ijobs, P->irows, P->nir, P->icols, P->nic, st);
+    hipError_t e = launch_describe_batched(P->djobs, P->dtiles, P->ndt_ref, P->c, st);
+    if (e == hipSuccess) e = hipEventRecord(P->ev_fork2, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(P->side_stream, P->ev_fork2, 0);
+    if (e == hipSuccess)
+        e = launch_integral_batched(P->ijobs, P->irows, P->nir, P->icols, P->nic, P->side_stream);
+    if (e == hipSuccess) e = hipEventRecord(P->ev_join2, P->side_stream);
+    if (e == hipSuccess)
+        e = launch_describe_batched(P->djobs, P->dtiles + P->ndt_ref, P->ndt - P->ndt_ref, P->c, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, P->ev_join2, 0);
     if (e == hipSuccess) e = enqueue_match(P, st);
     return e;
 }
@@ -171,6 +181,8 @@ void free_plan(sfoc_plan* P) {
     if (P->graph) (void)hipGraphDestroy(P->graph);
     if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
     if (P->ev_join) (void)hipEventDestroy(P->ev_join);
+    if (P->ev_fork2) (void)hipEventDestroy(P->ev_fork2);
+    if (P->ev_join2) (void)hipEventDestroy(P->ev_join2);
     if (P->side_stream) (void)hipStreamDestroy(P->side_stream);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
     if (P->mem) (void)hipFree(P->mem);
@@ -271,11 +283,15 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     std::vector<DescribeJob> djobs(2 * (size_t)n_pairs);
     std::vector<int4> dtiles;
     std::vector<uint8_t> mask;
-    for (int k = 0; k < n_pairs; ++k) {
+    for (int k = 0; k < n_pairs; ++k) {   // reference tiles first
         const sfoc_pair& q = pairs[k];
         const int ntyr = (int)((q.Hr + T - 1) / T), ntxr = (int)((q.Wr + T - 1) / T);
         for (int a = 0; a < ntyr; ++a)
             for (int b = 0; b < ntxr; ++b) dtiles.push_back(make_int4(2 * k, a * T, b * T, 0));
+    }
+    const int nref_tiles = (int)dtiles.size();
+    for (int k = 0; k < n_pairs; ++k) {
+        const sfoc_pair& q = pairs[k];
         const int ntys = (int)((q.Hs + T - 1) / T), ntxs = (int)((q.Ws + T - 1) / T);
         if (sparse) {
             mask.assign((size_t)ntys * ntxs, 0);
@@ -345,6 +361,8 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_fork2, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_join2, hipEventDisableTiming);
     if (e != hipSuccess) {
         free_plan(P);
         return hip_status(e);
@@ -363,6 +381,7 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     P->djobs = (DescribeJob*)(mem + o_djobs);
     P->dtiles = (int4*)(mem + o_dtiles);
     P->ndt = (int)dtiles.size();
+    P->ndt_ref = nref_tiles;
     P->ijobs = (IntegJob*)(mem + o_ijobs);
     P->irows = (int4*)(mem + o_irows);
     P->icols = (int4*)(mem + o_icols);
