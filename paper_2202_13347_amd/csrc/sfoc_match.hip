@@ -69,6 +69,16 @@ SFOC_DEV const void* elem_ptr(const void* base, int64_t idx) {
     return (const char*)base + idx * (DT == 0 ? 4 : 2);
 }
 
+// Orders one wave's LDS reads before its following writes.  Enough where
+// every location a lane writes is read only by lanes of its own wave in the
+// same round (the row-pair passes: a pair's tasks are consecutive lanes);
+// LDS instructions of one wave execute in order.
+SFOC_DEV void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---- small DFTs in registers -------------------------------------------
 template <bool INV>
 SFOC_DEV void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
@@ -219,21 +229,19 @@ SFOC_DEV void join_packed(float2 (&u)[NB], float2 (&v)[NB], int j) {
 // Rows [0, nrows) x columns [0, ncols) of one descriptor plane, zero padded
 // to L; result: buf row a holds the half spectrum (bins 0..L/2) of row a.
 // s1 / s2 (if given) accumulate the sum and sum of squares of the values.
-template <int L, int DT>
+template <int L, int DT, bool PIPE>
 SFOC_DEV void row_stage(const void* plane, int pitch, int y0, int x0, int nrows, int ncols, float2* buf,
                         const float2* tw, double* s1, double* s2) {
     using C = MatchCfg<L>;
     const int tid = tid_local();
     const int npair = (nrows + 1) / 2;
     const int tasksA = npair * C::NB;
-#pragma unroll 1
-    for (int task = tid; task < tasksA; task += C::NT) {
+    // Branch-free loads with 32-bit offsets from the plane base (a plane
+    // holds < 2^30 elements): the window lies inside the image, so columns
+    // past ncols are clamped to the last one and zeroed after the load, and
+    // a missing second row re-reads the first.
+    auto load = [&](int task, float2(&x)[C::NA]) {
         const int p = task / C::NB, n1 = task - p * C::NB;
-        float2 x[C::NA];
-        // Branch-free loads with 32-bit offsets from the plane base (a plane
-        // holds < 2^30 elements): the window lies inside the image, so
-        // columns past ncols are clamped to the last one and zeroed after
-        // the load, and a missing second row re-reads the first.
         const bool two = 2 * p + 1 < nrows;
         const int oa = (y0 + 2 * p) * pitch + x0;
         const int ob = oa + (two ? pitch : 0);
@@ -244,6 +252,9 @@ SFOC_DEV void row_stage(const void* plane, int pitch, int y0, int x0, int nrows,
             const float re = ldd<DT>(plane, oa + bc), im = ldd<DT>(plane, ob + bc);
             x[n2] = make_float2(b < ncols ? re : 0.f, (b < ncols && two) ? im : 0.f);
         }
+    };
+    auto finish = [&](int task, float2(&x)[C::NA]) {
+        const int p = task / C::NB, n1 = task - p * C::NB;
         if (s1) {
             double a = 0.0, q = 0.0;
 #pragma unroll
@@ -260,6 +271,25 @@ SFOC_DEV void row_stage(const void* plane, int pitch, int y0, int x0, int nrows,
 #pragma unroll
         for (int k2 = 0; k2 < C::NA; ++k2)
             reg[k2 * C::NB + (n1 ^ (k2 & (C::NB - 1)))] = k2 == 0 ? x[0] : cmul(x[k2], tw[n1 * k2]);
+    };
+    if (PIPE) {
+        // Two tasks per iteration with both tasks' loads issued first.
+#pragma unroll 1
+        for (int task = tid; task < tasksA; task += 2 * C::NT) {
+            float2 xa[C::NA], xb[C::NA];
+            const bool second = task + C::NT < tasksA;
+            load(task, xa);
+            if (second) load(task + C::NT, xb);
+            finish(task, xa);
+            if (second) finish(task + C::NT, xb);
+        }
+    } else {
+#pragma unroll 1
+        for (int task = tid; task < tasksA; task += C::NT) {
+            float2 x[C::NA];
+            load(task, x);
+            finish(task, x);
+        }
     }
     __syncthreads();
     const int tasksB = npair * C::HA;
@@ -281,7 +311,7 @@ SFOC_DEV void row_stage(const void* plane, int pitch, int y0, int x0, int nrows,
             dftn<C::NB, false>(u);
             dftn<C::NB, false>(v);
         }
-        __syncthreads();
+        wave_sync();   // this pair's reads before its in-place writes
         if (act) {
             // half spectra of the two real rows: A = (X + conj X~)/2, B = -i (X - conj X~)/2
             float2* ra = buf + (2 * p) * C::P;
@@ -316,14 +346,13 @@ SFOC_DEV void row_stage(const void* plane, int pitch, int y0, int x0, int nrows,
 // column 0 as stored).  Rows >= nvalid read as zero.  out[rd][q] receives
 // bin bin_of(j, q) of task rd (column cc = task / HA, j = task % HA):
 // sink(rd, cc, j, u, v) gets values q < NB in u and q >= NB in v (writable).
-template <int L, bool INV, typename Sink>
+template <int L, bool INV, bool PIPE, typename Sink>
 SFOC_DEV void col_stage(float2* buf, const float2* tw, int nvalid, Sink&& sink) {
     using C = MatchCfg<L>;
     const int tid = tid_local();
-#pragma unroll 1
-    for (int task = tid; task < C::COLS * C::NB; task += C::NT) {
+    // task (cc, n1) reads and rewrites rows n1 + NB m of column cc only
+    auto load = [&](int task, float2(&x)[C::NA]) {
         const int cc = task / C::NB, n1 = task - cc * C::NB;
-        float2 x[C::NA];
 #pragma unroll
         for (int n2 = 0; n2 < C::NA; ++n2) {
             const int row = n1 + C::NB * n2;
@@ -334,12 +363,33 @@ SFOC_DEV void col_stage(float2* buf, const float2* tw, int nvalid, Sink&& sink) 
             }
             x[n2] = v;
         }
+    };
+    auto finish = [&](int task, float2(&x)[C::NA]) {
+        const int cc = task / C::NB, n1 = task - cc * C::NB;
         dftn<C::NA, INV>(x);
 #pragma unroll
         for (int k2 = 0; k2 < C::NA; ++k2) {
             float2 w = tw[n1 * k2];
             if (INV) w.y = -w.y;
             buf[(n1 + C::NB * k2) * C::P + cc] = k2 == 0 ? x[0] : cmul(x[k2], w);
+        }
+    };
+    if (PIPE) {   // two tasks per iteration, both tasks' reads first
+#pragma unroll 1
+        for (int task = tid; task < C::COLS * C::NB; task += 2 * C::NT) {
+            float2 xa[C::NA], xb[C::NA];
+            const bool second = task + C::NT < C::COLS * C::NB;
+            load(task, xa);
+            if (second) load(task + C::NT, xb);
+            finish(task, xa);
+            if (second) finish(task + C::NT, xb);
+        }
+    } else {
+#pragma unroll 1
+        for (int task = tid; task < C::COLS * C::NB; task += C::NT) {
+            float2 x[C::NA];
+            load(task, x);
+            finish(task, x);
         }
     }
     __syncthreads();
@@ -449,10 +499,10 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
     float2 xsp[C::RB][C::BINS];   // search-window spectrum of the current channel
     for (int h = 0; h < A.z; ++h) {
         stage_fence();
-        row_stage<L, DT>(elem_ptr<DT>(A.desc_ref, h * plane_r), (int)A.Wr, (int)(sy + u0), (int)(sx + v0), Mu, Mv,
+        row_stage<L, DT, true>(elem_ptr<DT>(A.desc_ref, h * plane_r), (int)A.Wr, (int)(sy + u0), (int)(sx + v0), Mu, Mv,
                          buf, tw, nullptr, nullptr);
         stage_fence();
-        col_stage<L, false>(buf, tw, Mpair2, [&](int rd, int cc, int j, float2(&u)[C::NB], float2(&v)[C::NB]) {
+        col_stage<L, false, true>(buf, tw, Mpair2, [&](int rd, int cc, int j, float2(&u)[C::NB], float2(&v)[C::NB]) {
             if (cc == 0) separate_packed<C::NB>(u, v, j);
 #pragma unroll
             for (int q = 0; q < C::NB; ++q) {
@@ -462,9 +512,9 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
         });
         __syncthreads();
         stage_fence();
-        row_stage<L, DT>(elem_ptr<DT>(A.desc_sen, h * plane_s), (int)A.Ws, (int)ty, (int)tx, m, m, buf, tw, &s1, &s2);
+        row_stage<L, DT, false>(elem_ptr<DT>(A.desc_sen, h * plane_s), (int)A.Ws, (int)ty, (int)tx, m, m, buf, tw, &s1, &s2);
         stage_fence();
-        col_stage<L, false>(buf, tw, mpair2, [&](int rd, int cc, int j, float2(&u)[C::NB], float2(&v)[C::NB]) {
+        col_stage<L, false, false>(buf, tw, mpair2, [&](int rd, int cc, int j, float2(&u)[C::NB], float2(&v)[C::NB]) {
             if (cc == 0) separate_packed<C::NB>(u, v, j);
             const bool self = cc == 0 && j == 0;   // slots 0 and NB/2 hold (F_dc, F_nyq) as reals
 #pragma unroll
@@ -534,7 +584,7 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
     __syncthreads();
     {
         float2 zc[C::RB][C::BINS];
-        col_stage<L, true>(buf, tw, L, [&](int rd, int, int, float2(&u)[C::NB], float2(&v)[C::NB]) {
+        col_stage<L, true, true>(buf, tw, L, [&](int rd, int, int, float2(&u)[C::NB], float2(&v)[C::NB]) {
 #pragma unroll
             for (int q = 0; q < C::NB; ++q) {
                 zc[rd][q] = u[q];
@@ -589,7 +639,7 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
                 }
                 dftn<C::NA, true>(x);
             }
-            __syncthreads();
+            wave_sync();   // this pair's reads before its in-place writes
             if (act) {
                 float2* reg = buf + 2 * p * C::P;
 #pragma unroll
@@ -617,7 +667,7 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
                 dftn<C::NB, true>(u);
                 dftn<C::NB, true>(v);
             }
-            __syncthreads();
+            wave_sync();   // this pair's reads before its in-place writes
             if (act) {
                 float* rr = reinterpret_cast<float*>(reg);   // R[2p][v] at rr[v], R[2p+1][v] at rr[L + v]
 #pragma unroll
