@@ -165,7 +165,8 @@ def run_batched(args, S, synth, torch, p, dev):
             "value": n_ips / batch_s, "unit": "CPs/s", "ms_per_step": 1e3 * batch_s,
             "plain_value": n_ips / plain_s, "plain_ms_per_step": 1e3 * plain_s, "gain": plain_s / batch_s,
             "identical_cps": same, "ips": n_ips, "steps": args.batched_steps,
-            "sides": classes, "describe_tiles": info["describe_tiles"], "match_items": info["match_items"],
+            "sides": classes, "persistent": info["persistent"], "describe_tiles": info["describe_tiles"],
+            "match_items": info["match_items"],
             "tuned_classes": info["tuned_classes"], "plan_create_s": create_s, "generate_s": gen_s,
             "device_gb": info["device_bytes"] / 2 ** 30}
 

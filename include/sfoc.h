@@ -243,6 +243,10 @@ int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr,
  * NULL (read at creation, rewritten when a new entry was timed).
  * With SFOC_PLAN_GRAPH the first sfoc_register_cps_batched captures the
  * whole sequence on its stream into a hipGraph and every call replays it.
+ * Match launches are one workgroup per item, or persistent grids (about two
+ * workgroups per CU taking items from a counter) with SFOC_PLAN_PERSISTENT;
+ * with SFOC_PLAN_AUTOTUNE each transform side's launch form is also timed
+ * at creation and the faster kept.
  *
  * Ownership and lifetime: the caller owns every pair buffer (device
  * pointers) and keeps them allocated for the plan's lifetime; the plan
@@ -271,9 +275,10 @@ typedef struct sfoc_pair {
 
 typedef struct sfoc_plan sfoc_plan;
 
-#define SFOC_PLAN_GRAPH      1
-#define SFOC_PLAN_AUTOTUNE   2
-#define SFOC_PLAN_DENSE_SEN  4
+#define SFOC_PLAN_GRAPH       1
+#define SFOC_PLAN_AUTOTUNE    2
+#define SFOC_PLAN_DENSE_SEN   4
+#define SFOC_PLAN_PERSISTENT  8
 
 int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params* p, int32_t flags,
                      const char* tune_cache, void* stream, sfoc_plan** plan);
@@ -292,6 +297,8 @@ typedef struct sfoc_plan_info {
     int32_t tuned_classes;      /* (m, r) classes timed at creation */
     int32_t cached_classes;     /* (m, r) classes taken from tune_cache */
     int32_t graph;              /* 1 once a graph is captured */
+    int32_t persistent[2];      /* L = 64 / L = 128 match launches persistent */
+    int32_t reserved;
     int64_t device_bytes;
 } sfoc_plan_info;
 int sfoc_plan_get_info(const sfoc_plan* plan, sfoc_plan_info* info, int32_t* fft_side, int32_t* blocks,

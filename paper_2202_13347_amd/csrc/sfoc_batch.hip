@@ -40,6 +40,9 @@ struct sfoc_plan {
     int nitems[2] = {0, 0};
     int4* peak = nullptr;
     int npeak = 0;
+    int* counters = nullptr;            // work counters of the persistent launches (one per side)
+    bool persist[2] = {false, false};   // persistent match launch per transform side
+    int grid = 0;                       // persistent grid: two workgroups per CU
     hipStream_t side_stream = nullptr;   // second graph branch
     hipStream_t cap_stream = nullptr;    // capture happens here (the caller's may be the null stream)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;     // match sides
@@ -144,15 +147,18 @@ hipError_t enqueue_match(sfoc_plan* P, hipStream_t st) {
     if (both) {
         if ((e = hipEventRecord(P->ev_fork, st)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(P->side_stream, P->ev_fork, 0)) != hipSuccess) return e;
-        e = launch_match_items(64, P->dtype, P->margs, P->items[0], P->nitems[0], P->side_stream);
+        e = launch_match_items(64, P->dtype, P->margs, P->items[0], P->nitems[0], P->persist[0] ? P->counters : nullptr,
+                               P->grid, P->side_stream);
         if (e != hipSuccess) return e;
         if ((e = hipEventRecord(P->ev_join, P->side_stream)) != hipSuccess) return e;
-        e = launch_match_items(128, P->dtype, P->margs, P->items[1], P->nitems[1], st);
+        e = launch_match_items(128, P->dtype, P->margs, P->items[1], P->nitems[1],
+                               P->persist[1] ? P->counters + 1 : nullptr, P->grid, st);
         if (e != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(st, P->ev_join, 0)) != hipSuccess) return e;
     } else {
         for (int b = 0; b < 2; ++b) {
-            e = launch_match_items(b ? 128 : 64, P->dtype, P->margs, P->items[b], P->nitems[b], st);
+            e = launch_match_items(b ? 128 : 64, P->dtype, P->margs, P->items[b], P->nitems[b],
+                                   P->persist[b] ? P->counters + b : nullptr, P->grid, st);
             if (e != hipSuccess) return e;
         }
     }
@@ -190,8 +196,8 @@ void free_plan(sfoc_plan* P) {
 }
 
 // Median time of `reps` launches of one candidate side over `items`.
-float time_items(int L, int dtype, const MatchArgs* margs, const int4* items, int nitems, hipStream_t st, int reps,
-                 hipError_t* err) {
+float time_items(int L, int dtype, const MatchArgs* margs, const int4* items, int nitems, int* counter, int grid,
+                 hipStream_t st, int reps, hipError_t* err) {
     hipEvent_t a, b;
     *err = hipEventCreate(&a);
     if (*err != hipSuccess) return 0.f;
@@ -201,10 +207,10 @@ float time_items(int L, int dtype, const MatchArgs* margs, const int4* items, in
         return 0.f;
     }
     std::vector<float> t;
-    *err = launch_match_items(L, dtype, margs, items, nitems, st);   // warm-up
+    *err = launch_match_items(L, dtype, margs, items, nitems, counter, grid, st);   // warm-up
     for (int k = 0; k < reps && *err == hipSuccess; ++k) {
         *err = hipEventRecord(a, st);
-        if (*err == hipSuccess) *err = launch_match_items(L, dtype, margs, items, nitems, st);
+        if (*err == hipSuccess) *err = launch_match_items(L, dtype, margs, items, nitems, counter, grid, st);
         if (*err == hipSuccess) *err = hipEventRecord(b, st);
         if (*err == hipSuccess) *err = hipEventSynchronize(b);
         float ms = 0.f;
@@ -226,7 +232,8 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
                      const char* tune_cache, void* stream, sfoc_plan** plan) {
     if (!plan || !pairs || n_pairs < 1) return SFOC_E_INVALID_ARG;
     *plan = nullptr;
-    if (flags & ~(SFOC_PLAN_GRAPH | SFOC_PLAN_AUTOTUNE | SFOC_PLAN_DENSE_SEN)) return SFOC_E_INVALID_ARG;
+    if (flags & ~(SFOC_PLAN_GRAPH | SFOC_PLAN_AUTOTUNE | SFOC_PLAN_DENSE_SEN | SFOC_PLAN_PERSISTENT))
+        return SFOC_E_INVALID_ARG;
     int32_t z = 0;
     int rc = check_params(p, &z);
     if (rc) return rc;
@@ -355,6 +362,7 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     const size_t o_items0 = cur.take(max_items[0] * sizeof(int4));
     const size_t o_items1 = cur.take(max_items[1] * sizeof(int4));
     const size_t o_peak = cur.take(max_peak * sizeof(int4));
+    const size_t o_counters = cur.take(2 * sizeof(int));
     P->bytes = cur.off;
     e = hipMalloc((void**)&P->mem, P->bytes);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->side_stream, hipStreamNonBlocking);
@@ -391,6 +399,12 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     P->items[0] = (int4*)(mem + o_items0);
     P->items[1] = (int4*)(mem + o_items1);
     P->peak = (int4*)(mem + o_peak);
+    P->counters = (int*)(mem + o_counters);
+    {
+        int cus = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device);
+        P->grid = 2 * (cus > 0 ? cus : 1);
+    }
     auto up = [&](void* dst, const void* src, size_t n) {
         if (e == hipSuccess && n) e = hipMemcpy(dst, src, n, hipMemcpyHostToDevice);
     };
@@ -452,7 +466,7 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
                     int4* dit = P->items[bucket_of(L)];
                     up(dit, items.data(), items.size() * sizeof(int4));
                     if (e != hipSuccess) break;
-                    const float t = time_items(L, P->dtype, P->margs, dit, (int)items.size(), st, 3, &e);
+                    const float t = time_items(L, P->dtype, P->margs, dit, (int)items.size(), nullptr, 0, st, 3, &e);
                     if (c == 0 || t < tbest) {
                         tbest = t;
                         best = L;
@@ -503,6 +517,19 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     }
     up(P->peak, peak.data(), peak.size() * sizeof(int4));
     P->npeak = (int)peak.size();
+    // launch form per side: persistent when asked; with autotuning the
+    // faster of the two on this plan's items
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+        P->persist[b] = (flags & SFOC_PLAN_PERSISTENT) != 0;
+        if (tune && P->nitems[b] > 0) {
+            const int L = b ? 128 : 64;
+            const float tg = time_items(L, P->dtype, P->margs, P->items[b], P->nitems[b], nullptr, 0, st, 3, &e);
+            if (e != hipSuccess) break;
+            const float tp = time_items(L, P->dtype, P->margs, P->items[b], P->nitems[b], P->counters + b, P->grid, st,
+                                        3, &e);
+            P->persist[b] = tp < tg;
+        }
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         free_plan(P);
@@ -561,6 +588,9 @@ int sfoc_plan_get_info(const sfoc_plan* P, sfoc_plan_info* info, int32_t* fft_si
     info->tuned_classes = P->tuned;
     info->cached_classes = P->cached;
     info->graph = P->exec != nullptr;
+    info->persistent[0] = P->persist[0];
+    info->persistent[1] = P->persist[1];
+    info->reserved = 0;
     info->device_bytes = (int64_t)P->bytes;
     const int n = std::min<int>(cap, (int)P->pairs.size());
     for (int k = 0; k < n; ++k) {

@@ -78,10 +78,17 @@ constexpr int kPrepCount = kCh * 9 + 3 * kCh * kCh * 9 + kCh * kFcIn + 3 * kCh;
 
 // ---- convolution forward --------------------------------------------------
 // out[b][o][y][x] = relu(bias[o] + sum_{c,i,j} w[o][c][i][j] in[b][c][S y + i - 1][S x + j - 1]).
+// One thread per output pixel with the 32 output channels in registers; the
+// layer's weights are staged in LDS once per workgroup (read back as
+// wave-uniform broadcasts) and the input loads of several channels are
+// issued together.
 template <int CIN, int S, int HIN, int HOUT>
 __global__ __launch_bounds__(256) void conv_fwd_kernel(const float* __restrict__ in, const float* __restrict__ wf,
                                                        const float* __restrict__ bias, float* __restrict__ out,
                                                        int B) {
+    __shared__ float4 sw[CIN * 9 * kCh / 4];
+    for (int e = threadIdx.x; e < CIN * 9 * kCh / 4; e += 256) sw[e] = reinterpret_cast<const float4*>(wf)[e];
+    __syncthreads();
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= B * HOUT * HOUT) return;
     const int b = idx / (HOUT * HOUT), p = idx - b * HOUT * HOUT;
@@ -89,20 +96,39 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const float* __restrict__
     float acc[kCh];
 #pragma unroll
     for (int o = 0; o < kCh; ++o) acc[o] = bias[o];
-    for (int c = 0; c < CIN; ++c) {
-        const float* src = in + ((size_t)b * CIN + c) * HIN * HIN;
+    int off[9];
+    bool ok[9];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const int yy = S * y + i - 1;
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const int xx = S * x + j - 1;
-                const float v = (yy >= 0 && yy < HIN && xx >= 0 && xx < HIN) ? src[yy * HIN + xx] : 0.f;
-                const float* w = wf + (c * 9 + i * 3 + j) * kCh;
-#pragma unroll
-                for (int o = 0; o < kCh; ++o) acc[o] = fmaf(w[o], v, acc[o]);
-            }
+        for (int j = 0; j < 3; ++j) {
+            const int yy = S * y + i - 1, xx = S * x + j - 1;
+            ok[i * 3 + j] = yy >= 0 && yy < HIN && xx >= 0 && xx < HIN;
+            off[i * 3 + j] = ok[i * 3 + j] ? yy * HIN + xx : 0;
         }
+    const float* src = in + (size_t)b * CIN * HIN * HIN;
+    constexpr int CU = CIN >= 4 ? 4 : CIN;   // channels whose loads are issued together
+#pragma unroll 1
+    for (int c0 = 0; c0 < CIN; c0 += CU) {
+        float v[CU][9];
+#pragma unroll
+        for (int cc = 0; cc < CU; ++cc)
+#pragma unroll
+            for (int k = 0; k < 9; ++k) v[cc][k] = ok[k] ? src[(size_t)(c0 + cc) * HIN * HIN + off[k]] : 0.f;
+#pragma unroll
+        for (int cc = 0; cc < CU; ++cc)
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const float4* w = sw + ((c0 + cc) * 9 + k) * (kCh / 4);
+#pragma unroll
+                for (int q = 0; q < kCh / 4; ++q) {
+                    const float4 wq = w[q];
+                    acc[4 * q] = fmaf(wq.x, v[cc][k], acc[4 * q]);
+                    acc[4 * q + 1] = fmaf(wq.y, v[cc][k], acc[4 * q + 1]);
+                    acc[4 * q + 2] = fmaf(wq.z, v[cc][k], acc[4 * q + 2]);
+                    acc[4 * q + 3] = fmaf(wq.w, v[cc][k], acc[4 * q + 3]);
+                }
+            }
     }
 #pragma unroll
     for (int o = 0; o < kCh; ++o) out[(((size_t)b * kCh + o) * HOUT + y) * HOUT + x] = fmaxf(acc[o], 0.f);
@@ -409,11 +435,24 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatArgs A) {
     const int64_t plane = A.Hs * A.Ws;
     double t1 = 0.0, t2 = 0.0;
     const int mm = m * m;
-    for (int e = t; e < mm * A.z; e += 256) {
-        const int h = e / mm, q = e - h * mm, yy = q / m, xx = q - yy * m;
-        const double d = ld_desc<DT>(A.desc_sen, h * plane + (ty + yy) * A.Ws + tx + xx);
-        t1 += d;
-        t2 += d * d;
+    // eight loads in flight per step; the sums stay in element order
+    const int ntot = mm * A.z;
+    for (int e0 = t; e0 < ntot; e0 += 8 * 256) {
+        double d[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * 256;
+            d[u] = 0.0;
+            if (e < ntot) {
+                const int h = e / mm, q = e - h * mm, yy = q / m, xx = q - yy * m;
+                d[u] = ld_desc<DT>(A.desc_sen, h * plane + (ty + yy) * A.Ws + tx + xx);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            t1 += d[u];
+            t2 += d[u] * d[u];
+        }
     }
     rd[0][t] = s1;
     rd[1][t] = s2;

@@ -79,9 +79,11 @@ hipError_t launch_describe_batched(const DescribeJob* jobs, const int4* tiles, i
 // rows[k] = {job, row 0..H, 0, 0};  cols[k] = {job, column block, row block, 0}
 hipError_t launch_integral_batched(const IntegJob* jobs, const int4* rows, int nrows, const int4* cols, int ncols,
                                    hipStream_t st);
-// items[k] = {pair, IP, offset block, 0}, all with transform side L
-hipError_t launch_match_items(int L, int dtype, const MatchArgs* pairs, const int4* items, int nitems,
-                              hipStream_t st);
+// items[k] = {pair, IP, offset block, 0}, all with transform side L; one
+// workgroup per item, or (counter != null) a persistent grid of `grid`
+// workgroups taking items from *counter (zeroed by the launch)
+hipError_t launch_match_items(int L, int dtype, const MatchArgs* pairs, const int4* items, int nitems, int* counter,
+                              int grid, hipStream_t st);
 // items[k] = {pair, first IP of a run of 256, 0, 0} over pairs with split offsets
 hipError_t launch_peak_batched(const MatchArgs* pairs, const int4* items, int nitems, hipStream_t st);
 // one workgroup per pair

@@ -414,36 +414,27 @@ SFOC_DEV bool in_image(int64_t y, int64_t x, int h, int w, int64_t H, int64_t W)
     return y >= 0 && x >= 0 && y + h <= H && x + w <= W;
 }
 
-template <int L, int DT, bool BATCH>
-__global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchArgs single,
-                                                                   const MatchArgs* __restrict__ pairs,
-                                                                   const int4* __restrict__ items) {
-    using C = MatchCfg<L>;
-    extern __shared__ float4 lds_raw[];
-    float2* tw = reinterpret_cast<float2*>(lds_raw);
-    float2* buf = tw + L;
-    double* red = reinterpret_cast<double*>(buf + C::buf_elems);   // 1 KB scratch
-
-    // Work item: interest point i, offset block (bu, bv).  With M <= L there
-    // is one block and this workgroup finishes the CP; otherwise each block
-    // covers offsets [u0, u0 + Vu) x [v0, v0 + Vv) with a search window of
-    // (m + Vu - 1) x (m + Vv - 1) <= L x L, writes its part of the surface and
-    // its best score, and peak_kernel combines the blocks.
-    // One pair per launch (blockIdx.x -> IP, block), or (BATCH) a table of
-    // (pair, IP, block) items over several pairs.
-    int i, bq, slot;
-    const MatchArgs A = BATCH ? load_table(pairs, items[blockIdx.x].x) : single;
-    const int nblk = A.nbu * A.nbv;
-    if (BATCH) {
-        const int4 it = items[blockIdx.x];
-        i = it.y;
-        bq = it.z;
-        slot = i * nblk + bq;
-    } else {
-        i = blockIdx.x / nblk;
-        bq = blockIdx.x - i * nblk;
-        slot = blockIdx.x;
+// Twiddles W_L^k, k < L, into LDS (once per workgroup).
+template <int L>
+SFOC_DEV void init_twiddles(float2* tw) {
+    for (int k = threadIdx.x; k < L; k += MatchCfg<L>::NT) {
+        float sn, cs;
+        sincospif(-2.0f * (float)k / (float)L, &sn, &cs);
+        tw[k] = make_float2(cs, sn);
     }
+}
+
+// One work item: interest point i, offset block bq (record slot `slot`).
+// With M <= L there is one block and this workgroup finishes the CP;
+// otherwise each block covers offsets [u0, u0 + Vu) x [v0, v0 + Vv) with a
+// search window of (m + Vu - 1) x (m + Vv - 1) <= L x L, writes its part of
+// the surface and its best score, and peak_kernel combines the blocks.
+// Every thread of the workgroup calls it with the same item; it returns
+// with the workgroup synchronised.
+template <int L, int DT>
+SFOC_DEV void match_item(const MatchArgs& A, int i, int bq, int slot, const float2* tw, float2* buf, double* red) {
+    using C = MatchCfg<L>;
+    const int nblk = A.nbu * A.nbv;
     const int bu = bq / A.nbv, bv = bq - bu * A.nbv;
     const int t = threadIdx.x;
     const int m = A.m, r = A.r, M = m + 2 * r, V = 2 * r + 1;
@@ -478,12 +469,6 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
             }
         return;
     }
-    for (int k = t; k < L; k += C::NT) {
-        float sn, cs;
-        sincospif(-2.0f * (float)k / (float)L, &sn, &cs);
-        tw[k] = make_float2(cs, sn);
-    }
-    __syncthreads();
 
     float2 acc[C::RB][C::BINS];   // sum over channels of F(S_h) conj(F(T_h))
 #pragma unroll
@@ -803,6 +788,59 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
     }
 }
 
+template <int L, int DT, bool BATCH>
+__global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchArgs single,
+                                                                   const MatchArgs* __restrict__ pairs,
+                                                                   const int4* __restrict__ items) {
+    using C = MatchCfg<L>;
+    extern __shared__ float4 lds_raw[];
+    float2* tw = reinterpret_cast<float2*>(lds_raw);
+    float2* buf = tw + L;
+    double* red = reinterpret_cast<double*>(buf + C::buf_elems);   // 1 KB scratch
+    // One pair per launch (blockIdx.x -> IP, block), or (BATCH) a table of
+    // (pair, IP, block) items over several pairs.
+    init_twiddles<L>(tw);
+    __syncthreads();
+    if (BATCH) {
+        const int4 it = items[blockIdx.x];
+        const MatchArgs A = load_table(pairs, it.x);
+        match_item<L, DT>(A, it.y, it.z, it.y * A.nbu * A.nbv + it.z, tw, buf, red);
+    } else {
+        const int nblk = single.nbu * single.nbv;
+        const int i = blockIdx.x / nblk;
+        match_item<L, DT>(single, i, blockIdx.x - i * nblk, blockIdx.x, tw, buf, red);
+    }
+}
+
+// Persistent form for batched plans: a grid of about two workgroups per CU
+// takes items in order from a counter (zeroed before the launch) until the
+// table is exhausted; every workgroup then exits.
+template <int L, int DT>
+__global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_persistent_kernel(const MatchArgs* __restrict__ pairs,
+                                                                              const int4* __restrict__ items,
+                                                                              int nitems, int* __restrict__ counter) {
+    using C = MatchCfg<L>;
+    extern __shared__ float4 lds_raw[];
+    float2* tw = reinterpret_cast<float2*>(lds_raw);
+    float2* buf = tw + L;
+    double* red = reinterpret_cast<double*>(buf + C::buf_elems);
+    __shared__ int next;
+    init_twiddles<L>(tw);
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int k = next;
+        __syncthreads();   // every thread has read `next` before it is replaced
+        if (k >= nitems) break;
+        const int4 it = items[k];
+        const MatchArgs A = load_table(pairs, it.x);
+        match_item<L, DT>(A, it.y, it.z, it.y * A.nbu * A.nbv + it.z, tw, buf, red);
+        __syncthreads();
+    }
+}
+
+__global__ void zero_counter_kernel(int* counter) { *counter = 0; }
+
 // ---- combining offset blocks --------------------------------------------
 // One thread per interest point: the best score over its blocks (ties: the
 // smallest row-major surface index), the flags, and the parabola from the
@@ -1066,30 +1104,43 @@ hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void
 
 // ---- batched launches ---------------------------------------------------
 template <int L, int DT>
-static hipError_t launch_match_items_L(const MatchArgs* pairs, const int4* items, int nitems, hipStream_t st) {
+static hipError_t launch_match_items_L(const MatchArgs* pairs, const int4* items, int nitems, int* counter, int grid,
+                                       hipStream_t st) {
     using C = MatchCfg<L>;
-    auto kern = match_kernel<L, DT, true>;
-    hipError_t e = ensure_dynamic_lds((const void*)kern, (int)C::lds_bytes);
-    if (e != hipSuccess) return e;
     MatchArgs none{};
-    trace_begin(st, SFOC_K_MATCH);
-    hipLaunchKernelGGL(kern, dim3(nitems), dim3(C::NT), C::lds_bytes, st, none, pairs, items);
-    trace_end(st, SFOC_K_MATCH);
+    hipError_t e;
+    if (counter) {
+        auto kern = match_persistent_kernel<L, DT>;
+        if ((e = ensure_dynamic_lds((const void*)kern, (int)C::lds_bytes)) != hipSuccess) return e;
+        trace_begin(st, SFOC_K_MATCH);
+        hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, st, counter);
+        hipLaunchKernelGGL(kern, dim3(grid < nitems ? grid : nitems), dim3(C::NT), C::lds_bytes, st, pairs, items,
+                           nitems, counter);
+        trace_end(st, SFOC_K_MATCH);
+    } else {
+        auto kern = match_kernel<L, DT, true>;
+        if ((e = ensure_dynamic_lds((const void*)kern, (int)C::lds_bytes)) != hipSuccess) return e;
+        trace_begin(st, SFOC_K_MATCH);
+        hipLaunchKernelGGL(kern, dim3(nitems), dim3(C::NT), C::lds_bytes, st, none, pairs, items);
+        trace_end(st, SFOC_K_MATCH);
+    }
     return hipGetLastError();
 }
 
-// One launch over (pair, IP, block) items that share the transform side L.
-hipError_t launch_match_items(int L, int dtype, const MatchArgs* pairs, const int4* items, int nitems,
-                              hipStream_t st) {
+// One launch over (pair, IP, block) items that share the transform side L:
+// one workgroup per item, or (counter != null) a persistent grid of `grid`
+// workgroups taking items from *counter.
+hipError_t launch_match_items(int L, int dtype, const MatchArgs* pairs, const int4* items, int nitems, int* counter,
+                              int grid, hipStream_t st) {
     if (nitems == 0) return hipSuccess;
     if (L == 64)
-        return dtype == 0 ? launch_match_items_L<64, 0>(pairs, items, nitems, st)
-             : dtype == 1 ? launch_match_items_L<64, 1>(pairs, items, nitems, st)
-                          : launch_match_items_L<64, 2>(pairs, items, nitems, st);
+        return dtype == 0 ? launch_match_items_L<64, 0>(pairs, items, nitems, counter, grid, st)
+             : dtype == 1 ? launch_match_items_L<64, 1>(pairs, items, nitems, counter, grid, st)
+                          : launch_match_items_L<64, 2>(pairs, items, nitems, counter, grid, st);
     if (L == 128)
-        return dtype == 0 ? launch_match_items_L<128, 0>(pairs, items, nitems, st)
-             : dtype == 1 ? launch_match_items_L<128, 1>(pairs, items, nitems, st)
-                          : launch_match_items_L<128, 2>(pairs, items, nitems, st);
+        return dtype == 0 ? launch_match_items_L<128, 0>(pairs, items, nitems, counter, grid, st)
+             : dtype == 1 ? launch_match_items_L<128, 1>(pairs, items, nitems, counter, grid, st)
+                          : launch_match_items_L<128, 2>(pairs, items, nitems, counter, grid, st);
     return hipErrorInvalidValue;
 }
 

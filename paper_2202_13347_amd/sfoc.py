@@ -63,10 +63,10 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("n_pairs", ctypes.c_int32), ("describe_tiles", ctypes.c_int32),
                 ("match_items", ctypes.c_int32 * 2), ("peak_items", ctypes.c_int32),
                 ("tuned_classes", ctypes.c_int32), ("cached_classes", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("device_bytes", ctypes.c_int64)]
+                ("persistent", ctypes.c_int32 * 2), ("reserved", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
 
 
-PLAN_GRAPH, PLAN_AUTOTUNE, PLAN_DENSE_SEN = 1, 2, 4
+PLAN_GRAPH, PLAN_AUTOTUNE, PLAN_DENSE_SEN, PLAN_PERSISTENT = 1, 2, 4, 8
 
 _lib = None
 
@@ -339,6 +339,7 @@ class Plan:
         return {"n_pairs": inf.n_pairs, "describe_tiles": inf.describe_tiles,
                 "match_items": (inf.match_items[0], inf.match_items[1]), "peak_items": inf.peak_items,
                 "tuned_classes": inf.tuned_classes, "cached_classes": inf.cached_classes, "graph": inf.graph,
+                "persistent": (inf.persistent[0], inf.persistent[1]),
                 "device_bytes": inf.device_bytes, "fft_side": list(L), "blocks": list(nb)}
 
     def close(self):

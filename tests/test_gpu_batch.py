@@ -87,7 +87,8 @@ def assert_same(plan, ref_res):
         np.testing.assert_array_equal(plan.ncc[k].cpu().numpy(), n, err_msg=f"pair {k}")
 
 
-@pytest.mark.parametrize("flags", [0, S.PLAN_GRAPH, S.PLAN_DENSE_SEN])
+@pytest.mark.parametrize("flags", [0, S.PLAN_GRAPH, S.PLAN_DENSE_SEN, S.PLAN_PERSISTENT,
+                                   S.PLAN_PERSISTENT | S.PLAN_GRAPH])
 def test_batched_equals_per_pair(flags):
     say(f"batched vs per-pair, flags {flags}")
     p = S.preset("baseline")
@@ -103,6 +104,7 @@ def test_batched_equals_per_pair(flags):
         assert_same(plan, want)
     if flags & S.PLAN_GRAPH:
         assert plan.info()["graph"] == 1
+    assert plan.info()["persistent"] == ((1, 1) if flags & S.PLAN_PERSISTENT else (0, 0))
     plan.close()
 
 
