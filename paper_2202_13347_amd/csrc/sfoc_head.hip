@@ -82,6 +82,8 @@ constexpr int kPrepCount = kCh * 9 + 3 * kCh * kCh * 9 + kCh * kFcIn + 3 * kCh;
 // layer's weights are staged in LDS once per workgroup (read back as
 // wave-uniform broadcasts) and the input loads of several channels are
 // issued together.
+constexpr int kOG = 4;            // output-channel groups per pixel
+constexpr int kOPG = kCh / kOG;   // output channels per thread
 template <int CIN, int S, int HIN, int HOUT>
 __global__ __launch_bounds__(256) void conv_fwd_kernel(const float* __restrict__ in, const float* __restrict__ wf,
                                                        const float* __restrict__ bias, float* __restrict__ out,
@@ -89,13 +91,16 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const float* __restrict__
     __shared__ float4 sw[CIN * 9 * kCh / 4];
     for (int e = threadIdx.x; e < CIN * 9 * kCh / 4; e += 256) sw[e] = reinterpret_cast<const float4*>(wf)[e];
     __syncthreads();
+    // thread -> (output pixel, group of kOPG output channels); the groups of
+    // a pixel are adjacent lanes, so their input loads coincide
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= B * HOUT * HOUT) return;
-    const int b = idx / (HOUT * HOUT), p = idx - b * HOUT * HOUT;
+    if (idx >= B * HOUT * HOUT * kOG) return;
+    const int g = idx % kOG, pix = idx / kOG;
+    const int b = pix / (HOUT * HOUT), p = pix - b * HOUT * HOUT;
     const int y = p / HOUT, x = p - y * HOUT;
-    float acc[kCh];
+    float acc[kOPG];
 #pragma unroll
-    for (int o = 0; o < kCh; ++o) acc[o] = bias[o];
+    for (int o = 0; o < kOPG; ++o) acc[o] = bias[g * kOPG + o];
     int off[9];
     bool ok[9];
 #pragma unroll
@@ -119,9 +124,9 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const float* __restrict__
         for (int cc = 0; cc < CU; ++cc)
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
-                const float4* w = sw + ((c0 + cc) * 9 + k) * (kCh / 4);
+                const float4* w = sw + ((c0 + cc) * 9 + k) * (kCh / 4) + g * (kOPG / 4);
 #pragma unroll
-                for (int q = 0; q < kCh / 4; ++q) {
+                for (int q = 0; q < kOPG / 4; ++q) {
                     const float4 wq = w[q];
                     acc[4 * q] = fmaf(wq.x, v[cc][k], acc[4 * q]);
                     acc[4 * q + 1] = fmaf(wq.y, v[cc][k], acc[4 * q + 1]);
@@ -131,7 +136,8 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const float* __restrict__
             }
     }
 #pragma unroll
-    for (int o = 0; o < kCh; ++o) out[(((size_t)b * kCh + o) * HOUT + y) * HOUT + x] = fmaxf(acc[o], 0.f);
+    for (int o = 0; o < kOPG; ++o)
+        out[(((size_t)b * kCh + g * kOPG + o) * HOUT + y) * HOUT + x] = fmaxf(acc[o], 0.f);
 }
 
 // ---- fully connected forward: one 64-thread workgroup per sample ----------
@@ -398,23 +404,24 @@ struct FeatArgs {
     int z, m, r;
 };
 
+constexpr int kFeatNT = 1024;
 template <int DT>
-__global__ __launch_bounds__(256) void features_kernel(const FeatArgs A) {
-    __shared__ double rd[4][256];
-    __shared__ float rmax[256];
+__global__ __launch_bounds__(kFeatNT) void features_kernel(const FeatArgs A) {
+    __shared__ double rd[4][kFeatNT];
+    __shared__ float rmax[kFeatNT];
     const int i = blockIdx.x, t = threadIdx.x;
     const sfoc_cp cp = A.cps[i];
     float* crop = A.crops + (size_t)i * kCrop * kCrop;
     float* st = A.stats + (size_t)i * kNStat;
     if (!(cp.flags & kEligible)) {
-        for (int e = t; e < kCrop * kCrop; e += 256) crop[e] = 0.f;
+        for (int e = t; e < kCrop * kCrop; e += kFeatNT) crop[e] = 0.f;
         if (t < kNStat) st[t] = 0.f;
         return;
     }
     const int r = A.r, m = A.m, V = 2 * r + 1;
     const int u = cp.dy + r, v = cp.dx + r;
     const float* S = A.ncc + (size_t)i * V * V;
-    for (int e = t; e < kCrop * kCrop; e += 256) {
+    for (int e = t; e < kCrop * kCrop; e += kFeatNT) {
         const int a = e / kCrop, b = e - a * kCrop;
         const int y = u - kHalf + a, x = v - kHalf + b;
         crop[e] = (y >= 0 && y < V && x >= 0 && x < V) ? S[y * V + x] : -1.f;
@@ -422,7 +429,7 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatArgs A) {
     // surface sums and the best value outside the 3 x 3 block
     double s1 = 0.0, s2 = 0.0;
     float best = -1.f;
-    for (int e = t; e < V * V; e += 256) {
+    for (int e = t; e < V * V; e += kFeatNT) {
         const int y = e / V, x = e - y * V;
         const float s = S[e];
         s1 += s;
@@ -437,11 +444,11 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatArgs A) {
     const int mm = m * m;
     // eight loads in flight per step; the sums stay in element order
     const int ntot = mm * A.z;
-    for (int e0 = t; e0 < ntot; e0 += 8 * 256) {
+    for (int e0 = t; e0 < ntot; e0 += 8 * kFeatNT) {
         double d[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * 256;
+            const int e = e0 + u * kFeatNT;
             d[u] = 0.0;
             if (e < ntot) {
                 const int h = e / mm, q = e - h * mm, yy = q / m, xx = q - yy * m;
@@ -460,7 +467,7 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatArgs A) {
     rd[3][t] = t2;
     rmax[t] = best;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
+    for (int s = kFeatNT / 2; s > 0; s >>= 1) {
         if (t < s) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) rd[k][t] += rd[k][t + s];
@@ -579,13 +586,13 @@ static hipError_t forward(const float* th, const float* crops, const float* stat
     float* h1 = (float*)(ws + L.h1);
     trace_begin(st, SFOC_K_HEAD_FWD);
     hipLaunchKernelGGL(prep_weights_kernel, dim3(blocks(kPrepCount, 256)), dim3(256), 0, st, th, q);
-    hipLaunchKernelGGL((conv_fwd_kernel<1, 1, kS0, kS1>), dim3(blocks((size_t)n * kS1 * kS1, 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL((conv_fwd_kernel<1, 1, kS0, kS1>), dim3(blocks((size_t)n * kS1 * kS1 * kOG, 256)), dim3(256), 0, st,
                        crops, q.wf[0], th + kB1, a1, n);
-    hipLaunchKernelGGL((conv_fwd_kernel<kCh, 2, kS1, kS2>), dim3(blocks((size_t)n * kS2 * kS2, 256)), dim3(256), 0,
+    hipLaunchKernelGGL((conv_fwd_kernel<kCh, 2, kS1, kS2>), dim3(blocks((size_t)n * kS2 * kS2 * kOG, 256)), dim3(256), 0,
                        st, a1, q.wf[1], th + kB2, a2, n);
-    hipLaunchKernelGGL((conv_fwd_kernel<kCh, 2, kS2, kS3>), dim3(blocks((size_t)n * kS3 * kS3, 256)), dim3(256), 0,
+    hipLaunchKernelGGL((conv_fwd_kernel<kCh, 2, kS2, kS3>), dim3(blocks((size_t)n * kS3 * kS3 * kOG, 256)), dim3(256), 0,
                        st, a2, q.wf[2], th + kB3, a3, n);
-    hipLaunchKernelGGL((conv_fwd_kernel<kCh, 2, kS3, kS4>), dim3(blocks((size_t)n * kS4 * kS4, 256)), dim3(256), 0,
+    hipLaunchKernelGGL((conv_fwd_kernel<kCh, 2, kS3, kS4>), dim3(blocks((size_t)n * kS4 * kS4 * kOG, 256)), dim3(256), 0,
                        st, a3, q.wf[3], th + kB4, a4, n);
     hipLaunchKernelGGL(fc_fwd_kernel, dim3(n), dim3(64), 0, st, a4, stats, q.fc1q, th, q.fc2q, h1, out);
     trace_end(st, SFOC_K_HEAD_FWD);
@@ -634,9 +641,9 @@ int sfoc_head_features(const void* desc_sen, int64_t Hs, int64_t Ws, const doubl
     FeatArgs A{desc_sen, integ1, integ2, ips, prior, ncc, cps, crops, stats, Hs, Ws, Wr, z, m, r};
     hipStream_t st = (hipStream_t)stream;
     trace_begin(st, SFOC_K_HEAD_FEAT);
-    if (dtype == SFOC_DTYPE_F32) hipLaunchKernelGGL(features_kernel<SFOC_DTYPE_F32>, dim3(n), dim3(256), 0, st, A);
-    else if (dtype == SFOC_DTYPE_BF16) hipLaunchKernelGGL(features_kernel<SFOC_DTYPE_BF16>, dim3(n), dim3(256), 0, st, A);
-    else hipLaunchKernelGGL(features_kernel<SFOC_DTYPE_F16>, dim3(n), dim3(256), 0, st, A);
+    if (dtype == SFOC_DTYPE_F32) hipLaunchKernelGGL(features_kernel<SFOC_DTYPE_F32>, dim3(n), dim3(kFeatNT), 0, st, A);
+    else if (dtype == SFOC_DTYPE_BF16) hipLaunchKernelGGL(features_kernel<SFOC_DTYPE_BF16>, dim3(n), dim3(kFeatNT), 0, st, A);
+    else hipLaunchKernelGGL(features_kernel<SFOC_DTYPE_F16>, dim3(n), dim3(kFeatNT), 0, st, A);
     trace_end(st, SFOC_K_HEAD_FEAT);
     return hip_status(hipGetLastError());
 }
