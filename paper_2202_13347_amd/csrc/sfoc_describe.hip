@@ -233,16 +233,30 @@ __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const De
     float* sbas = lds;   // written once the image and row-pass maps are dead
     const int BB = BSP * BPP;   // one basis / channel map
 
-    // 1. input region (top-left at tile origin - Q - R), reflect-101 borders.
+    // 1. input region (top-left at tile origin - Q - R), reflect-101 borders;
+    //    four rows' loads are issued before any of their LDS stores.
     {
         const int y0 = ty0 - Q - R, x0 = tx0 - Q - R;
         const bool inside = y0 >= 0 && x0 >= 0 && y0 + ISX <= H && x0 + ISX <= W;
-        for (int a = t / 64; a < ISX; a += kNT / 64) {
-            const int gy = inside ? y0 + a : reflect101(y0 + a, H);
-            const float* row = img + (int64_t)gy * ld;
-            for (int b = t % 64; b < ISX; b += 64) {
-                const int gx = inside ? x0 + b : reflect101(x0 + b, W);
-                simg[a * IPP + b] = row[gx];
+        constexpr int kRows = kNT / 64, kU = 4;
+        for (int b = t % 64; b < ISX; b += 64) {
+            const int gx = inside ? x0 + b : reflect101(x0 + b, W);
+            for (int a0 = t / 64; a0 < ISX; a0 += kRows * kU) {
+                float v[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int a = a0 + u * kRows;
+                    v[u] = 0.f;
+                    if (a < ISX) {
+                        const int gy = inside ? y0 + a : reflect101(y0 + a, H);
+                        v[u] = img[(int64_t)gy * ld + gx];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int a = a0 + u * kRows;
+                    if (a < ISX) simg[a * IPP + b] = v[u];
+                }
             }
         }
     }
