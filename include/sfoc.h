@@ -388,6 +388,73 @@ int sfoc_head_infer(const float* params, const float* crops, const float* stats,
                     void* stream);
 
 /*
+ * RANSAC outlier rejection over the CPs of one pair (Section 3.2.3: after
+ * matching, random sample consensus removes the mismatched CPs, under a
+ * projective model in general and an affine compensation model in the
+ * RPC-based variant, which needs RPC metadata and is not provided here).
+ * A drop-in alternative to the median-displacement consistency check for
+ * pairs related by more than a translation.
+ *
+ * Candidates are the CPs with an interior peak (none of OOB, FLAT_T,
+ * FLAT_S, EDGE_PEAK, NONFINITE), in CP order; each maps the sensed point
+ * (sen_row, sen_col) to the reference point of sfoc_cp's definition.  Both
+ * point sets are normalised per image, v_n = (v - (size-1)/2) / (max(H,W)/2),
+ * and every step runs in float64:
+ *  - hypothesis h draws its k sample indices (k = 3 affine, 4 projective)
+ *    from words[h*k .. h*k+k-1]: index = floor(word * n_cand / 2^32).  The
+ *    words are the caller's uniform 32-bit random numbers; the library
+ *    draws none.  A sample with a repeated index, or three points whose
+ *    cross product is <= 1e-9 (normalised units) in either image, is
+ *    degenerate (count -1);
+ *  - the minimal model is the unique affine map through 3 correspondences,
+ *    or the unique homography (h22 = 1) through 4;
+ *  - a candidate is an inlier when its reprojection distance is <=
+ *    threshold reference pixels (a projective denominator <= 0 is an
+ *    outlier); counts[h] is the number of inliers;
+ *  - the best hypothesis has the most inliers (lowest index on ties); then
+ *    n_refine times: least squares over the current inliers (for the
+ *    projective model the linear one with h22 = 1) and a new inlier set.
+ *    Fewer than k inliers, or a system whose pivot falls below 1e-12 of its
+ *    largest entry, stops the refinement with the current model.
+ * Result: the VALID / INCONSISTENT bits of every candidate are cleared and
+ * VALID (inlier) or INCONSISTENT (outlier) set; other CPs are unchanged.
+ * With fewer than k candidates or no non-degenerate hypothesis, every
+ * candidate is INCONSISTENT and info[3] = 1.
+ *  cps        n records, updated in place.                    (in/out)
+ *  prior      n x 2 int32 or NULL, as given to the matching.
+ *  words      n_hyp * k uint32.
+ *  model      9 float64: the model in pixels, row-major 3x3, mapping the
+ *             sensed (row, col, 1) to the reference, entry (2,2) = 1
+ *             (zeros without a model).                          (output)
+ *  info       4 int32: candidates, final inliers, best hypothesis (-1
+ *             without a model), status (0 model, 1 none).       (output)
+ *  counts     n_hyp int32 inlier counts, or NULL.               (output)
+ *  hyp_models n_hyp x 9 float64 minimal models in normalised
+ *             coordinates (written for non-degenerate hypotheses), or NULL.
+ * All device pointers; ws of sfoc_ransac_workspace bytes.  The result is
+ * bit-reproducible (fixed-order reductions).
+ * Limits: n <= 2^22, n_hyp <= 2^20 (SFOC_E_UNSUPPORTED beyond).
+ * Errors: SFOC_E_INVALID_ARG (null pointers, n < 0, unknown model, n_hyp <
+ * 1, n_refine outside 0..16, threshold <= 0, sizes < 1), SFOC_E_WORKSPACE,
+ * SFOC_E_HIP.  n == 0 is valid (no model, info = {0, 0, -1, 1}).
+ */
+#define SFOC_MODEL_AFFINE      6
+#define SFOC_MODEL_PROJECTIVE  8
+typedef struct sfoc_ransac_params {
+    int32_t model;       /* SFOC_MODEL_* */
+    int32_t n_hyp;       /* hypotheses */
+    int32_t n_refine;    /* least-squares refits, 0..16 */
+    int32_t reserved;
+    double  threshold;   /* inlier distance, reference pixels (1.5) */
+    int32_t Hs, Ws;      /* sensed image size (normalisation) */
+    int32_t Hr, Wr;      /* reference image size */
+} sfoc_ransac_params;
+int sfoc_ransac_workspace(int32_t n, const sfoc_ransac_params* p, size_t* bytes);
+int sfoc_ransac_cps(sfoc_cp* cps, const int32_t* prior, int32_t n, const uint32_t* words,
+                    const sfoc_ransac_params* p, void* ws, size_t ws_bytes, double* model,
+                    int32_t* info, int32_t* counts, double* hyp_models, void* stream);
+
+/*
  * Kernel timing (tracing).  While enabled, the library records a pair of
  * HIP events on the launch stream around every kernel it enqueues.
  * sfoc_trace_collect waits for those events, writes per-kernel totals into
@@ -405,7 +472,8 @@ int sfoc_head_infer(const float* params, const float* crops, const float* stats,
 #define SFOC_K_HEAD_FWD     6
 #define SFOC_K_HEAD_BWD     7
 #define SFOC_K_HEAD_ADAM    8
-#define SFOC_K_COUNT        9
+#define SFOC_K_RANSAC       9
+#define SFOC_K_COUNT       10
 #define SFOC_TRACE_MAX   4096
 int sfoc_trace_enable(int on);
 int sfoc_trace_collect(double* ms, int64_t* counts, int n);

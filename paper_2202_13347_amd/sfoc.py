@@ -68,6 +68,16 @@ class PlanInfo(ctypes.Structure):
 
 PLAN_GRAPH, PLAN_AUTOTUNE, PLAN_DENSE_SEN, PLAN_PERSISTENT = 1, 2, 4, 8
 
+
+class RansacParams(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("n_hyp", ctypes.c_int32), ("n_refine", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("threshold", ctypes.c_double), ("Hs", ctypes.c_int32),
+                ("Ws", ctypes.c_int32), ("Hr", ctypes.c_int32), ("Wr", ctypes.c_int32)]
+
+
+MODEL_AFFINE, MODEL_PROJECTIVE = 6, 8
+MODEL_SAMPLE = {MODEL_AFFINE: 3, MODEL_PROJECTIVE: 4}
+
 _lib = None
 
 
@@ -108,6 +118,8 @@ def lib() -> ctypes.CDLL:
         L.sfoc_head_train_step.argtypes = [vp, vp, vp, i32, ctypes.c_float, vp, vp, vp, vp, i32, vp, vp, vp, sz,
                                            vp]
         L.sfoc_head_infer.argtypes = [vp, vp, vp, i32, ctypes.c_float, vp, vp, vp, sz, vp]
+        L.sfoc_ransac_workspace.argtypes = [i32, ctypes.POINTER(RansacParams), ctypes.POINTER(sz)]
+        L.sfoc_ransac_cps.argtypes = [vp, vp, i32, vp, ctypes.POINTER(RansacParams), vp, sz, vp, vp, vp, vp, vp]
         L.sfoc_trace_enable.argtypes = [ctypes.c_int]
         L.sfoc_trace_collect.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.c_int]
@@ -115,7 +127,8 @@ def lib() -> ctypes.CDLL:
                      "sfoc_match_workspace", "sfoc_fastncc_match", "sfoc_register_workspace",
                      "sfoc_register_cps", "sfoc_plan_create", "sfoc_register_cps_batched", "sfoc_plan_destroy",
                      "sfoc_plan_get_info", "sfoc_match_candidates", "sfoc_head_features", "sfoc_head_workspace",
-                     "sfoc_head_forward", "sfoc_head_train_step", "sfoc_head_infer"):
+                     "sfoc_head_forward", "sfoc_head_train_step", "sfoc_head_infer", "sfoc_ransac_workspace",
+                     "sfoc_ransac_cps"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -462,7 +475,68 @@ class Head:
 
 
 KERNEL_NAMES = ("describe", "integral", "match", "consistency", "peak", "head_features", "head_forward",
-                "head_backward", "head_adam")
+                "head_backward", "head_adam", "ransac")
+
+
+def ransac_params(model: int, n_hyp: int, sizes, threshold: float = 1.5, n_refine: int = 2) -> RansacParams:
+    """sizes = (Hs, Ws, Hr, Wr)."""
+    Hs, Ws, Hr, Wr = (int(v) for v in sizes)
+    return RansacParams(int(model), int(n_hyp), int(n_refine), 0, float(threshold), Hs, Ws, Hr, Wr)
+
+
+def ransac_workspace(n: int, rp: RansacParams) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().sfoc_ransac_workspace(int(n), ctypes.byref(rp), ctypes.byref(b)), "sfoc_ransac_workspace")
+    return b.value
+
+
+class Ransac:
+    """sfoc_ransac_cps with its workspace and outputs allocated once, for n
+    CPs and the given parameters.  Calling it updates the CP flags in place
+    and returns the device tensors (model (9,) float64, info (4,) int32)."""
+
+    def __init__(self, n: int, rp: RansacParams, device="cuda"):
+        torch = _torch()
+        self.n, self.rp = int(n), rp
+        self.k = MODEL_SAMPLE[rp.model]
+        self.ws = torch.empty(ransac_workspace(n, rp), dtype=torch.uint8, device=device)
+        self.model = torch.zeros(9, dtype=torch.float64, device=device)
+        self.info = torch.zeros(4, dtype=torch.int32, device=device)
+
+    def __call__(self, cps, words, prior=None, counts=None, hyp_models=None, stream=None):
+        if cps.shape[0] != self.n:
+            raise ValueError(f"{cps.shape[0]} CPs, plan for {self.n}")
+        if words.numel() != self.rp.n_hyp * self.k or words.element_size() != 4 or not words.is_contiguous():
+            raise ValueError("words: n_hyp * k contiguous 32-bit values")
+        _check(lib().sfoc_ransac_cps(_ptr(cps), _ptr(prior), self.n, _ptr(words), ctypes.byref(self.rp),
+                                     _ptr(self.ws), self.ws.numel(), _ptr(self.model), _ptr(self.info),
+                                     _ptr(counts), _ptr(hyp_models), _stream(stream)), "sfoc_ransac_cps")
+        return self.model, self.info
+
+
+def ransac(cps, words, model: int, sizes, threshold: float = 1.5, n_refine: int = 2, prior=None,
+           want_counts: bool = False, want_models: bool = False, stream=None) -> dict:
+    """RANSAC over the CPs of one pair (device tensor (n, 8) int32, updated
+    in place).  words: device tensor of n_hyp * k 32-bit random words
+    (int32 holding the uint32 bit patterns).  Synchronises and returns host
+    values: model (3x3, pixels), n_cand, inliers, best, status, and the
+    per-hypothesis counts / minimal models when asked for."""
+    torch = _torch()
+    k = MODEL_SAMPLE[model]
+    n_hyp = words.numel() // k
+    rp = ransac_params(model, n_hyp, sizes, threshold, n_refine)
+    R = Ransac(cps.shape[0], rp, device=words.device)
+    counts = torch.full((n_hyp,), -2, dtype=torch.int32, device=words.device) if want_counts else None
+    hyp = torch.zeros((n_hyp, 9), dtype=torch.float64, device=words.device) if want_models else None
+    m, info = R(cps, words, prior=prior, counts=counts, hyp_models=hyp, stream=stream)
+    info = info.cpu().numpy()
+    out = dict(model=m.cpu().numpy().reshape(3, 3), n_cand=int(info[0]), inliers=int(info[1]), best=int(info[2]),
+               status=int(info[3]))
+    if want_counts:
+        out["counts"] = counts.cpu().numpy()
+    if want_models:
+        out["hyp_models"] = hyp.cpu().numpy().reshape(-1, 3, 3)
+    return out
 
 
 def trace_enable(on: bool = True):

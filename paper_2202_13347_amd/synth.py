@@ -309,6 +309,92 @@ def head_init_params(seed: int) -> np.ndarray:
     return np.concatenate([q.ravel() for q in parts]).astype(np.float32)
 
 
+def ransac_words(seed: int, n_hyp: int, k: int) -> np.ndarray:
+    """n_hyp * k uniform 32-bit random words (the sample draws of RANSAC)."""
+    rng = np.random.default_rng(np.random.PCG64(seed + 7919))
+    return rng.integers(0, 2 ** 32, n_hyp * k, dtype=np.uint64).astype(np.uint32)
+
+
+# Pairs related by a projective map: a rotation about the image centre, a
+# scale, a translation and a small perspective term, with occlusion patches
+# on the sensed image (the mismatches that outlier rejection removes).
+WARP = dict(size=2048, n_side=20, m=64, r=32, rot_deg=0.75, scale=0.004, persp=1e-6, max_shift=5.0, speckle=4,
+            occluded=True)
+
+
+@dataclass
+class WarpPair:
+    ref: np.ndarray        # (H, W) float32
+    sen: np.ndarray        # (H, W) float32
+    model: np.ndarray      # (3, 3) float64: sensed (row, col, 1) -> reference, entry (2, 2) = 1
+    mask: np.ndarray | None   # occluded sensed pixels
+    seed: int
+
+
+def warp_model(rng, size: int, rot_deg: float, scale: float, persp: float, max_shift: float) -> np.ndarray:
+    """Random projective map in (row, col) pixels about the image centre;
+    the rotation and scale change have magnitudes in [1/2, 1] of their
+    bounds, with random signs."""
+    a = np.deg2rad(rot_deg * rng.uniform(0.5, 1.0) * rng.choice([-1.0, 1.0]))
+    sc = 1.0 + scale * rng.uniform(0.5, 1.0) * rng.choice([-1.0, 1.0])
+    t = rng.uniform(-max_shift, max_shift, 2)
+    g, h = rng.uniform(-persp, persp, 2)
+    c = 0.5 * (size - 1)
+    R = np.array([[sc * np.cos(a), -sc * np.sin(a), 0.0], [sc * np.sin(a), sc * np.cos(a), 0.0], [0.0, 0.0, 1.0]])
+    K = np.array([[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [g, h, 1.0]])
+    C = np.array([[1.0, 0.0, c], [0.0, 1.0, c], [0.0, 0.0, 1.0]])
+    Ci = np.array([[1.0, 0.0, -c], [0.0, 1.0, -c], [0.0, 0.0, 1.0]])
+    T = np.array([[1.0, 0.0, t[0]], [0.0, 1.0, t[1]], [0.0, 0.0, 1.0]])
+    M = T @ C @ K @ R @ Ci
+    return M / M[2, 2]
+
+
+def apply_model(M: np.ndarray, pts: np.ndarray) -> np.ndarray:
+    """(n, 2) (row, col) points through a 3x3 projective map."""
+    q = np.column_stack([pts, np.ones(len(pts))]) @ np.asarray(M).T
+    return q[:, :2] / q[:, 2:3]
+
+
+def make_warp_pair(seed: int, recipe: dict = WARP, noise_std: float = 0.05) -> WarpPair:
+    """A multimodal pair as make_pair draws it (regions, per-region cubic
+    responses, blur, noise, speckle) whose sensed pixel p shows the scene
+    point that the reference shows at model(p): the blurred sensed scene is
+    resampled (cubic spline) at model(p)."""
+    rng = np.random.default_rng(np.random.PCG64(seed + 424243))
+    size = recipe["size"]
+    M = warp_model(rng, size, recipe["rot_deg"], recipe["scale"], recipe["persp"], recipe["max_shift"])
+    corners = np.array([[0, 0], [0, size - 1], [size - 1, 0], [size - 1, size - 1]], np.float64)
+    reach = np.abs(apply_model(M, corners) - corners).max()
+    pad = int(np.ceil(reach)) + 16
+    ch = cw = size + 2 * pad
+    n_shapes = max(8, int(round(40 * size * size / 256.0 ** 2)))
+    lab = _label_map(rng, ch, cw, n_shapes, 8.0, min(96.0, max(16.0, size / 2)))
+    vals = rng.uniform(0, 1, n_shapes + 1)
+    maps = _cubic_maps(rng, n_shapes + 1)
+    flip = rng.random(n_shapes + 1) < 0.5
+    scene_r = vals[lab] + _value_noise(rng, ch, cw, 16, 0.1)
+    scene_s = _blur_shift(_apply_maps(scene_r, lab, maps, flip), 1.0, (0.0, 0.0))
+    scene_r = _blur_shift(scene_r, 1.0, (0.0, 0.0))
+    ref = scene_r[pad:pad + size, pad:pad + size]
+    sen = np.empty((size, size), np.float64)
+    cols = np.arange(size, dtype=np.float64)
+    for y0 in range(0, size, 256):
+        rows = np.arange(y0, min(size, y0 + 256), dtype=np.float64)
+        pts = np.stack(np.meshgrid(rows, cols, indexing="ij"), -1).reshape(-1, 2)
+        q = apply_model(M, pts) + pad
+        sen[y0:y0 + len(rows)] = ndimage.map_coordinates(scene_s, q.T, order=3, mode="nearest").reshape(len(rows), size)
+    if noise_std > 0:
+        sen = sen + rng.normal(0.0, noise_std, sen.shape)
+    if recipe.get("speckle", 0) > 0:
+        L = float(recipe["speckle"])
+        sen = sen * rng.gamma(L, 1.0 / L, sen.shape)
+    mask = None
+    if recipe.get("occluded"):
+        sen, mask = occlude(sen.astype(np.float32), seed, n_patches=(4, 9), side=(96, 256))
+    return WarpPair(ref=np.ascontiguousarray(ref, np.float32), sen=np.ascontiguousarray(sen, np.float32), model=M,
+                    mask=mask, seed=seed)
+
+
 def workload(recipe: dict, seed: int):
     """(pair, ips, m, r) for a recipe; IP margin = ceil(m/2) + r."""
     p = make_pair(seed, recipe["size"], recipe["max_shift"], speckle_looks=recipe["speckle"])
