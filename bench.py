@@ -211,6 +211,85 @@ def run_learned(args, S, synth, torch, p, dev, ref, sen, dips, m, r):
             "accuracy": res}
 
 
+RANSAC_HYP = 2048
+
+
+def ransac_flops_per_eval(model: int) -> float:
+    """FP64 flops of one inlier test (one hypothesis against one candidate):
+    projective: denominator 4, two numerators 8, minus X w and Y w 4, squared
+    distance 3, threshold times w^2 2 = 21; affine: numerators 8, minus X
+    and Y 2, squared distance 3 = 13."""
+    return 21.0 if model == 8 else 13.0
+
+
+def run_ransac(args, S, synth, torch, p, dev):
+    """Registration of a pair related by a projective map (rotation, scale,
+    shift, perspective; occlusion patches on the sensed image): the scene
+    step followed by projective RANSAC over its CPs, against the same step
+    with the median-translation check; accuracy against the known map."""
+    import numpy as np
+    rec = synth.WARP
+    w = synth.make_warp_pair(args.seed, rec)
+    size, m, r = rec["size"], rec["m"], rec["r"]
+    ips = synth.grid_ips(size, size, rec["n_side"], (m + 1) // 2 + r)
+    n = len(ips)
+    ref = torch.from_numpy(w.ref).to(dev)
+    sen = torch.from_numpy(w.sen).to(dev)
+    dips = torch.from_numpy(ips).to(dev)
+    Rg = S.Registrar(size, size, size, size, n, m, r, p, device=dev)
+    rp = S.ransac_params(S.MODEL_PROJECTIVE, RANSAC_HYP, (size, size, size, size), 1.5, 2)
+    RS = S.Ransac(n, rp, device=dev)
+    words = torch.from_numpy(synth.ransac_words(args.seed, RANSAC_HYP, 4).view(np.int32)).to(dev)
+    plain = S.cps_to_numpy(Rg(ref, sen, dips)).copy()
+
+    def step():
+        cps = Rg(ref, sen, dips)
+        RS(cps, words)
+        return cps
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    S.trace_enable(True)
+    S.trace_collect()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cps = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    kt = S.trace_collect()
+    S.trace_enable(False)
+    got = S.cps_to_numpy(cps)
+    info = RS.info.cpu().numpy()
+    model = RS.model.cpu().numpy().reshape(3, 3)
+    src = np.stack([plain["sen_row"], plain["sen_col"]], 1).astype(np.float64)
+    pred = src + np.stack([plain["dy"] + plain["sub_dy"].astype(np.float64),
+                           plain["dx"] + plain["sub_dx"].astype(np.float64)], 1)
+    correct = np.hypot(*(pred - synth.apply_model(w.model, src)).T) <= 1.5
+    elig = (plain["flags"] & (S.VALID | S.INCONSISTENT)) != 0
+
+    def pr(flags):
+        v = (flags & S.VALID) != 0
+        tp = int((v & correct).sum())
+        return {"valid": int(v.sum()), "precision": tp / max(1, int(v.sum())),
+                "recall": tp / max(1, int((elig & correct).sum()))}
+
+    grid = np.stack(np.meshgrid(np.linspace(0, size - 1, 9), np.linspace(0, size - 1, 9)), -1).reshape(-1, 2)
+    ms_r = kt["ransac"][0] / max(1, kt["ransac"][1])
+    evals = int(info[0]) * RANSAC_HYP
+    return {"workload": f"one seeded {size}x{size} pair related by a projective map (rotation 0.375-0.75 deg, "
+                        f"scale 0.2-0.4 %, shift <= 5 px, perspective <= 1e-6/px; sensed speckled, 4-8 occlusion "
+                        f"patches), {n} IPs on a grid, m {m}, r {r}; describe + match + projective RANSAC "
+                        f"({RANSAC_HYP} hypotheses, 2 refits, 1.5 px)",
+            "value": n / dt, "unit": "CPs/s", "ms_per_step": 1e3 * dt, "ransac_ms_per_call": ms_r,
+            "hypothesis_tests_per_s": evals / (ms_r * 1e-3) if ms_r > 0 else None,
+            "fp64_tflops_hypotheses": evals * ransac_flops_per_eval(8) / (ms_r * 1e-3) / 1e12 if ms_r > 0 else None,
+            "candidates": int(info[0]), "inliers": int(info[1]),
+            "model_error_px": float(np.abs(synth.apply_model(model, grid) - synth.apply_model(w.model, grid)).max()),
+            "accuracy": {"correct_candidates": int((elig & correct).sum()), "ransac": pr(got["flags"]),
+                         "median_check": pr(plain["flags"])}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,6 +300,7 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=5, help="timed steps of the batching workload (0: skip)")
     ap.add_argument("--batched-warmup", type=int, default=2)
     ap.add_argument("--learned-pairs", type=int, default=100, help="held-out pairs for the head (0: skip)")
+    ap.add_argument("--ransac", type=int, default=1, help="warped-pair registration with RANSAC (0: skip)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -315,6 +395,8 @@ def main():
         "accuracy": {"valid": int(valid.sum()), "correct_1p5px": int((err[valid] <= 1.5).sum()),
                      "rmse_valid_px": float(np.sqrt(np.mean(err[valid] ** 2))) if valid.any() else None},
     }
+    if args.ransac:
+        out["ransac"] = run_ransac(args, S, synth, torch, p, dev)
     if args.learned_pairs > 0:
         out["learned"] = run_learned(args, S, synth, torch, p, dev, ref, sen, dips, m, r)
     if args.batched_steps > 0:

@@ -414,8 +414,9 @@ int sfoc_head_infer(const float* params, const float* crops, const float* stats,
  *  - the best hypothesis has the most inliers (lowest index on ties); then
  *    n_refine times: least squares over the current inliers (for the
  *    projective model the linear one with h22 = 1) and a new inlier set.
- *    Fewer than k inliers, or a system whose pivot falls below 1e-12 of its
- *    largest entry, stops the refinement with the current model.
+ *    Fewer than k inliers, or a normal matrix whose squared Cholesky pivot
+ *    falls to 1e-12 of its largest diagonal entry, stops the refinement
+ *    with the current model.
  * Result: the VALID / INCONSISTENT bits of every candidate are cleared and
  * VALID (inlier) or INCONSISTENT (outlier) set; other CPs are unchanged.
  * With fewer than k candidates or no non-degenerate hypothesis, every

@@ -1,21 +1,24 @@
 // RANSAC outlier rejection over CP records (Section 3.2.3: after matching,
 // random sample consensus removes mismatched CPs under a projective model,
-// or an affine one).  Three launches, all float64:
+// or an affine one).  Four launches, all float64:
 //
 //  1. prepare   (one workgroup): ordered compaction of the CPs with an
 //               interior peak into candidate correspondences, in
 //               normalised coordinates.
-//  2. hypotheses (a thread per hypothesis): sample indices from the caller's
+//  2. fit      (a thread per hypothesis): sample indices from the caller's
 //               random words, degeneracy test, closed-form minimal fit
 //               (Cramer's rule for three points; for four, the projective
 //               map of the unit square onto each quadrilateral, one
-//               composed with the adjugate of the other), then the inlier
-//               count over every candidate, the candidates streamed through
-//               LDS in tiles that every lane of a wave reads at the same
-//               address (broadcast).
-//  3. finish    (one workgroup): best hypothesis (most inliers, lowest
+//               composed with the adjugate of the other); count zeroed.
+//  3. score    (hypothesis blocks x candidate chunks): each workgroup
+//               stages one chunk of candidates in LDS, every lane of a
+//               wave reading the same address (broadcast), counts the
+//               inliers of its hypotheses and adds them to the totals with
+//               integer atomics (exact in any order).
+//  4. finish   (one workgroup): best hypothesis (most inliers, lowest
 //               index on ties), least-squares refits over the inliers from
-//               normal equations accumulated in a fixed order (so the
+//               normal equations accumulated in a fixed order and solved
+//               by a register-resident Cholesky factorisation (so the
 //               result is bit-reproducible), the final inlier set, the CP
 //               flags and the model in pixel coordinates.
 #include <hip/hip_runtime.h>
@@ -35,6 +38,7 @@ constexpr uint32_t kBad = SFOC_CP_OOB | SFOC_CP_FLAT_T | SFOC_CP_FLAT_S | SFOC_C
 constexpr double kCollinearEps = 1e-9;   // |cross| in normalised units
 constexpr double kSingular = 1e-12;      // relative pivot of a refit system
 constexpr int kPrepNT = 1024, kHypNT = 256, kTile = 1024, kFinNT = 256;
+constexpr int kScoreBlocks = 1024, kMinChunk = 32;   // target grid of the score launch
 constexpr int kMaxN = 1 << 22, kMaxHyp = 1 << 20, kMaxRefine = 16;
 
 struct Norm {
@@ -50,6 +54,7 @@ struct Args {
     double s_ref;       // reference pixels per normalised unit
     double thr_n2;      // (threshold / s_ref)^2
     int model, k, n_hyp, n_refine;
+    int chunk;          // candidates per score workgroup
     const uint32_t* words;
     double4* cand;      // (src row, src col, dst row, dst col), normalised
     int* cidx;          // candidate -> CP index
@@ -118,40 +123,55 @@ SFOC_DEV bool inlier(const double (&M)[9], bool proj, double4 c, double thr_n2) 
 }
 
 // ---- 1. candidates ---------------------------------------------------------
+// Rounds of kPrepU * kPrepNT consecutive CPs; in each round every thread
+// loads kPrepU flags at once (coalesced), then the kPrepU blocks of kPrepNT
+// CPs are compacted in CP order: wave ballots give the rank within a wave,
+// a prefix over the wave totals the rank within the workgroup.
+constexpr int kPrepU = 4;
 __global__ __launch_bounds__(kPrepNT) void prepare_kernel(Args a) {
-    __shared__ int scan[kPrepNT];
-    const int t = threadIdx.x;
-    const int chunk = (a.n + kPrepNT - 1) / kPrepNT;
-    const int lo = min(a.n, t * chunk), hi = min(a.n, lo + chunk);
-    int c = 0;
-    for (int i = lo; i < hi; ++i) c += (a.cps_in[i].flags & kBad) == 0;
-    scan[t] = c;
-    __syncthreads();
-    for (int d = 1; d < kPrepNT; d <<= 1) {   // inclusive scan
-        const int v = t >= d ? scan[t - d] : 0;
-        __syncthreads();
-        scan[t] += v;
-        __syncthreads();
+    constexpr int kW = kPrepNT / 64;
+    __shared__ int wsum[kW];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    int base = 0;
+    for (int r0 = 0; r0 < a.n; r0 += kPrepU * kPrepNT) {
+        uint32_t fl[kPrepU];
+#pragma unroll
+        for (int u = 0; u < kPrepU; ++u) {
+            const int i = r0 + u * kPrepNT + t;
+            fl[u] = i < a.n ? a.cps_in[i].flags : kBad;
+        }
+#pragma unroll
+        for (int u = 0; u < kPrepU; ++u) {
+            const int i = r0 + u * kPrepNT + t;
+            const bool e = (fl[u] & kBad) == 0;
+            const uint64_t bal = __ballot(e);
+            if (lane == 0) wsum[wv] = __popcll(bal);
+            __syncthreads();
+            int off = base, tot = 0;
+            for (int w = 0; w < kW; ++w) {
+                off += w < wv ? wsum[w] : 0;
+                tot += wsum[w];
+            }
+            if (e) {
+                const int o = off + __popcll(bal & ((1ull << lane) - 1ull));
+                const sfoc_cp p = a.cps_in[i];
+                const int py = a.prior ? a.prior[2 * i] : 0, px = a.prior ? a.prior[2 * i + 1] : 0;
+                const double sr = (double)p.sen_row, sc = (double)p.sen_col;
+                const double dr = (double)(p.sen_row + py + p.dy) + (double)p.sub_dy;
+                const double dc = (double)(p.sen_col + px + p.dx) + (double)p.sub_dx;
+                a.cand[o] = make_double4((sr - a.ns.cr) * a.ns.s, (sc - a.ns.cc) * a.ns.s,
+                                         (dr - a.nr.cr) * a.nr.s, (dc - a.nr.cc) * a.nr.s);
+                a.cidx[o] = i;
+            }
+            base += tot;
+            __syncthreads();   // wsum is rewritten by the next block
+        }
     }
-    int o = scan[t] - c;
-    for (int i = lo; i < hi; ++i) {
-        const sfoc_cp p = a.cps_in[i];
-        if (p.flags & kBad) continue;
-        const int py = a.prior ? a.prior[2 * i] : 0, px = a.prior ? a.prior[2 * i + 1] : 0;
-        const double sr = (double)p.sen_row, sc = (double)p.sen_col;
-        const double dr = (double)(p.sen_row + py + p.dy) + (double)p.sub_dy;
-        const double dc = (double)(p.sen_col + px + p.dx) + (double)p.sub_dx;
-        a.cand[o] = make_double4((sr - a.ns.cr) * a.ns.s, (sc - a.ns.cc) * a.ns.s, (dr - a.nr.cr) * a.nr.s,
-                                 (dc - a.nr.cc) * a.nr.s);
-        a.cidx[o] = i;
-        ++o;
-    }
-    if (t == kPrepNT - 1) *a.ncand = scan[t];
+    if (t == 0) *a.ncand = base;
 }
 
-// ---- 2. hypotheses -----------------------------------------------------------
-__global__ __launch_bounds__(kHypNT) void hypotheses_kernel(Args a) {
-    __shared__ double4 tile[kTile];
+// ---- 2. minimal fits ---------------------------------------------------------
+__global__ __launch_bounds__(kHypNT) void fit_kernel(Args a) {
     const int h = blockIdx.x * kHypNT + threadIdx.x;
     const int n = *a.ncand;
     const bool proj = a.model == SFOC_MODEL_PROJECTIVE;
@@ -219,54 +239,83 @@ __global__ __launch_bounds__(kHypNT) void hypotheses_kernel(Args a) {
         if (ok)
             for (int q = 0; q < 9; ++q) a.hyp[(int64_t)h * 9 + q] = M[q];
     }
-    // inlier counts: every thread of the workgroup stages the tiles
+    if (h < a.n_hyp) a.counts[h] = ok ? 0 : -1;
+}
+
+// ---- 3. inlier counts -----------------------------------------------------------
+// blockIdx.x: a block of kHypNT hypotheses; blockIdx.y: candidates
+// [y * chunk, (y + 1) * chunk).
+__global__ __launch_bounds__(kHypNT) void score_kernel(Args a) {
+    __shared__ double4 tile[kTile];
+    const int h = blockIdx.x * kHypNT + threadIdx.x;
+    const int n = *a.ncand;
+    const int c0 = blockIdx.y * a.chunk, c1 = min(n, c0 + a.chunk);
+    if (c0 >= c1) return;   // uniform over the workgroup
+    const bool proj = a.model == SFOC_MODEL_PROJECTIVE;
+    const bool ok = h < a.n_hyp && a.counts[h] >= 0;
+    double M[9];
+    if (ok)
+        for (int q = 0; q < 9; ++q) M[q] = a.hyp[(int64_t)h * 9 + q];
     int cnt = 0;
-    for (int base = 0; base < n; base += kTile) {
-        const int len = min(kTile, n - base);
+    for (int base = c0; base < c1; base += kTile) {
+        const int len = min(kTile, c1 - base);
         __syncthreads();
         for (int e = threadIdx.x; e < len; e += kHypNT) tile[e] = a.cand[base + e];
         __syncthreads();
         if (ok)
             for (int e = 0; e < len; ++e) cnt += inlier(M, proj, tile[e], a.thr_n2);
     }
-    if (h < a.n_hyp) a.counts[h] = ok ? cnt : -1;
+    if (ok && cnt) atomicAdd(&a.counts[h], cnt);
 }
 
-// ---- 3. selection, refinement, flags ---------------------------------------
-// Solve the n x n system in S (row-major, n x (n + nr) augmented with nr
-// right-hand sides) by Gaussian elimination with partial pivoting; false if
-// a pivot is below kSingular times the largest entry of the matrix.
-SFOC_DEV bool solve(double* S, int n, int nr) {
-    const int w = n + nr;
+// ---- 4. selection, refinement, flags ---------------------------------------
+// Solve A x = b for the NR right-hand sides in b, A symmetric positive
+// definite (a normal matrix; only its lower triangle is read), by a
+// Cholesky factorisation held in registers (every index is a compile-time
+// constant).  False if a squared pivot falls to kSingular times the largest
+// diagonal entry or below (the inliers do not determine the model).
+template <int N, int NR>
+SFOC_DEV bool cholesky_solve(double (&A)[N][N], double (&b)[NR][N]) {
     double big = 0.0;
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) big = fmax(big, fabs(S[i * w + j]));
+#pragma unroll
+    for (int i = 0; i < N; ++i) big = fmax(big, A[i][i]);
     if (!(big > 0.0) || !isfinite(big)) return false;
-    for (int c = 0; c < n; ++c) {
-        int p = c;
-        for (int i = c + 1; i < n; ++i)
-            if (fabs(S[i * w + c]) > fabs(S[p * w + c])) p = i;
-        if (!(fabs(S[p * w + c]) > kSingular * big)) return false;
-        if (p != c)
-            for (int j = 0; j < w; ++j) {
-                const double tmp = S[c * w + j];
-                S[c * w + j] = S[p * w + j];
-                S[p * w + j] = tmp;
-            }
-        const double inv = 1.0 / S[c * w + c];
-        for (int i = c + 1; i < n; ++i) {
-            const double f = S[i * w + c] * inv;
-            if (f == 0.0) continue;
-            for (int j = c; j < w; ++j) S[i * w + j] = fma(-f, S[c * w + j], S[i * w + j]);
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double d = A[j][j];
+#pragma unroll
+        for (int q = 0; q < j; ++q) d = fma(-A[j][q], A[j][q], d);
+        ok = ok && d > kSingular * big;
+        const double l = sqrt(fmax(d, kSingular * big));
+        const double inv = 1.0 / l;
+        A[j][j] = l;
+#pragma unroll
+        for (int i = j + 1; i < N; ++i) {
+            double v = A[i][j];
+#pragma unroll
+            for (int q = 0; q < j; ++q) v = fma(-A[i][q], A[j][q], v);
+            A[i][j] = v * inv;
         }
     }
-    for (int r = 0; r < nr; ++r)
-        for (int i = n - 1; i >= 0; --i) {
-            double v = S[i * w + n + r];
-            for (int j = i + 1; j < n; ++j) v = fma(-S[i * w + j], S[j * w + n + r], v);
-            S[i * w + n + r] = v / S[i * w + i];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {   // L y = b
+            double v = b[r][i];
+#pragma unroll
+            for (int q = 0; q < i; ++q) v = fma(-A[i][q], b[r][q], v);
+            b[r][i] = v / A[i][i];
         }
-    return true;
+#pragma unroll
+        for (int i = N - 1; i >= 0; --i) {   // L^T x = y
+            double v = b[r][i];
+#pragma unroll
+            for (int q = i + 1; q < N; ++q) v = fma(-A[q][i], b[r][q], v);
+            b[r][i] = v / A[i][i];
+        }
+    }
+    return ok;
 }
 
 constexpr int kSumsAff = 12, kSumsProj = 44;
@@ -306,7 +355,6 @@ template <bool PROJ>
 __global__ __launch_bounds__(kFinNT) void finish_kernel(Args a) {
     __shared__ double sM[9];
     __shared__ double part[kFinNT / 64][kSumsProj];
-    __shared__ double S[8 * 9];
     __shared__ int bc[kFinNT / 64], bi[kFinNT / 64], ci[kFinNT / 64];
     __shared__ int flag;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -392,7 +440,8 @@ __global__ __launch_bounds__(kFinNT) void finish_kernel(Args a) {
         }
         __syncthreads();
         if (t == 0) {
-            double tot[kSumsProj];
+            double tot[nsum];
+#pragma unroll
             for (int q = 0; q < nsum; ++q) {
                 double v = 0.0;
                 for (int w = 0; w < kFinNT / 64; ++w) v += part[w][q];
@@ -400,33 +449,45 @@ __global__ __launch_bounds__(kFinNT) void finish_kernel(Args a) {
             }
             bool good;
             if (!proj) {   // [x y 1] normal matrix, right-hand sides X and Y
-                const int o[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+                double A[3][3], b[2][3];
+                int o = 0;
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = i; j < 3; ++j, ++o) {
+                        A[i][j] = tot[o];
+                        A[j][i] = tot[o];
+                    }
+#pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    for (int j = 0; j < 3; ++j) S[i * 5 + j] = tot[o[i][j]];
-                    S[i * 5 + 3] = tot[6 + i];
-                    S[i * 5 + 4] = tot[9 + i];
+                    b[0][i] = tot[6 + i];
+                    b[1][i] = tot[9 + i];
                 }
-                good = solve(S, 3, 2);
+                good = cholesky_solve<3, 2>(A, b);
                 if (good) {
                     for (int j = 0; j < 3; ++j) {
-                        sM[j] = S[j * 5 + 3];
-                        sM[3 + j] = S[j * 5 + 4];
+                        sM[j] = b[0][j];
+                        sM[3 + j] = b[1][j];
                     }
                     sM[6] = 0.0;
                     sM[7] = 0.0;
                     sM[8] = 1.0;
                 }
             } else {
+                double A[8][8], b[1][8];
                 int o = 0;
+#pragma unroll
                 for (int i = 0; i < 8; ++i)
+#pragma unroll
                     for (int j = i; j < 8; ++j, ++o) {
-                        S[i * 9 + j] = tot[o];
-                        S[j * 9 + i] = tot[o];
+                        A[i][j] = tot[o];
+                        A[j][i] = tot[o];
                     }
-                for (int i = 0; i < 8; ++i) S[i * 9 + 8] = tot[36 + i];
-                good = solve(S, 8, 1);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) b[0][i] = tot[36 + i];
+                good = cholesky_solve<8, 1>(A, b);
                 if (good) {
-                    for (int i = 0; i < 8; ++i) sM[i] = S[i * 9 + 8];
+                    for (int i = 0; i < 8; ++i) sM[i] = b[0][i];
                     sM[8] = 1.0;
                 }
             }
@@ -559,7 +620,11 @@ extern "C" int sfoc_ransac_cps(sfoc_cp* cps, const int32_t* prior, int32_t n, co
     hipStream_t st = (hipStream_t)stream;
     trace_begin(st, SFOC_K_RANSAC);
     hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(kPrepNT), 0, st, a);
-    hipLaunchKernelGGL(hypotheses_kernel, dim3((p->n_hyp + kHypNT - 1) / kHypNT), dim3(kHypNT), 0, st, a);
+    const int hblocks = (p->n_hyp + kHypNT - 1) / kHypNT;
+    const int chunks = std::max(1, std::min(std::max(1, kScoreBlocks / hblocks), (n + kMinChunk - 1) / kMinChunk));
+    a.chunk = std::max(1, (n + chunks - 1) / chunks);
+    hipLaunchKernelGGL(fit_kernel, dim3(hblocks), dim3(kHypNT), 0, st, a);
+    hipLaunchKernelGGL(score_kernel, dim3(hblocks, chunks), dim3(kHypNT), 0, st, a);
     if (p->model == SFOC_MODEL_PROJECTIVE)
         hipLaunchKernelGGL(finish_kernel<true>, dim3(1), dim3(kFinNT), 0, st, a);
     else
