@@ -26,8 +26,8 @@ PEAK_FP32_VALU = 157.3e12       # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (pack
 PEAK_HBM = 8.0e12
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_scene2048.md")
-KERNEL_SOURCES = {"describe": "sfoc_describe.hip", "match": "sfoc_match.hip"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_scene2048_rectify10000.md")
+KERNEL_SOURCES = {"describe": "sfoc_describe.hip", "match": "sfoc_match.hip", "rectify": "sfoc_rectify.hip"}
 
 
 def stored_traffic(kernel: str):
@@ -290,6 +290,50 @@ def run_ransac(args, S, synth, torch, p, dev):
                          "median_check": pr(plain["flags"])}}
 
 
+RECT_SIDE = 10000
+RECT_BYTES_PER_PX = 8.0   # one float32 written, one float32 of sensed image read (each sensed pixel once)
+
+
+def run_rectify(args, S, torch, dev):
+    """Rectification of a 10000 x 10000 float32 image (seeded uniform
+    values) through a projective map (rotation 0.5 deg, scale 1.002,
+    perspective 1e-7 / px), HIP-event time per launch against the HBM roof
+    at 8 algorithmic bytes per output pixel."""
+    import numpy as np
+    n = RECT_SIDE
+    gen = torch.Generator(device=dev).manual_seed(args.seed)
+    sen = torch.rand((n, n), dtype=torch.float32, device=dev, generator=gen)
+    out = torch.empty_like(sen)
+    a = np.deg2rad(0.5)
+    c = 0.5 * (n - 1)
+    M = np.array([[1.002 * np.cos(a), -1.002 * np.sin(a), 0.0], [1.002 * np.sin(a), 1.002 * np.cos(a), 0.0],
+                  [1e-7, -1e-7, 1.0]])
+    C = np.array([[1, 0, c], [0, 1, c], [0, 0, 1.0]])
+    Ci = np.array([[1, 0, -c], [0, 1, -c], [0, 0, 1.0]])
+    M = C @ M @ Ci
+    model = torch.from_numpy((M / M[2, 2]).reshape(9)).to(dev)
+    for _ in range(args.warmup):
+        S.rectify(sen, model, (n, n), out=out)
+    torch.cuda.synchronize()
+    S.trace_enable(True)
+    S.trace_collect()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        S.rectify(sen, model, (n, n), out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    kt = S.trace_collect()
+    S.trace_enable(False)
+    ms = kt["rectify"][0] / max(1, kt["rectify"][1])
+    gbs = n * n * RECT_BYTES_PER_PX / (ms * 1e-3) / 1e9
+    return {"workload": f"{n}x{n} float32 image rectified through a projective map (rotation 0.5 deg, scale 1.002, "
+                        f"perspective 1e-7/px) into a {n}x{n} reference grid, bilinear",
+            "ms_per_call": ms, "wall_ms_per_call": 1e3 * dt, "gpx_per_s": n * n / (ms * 1e-3) / 1e9,
+            "roofline": {"kernel": "rectify", "bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
+                         "frac": gbs / 8000.0, "traffic": stored_traffic("rectify"),
+                         "algorithmic_bytes_per_px": RECT_BYTES_PER_PX}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,6 +345,7 @@ def main():
     ap.add_argument("--batched-warmup", type=int, default=2)
     ap.add_argument("--learned-pairs", type=int, default=100, help="held-out pairs for the head (0: skip)")
     ap.add_argument("--ransac", type=int, default=1, help="warped-pair registration with RANSAC (0: skip)")
+    ap.add_argument("--rectify", type=int, default=1, help="10000^2 rectification (0: skip)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -397,6 +442,8 @@ def main():
     }
     if args.ransac:
         out["ransac"] = run_ransac(args, S, synth, torch, p, dev)
+    if args.rectify:
+        out["rectify"] = run_rectify(args, S, torch, dev)
     if args.learned_pairs > 0:
         out["learned"] = run_learned(args, S, synth, torch, p, dev, ref, sen, dips, m, r)
     if args.batched_steps > 0:

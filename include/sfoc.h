@@ -456,6 +456,27 @@ int sfoc_ransac_cps(sfoc_cp* cps, const int32_t* prior, int32_t n, const uint32_
                     int32_t* info, int32_t* counts, double* hyp_models, void* stream);
 
 /*
+ * Rectification (Section 3.2.3: after outlier removal the sensed image is
+ * resampled into the reference image's coordinate system by bilinear
+ * interpolation).  model is the sensed -> reference map of
+ * sfoc_ransac_cps (9 float64, device memory, row-major 3x3 on (row, col,
+ * 1)); output pixel (r, c) of the Ho x Wo reference grid takes the sensed
+ * image at p = model^-1 (r, c, 1) (inverse in float64, dehomogenised):
+ * bilinear between the four pixels around p when p lies in [0, Hs-1] x
+ * [0, Ws-1] (a neighbour past the last row or column only ever has weight
+ * 0), else fill; a point whose homogeneous coordinate is <= 0, or a
+ * singular model, also gives fill.  Coordinates in float64, the
+ * interpolation in float32.
+ *  sen   Hs x Ws float32, pitch lds (elements).             (input)
+ *  out   Ho x Wo float32, pitch ldo.                        (output)
+ * Limits: every side <= 2^20 and Hs * lds < 2^31.  Errors:
+ * SFOC_E_INVALID_ARG (null pointers,
+ * sizes < 1, pitches below the widths), SFOC_E_UNSUPPORTED, SFOC_E_HIP.
+ */
+int sfoc_rectify(const float* sen, int64_t Hs, int64_t Ws, int64_t lds, const double* model,
+                 float* out, int64_t Ho, int64_t Wo, int64_t ldo, float fill, void* stream);
+
+/*
  * Kernel timing (tracing).  While enabled, the library records a pair of
  * HIP events on the launch stream around every kernel it enqueues.
  * sfoc_trace_collect waits for those events, writes per-kernel totals into
@@ -474,7 +495,8 @@ int sfoc_ransac_cps(sfoc_cp* cps, const int32_t* prior, int32_t n, const uint32_
 #define SFOC_K_HEAD_BWD     7
 #define SFOC_K_HEAD_ADAM    8
 #define SFOC_K_RANSAC       9
-#define SFOC_K_COUNT       10
+#define SFOC_K_RECTIFY     10
+#define SFOC_K_COUNT       11
 #define SFOC_TRACE_MAX   4096
 int sfoc_trace_enable(int on);
 int sfoc_trace_collect(double* ms, int64_t* counts, int n);

@@ -120,6 +120,7 @@ def lib() -> ctypes.CDLL:
         L.sfoc_head_infer.argtypes = [vp, vp, vp, i32, ctypes.c_float, vp, vp, vp, sz, vp]
         L.sfoc_ransac_workspace.argtypes = [i32, ctypes.POINTER(RansacParams), ctypes.POINTER(sz)]
         L.sfoc_ransac_cps.argtypes = [vp, vp, i32, vp, ctypes.POINTER(RansacParams), vp, sz, vp, vp, vp, vp, vp]
+        L.sfoc_rectify.argtypes = [vp, i64, i64, i64, vp, vp, i64, i64, i64, ctypes.c_float, vp]
         L.sfoc_trace_enable.argtypes = [ctypes.c_int]
         L.sfoc_trace_collect.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.c_int]
@@ -128,7 +129,7 @@ def lib() -> ctypes.CDLL:
                      "sfoc_register_cps", "sfoc_plan_create", "sfoc_register_cps_batched", "sfoc_plan_destroy",
                      "sfoc_plan_get_info", "sfoc_match_candidates", "sfoc_head_features", "sfoc_head_workspace",
                      "sfoc_head_forward", "sfoc_head_train_step", "sfoc_head_infer", "sfoc_ransac_workspace",
-                     "sfoc_ransac_cps"):
+                     "sfoc_ransac_cps", "sfoc_rectify"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -475,7 +476,7 @@ class Head:
 
 
 KERNEL_NAMES = ("describe", "integral", "match", "consistency", "peak", "head_features", "head_forward",
-                "head_backward", "head_adam", "ransac")
+                "head_backward", "head_adam", "ransac", "rectify")
 
 
 def ransac_params(model: int, n_hyp: int, sizes, threshold: float = 1.5, n_refine: int = 2) -> RansacParams:
@@ -536,6 +537,25 @@ def ransac(cps, words, model: int, sizes, threshold: float = 1.5, n_refine: int 
         out["counts"] = counts.cpu().numpy()
     if want_models:
         out["hyp_models"] = hyp.cpu().numpy().reshape(-1, 3, 3)
+    return out
+
+
+def rectify(sen, model, out_shape, fill: float = 0.0, out=None, stream=None):
+    """Resample the sensed image (Hs x Ws float32 device tensor, rows may be
+    padded) into an out_shape reference grid through the sensed -> reference
+    model (device float64 tensor of 9, e.g. Ransac.model, or a host 3x3)."""
+    torch = _torch()
+    Ho, Wo = (int(v) for v in out_shape)
+    if not torch.is_tensor(model):
+        model = torch.from_numpy(np.ascontiguousarray(model, np.float64).reshape(9)).to(sen.device)
+    if model.dtype != torch.float64 or model.numel() != 9 or not model.is_contiguous():
+        raise ValueError("model: 9 contiguous float64 values")
+    if sen.dtype != torch.float32 or sen.dim() != 2 or sen.stride(1) != 1:
+        raise ValueError("sen: 2-D float32 with unit column stride")
+    if out is None:
+        out = torch.empty((Ho, Wo), dtype=torch.float32, device=sen.device)
+    _check(lib().sfoc_rectify(_ptr(sen), sen.shape[0], sen.shape[1], sen.stride(0), _ptr(model), _ptr(out), Ho, Wo,
+                              out.stride(0), float(fill), _stream(stream)), "sfoc_rectify")
     return out
 
 

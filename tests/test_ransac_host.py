@@ -92,3 +92,20 @@ def test_rejects_null_pointers_and_small_workspace():
     need = S.ransac_workspace(10, rp)
     assert L.sfoc_ransac_cps(FAKE, None, 10, FAKE, ctypes.byref(rp), FAKE, need - 1, FAKE, FAKE, None, None,
                              None) == S.SFOC_E_WORKSPACE
+
+
+def test_rectify_rejects_bad_arguments():
+    L = S.lib()
+    ok = dict(sen=FAKE, Hs=10, Ws=10, lds=10, model=FAKE, out=FAKE, Ho=10, Wo=10, ldo=10)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return L.sfoc_rectify(a["sen"], a["Hs"], a["Ws"], a["lds"], a["model"], a["out"], a["Ho"], a["Wo"], a["ldo"],
+                              0.0, None)
+    for kw in ({"sen": None}, {"model": None}, {"out": None}, {"Hs": 0}, {"Ws": 0}, {"lds": 9}, {"Ho": 0},
+               {"Wo": 0}, {"ldo": 9}):
+        assert call(**kw) == S.SFOC_E_INVALID_ARG, kw
+    for kw in ({"Hs": (1 << 20) + 1}, {"Wo": (1 << 20) + 1, "ldo": (1 << 20) + 1},
+               {"Hs": 1 << 16, "Ws": 1 << 15, "lds": 1 << 15}):
+        assert call(**kw) == S.SFOC_E_UNSUPPORTED, kw
+    assert S.KERNEL_NAMES[10] == "rectify"
