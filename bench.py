@@ -334,6 +334,75 @@ def run_rectify(args, S, torch, dev):
                          "algorithmic_bytes_per_px": RECT_BYTES_PER_PX}}
 
 
+FAST_OPS_PER_PX = 176.0   # 16 differences, 3 x 32 pairwise min / max, 16 x 4 to close the arcs
+PEAK_FP32_OPS = 39.3e12   # single-issue FP32 lane operations: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
+
+
+def run_fast(args, S, synth, torch, dev):
+    """Block-based FAST: on the scene's sensed image (20 x 20 blocks, one
+    interest point each, matching margin) followed by registration from
+    those points; and on a 10000 x 10000 image (seeded uniform values,
+    Gaussian-smoothed on the device by a 5 x 5 box twice) for throughput."""
+    import numpy as np
+    pr, _, m, r = synth.workload(synth.SCENE, args.seed)
+    margin = (m + 1) // 2 + r
+    sen = torch.from_numpy(pr.sen).to(dev)
+    ref = torch.from_numpy(pr.ref).to(dev)
+    D = S.Detector(sen.shape[0], sen.shape[1], 20, 20, 1, 0.05, margin, device=dev)
+    Rg = S.Registrar(ref.shape[0], ref.shape[1], sen.shape[0], sen.shape[1], 400, m, r, S.preset("baseline"),
+                     device=dev)
+
+    def step():
+        ips, _, _, n = D(sen)
+        return Rg(ref, sen, ips[:400])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    S.trace_enable(True)
+    S.trace_collect()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cps = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    kt = S.trace_collect()
+    S.trace_enable(False)
+    n = int(D.n_out.item())
+    c = S.cps_to_numpy(cps)[:n]
+    v = (c["flags"] & S.VALID) != 0
+    err = np.hypot(c["dy"] + c["sub_dy"] - pr.shift[0], c["dx"] + c["sub_dx"] - pr.shift[1])
+    ms_scene = kt["fast"][0] / max(1, kt["fast"][1])
+    # throughput image
+    side = 10000
+    gen = torch.Generator(device=dev).manual_seed(args.seed)
+    big = torch.rand((1, 1, side, side), dtype=torch.float32, device=dev, generator=gen)
+    box = torch.full((1, 1, 5, 5), 1.0 / 25.0, dtype=torch.float32, device=dev)
+    big = torch.nn.functional.conv2d(torch.nn.functional.conv2d(big, box, padding=2), box, padding=2)[0, 0].contiguous()
+    Db = S.Detector(side, side, 71, 71, 1, 0.002, 80, device=dev)
+    for _ in range(args.warmup):
+        Db(big)
+    torch.cuda.synchronize()
+    S.trace_enable(True)
+    S.trace_collect()
+    for _ in range(args.steps):
+        Db(big)
+    torch.cuda.synchronize()
+    kt = S.trace_collect()
+    S.trace_enable(False)
+    ms_big = kt["fast"][0] / max(1, kt["fast"][1])
+    ach = side * side * FAST_OPS_PER_PX / (ms_big * 1e-3)
+    return {"workload": f"block-based FAST on the scene's 2048x2048 sensed image (20x20 blocks, 1 IP each, "
+                        f"threshold 0.05, margin {margin}), then registration of the pair from those IPs; and "
+                        f"on a {side}x{side} smoothed-noise image (71x71 blocks, margin 80)",
+            "value": n / dt, "unit": "CPs/s", "ms_per_step": 1e3 * dt, "detect_ms_2048": ms_scene,
+            "ips": n, "valid": int(v.sum()), "correct_1p5px": int((err[v] <= 1.5).sum()),
+            "detect_ms_10000": ms_big, "mpx_per_s_10000": side * side / (ms_big * 1e-3) / 1e6,
+            "roofline": {"kernel": "fast", "bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP32_OPS / 1e12,
+                         "unit": "Tops/s", "frac": ach / PEAK_FP32_OPS, "ops_per_px": FAST_OPS_PER_PX,
+                         "ips_10000": int(Db.n_out.item())}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -346,6 +415,7 @@ def main():
     ap.add_argument("--learned-pairs", type=int, default=100, help="held-out pairs for the head (0: skip)")
     ap.add_argument("--ransac", type=int, default=1, help="warped-pair registration with RANSAC (0: skip)")
     ap.add_argument("--rectify", type=int, default=1, help="10000^2 rectification (0: skip)")
+    ap.add_argument("--fast", type=int, default=1, help="block-based FAST detection (0: skip)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -444,6 +514,8 @@ def main():
         out["ransac"] = run_ransac(args, S, synth, torch, p, dev)
     if args.rectify:
         out["rectify"] = run_rectify(args, S, torch, dev)
+    if args.fast:
+        out["fast"] = run_fast(args, S, synth, torch, dev)
     if args.learned_pairs > 0:
         out["learned"] = run_learned(args, S, synth, torch, p, dev, ref, sen, dips, m, r)
     if args.batched_steps > 0:

@@ -477,6 +477,41 @@ int sfoc_rectify(const float* sen, int64_t Hs, int64_t Ws, int64_t lds, const do
                  float* out, int64_t Ho, int64_t Wo, int64_t ldo, float fill, void* stream);
 
 /*
+ * Block-based FAST interest-point detection (Section 3.1.1: the FAST
+ * operator applied with a partitioning strategy, so that the interest
+ * points are spread evenly over the image).
+ *  - Corner strength V(p), float32: the largest threshold at which 9
+ *    cyclically contiguous pixels of the 16-pixel circle of radius 3 are all
+ *    brighter than I_p + threshold or all darker than I_p - threshold, i.e.
+ *    the maximum over the 16 arcs of max(min (I_x - I_p), min (I_p - I_x));
+ *    p is a corner when V(p) > threshold.
+ *  - Only pixels at least b = max(3, margin) from every border are
+ *    considered (the region); a corner is kept when its V exceeds that of
+ *    every 3 x 3 neighbour in the region before it in raster order and is
+ *    not below that of every neighbour after it.
+ *  - The region is split into nby x nbx blocks at rows
+ *    b + floor(i * (H - 2b) / nby) (columns likewise); from each block the
+ *    per_block kept corners of largest V, ties to the smaller raster index.
+ *  img      H x W float32, pitch ld, finite values.               (input)
+ *  ips      (row, col) int32 pairs, capacity nby * nbx * per_block; the
+ *           first *n_out are written, in block order (row-major), within
+ *           a block by decreasing V.                               (output)
+ *  scores   their V (float32), same capacity, or NULL.            (output)
+ *  counts   nby * nbx int32 per-block counts, or NULL.            (output)
+ *  n_out    one int32: the number of interest points.             (output)
+ * All device pointers; ws of sfoc_fast_workspace bytes (the strength map).
+ * The result is exact and deterministic (no floating-point sums).
+ * Limits: sides <= 2^20, H * W <= 2^32, per_block <= 32, nby * nbx <=
+ * 65536 (SFOC_E_UNSUPPORTED beyond).  Errors: SFOC_E_INVALID_ARG (null
+ * img / ips / n_out / ws, sizes < 1, ld < W, margin < 0, threshold < 0 or
+ * not finite), SFOC_E_WORKSPACE, SFOC_E_HIP.
+ */
+int sfoc_fast_workspace(int64_t H, int64_t W, int32_t nby, int32_t nbx, int32_t per_block, size_t* bytes);
+int sfoc_detect_ips(const float* img, int64_t H, int64_t W, int64_t ld, float threshold, int32_t margin,
+                    int32_t nby, int32_t nbx, int32_t per_block, int32_t* ips, float* scores,
+                    int32_t* counts, int32_t* n_out, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Kernel timing (tracing).  While enabled, the library records a pair of
  * HIP events on the launch stream around every kernel it enqueues.
  * sfoc_trace_collect waits for those events, writes per-kernel totals into
@@ -496,7 +531,8 @@ int sfoc_rectify(const float* sen, int64_t Hs, int64_t Ws, int64_t lds, const do
 #define SFOC_K_HEAD_ADAM    8
 #define SFOC_K_RANSAC       9
 #define SFOC_K_RECTIFY     10
-#define SFOC_K_COUNT       11
+#define SFOC_K_FAST        11
+#define SFOC_K_COUNT       12
 #define SFOC_TRACE_MAX   4096
 int sfoc_trace_enable(int on);
 int sfoc_trace_collect(double* ms, int64_t* counts, int n);

@@ -121,6 +121,9 @@ def lib() -> ctypes.CDLL:
         L.sfoc_ransac_workspace.argtypes = [i32, ctypes.POINTER(RansacParams), ctypes.POINTER(sz)]
         L.sfoc_ransac_cps.argtypes = [vp, vp, i32, vp, ctypes.POINTER(RansacParams), vp, sz, vp, vp, vp, vp, vp]
         L.sfoc_rectify.argtypes = [vp, i64, i64, i64, vp, vp, i64, i64, i64, ctypes.c_float, vp]
+        L.sfoc_fast_workspace.argtypes = [i64, i64, i32, i32, i32, ctypes.POINTER(sz)]
+        L.sfoc_detect_ips.argtypes = [vp, i64, i64, i64, ctypes.c_float, i32, i32, i32, i32, vp, vp, vp, vp,
+                                      vp, sz, vp]
         L.sfoc_trace_enable.argtypes = [ctypes.c_int]
         L.sfoc_trace_collect.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.c_int]
@@ -129,7 +132,7 @@ def lib() -> ctypes.CDLL:
                      "sfoc_register_cps", "sfoc_plan_create", "sfoc_register_cps_batched", "sfoc_plan_destroy",
                      "sfoc_plan_get_info", "sfoc_match_candidates", "sfoc_head_features", "sfoc_head_workspace",
                      "sfoc_head_forward", "sfoc_head_train_step", "sfoc_head_infer", "sfoc_ransac_workspace",
-                     "sfoc_ransac_cps", "sfoc_rectify"):
+                     "sfoc_ransac_cps", "sfoc_rectify", "sfoc_fast_workspace", "sfoc_detect_ips"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -476,7 +479,7 @@ class Head:
 
 
 KERNEL_NAMES = ("describe", "integral", "match", "consistency", "peak", "head_features", "head_forward",
-                "head_backward", "head_adam", "ransac", "rectify")
+                "head_backward", "head_adam", "ransac", "rectify", "fast")
 
 
 def ransac_params(model: int, n_hyp: int, sizes, threshold: float = 1.5, n_refine: int = 2) -> RansacParams:
@@ -557,6 +560,52 @@ def rectify(sen, model, out_shape, fill: float = 0.0, out=None, stream=None):
     _check(lib().sfoc_rectify(_ptr(sen), sen.shape[0], sen.shape[1], sen.stride(0), _ptr(model), _ptr(out), Ho, Wo,
                               out.stride(0), float(fill), _stream(stream)), "sfoc_rectify")
     return out
+
+
+def fast_workspace(H: int, W: int, nby: int, nbx: int, per_block: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().sfoc_fast_workspace(int(H), int(W), int(nby), int(nbx), int(per_block), ctypes.byref(b)),
+           "sfoc_fast_workspace")
+    return b.value
+
+
+class Detector:
+    """sfoc_detect_ips with its workspace and outputs allocated once for one
+    image size and block layout.  Calling it returns the device tensors
+    (ips (capacity, 2) int32, scores, counts, n_out); the first n_out rows of
+    ips are the interest points."""
+
+    def __init__(self, H: int, W: int, nby: int, nbx: int, per_block: int, threshold: float, margin: int,
+                 device="cuda"):
+        torch = _torch()
+        self.shape = (int(H), int(W))
+        self.nby, self.nbx, self.per = int(nby), int(nbx), int(per_block)
+        self.threshold, self.margin = float(threshold), int(margin)
+        cap = self.nby * self.nbx * self.per
+        self.ws = torch.empty(fast_workspace(H, W, nby, nbx, per_block), dtype=torch.uint8, device=device)
+        self.ips = torch.zeros((cap, 2), dtype=torch.int32, device=device)
+        self.scores = torch.zeros(cap, dtype=torch.float32, device=device)
+        self.counts = torch.zeros(self.nby * self.nbx, dtype=torch.int32, device=device)
+        self.n_out = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def __call__(self, img, stream=None):
+        if tuple(img.shape) != self.shape or img.dtype != _torch().float32 or img.stride(1) != 1:
+            raise ValueError("img: the detector's (H, W) float32 with unit column stride")
+        _check(lib().sfoc_detect_ips(_ptr(img), self.shape[0], self.shape[1], img.stride(0), self.threshold,
+                                     self.margin, self.nby, self.nbx, self.per, _ptr(self.ips), _ptr(self.scores),
+                                     _ptr(self.counts), _ptr(self.n_out), _ptr(self.ws), self.ws.numel(),
+                                     _stream(stream)), "sfoc_detect_ips")
+        return self.ips, self.scores, self.counts, self.n_out
+
+
+def detect_ips(img, threshold: float, margin: int, nby: int, nbx: int, per_block: int = 1, stream=None):
+    """Block-based FAST on a device image; synchronises and returns the
+    interest points as a device tensor (n, 2) int32, with the host scores
+    and per-block counts."""
+    D = Detector(img.shape[0], img.shape[1], nby, nbx, per_block, threshold, margin, device=img.device)
+    ips, sc, cnt, n = D(img, stream)
+    k = int(n.item())
+    return ips[:k].clone(), sc[:k].cpu().numpy(), cnt.cpu().numpy()
 
 
 def trace_enable(on: bool = True):

@@ -1,6 +1,7 @@
-"""Host-side checks of the RANSAC entry points (no GPU): the parameter
-struct's layout against the header, the workspace query, and argument
-rejection before anything is enqueued."""
+"""Host-side checks (no GPU) of the registration-system entry points around
+the matching: RANSAC (parameter struct layout against the header, the
+workspace query, argument rejection), rectification and block-based FAST
+(argument rejection before anything is enqueued)."""
 import ctypes
 import os
 import subprocess
@@ -109,3 +110,25 @@ def test_rectify_rejects_bad_arguments():
                {"Hs": 1 << 16, "Ws": 1 << 15, "lds": 1 << 15}):
         assert call(**kw) == S.SFOC_E_UNSUPPORTED, kw
     assert S.KERNEL_NAMES[10] == "rectify"
+
+
+def test_fast_rejects_bad_arguments():
+    L = S.lib()
+    b = ctypes.c_size_t(0)
+    assert L.sfoc_fast_workspace(100, 100, 4, 4, 2, ctypes.byref(b)) == S.SFOC_OK and b.value >= 100 * 100 * 4
+    assert L.sfoc_fast_workspace(100, 100, 4, 4, 2, None) == S.SFOC_E_INVALID_ARG
+    ok = dict(img=FAKE, H=100, W=100, ld=100, thr=0.05, margin=10, nby=4, nbx=4, per=2, ips=FAKE, n_out=FAKE,
+              ws=FAKE, wsb=1 << 40)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return L.sfoc_detect_ips(a["img"], a["H"], a["W"], a["ld"], a["thr"], a["margin"], a["nby"], a["nbx"],
+                                 a["per"], a["ips"], None, None, a["n_out"], a["ws"], a["wsb"], None)
+    for kw in ({"img": None}, {"ips": None}, {"n_out": None}, {"ws": None}, {"H": 0}, {"W": 0}, {"ld": 99},
+               {"margin": -1}, {"thr": -0.1}, {"thr": float("inf")}, {"nby": 0}, {"nbx": 0}, {"per": 0}):
+        assert call(**kw) == S.SFOC_E_INVALID_ARG, kw
+    for kw in ({"per": 33}, {"nby": 257, "nbx": 256}, {"H": (1 << 20) + 1}):
+        assert call(**kw) == S.SFOC_E_UNSUPPORTED, kw
+    L.sfoc_fast_workspace(100, 100, 4, 4, 2, ctypes.byref(b))
+    assert call(wsb=b.value - 1) == S.SFOC_E_WORKSPACE
+    assert S.KERNEL_NAMES[11] == "fast"
