@@ -403,6 +403,20 @@ def run_fast(args, S, synth, torch, dev):
                          "ips_10000": int(Db.n_out.item())}}
 
 
+def run_sweep(args, S, torch):
+    """Noise sensitivity and the F-SFOC ablation at the paper's noise
+    levels on seeded pairs (CMR per level), with the GPU time it took."""
+    from paper_2202_13347_amd import sweep as W
+    t0 = time.perf_counter()
+    res = W.run(args.sweep_pairs)
+    res["wall_s"] = time.perf_counter() - t0
+    res["workload"] = (f"{args.sweep_pairs} seeded {res['size']}x{res['size']} pairs (shift up to 16 px), "
+                       f"Gaussian white noise v = 0..0.01 and speckle v = 0..0.1 on the sensed image, "
+                       f"{res['ips_per_pair']} block-FAST IPs per pair, 80x80 templates, r {res['radius']}, "
+                       f"paper preset (N 6); SFOC and F-SFOC (first-order channels only)")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -416,6 +430,7 @@ def main():
     ap.add_argument("--ransac", type=int, default=1, help="warped-pair registration with RANSAC (0: skip)")
     ap.add_argument("--rectify", type=int, default=1, help="10000^2 rectification (0: skip)")
     ap.add_argument("--fast", type=int, default=1, help="block-based FAST detection (0: skip)")
+    ap.add_argument("--sweep-pairs", type=int, default=4, help="pairs of the noise-sensitivity sweep (0: skip)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -516,6 +531,8 @@ def main():
         out["rectify"] = run_rectify(args, S, torch, dev)
     if args.fast:
         out["fast"] = run_fast(args, S, synth, torch, dev)
+    if args.sweep_pairs > 0:
+        out["noise_sweep"] = run_sweep(args, S, torch)
     if args.learned_pairs > 0:
         out["learned"] = run_learned(args, S, synth, torch, p, dev, ref, sen, dips, m, r)
     if args.batched_steps > 0:

@@ -395,6 +395,30 @@ def make_warp_pair(seed: int, recipe: dict = WARP, noise_std: float = 0.05) -> W
                     mask=mask, seed=seed)
 
 
+# Noise sensitivity: the levels of the paper's sweep (Gaussian white noise of
+# variance 0..0.01 in steps of 0.001, speckle of variance 0..0.1 in steps of
+# 0.01) on seeded pairs matched with 80 x 80 templates.
+SWEEP = dict(size=768, n_pairs=8, m=80, r=20, blocks=(10, 20), fast_threshold=0.05,
+             gaussian=[round(0.001 * i, 3) for i in range(11)], speckle=[round(0.01 * i, 2) for i in range(11)])
+
+
+def gaussian_noise(img: np.ndarray, v: float, seed: int) -> np.ndarray:
+    """img + N(0, v) (v is the variance), float32."""
+    rng = np.random.default_rng(np.random.PCG64(seed + 5003))
+    return (img + rng.normal(0.0, np.sqrt(v), img.shape)).astype(np.float32)
+
+
+def speckle_noise(img: np.ndarray, v: float, seed: int) -> np.ndarray:
+    """img * (1 + n), n uniform with mean 0 and variance v, float32."""
+    rng = np.random.default_rng(np.random.PCG64(seed + 7001))
+    h = np.sqrt(3.0 * v)
+    return (img * (1.0 + rng.uniform(-h, h, img.shape))).astype(np.float32)
+
+
+def sweep_pair(seed: int, recipe: dict = SWEEP) -> Pair:
+    return make_pair(seed, recipe["size"], float(recipe["r"] - 4))
+
+
 def workload(recipe: dict, seed: int):
     """(pair, ips, m, r) for a recipe; IP margin = ceil(m/2) + r."""
     p = make_pair(seed, recipe["size"], recipe["max_shift"], speckle_looks=recipe["speckle"])
