@@ -155,25 +155,33 @@ SFOC_DEV void dftn(float2 (&x)[N]) {
 // ---- geometry ----------------------------------------------------------
 template <int L>
 struct Fft;
+// LDS layout of the transform buffer: row r starts at r * PITCH + (r / 8) *
+// SKEW complex values.  The column passes read rows n1 + 8 k (k across the
+// lanes of a wave, or across the loop), whose starts would otherwise fall on
+// the same LDS banks; the pitch and the per-8-rows skew spread both kinds of
+// access over all banks, and keep each row (and each row pair) contiguous.
 template <>
 struct Fft<128> {
-    static constexpr int NA = 16, NB = 8, NT = 256, PITCH = 68;
+    static constexpr int NA = 16, NB = 8, NT = 256, PITCH = 68, SKEW = 8;
 };
 template <>
 struct Fft<64> {
-    static constexpr int NA = 8, NB = 8, NT = 128, PITCH = 36;
+    static constexpr int NA = 8, NB = 8, NT = 128, PITCH = 40, SKEW = 8;
 };
 
 template <int L>
 struct MatchCfg {
     using F = Fft<L>;
-    static constexpr int NA = F::NA, NB = F::NB, NT = F::NT, P = F::PITCH;
+    static constexpr int NA = F::NA, NB = F::NB, NT = F::NT, P = F::PITCH, SKEW = F::SKEW;
     static constexpr int HA = NA / 2;
     static constexpr int COLS = L / 2;                     // column transforms (DC+Nyquist packed)
     static constexpr int RB = COLS * HA / NT;              // pass-B tasks per thread
     static constexpr int BINS = 2 * NB;                    // bins per pass-B task
     static_assert(COLS * HA % NT == 0 && COLS * NB % NT == 0, "balanced column passes");
-    static constexpr size_t buf_elems = (size_t)L * P;     // complex
+    static constexpr size_t buf_elems = (size_t)L * P + (size_t)(L / 8) * SKEW;   // complex
+    static SFOC_DEV int row(int r) { return r * P + (r >> 3) * SKEW; }
+    // row n1 + NB * k with n1 < NB (= 8): its 8-row group is k
+    static SFOC_DEV int rowg(int n1, int k) { return n1 * P + k * (NB * P + SKEW); }
     static constexpr size_t lds_bytes = sizeof(float2) * (buf_elems + L) + 1024;
 };
 
@@ -267,7 +275,7 @@ SFOC_DEV void row_stage(const void* plane, int pitch, int y0, int x0, int nrows,
             *s2 += q;
         }
         dftn<C::NA, false>(x);
-        float2* reg = buf + 2 * p * C::P;
+        float2* reg = buf + C::row(2 * p);
 #pragma unroll
         for (int k2 = 0; k2 < C::NA; ++k2)
             reg[k2 * C::NB + (n1 ^ (k2 & (C::NB - 1)))] = k2 == 0 ? x[0] : cmul(x[k2], tw[n1 * k2]);
@@ -300,7 +308,7 @@ SFOC_DEV void row_stage(const void* plane, int pitch, int y0, int x0, int nrows,
         const bool act = task < tasksB;
         const int p = task / C::HA, j = task - p * C::HA;
         float2 u[C::NB], v[C::NB];
-        float2* reg = buf + 2 * p * C::P;
+        float2* reg = buf + C::row(2 * p);
         if (act) {
             const int ka = j, kb = j == 0 ? C::HA : C::NA - j;
 #pragma unroll
@@ -314,7 +322,7 @@ SFOC_DEV void row_stage(const void* plane, int pitch, int y0, int x0, int nrows,
         wave_sync();   // this pair's reads before its in-place writes
         if (act) {
             // half spectra of the two real rows: A = (X + conj X~)/2, B = -i (X - conj X~)/2
-            float2* ra = buf + (2 * p) * C::P;
+            float2* ra = buf + C::row(2 * p);
             float2* rb = ra + C::P;
             const int ka = j, kb = j == 0 ? C::HA : C::NA - j;
 #pragma unroll
@@ -358,8 +366,8 @@ SFOC_DEV void col_stage(float2* buf, const float2* tw, int nvalid, Sink&& sink) 
             const int row = n1 + C::NB * n2;
             float2 v = make_float2(0.f, 0.f);
             if (row < nvalid) {
-                if (cc == 0 && !INV) v = make_float2(buf[row * C::P].x, buf[row * C::P + L / 2].x);
-                else v = buf[row * C::P + cc];
+                if (cc == 0 && !INV) v = make_float2(buf[C::rowg(n1, n2)].x, buf[C::rowg(n1, n2) + L / 2].x);
+                else v = buf[C::rowg(n1, n2) + cc];
             }
             x[n2] = v;
         }
@@ -371,7 +379,7 @@ SFOC_DEV void col_stage(float2* buf, const float2* tw, int nvalid, Sink&& sink) 
         for (int k2 = 0; k2 < C::NA; ++k2) {
             float2 w = tw[n1 * k2];
             if (INV) w.y = -w.y;
-            buf[(n1 + C::NB * k2) * C::P + cc] = k2 == 0 ? x[0] : cmul(x[k2], w);
+            buf[C::rowg(n1, k2) + cc] = k2 == 0 ? x[0] : cmul(x[k2], w);
         }
     };
     if (PIPE) {   // two tasks per iteration, both tasks' reads first
@@ -401,8 +409,8 @@ SFOC_DEV void col_stage(float2* buf, const float2* tw, int nvalid, Sink&& sink) 
         float2 u[C::NB], v[C::NB];
 #pragma unroll
         for (int n1 = 0; n1 < C::NB; ++n1) {
-            u[n1] = buf[(n1 + C::NB * ka) * C::P + cc];
-            v[n1] = buf[(n1 + C::NB * kb) * C::P + cc];
+            u[n1] = buf[C::rowg(n1, ka) + cc];
+            v[n1] = buf[C::rowg(n1, kb) + cc];
         }
         dftn<C::NB, INV>(u);
         dftn<C::NB, INV>(v);
@@ -564,7 +572,7 @@ SFOC_DEV void match_item(const MatchArgs& A, int i, int bq, int slot, const floa
             }
         }
 #pragma unroll
-        for (int q = 0; q < C::BINS; ++q) buf[bin_of<L>(j, q) * C::P + cc] = acc[rd][q];
+        for (int q = 0; q < C::BINS; ++q) buf[C::row(bin_of<L>(j, q)) + cc] = acc[rd][q];
     }
     __syncthreads();
     {
@@ -584,7 +592,7 @@ SFOC_DEV void match_item(const MatchArgs& A, int i, int bq, int slot, const floa
 #pragma unroll
             for (int q = 0; q < C::BINS; ++q) {
                 const int u = bin_of<L>(j, q);
-                if (u < Vu) buf[u * C::P + cc] = zc[rd][q];
+                if (u < Vu) buf[C::row(u) + cc] = zc[rd][q];
             }
         }
     }
@@ -601,7 +609,7 @@ SFOC_DEV void match_item(const MatchArgs& A, int i, int bq, int slot, const floa
             const int p = task / C::NB, n1 = task - p * C::NB;
             float2 x[C::NA];
             if (act) {
-                const float2* ra = buf + (2 * p) * C::P;
+                const float2* ra = buf + C::row(2 * p);
                 const float2* rb = ra + C::P;
 #pragma unroll
                 for (int n2 = 0; n2 < C::NA; ++n2) {
@@ -626,7 +634,7 @@ SFOC_DEV void match_item(const MatchArgs& A, int i, int bq, int slot, const floa
             }
             wave_sync();   // this pair's reads before its in-place writes
             if (act) {
-                float2* reg = buf + 2 * p * C::P;
+                float2* reg = buf + C::row(2 * p);
 #pragma unroll
                 for (int k2 = 0; k2 < C::NA; ++k2)
                     reg[k2 * C::NB + (n1 ^ (k2 & (C::NB - 1)))] = k2 == 0 ? x[0] : cmul(x[k2], cconj(tw[n1 * k2]));
@@ -641,7 +649,7 @@ SFOC_DEV void match_item(const MatchArgs& A, int i, int bq, int slot, const floa
             const bool act = task < tasksB;
             const int p = task / C::HA, j = task - p * C::HA;
             float2 u[C::NB], v[C::NB];
-            float2* reg = buf + 2 * p * C::P;
+            float2* reg = buf + C::row(2 * p);
             const int ka = j, kb = j == 0 ? C::HA : C::NA - j;
             if (act) {
 #pragma unroll
@@ -675,7 +683,7 @@ SFOC_DEV void match_item(const MatchArgs& A, int i, int bq, int slot, const floa
     // NCC at offset (u, v); flags: bit 0 non-flat search window, bit 1 non-finite.
     // (u, v) are offsets within this block; the surface offset is (u0 + u, v0 + v).
     auto ncc_at = [&](int u, int v, int& fl) -> float {
-        const float* rr = reinterpret_cast<const float*>(buf + (u >> 1) * 2 * C::P);
+        const float* rr = reinterpret_cast<const float*>(buf + C::row((u >> 1) * 2));
         const float rst = rr[(u & 1) * L + v];
         const int64_t y = sy + u0 + u, x = sx + v0 + v;
         const int64_t a00 = y * IW + x, a01 = a00 + m, a10 = a00 + (int64_t)m * IW, a11 = a10 + m;
