@@ -22,12 +22,16 @@ VALID, OOB, FLAT_T, FLAT_S, EDGE_PEAK, INCONSISTENT, LEARNED, NONFINITE = 1, 2, 
 
 
 class SfocError(RuntimeError):
+    """A library call returned a status other than SFOC_OK."""
+
     def __init__(self, status: int, what: str):
         super().__init__(f"{what}: {status_string(status)} ({status})")
         self.status = status
 
 
 class Params(ctypes.Structure):
+    """sfoc_params: the SFOC filter bank (Section 3.1.2) and descriptor
+    options, field for field as include/sfoc.h lays it out."""
     _fields_ = [("n_orient", ctypes.c_int32), ("n_s1", ctypes.c_int32), ("s1", ctypes.c_double * 8),
                 ("n_s2", ctypes.c_int32), ("n_dil", ctypes.c_int32), ("s2", ctypes.c_double * 8),
                 ("trunc", ctypes.c_double), ("sd1", ctypes.c_double), ("sd2", ctypes.c_double),
@@ -60,6 +64,8 @@ class Pair(ctypes.Structure):
 
 
 class PlanInfo(ctypes.Structure):
+    """sfoc_plan_info: what a batched plan decided (work items, tuned and
+    cached shape classes, graph and persistent launches, device bytes)."""
     _fields_ = [("n_pairs", ctypes.c_int32), ("describe_tiles", ctypes.c_int32),
                 ("match_items", ctypes.c_int32 * 2), ("peak_items", ctypes.c_int32),
                 ("tuned_classes", ctypes.c_int32), ("cached_classes", ctypes.c_int32), ("graph", ctypes.c_int32),
@@ -70,6 +76,8 @@ PLAN_GRAPH, PLAN_AUTOTUNE, PLAN_DENSE_SEN, PLAN_PERSISTENT = 1, 2, 4, 8
 
 
 class RansacParams(ctypes.Structure):
+    """sfoc_ransac_params: model kind, hypotheses, refinement passes, inlier
+    threshold in pixels and the two image sizes (Section 3.2.3)."""
     _fields_ = [("model", ctypes.c_int32), ("n_hyp", ctypes.c_int32), ("n_refine", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("threshold", ctypes.c_double), ("Hs", ctypes.c_int32),
                 ("Ws", ctypes.c_int32), ("Hr", ctypes.c_int32), ("Wr", ctypes.c_int32)]
@@ -82,6 +90,8 @@ _lib = None
 
 
 def lib() -> ctypes.CDLL:
+    """The loaded C-ABI library with its argument types set (loaded once;
+    raises if it has not been built)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
@@ -146,6 +156,7 @@ def header_functions() -> list[str]:
 
 
 def status_string(s: int) -> str:
+    """Text of a library status code."""
     return lib().sfoc_status_string(int(s)).decode()
 
 
@@ -165,6 +176,9 @@ def preset(which: str | int = "baseline", dtype: int = DTYPE_F32) -> Params:
 
 def params(n_orient=8, s1=(1.0, 2.0, 3.0), s2=(1.0, 2.0, 3.0), trunc=3.0, sd1=1.0, sd2=1.5, K=1,
            dil=(1, 2, 3), eps=1e-8, rectify=0, second_order=True, dtype=DTYPE_F32) -> Params:
+    """A Params from explicit values: orientations, first- and second-order
+    scales, truncation, the two smoothing deviations, K, dilations, the
+    rectification mode (abs / signed / relu) and the descriptor dtype."""
     p = Params()
     p.n_orient = n_orient
     p.n_s1 = len(s1)
@@ -184,6 +198,7 @@ def params(n_orient=8, s1=(1.0, 2.0, 3.0), s2=(1.0, 2.0, 3.0), trunc=3.0, sd1=1.
 
 
 def check_params(p: Params) -> int:
+    """Validates p in the library and returns its descriptor depth z."""
     z = ctypes.c_int32(0)
     _check(lib().sfoc_params_check(ctypes.byref(p), ctypes.byref(z)), "sfoc_params_check")
     return z.value
@@ -211,6 +226,7 @@ def _desc_torch_dtype(dt: int):
 
 
 def describe_workspace(H: int, W: int, p: Params) -> int:
+    """Bytes of scratch sfoc_describe needs for an (H, W) image."""
     b = ctypes.c_size_t(0)
     _check(lib().sfoc_describe_workspace(H, W, ctypes.byref(p), ctypes.byref(b)), "sfoc_describe_workspace")
     return b.value
@@ -261,6 +277,7 @@ def fastncc_match(desc_sen, desc_ref, integ1, integ2, ips, m: int, r: int, prior
 
 
 def register_workspace(Hr, Wr, Hs, Ws, n, m, r, p: Params) -> int:
+    """Bytes of scratch sfoc_register_cps needs for these sizes."""
     b = ctypes.c_size_t(0)
     _check(lib().sfoc_register_workspace(Hr, Wr, Hs, Ws, n, m, r, ctypes.byref(p), ctypes.byref(b)),
            "sfoc_register_workspace")
@@ -292,6 +309,9 @@ class Registrar:
 
 
 def register_cps(ref, sen, ips, m: int, r: int, p: Params, prior=None, want_ncc=False, stream=None):
+    """One-shot describe + Fast-NCC matching of a pair (allocates its own
+    workspace; Registrar reuses one).  Returns the CPs, and the NCC
+    surfaces when want_ncc."""
     R = Registrar(ref.shape[0], ref.shape[1], sen.shape[0], sen.shape[1], ips.shape[0], m, r, p,
                   device=ref.device, want_ncc=want_ncc)
     cps = R(ref, sen, ips, prior, stream)
@@ -414,6 +434,8 @@ def head_features(desc_sen, desc_ref, integ1, integ2, ips, m: int, r: int, ncc, 
 
 
 def head_workspace(n: int, train: bool) -> int:
+    """Bytes of scratch the learned head needs for n CPs (more when
+    training, for the saved activations)."""
     b = ctypes.c_size_t(0)
     _check(lib().sfoc_head_workspace(n, int(train), ctypes.byref(b)), "sfoc_head_workspace")
     return b.value
@@ -489,6 +511,7 @@ def ransac_params(model: int, n_hyp: int, sizes, threshold: float = 1.5, n_refin
 
 
 def ransac_workspace(n: int, rp: RansacParams) -> int:
+    """Bytes of scratch sfoc_ransac_cps needs for n CPs."""
     b = ctypes.c_size_t(0)
     _check(lib().sfoc_ransac_workspace(int(n), ctypes.byref(rp), ctypes.byref(b)), "sfoc_ransac_workspace")
     return b.value
@@ -563,6 +586,7 @@ def rectify(sen, model, out_shape, fill: float = 0.0, out=None, stream=None):
 
 
 def fast_workspace(H: int, W: int, nby: int, nbx: int, per_block: int) -> int:
+    """Bytes of scratch sfoc_detect_ips needs for this image and block layout."""
     b = ctypes.c_size_t(0)
     _check(lib().sfoc_fast_workspace(int(H), int(W), int(nby), int(nbx), int(per_block), ctypes.byref(b)),
            "sfoc_fast_workspace")
@@ -609,6 +633,7 @@ def detect_ips(img, threshold: float, margin: int, nby: int, nbx: int, per_block
 
 
 def trace_enable(on: bool = True):
+    """Switches the per-kernel event timing of the library on or off."""
     _check(lib().sfoc_trace_enable(int(on)), "sfoc_trace_enable")
 
 
