@@ -58,39 +58,45 @@ static DescribeGeom describe_geom(const DescribeConsts& c, int CG) {
 }
 
 // Dilated Gaussian smoothing of one channel for a horizontal run of kRun
-// outputs, base 3x3 (K = 1) at rates 1, 2, 3: neighbours shared by the run
-// are read once.  ch points at the run's first output in a map of pitch P.
-SFOC_DEV void smooth_run_k1_123(const float* ch, int P, float wc, float we, float wk, float out[kRun]) {
-    float v[kRun + 6];
+// outputs, base 3x3 (K = 1) at rates 1, 2, 3.  With weights wc (centre), we
+// (edge) and wk (corner) shared by the three rates,
+//   out = 3 wc I(p) + we sum_r E_r(p) + wk sum_r C_r(p),
+// where E_r / C_r sum the 4 edge / 4 corner neighbours at distance r.  Per
+// rate, the vertical pair sums S_r(x) = I(y - r, x) + I(y + r, x) over the
+// run's columns widened by r give both: E_r = S_r(x) + I(y, x - r) +
+// I(y, x + r) and C_r = S_r(x - r) + S_r(x + r).
+// The run's first output is element i0 of map s (pitch P).  Reads are
+// addressed from the neighbourhood's top-left element, whose index is kept
+// opaque to the compiler: the address then stays in one register and each
+// read's constant offset (at most 6 P + kRun + 5 elements) fits the LDS
+// instruction's offset field instead of costing an address add.
+SFOC_DEV void smooth_run_k1_123(const float* s, int i0, int P, float wc, float we, float wk, float out[kRun]) {
+    int b = i0 - 3 * P - 3;
+    asm volatile("" : "+v"(b));
+    const float* n = s + b;
+    float c[kRun + 6];
 #pragma unroll
-    for (int q = 0; q < kRun + 6; ++q) v[q] = ch[q - 3];
+    for (int q = 0; q < kRun + 6; ++q) c[q] = n[3 * P + q];
     float e[kRun], k[kRun];
 #pragma unroll
-    for (int j = 0; j < kRun; ++j) {
-        out[j] = 3.f * wc * v[j + 3];
-        e[j] = (v[j + 2] + v[j + 4]) + (v[j + 1] + v[j + 5]) + (v[j] + v[j + 6]);
-        k[j] = 0.f;
-    }
-#pragma unroll
     for (int r = 1; r <= 3; ++r) {
+        // one rate's reads in flight at a time keeps registers for the
+        // 4 x z accumulators the caller holds
+        __builtin_amdgcn_sched_barrier(0);
+        float S[kRun + 6];
 #pragma unroll
-        for (int sgn = -1; sgn <= 1; sgn += 2) {
-            // one tap row's reads in flight at a time keeps registers for the
-            // 4 x z accumulators the caller holds
-            __builtin_amdgcn_sched_barrier(0);
-            const float* row = ch + sgn * r * P;
-            float u[kRun + 6];
+        for (int q = 0; q < kRun + 2 * r; ++q) S[q] = n[(3 - r) * P + 3 - r + q] + n[(3 + r) * P + 3 - r + q];
 #pragma unroll
-            for (int q = 0; q < kRun + 2 * r; ++q) u[q] = row[q - r];
-#pragma unroll
-            for (int j = 0; j < kRun; ++j) {
-                e[j] += u[j + r];
-                k[j] += u[j] + u[j + 2 * r];
-            }
+        for (int j = 0; j < kRun; ++j) {
+            const float ej = S[j + r] + (c[j + 3 - r] + c[j + 3 + r]);
+            const float kj = S[j] + S[j + 2 * r];
+            e[j] = r == 1 ? ej : e[j] + ej;
+            k[j] = r == 1 ? kj : k[j] + kj;
         }
     }
+    const float wc3 = 3.f * wc;
 #pragma unroll
-    for (int j = 0; j < kRun; ++j) out[j] = fmaf(we, e[j], fmaf(wk, k[j], out[j]));
+    for (int j = 0; j < kRun; ++j) out[j] = fmaf(we, e[j], fmaf(wk, k[j], wc3 * c[j + 3]));
 }
 
 // Row pass for a horizontal run of kRun outputs with radius RHO: g, d, dd
@@ -122,13 +128,19 @@ SFOC_DEV void row_run(const float* p, const float* tg, const float* td, const fl
     }
 }
 
-// Even (te) and odd (to) column taps on one map for a vertical run; p points
-// at the first output's centre, pitch P.
+// Even (te) and odd (to) column taps on one map for a vertical run; the
+// first output's centre is element i0 of map s (pitch P).  The top element's
+// index is kept opaque to the compiler, so the reads share one base register
+// and fold their row offsets into the LDS instructions where those fit.
 template <int RHO>
-SFOC_DEV void col_run(const float* p, int P, const float* te, const float* to, float ev[kRun], float od[kRun]) {
+SFOC_DEV void col_run(const float* s, int i0, int P, const float* te, const float* to, float ev[kRun],
+                      float od[kRun]) {
+    int b = i0 - RHO * P;
+    asm volatile("" : "+v"(b));
+    const float* n = s + b;
     float x[2 * RHO + kRun];
 #pragma unroll
-    for (int q = 0; q < 2 * RHO + kRun; ++q) x[q] = p[(q - RHO) * P];
+    for (int q = 0; q < 2 * RHO + kRun; ++q) x[q] = n[q * P];
 #pragma unroll
     for (int j = 0; j < kRun; ++j) {
         const float c = x[j + RHO];
@@ -294,9 +306,9 @@ __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const De
             float* w = srow + a * BPP + b0;
 #pragma unroll
             for (int j = 0; j < kRun; ++j) {
-                w[j] = cn * og[j];
-                w[rows * BPP + j] = cn * od[j];
-                w[2 * rows * BPP + j] = cn * odd[j];
+                w[j] = og[j];
+                w[rows * BPP + j] = od[j];
+                w[2 * rows * BPP + j] = odd[j];
             }
         }
         __syncthreads();
@@ -304,6 +316,7 @@ __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const De
         const float* rg = srow;
         const float* rd = srow + rows * BPP;
         const float* rdd = srow + 2 * rows * BPP;
+        const int ig = ISX * IPP, id = ig + rows * BPP, idd = ig + 2 * rows * BPP;   // the same, as lds indices
         const int use = C.use[s];
 #pragma unroll
         for (int o = 0; o < kMaxOwn; ++o) {
@@ -316,9 +329,9 @@ __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const De
                 // rdd -> Bxx (even g).
 #define COL_T(RR)                                                \
     do {                                                         \
-        col_run<RR>(rg + c0, BPP, tdd, td, byy, by);             \
-        col_run<RR>(rd + c0, BPP, tg, td, bx, bxy);              \
-        col_run<RR>(rdd + c0, BPP, tg, nullptr, bxx, dummy);     \
+        col_run<RR>(lds, ig + c0, BPP, tdd, td, byy, by);        \
+        col_run<RR>(lds, id + c0, BPP, tg, td, bx, bxy);         \
+        col_run<RR>(lds, idd + c0, BPP, tg, nullptr, bxx, dummy); \
     } while (0)
 #define COL_ANY                                                  \
     do {                                                         \
@@ -332,14 +345,16 @@ __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const De
                 (void)dummy;
 #pragma unroll
                 for (int j = 0; j < kRun; ++j) {
+                    // the 2-D normalisation cn of this sigma, applied as the
+                    // response joins the sum over sigma
                     if (use & 1) {
-                        bas[o][0][j] += bx[j];
-                        bas[o][1][j] += by[j];
+                        bas[o][0][j] = fmaf(cn, bx[j], bas[o][0][j]);
+                        bas[o][1][j] = fmaf(cn, by[j], bas[o][1][j]);
                     }
                     if (use & 2) {
-                        bas[o][2][j] += bxx[j];
-                        bas[o][3][j] += byy[j];
-                        bas[o][4][j] += bxy[j];
+                        bas[o][2][j] = fmaf(cn, bxx[j], bas[o][2][j]);
+                        bas[o][3][j] = fmaf(cn, byy[j], bas[o][3][j]);
+                        bas[o][4][j] = fmaf(cn, bxy[j], bas[o][4][j]);
                     }
                 }
             }
@@ -391,7 +406,7 @@ __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const De
 #pragma unroll
             for (int c = 0; c < Z; ++c)
                 if (c >= lo && c < hi) s2 = fmaf(acc[c][j], acc[c][j], s2);
-            inv[j] = 1.0f / sqrtf(s2 + C.eps);
+            inv[j] = rsqrtf(s2 + C.eps);
         }
         if (gy >= H) return;
 #pragma unroll
@@ -471,7 +486,7 @@ __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const De
                 const float* w = (c < N) ? C.w1 : C.w2;
                 const float* ch = schan + cc * BB + obase;
                 if (FAST) {
-                    smooth_run_k1_123(ch, BPP, w[4], w[1], w[0], acc[c]);
+                    smooth_run_k1_123(lds, (5 + cc) * BB + obase, BPP, w[4], w[1], w[0], acc[c]);
                     // one channel's reads in flight at a time (the scheduler
                     // would otherwise hoist all of a group's LDS reads)
                     __builtin_amdgcn_sched_barrier(0);
