@@ -276,8 +276,10 @@ __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const De
 
     // 2. basis responses Gx, Gy, Gxx, Gyy, Gxy * I summed over sigma, held in
     //    registers by the thread that owns each vertical run of kRun pixels.
-    // runs per thread: (BSP / kRun) * BSP runs; BSP = 40 when Q = 3 (the
-    // K = 1, rates 1-3 path), at most 48 otherwise.
+    // runs: (BSP / kRun) vertical runs in each of the BSr = kTS + 2Q columns
+    // that steering reads (the padding columns up to BSP are skipped); BSP =
+    // 40 and BSr = 38 when Q = 3 (the K = 1, rates 1-3 path), BSP at most 48
+    // otherwise.
     constexpr int kMaxOwn = FAST ? 2 : 3;
     float bas[kMaxOwn][5][kRun];
 #pragma unroll
@@ -286,7 +288,8 @@ __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const De
         for (int m = 0; m < 5; ++m)
 #pragma unroll
             for (int j = 0; j < kRun; ++j) bas[o][m][j] = 0.f;
-    const int ncolrun = nrun * BSP;   // (row-run, column) pairs
+    const int BSr = kTS + 2 * Q;      // rows / columns of the basis maps that steering reads
+    const int ncolrun = nrun * BSr;   // (row-run, column) pairs
     for (int s = 0; s < C.nsig; ++s) {
         const int rho = C.rad[s];
         const float* tg = C.taps + C.off[s];
@@ -322,7 +325,7 @@ __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const De
         for (int o = 0; o < kMaxOwn; ++o) {
             const int e = t + o * kNT;
             if (e < ncolrun) {
-                const int b = e % BSP, a0 = (e / BSP) * kRun;
+                const int b = e % BSr, a0 = (e / BSr) * kRun;
                 float bx[kRun], by[kRun], bxx[kRun], byy[kRun], bxy[kRun], dummy[kRun];
                 const int c0 = (a0 + rho) * BPP + b;
                 // rg -> By (odd d), Byy (even dd); rd -> Bx (even g), Bxy (odd d);
@@ -365,7 +368,7 @@ __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const De
     for (int o = 0; o < kMaxOwn; ++o) {
         const int e = t + o * kNT;
         if (e < ncolrun) {
-            const int b = e % BSP, a0 = (e / BSP) * kRun;
+            const int b = e % BSr, a0 = (e / BSr) * kRun;
 #pragma unroll
             for (int m = 0; m < 5; ++m)
 #pragma unroll
@@ -382,7 +385,6 @@ __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const De
     const int N = FAST ? Z / 2 : C.N;
     const int B = 2 * C.K + 1;
     const int oy = t / (kTS / kRun), ox0 = (t % (kTS / kRun)) * kRun;
-    const int BSr = kTS + 2 * Q;   // rows / columns actually read
 
     // 4. (per order block) normalisation, rounding, store, channel sums.
     //    Each thread stores its run of kRun pixels of a channel as one
