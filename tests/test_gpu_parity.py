@@ -53,6 +53,11 @@ DESCRIBE_CASES = [
     ((33, 31), "paper", {"rectify": 2}),
     ((1, 7), "baseline", {}),
     ((20, 20), "baseline", {"n_orient": 6}),
+    # the generic smoothing path: other dilation sets and K = 2 (reach Q up to its limit of 8)
+    ((50, 41), "baseline", {"K": 2, "dil": (1, 2)}),
+    ((36, 60), "paper", {"K": 2, "dil": (1, 4)}),
+    ((30, 30), "baseline", {"dil": (2,)}),
+    ((29, 35), "baseline", {"dil": (1, 3), "second_order": 0}),
 ]
 
 
@@ -63,7 +68,12 @@ def test_describe_matches_oracle(shape, preset, mods):
         np.random.default_rng(1).uniform(0, 1, shape).astype(np.float32)
     p = S.preset(preset)
     for k, v in mods.items():
-        setattr(p, k, v)
+        if k == "dil":
+            p.n_dil = len(v)
+            for j, d in enumerate(v):
+                p.dil[j] = d
+        else:
+            setattr(p, k, v)
     desc, i1, i2 = S.describe(dev(img), p)
     torch.cuda.synchronize()
     F = O.sfoc(img.astype(np.float64), oparams(p))
