@@ -244,21 +244,37 @@ SFOC_DEV void row_stage(const void* plane, int pitch, int y0, int x0, int nrows,
     const int tid = tid_local();
     const int npair = (nrows + 1) / 2;
     const int tasksA = npair * C::NB;
-    // Branch-free loads with 32-bit offsets from the plane base (a plane
-    // holds < 2^30 elements): the window lies inside the image, so columns
-    // past ncols are clamped to the last one and zeroed after the load, and
-    // a missing second row re-reads the first.
+    // Loads from one pointer per row and task (32-bit offsets from the plane
+    // base: a plane holds < 2^30 elements); element n2 lies NB * n2 elements
+    // further on, a constant offset the load instruction encodes, so the
+    // loads need no per-element address arithmetic.  The window lies inside
+    // the image; a missing second row re-reads the first (then zeroed).
+    // Full-width windows (ncols == L) need no column test; narrower ones load
+    // only the columns below ncols and zero the rest.
+    const bool full = ncols == L;
     auto load = [&](int task, float2(&x)[C::NA]) {
         const int p = task / C::NB, n1 = task - p * C::NB;
         const bool two = 2 * p + 1 < nrows;
-        const int oa = (y0 + 2 * p) * pitch + x0;
+        const int oa = (y0 + 2 * p) * pitch + x0 + n1;
         const int ob = oa + (two ? pitch : 0);
+        const void* ra = elem_ptr<DT>(plane, oa);
+        const void* rb = elem_ptr<DT>(plane, ob);
+        if (full) {
 #pragma unroll
-        for (int n2 = 0; n2 < C::NA; ++n2) {
-            const int b = n1 + C::NB * n2;
-            const int bc = b < ncols ? b : ncols - 1;
-            const float re = ldd<DT>(plane, oa + bc), im = ldd<DT>(plane, ob + bc);
-            x[n2] = make_float2(b < ncols ? re : 0.f, (b < ncols && two) ? im : 0.f);
+            for (int n2 = 0; n2 < C::NA; ++n2) {
+                const float re = ldd<DT>(ra, C::NB * n2), im = ldd<DT>(rb, C::NB * n2);
+                x[n2] = make_float2(re, two ? im : 0.f);
+            }
+        } else {
+#pragma unroll
+            for (int n2 = 0; n2 < C::NA; ++n2) {
+                float re = 0.f, im = 0.f;
+                if (n1 + C::NB * n2 < ncols) {
+                    re = ldd<DT>(ra, C::NB * n2);
+                    im = ldd<DT>(rb, C::NB * n2);
+                }
+                x[n2] = make_float2(re, two ? im : 0.f);
+            }
         }
     };
     auto finish = [&](int task, float2(&x)[C::NA]) {
