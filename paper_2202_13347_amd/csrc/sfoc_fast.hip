@@ -51,15 +51,19 @@ struct Blocks {
 
 SFOC_DEV int bound(int lo, int n, int i, int nb) { return lo + (int)(((int64_t)i * n) / nb); }
 
-// The radius-3 circle, clockwise from the top, as (dy, dx).
-__constant__ int kCy[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3};
-__constant__ int kCx[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
+// The radius-3 circle, clockwise from the top, as (dy, dx).  Compile-time
+// constants: with the reads addressed from the 7 x 7 neighbourhood's
+// top-left element, every circle read is one LDS instruction with a constant
+// offset and no address arithmetic.
+constexpr int kCy[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3};
+constexpr int kCx[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
 
 SFOC_DEV float strength(const float* tile, int ty, int tx) {
-    const float c = tile[ty * kIS + tx];
+    const float* nb = tile + (ty - 3) * kIS + (tx - 3);
+    const float c = nb[3 * kIS + 3];
     float u[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) u[i] = tile[(ty + kCy[i]) * kIS + tx + kCx[i]] - c;
+    for (int i = 0; i < 16; ++i) u[i] = nb[(kCy[i] + 3) * kIS + kCx[i] + 3] - c;
     // windows of 9 starting at k (cyclic): min / max of u[k .. k+8]
     float mn2[16], mx2[16], mn4[16], mx4[16], mn8[16], mx8[16];
 #pragma unroll
