@@ -442,23 +442,23 @@ __global__ __launch_bounds__(kFeatNT) void features_kernel(const FeatArgs A) {
     const int64_t plane = A.Hs * A.Ws;
     double t1 = 0.0, t2 = 0.0;
     const int mm = m * m;
-    // eight loads in flight per step; the sums stay in element order
-    const int ntot = mm * A.z;
-    for (int e0 = t; e0 < ntot; e0 += 8 * kFeatNT) {
-        double d[8];
+    // A thread takes template positions q = t, t + kFeatNT, ... and, for each,
+    // all channels: one division per position instead of two per element,
+    // eight channels' loads in flight per step.  The summation order is
+    // fixed (position, then channel), so the sums are reproducible.
+    for (int q = t; q < mm; q += kFeatNT) {
+        const int yy = q / m, xx = q - yy * m;
+        const int64_t pos = (ty + yy) * A.Ws + tx + xx;
+        for (int h0 = 0; h0 < A.z; h0 += 8) {
+            double d[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * kFeatNT;
-            d[u] = 0.0;
-            if (e < ntot) {
-                const int h = e / mm, q = e - h * mm, yy = q / m, xx = q - yy * m;
-                d[u] = ld_desc<DT>(A.desc_sen, h * plane + (ty + yy) * A.Ws + tx + xx);
+            for (int k = 0; k < 8; ++k)
+                d[k] = h0 + k < A.z ? (double)ld_desc<DT>(A.desc_sen, (h0 + k) * plane + pos) : 0.0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                t1 += d[k];
+                t2 += d[k] * d[k];
             }
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            t1 += d[u];
-            t2 += d[u] * d[u];
         }
     }
     rd[0][t] = s1;
