@@ -537,7 +537,6 @@ constexpr int kScanPer = 8;
 template <bool BATCH>
 __global__ __launch_bounds__(kScanNT) void integral_row_scan(const IntegJob single, const IntegJob* __restrict__ jobs,
                                                               const int4* __restrict__ rows) {
-    __shared__ double sh[2][kScanNT * kScanPer];
     __shared__ double wsum[2][kScanNT / 64];
     const IntegJob J = BATCH ? load_table(jobs, rows[blockIdx.x].x) : single;
     const int y = BATCH ? rows[blockIdx.x].y : (int)blockIdx.x;   // 0..H
@@ -560,34 +559,36 @@ __global__ __launch_bounds__(kScanNT) void integral_row_scan(const IntegJob sing
     }
     const int seg = kScanNT * kScanPer;
     for (int x0 = 1; x0 <= W; x0 += seg) {
+        // thread t owns the kScanPer consecutive elements from x0 + t kScanPer,
+        // held in registers: serial sums, then a wave scan of the thread
+        // totals and the workgroup's wave offsets
+        const int xb = x0 + t * kScanPer;
+        double v[2][kScanPer];
         for (int q = 0; q < 2; ++q) {
-            double* g = q ? g2 : g1;
-            for (int i = 0; i < kScanPer; ++i) {
-                const int e = i * kScanNT + t;
-                const int x = x0 + e;
-                sh[q][e] = x <= W ? g[rowoff + x] : 0.0;
-            }
+            const double* g = q ? g2 : g1;
+#pragma unroll
+            for (int i = 0; i < kScanPer; ++i) v[q][i] = xb + i <= W ? g[rowoff + xb + i] : 0.0;
         }
-        __syncthreads();
         double tot[2];
         for (int q = 0; q < 2; ++q) {
             double s = 0.0;
+#pragma unroll
             for (int i = 0; i < kScanPer; ++i) {
-                s += sh[q][t * kScanPer + i];
-                sh[q][t * kScanPer + i] = s;
+                s += v[q][i];
+                v[q][i] = s;
             }
             tot[q] = s;
         }
         // inclusive scan of per-thread totals within the wave
         const int lane = t & 63, wv = t >> 6;
         for (int q = 0; q < 2; ++q) {
-            double v = tot[q];
+            double x = tot[q];
             for (int d = 1; d < 64; d <<= 1) {
-                const double u = __shfl_up(v, d, 64);
-                if (lane >= d) v += u;
+                const double u = __shfl_up(x, d, 64);
+                if (lane >= d) x += u;
             }
-            if (lane == 63) wsum[q][wv] = v;
-            const double ex = __shfl_up(v, 1, 64);
+            if (lane == 63) wsum[q][wv] = x;
+            const double ex = __shfl_up(x, 1, 64);
             tot[q] = lane == 0 ? 0.0 : ex;   // exclusive within wave
         }
         __syncthreads();
@@ -595,21 +596,19 @@ __global__ __launch_bounds__(kScanNT) void integral_row_scan(const IntegJob sing
             double pre = carry[q];
             for (int w = 0; w < wv; ++w) pre += wsum[q][w];
             const double add = pre + tot[q];
-            for (int i = 0; i < kScanPer; ++i) sh[q][t * kScanPer + i] += add;
+#pragma unroll
+            for (int i = 0; i < kScanPer; ++i) v[q][i] += add;
             double all = carry[q];
             for (int w = 0; w < kScanNT / 64; ++w) all += wsum[q][w];
             carry[q] = all;
         }
-        __syncthreads();
         for (int q = 0; q < 2; ++q) {
             double* g = q ? g2 : g1;
-            for (int i = 0; i < kScanPer; ++i) {
-                const int e = i * kScanNT + t;
-                const int x = x0 + e;
-                if (x <= W) g[rowoff + x] = sh[q][e];
-            }
+#pragma unroll
+            for (int i = 0; i < kScanPer; ++i)
+                if (xb + i <= W) g[rowoff + xb + i] = v[q][i];
         }
-        __syncthreads();
+        __syncthreads();   // wsum is rewritten by the next segment
     }
 }
 
