@@ -628,10 +628,26 @@ __global__ __launch_bounds__(kScanNT) void integral_col_blocksum(const IntegJob 
     const int x = bx * kScanNT + threadIdx.x;
     if (x > W) return;
     const int y0 = 1 + b * kScanRows, y1 = min(H, y0 + kScanRows - 1);
+    const int64_t P = W + 1;
     double s1 = 0.0, s2 = 0.0;
-    for (int y = y0; y <= y1; ++y) {
-        s1 += g1[(int64_t)y * (W + 1) + x];
-        s2 += g2[(int64_t)y * (W + 1) + x];
+    int y = y0;
+    // eight rows' loads in flight, then the sums in row order
+    for (; y + 7 <= y1; y += 8) {
+        double a1[8], a2[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            a1[k] = g1[(int64_t)(y + k) * P + x];
+            a2[k] = g2[(int64_t)(y + k) * P + x];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            s1 += a1[k];
+            s2 += a2[k];
+        }
+    }
+    for (; y <= y1; ++y) {
+        s1 += g1[(int64_t)y * P + x];
+        s2 += g2[(int64_t)y * P + x];
     }
     bs1[(int64_t)b * (W + 1) + x] = s1;
     bs2[(int64_t)b * (W + 1) + x] = s2;
@@ -651,14 +667,47 @@ __global__ __launch_bounds__(kScanNT) void integral_col_apply(const IntegJob sin
     const double* __restrict__ bs2 = J.bs2;
     const int x = bx * kScanNT + threadIdx.x;
     if (x > W) return;
+    const int64_t P = W + 1;
     double c1 = 0.0, c2 = 0.0;
-    for (int q = 0; q < b; ++q) {
-        c1 += bs1[(int64_t)q * (W + 1) + x];
-        c2 += bs2[(int64_t)q * (W + 1) + x];
+    // eight loads in flight per step; sums in block and row order
+    int q = 0;
+    for (; q + 7 < b; q += 8) {
+        double a1[8], a2[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            a1[k] = bs1[(int64_t)(q + k) * P + x];
+            a2[k] = bs2[(int64_t)(q + k) * P + x];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            c1 += a1[k];
+            c2 += a2[k];
+        }
+    }
+    for (; q < b; ++q) {
+        c1 += bs1[(int64_t)q * P + x];
+        c2 += bs2[(int64_t)q * P + x];
     }
     const int y0 = 1 + b * kScanRows, y1 = min(H, y0 + kScanRows - 1);
-    for (int y = y0; y <= y1; ++y) {
-        const int64_t o = (int64_t)y * (W + 1) + x;
+    int y = y0;
+    for (; y + 7 <= y1; y += 8) {
+        double a1[8], a2[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            a1[k] = g1[(int64_t)(y + k) * P + x];
+            a2[k] = g2[(int64_t)(y + k) * P + x];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t o = (int64_t)(y + k) * P + x;
+            c1 += a1[k];
+            c2 += a2[k];
+            g1[o] = c1;
+            g2[o] = c2;
+        }
+    }
+    for (; y <= y1; ++y) {
+        const int64_t o = (int64_t)y * P + x;
         c1 += g1[o];
         c2 += g2[o];
         g1[o] = c1;
