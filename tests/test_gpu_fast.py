@@ -1,7 +1,8 @@
 """Block-based FAST on the GPU (through the C ABI) against the FAST oracle:
 bit-exact interest points, strengths and per-block counts on structured
-random images of ragged sizes and on a 2048 x 2048 synthetic sensed image,
-the empty cases, and registration from the detected points."""
+random images of ragged sizes, on a 2048 x 2048 synthetic sensed image and
+on sampled blocks of the 10000 x 10000 throughput configuration, the empty
+cases, and registration from the detected points."""
 import sys
 
 import numpy as np
@@ -55,7 +56,7 @@ def run(img, thr, margin, nby, nbx, per, pad=0):
     (333, 257, 0.0, 12, 7, 3, 17, 3),
     (150, 300, 0.01, 40, 2, 6, 32, 0),
     (40, 1030, 0.003, 3, 1, 9, 5, 1),
-    (211, 173, 0.004, 9, 13, 11, 1, 2),       # one per block: the atomic path
+    (211, 173, 0.004, 9, 13, 11, 1, 2),       # one per block
     (90, 90, 0.002, 3, 70, 9, 1, 0),          # more blocks than region rows
 ])
 def test_parity(H, W, thr, margin, nby, nbx, per, pad):
@@ -80,6 +81,55 @@ def test_empty_cases():
     oi, osc, oc = F.detect(img, 0.001, 3, 40, 50, 1)
     np.testing.assert_array_equal(gc, oc)
     np.testing.assert_array_equal(gi, oi)
+
+
+def test_large_sampled_blocks():
+    """The benchmark's throughput configuration (10000 x 10000 smoothed
+    noise, 71 x 71 blocks, one point each, margin 80): the four corner blocks
+    and eight random ones against the oracle run on a crop that holds the
+    block, its suppression ring and the circle's reach (4 pixels), with the
+    strengths outside the detection region removed as in the full image."""
+    side, nb, thr, margin = 10000, 71, 0.002, 80
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    big = torch.rand((1, 1, side, side), dtype=torch.float32, device="cuda", generator=gen)
+    box = torch.full((1, 1, 5, 5), 1.0 / 25.0, dtype=torch.float32, device="cuda")
+    conv = torch.nn.functional.conv2d
+    big = conv(conv(big, box, padding=2), box, padding=2)[0, 0].contiguous()
+    D = S.Detector(side, side, nb, nb, 1, thr, margin)
+    ips, sc, cnt, n = D(big)
+    torch.cuda.synchronize()
+    k = int(n.item())
+    ips, sc, cnt = ips[:k].cpu().numpy(), sc[:k].cpu().numpy(), cnt.cpu().numpy()
+    img = big.cpu().numpy()
+    b = max(3, margin)
+    ys = F.block_bounds(b, side - 2 * b, nb)
+    xs = F.block_bounds(b, side - 2 * b, nb)
+    start = np.concatenate([[0], np.cumsum(cnt)])
+    rng = np.random.default_rng(0)
+    picks = [(0, 0), (0, nb - 1), (nb - 1, 0), (nb - 1, nb - 1)] + \
+            [tuple(int(v) for v in rng.integers(0, nb, 2)) for _ in range(8)]
+    h = 4
+    for i, j in picks:
+        y0, y1, x0, x1 = ys[i], ys[i + 1], xs[j], xs[j + 1]
+        crop = img[y0 - h:y1 + h, x0 - h:x1 + h]
+        V = F.strength(crop, 3)
+        gy = np.arange(crop.shape[0])[:, None] + (y0 - h)
+        gx = np.arange(crop.shape[1])[None, :] + (x0 - h)
+        V[(gy < b) | (gy >= side - b) | (gx < b) | (gx >= side - b)] = -np.inf
+        keep = F.suppress(V, thr)[h:h + y1 - y0, h:h + x1 - x0]
+        vb = V[h:h + y1 - y0, h:h + x1 - x0]
+        blk = i * nb + j
+        cand = np.argwhere(keep)
+        say(f"block ({i},{j}): {len(cand)} kept corners")
+        if len(cand) == 0:
+            assert cnt[blk] == 0
+            continue
+        vals = vb[cand[:, 0], cand[:, 1]]
+        order = np.lexsort((cand[:, 0] * side + cand[:, 1], -vals.astype(np.float64)))
+        best = cand[order[0]]
+        assert cnt[blk] == 1
+        assert tuple(ips[start[blk]]) == (y0 + best[0], x0 + best[1])
+        assert sc[start[blk]] == vb[best[0], best[1]]
 
 
 def test_scene_sensed_image():
