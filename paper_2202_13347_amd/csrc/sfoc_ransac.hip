@@ -281,6 +281,7 @@ SFOC_DEV bool cholesky_solve(double (&A)[N][N], double (&b)[NR][N]) {
     for (int i = 0; i < N; ++i) big = fmax(big, A[i][i]);
     if (!(big > 0.0) || !isfinite(big)) return false;
     bool ok = true;
+    double invd[N];   // 1 / L[j][j]: the substitutions multiply instead of dividing
 #pragma unroll
     for (int j = 0; j < N; ++j) {
         double d = A[j][j];
@@ -289,6 +290,7 @@ SFOC_DEV bool cholesky_solve(double (&A)[N][N], double (&b)[NR][N]) {
         ok = ok && d > kSingular * big;
         const double l = sqrt(fmax(d, kSingular * big));
         const double inv = 1.0 / l;
+        invd[j] = inv;
         A[j][j] = l;
 #pragma unroll
         for (int i = j + 1; i < N; ++i) {
@@ -305,14 +307,14 @@ SFOC_DEV bool cholesky_solve(double (&A)[N][N], double (&b)[NR][N]) {
             double v = b[r][i];
 #pragma unroll
             for (int q = 0; q < i; ++q) v = fma(-A[i][q], b[r][q], v);
-            b[r][i] = v / A[i][i];
+            b[r][i] = v * invd[i];
         }
 #pragma unroll
         for (int i = N - 1; i >= 0; --i) {   // L^T x = y
             double v = b[r][i];
 #pragma unroll
             for (int q = i + 1; q < N; ++q) v = fma(-A[q][i], b[r][q], v);
-            b[r][i] = v / A[i][i];
+            b[r][i] = v * invd[i];
         }
     }
     return ok;
@@ -432,12 +434,14 @@ __global__ __launch_bounds__(kFinNT) void finish_kernel(Args a) {
         for (int q = 0; q < nsum; ++q) s[q] = 0.0;
         for (int j = t; j < n; j += kFinNT)
             if (a.inl[j]) terms<PROJ>(a.cand[j], s);
+        // all sums step by step, so each step's shuffles are independent
 #pragma unroll
-        for (int q = 0; q < nsum; ++q) {
-            double v = s[q];
-            for (int d = 32; d >= 1; d >>= 1) v += __shfl_down(v, d, 64);
-            if (lane == 0) part[wv][q] = v;
-        }
+        for (int d = 32; d >= 1; d >>= 1)
+#pragma unroll
+            for (int q = 0; q < nsum; ++q) s[q] += __shfl_down(s[q], d, 64);
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < nsum; ++q) part[wv][q] = s[q];
         __syncthreads();
         if (t == 0) {
             double tot[nsum];
