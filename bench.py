@@ -77,12 +77,15 @@ def timed_and_traced(S, torch, step, steps: int):
     return dt, dt_traced, kt, out
 
 
-def sfoc_flops_per_px(p) -> float:
-    """Algorithmic flops per output pixel of SFOC (separable form): per sigma
-    the row pass (g, d, dd) and column pass (5 basis maps), each a (2R+1)-tap
-    FMA; steering 3 flops per first-order and 5 per second-order channel;
-    dilated smoothing separable per rate (2 * (4K+1) flops) plus the sum over
-    rates; normalisation 3 flops per channel plus a root and a divide per order."""
+def sfoc_fma_per_px(p) -> float:
+    """Algorithmic FMAs per output pixel of SFOC in separable form, counting
+    every tap as one FMA: per sigma a (2R+1)-tap row pass for each of g, d
+    (and dd when the second order uses the sigma) and a column pass for each
+    basis map it feeds (2 first-order, 3 second-order); steering 2 per
+    first-order and 3 per second-order channel; the dilated smoothing a
+    separable (2K+1) + (2K+1) per rate and channel; normalisation 2 per
+    channel plus one root per order.  Baseline (N 8, sigma 1/2/3): 312 + 40
+    + 288 + 34 = 674."""
     sig = {}
     for s in p.s1[:p.n_s1]:
         sig[s] = sig.get(s, 0) | 1
@@ -94,31 +97,87 @@ def sfoc_flops_per_px(p) -> float:
         R = math.ceil(p.trunc * s - 1e-9)
         rows = 3 if use & 2 else 2
         cols = (2 if use & 1 else 0) + (3 if use & 2 else 0)
-        conv += 2.0 * (rows + cols) * (2 * R + 1)
+        conv += (rows + cols) * (2 * R + 1)
     N = p.n_orient
-    z = N * (2 if p.second_order else 1)
-    steer = 3 * N + (5 * N if p.second_order else 0)
-    smooth = z * (p.n_dil * 2 * (4 * p.K + 1) + (p.n_dil - 1))
-    norm = 3 * z + 2 * (2 if p.second_order else 1)
+    orders = 2 if p.second_order else 1
+    z = N * orders
+    steer = 2 * N + (3 * N if p.second_order else 0)
+    smooth = z * p.n_dil * 2 * (2 * p.K + 1)
+    norm = 2 * z + orders
     return conv + steer + smooth + norm
 
 
-def fastncc_flops_per_ip(M: int, z: int) -> float:
+def sfoc_flops_per_px(p) -> float:
+    """Two flops per algorithmic FMA: 1348 at the baseline."""
+    return 2.0 * sfoc_fma_per_px(p)
+
+
+def sfoc_bytes_per_px(es: int, z: int) -> float:
+    """Bytes SFOC must move per pixel: the float32 input and the stored
+    descriptor (z channels of es bytes): 68 at float32, 36 at bfloat16 /
+    float16 for z = 16."""
+    return 4.0 + z * es
+
+
+INTEGRAL_BYTES_PER_PX = 24.0   # two float32 channel sums in, two float64 prefix sums out
+
+
+def fastncc_flops_per_ip(M: int, z: int, V: int) -> float:
     """Algorithmic flops per interest point of Fast-NCC_SFOC with FFT side
     L = M (Eq. 13): 2z forward real 2-D FFTs and one inverse at
-    2.5 L^2 log2(L^2) flops each, plus the spectrum product summed over
-    channels (8 flops per half-spectrum bin per channel)."""
+    2.5 L^2 log2(L^2) flops each, the spectrum product summed over channels
+    (8 flops per half-spectrum bin per channel) and the NCC assembly of
+    Eq. 9 (about 20 flops per offset, V^2 offsets): 20.07 M for m 64, r 32."""
     L = M
     fft = 2.5 * L * L * math.log2(L * L)
-    return (2 * z + 1) * fft + z * L * (L // 2 + 1) * 8
+    return (2 * z + 1) * fft + z * L * (L // 2 + 1) * 8 + 20.0 * V * V
+
+
+def fastncc_bytes_per_ip(m: int, M: int, z: int, es: int) -> float:
+    """Bytes the matching must move per interest point: the template and
+    search windows of every channel (655 KB at bfloat16 for m 64, M 128)."""
+    return float(z * es * (m * m + M * M))
+
+
+def roof_entry(name, ms, flops, nbytes, launches=1):
+    """Per-kernel figures: achieved rates from the algorithmic flops and
+    bytes per launch and the measured duration, against the FP32 VALU and
+    HBM peaks, and against the binding roof min(peak, HBM x intensity)."""
+    if not ms or ms <= 0:
+        return None
+    t = ms * 1e-3
+    ach_f = flops / t
+    ach_b = nbytes / t
+    roof = min(PEAK_FP32_VALU, PEAK_HBM * flops / nbytes) if flops > 0 else PEAK_HBM
+    return {"ms_per_launch": ms, "launches_per_step": launches,
+            "algorithmic_flop": flops, "algorithmic_bytes": nbytes,
+            "achieved_tflops": ach_f / 1e12, "achieved_gbs": ach_b / 1e9,
+            "frac_valu_peak": ach_f / PEAK_FP32_VALU, "frac_hbm_peak": ach_b / PEAK_HBM,
+            "binding_roof": "hbm" if flops <= 0 or PEAK_HBM * flops / nbytes < PEAK_FP32_VALU else "valu",
+            "frac_binding_roof": (ach_f / roof) if flops > 0 else ach_b / PEAK_HBM}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(pr, ips, m, r, budget_s: float):
-    """The FP64 oracle on a bounded sample: complete CPs (SFOC of the
-    template and search crops + Eq. 9-16 + peak) until the time budget is
-    used, one process, one thread."""
+    """The FP64 oracle as it stands, on the host cores: every CP of the same
+    scene (SFOC of the template and search crops + Eq. 9-16 + peak) over a
+    pool of worker processes, and a bounded single-core sample."""
     from oracle import sfoc_oracle as O
+    from tests.oracle_pool import oracle_cps, pool_workers
     p = O.Params()
+    workers = pool_workers()
+    t0 = time.perf_counter()
+    oracle_cps(pr.ref, pr.sen, ips, m, r, p, keep_surfaces=False, workers=workers)
+    dt_pool = time.perf_counter() - t0
     t0 = time.perf_counter()
     done = 0
     order = list(range(0, len(ips), 7)) + [i for i in range(len(ips)) if i % 7]
@@ -127,11 +186,125 @@ def cpu_baseline(pr, ips, m, r, budget_s: float):
         done += 1
         if time.perf_counter() - t0 >= budget_s and done >= 2:
             break
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "CPs/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} of the {len(ips)} CPs of the same scene, each computed from its template and "
-                      f"search crops (FP64 SFOC with reflect-101 halo, FFT NCC with integral images, peak), "
-                      f"{dt:.1f} s on one core"}
+    dt1 = time.perf_counter() - t0
+    return {"value": len(ips) / dt_pool, "unit": "CPs/s", "cores": workers, "kind": "oracle",
+            "sample": f"all {len(ips)} CPs of the same scene, each computed from its template and search crops "
+                      f"(FP64 SFOC with reflect-101 halo, FFT NCC with integral images, peak) over a pool of "
+                      f"{workers} worker processes, {dt_pool:.1f} s including their start-up",
+            "single_core": {"value": done / dt1, "unit": "CPs/s", "cores": 1,
+                            "sample": f"{done} of the {len(ips)} CPs in one process, {dt1:.1f} s"},
+            "os_cpu_count": os.cpu_count(), "cpu_model": cpu_model()}
+
+
+def parity_vs_stored_oracle(S, name, cps, kind="o64", ref_kind=None):
+    """The GPU's CPs against the oracle's stored decisions for the same
+    seeded workload (tests/golden/make_oracle_cps.py): integer CPs equal,
+    tie-set answers, largest score and sub-pixel differences."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_cps_{name}.npz")
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        rec, flags, ties = z[kind + "_rec"], z[kind + "_flags"], z[kind + "_ties"]
+        base = z[(ref_kind or kind) + "_rec"]
+    g = S.cps_to_numpy(cps)
+    tie = {}
+    for i, dy, dx in ties:
+        tie.setdefault(int(i), set()).add((int(dy), int(dx)))
+    bad = S.OOB | S.FLAT_T | S.FLAT_S | S.NONFINITE
+    ok = (flags & bad) == 0
+    same = ok & (g["dy"] == rec[:, 0]) & (g["dx"] == rec[:, 1])
+    taken = [i for i in np.nonzero(ok & ~same)[0] if (int(g["dy"][i]), int(g["dx"][i])) in tie.get(int(i), ())]
+    other = int(ok.sum() - same.sum()) - len(taken)
+    out = {"oracle": kind, "cps": int(len(g)), "compared": int(ok.sum()), "integer_equal": int(same.sum()),
+           "ambiguous": len(tie), "ambiguous_other_index": len(taken), "mismatched": other,
+           "max_score_err": float(np.max(np.abs(g["score"][same] - rec[same, 4]))) if same.any() else None,
+           "max_subpx_err": float(np.max(np.abs(np.stack([g["sub_dy"][same] - rec[same, 2],
+                                                         g["sub_dx"][same] - rec[same, 3]])))) if same.any() else None}
+    if ref_kind:
+        tot_g = np.stack([g["dy"] + g["sub_dy"], g["dx"] + g["sub_dx"]], 1).astype(np.float64)
+        tot_o = np.stack([base[:, 0] + base[:, 2], base[:, 1] + base[:, 3]], 1)
+        e = np.abs(tot_g - tot_o).max(axis=1)[ok]
+        s64 = ok & (g["dy"] == base[:, 0]) & (g["dx"] == base[:, 1])
+        out["vs_" + ref_kind] = {"integer_equal": int(s64.sum()),
+                                 "max_score_err": float(np.max(np.abs(g["score"][s64] - base[s64, 4]))),
+                                 "max_offset_err_px": float(e.max()), "median_offset_err_px": float(np.median(e))}
+    return out
+
+
+def kernel_table(kt, steps, p, H, W, n, m, r):
+    """Roof entries of the describe, integral and match launches of one
+    register step (HIP-event durations from the library's trace)."""
+    z = p.z
+    es = 4 if p.desc_dtype == 0 else 2
+    avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kt.items()}
+    per = {k: kt[k][1] / steps for k in kt}
+    M, V = m + 2 * r, 2 * r + 1
+    return {
+        "describe": roof_entry("describe", avg["describe"], sfoc_flops_per_px(p) * H * W,
+                               sfoc_bytes_per_px(es, z) * H * W, per["describe"]),
+        "integral": roof_entry("integral", avg["integral"], 0.0, INTEGRAL_BYTES_PER_PX * H * W, per["integral"]),
+        "match": roof_entry("match", avg["match"], fastncc_flops_per_ip(M, z, V) * n,
+                            fastncc_bytes_per_ip(m, M, z, es) * n, per["match"]),
+    }
+
+
+def run_precision(args, S, synth, torch, dev, scene):
+    """Descriptor storage in bfloat16 and float16 (FFT in float32, integral
+    images and variance in float64): the scene step and the 10000 x 10000
+    precision workload (5000 IPs, m 64, r 48), with per-kernel roofs at the
+    2-byte storage and every CP against the oracle's stored decisions on the
+    same rounded descriptors (O64q) and on unrounded ones (O64)."""
+    import numpy as np
+    out = {}
+    pr, ips, m, r = scene
+    H, W = pr.ref.shape
+    ref = torch.from_numpy(pr.ref).to(dev)
+    sen = torch.from_numpy(pr.sen).to(dev)
+    dips = torch.from_numpy(ips).to(dev)
+    for kind, dt in (("bf16", S.DTYPE_BF16), ("f16", S.DTYPE_F16)):
+        p = S.preset("baseline", dtype=dt)
+        R = S.Registrar(H, W, H, W, len(ips), m, r, p, device=dev)
+        for _ in range(args.warmup):
+            R(ref, sen, dips)
+        dts, _, kt, cps = timed_and_traced(S, torch, lambda: R(ref, sen, dips), args.steps)
+        d_ms = kt["describe"][0] / max(1, kt["describe"][1])
+        out["scene_" + kind] = {
+            "value": len(ips) / dts, "unit": "CPs/s", "ms_per_step": 1e3 * dts,
+            "sfoc_mpixel_per_s": H * W / (d_ms * 1e-3) / 1e6 if d_ms > 0 else None,
+            "kernels": kernel_table(kt, args.steps, p, H, W, len(ips), m, r),
+            "parity": parity_vs_stored_oracle(S, "scene", cps, kind, ref_kind="o64")}
+        del R
+    del ref, sen, dips
+    if args.large:
+        t0 = time.perf_counter()
+        lp, lips, lm, lr = synth.workload(synth.LARGE, 0)
+        gen_s = time.perf_counter() - t0
+        H, W = lp.ref.shape
+        ref = torch.from_numpy(lp.ref).to(dev)
+        sen = torch.from_numpy(lp.sen).to(dev)
+        dips = torch.from_numpy(lips).to(dev)
+        for kind, dt in (("bf16", S.DTYPE_BF16), ("f16", S.DTYPE_F16)):
+            p = S.preset("baseline", dtype=dt)
+            R = S.Registrar(H, W, H, W, len(lips), lm, lr, p, device=dev)
+            R(ref, sen, dips)
+            torch.cuda.synchronize()
+            dts, _, kt, cps = timed_and_traced(S, torch, lambda: R(ref, sen, dips), args.large_steps)
+            d_ms = kt["describe"][0] / max(1, kt["describe"][1])
+            out["large_" + kind] = {
+                "workload": f"one {H}x{W} seeded pair (speckled sensed image), {len(lips)} IPs (71x71 grid truncated), "
+                            f"template {lm}, search +-{lr}, N=8, sigma 1/2/3, {kind} descriptors, float32 FFT, "
+                            f"float64 integral images and variance; whole images resident in HBM",
+                "value": len(lips) / dts, "unit": "CPs/s", "ms_per_step": 1e3 * dts, "steps": args.large_steps,
+                "sfoc_mpixel_per_s": H * W / (d_ms * 1e-3) / 1e6 if d_ms > 0 else None,
+                "kernels": kernel_table(kt, args.large_steps, p, H, W, len(lips), lm, lr),
+                "parity": parity_vs_stored_oracle(S, "large", cps, kind, ref_kind="o64"),
+                "generate_s": gen_s}
+            del R
+            torch.cuda.empty_cache()
+        del ref, sen, dips
+        torch.cuda.empty_cache()
+    return out
 
 
 def run_batched(args, S, synth, torch, p, dev):
@@ -165,17 +338,31 @@ def run_batched(args, S, synth, torch, p, dev):
     torch.cuda.synchronize()
     plain_s = (time.perf_counter() - t0) / args.batched_steps
 
-    t0 = time.perf_counter()
-    plan = S.Plan(dp, p, flags=S.PLAN_GRAPH | S.PLAN_AUTOTUNE)
-    create_s = time.perf_counter() - t0
-    for _ in range(args.batched_warmup):
-        plan()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.batched_steps):
-        plan()
-    torch.cuda.synchronize()
-    batch_s = (time.perf_counter() - t0) / args.batched_steps
+    def time_plan(flags, pp):
+        t0 = time.perf_counter()
+        plan = S.Plan(dp, pp, flags=flags)
+        create_s = time.perf_counter() - t0
+        for _ in range(args.batched_warmup):
+            plan()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.batched_steps):
+            plan()
+        torch.cuda.synchronize()
+        return plan, (time.perf_counter() - t0) / args.batched_steps, create_s
+
+    def correct(cps_list):
+        n_ok = n_valid = 0
+        for (spec, pr, _), c in zip(work, cps_list):
+            g = S.cps_to_numpy(c)
+            v = (g["flags"] & S.VALID) != 0
+            e = np.hypot(g["dy"] + g["sub_dy"] - pr.shift[0], g["dx"] + g["sub_dx"] - pr.shift[1])
+            n_valid += int(v.sum())
+            n_ok += int((e[v] <= 1.5).sum())
+        return {"valid": n_valid, "correct_1p5px": n_ok}
+
+    plain_cps = [R.cps.clone() for R in regs]
+    plan, batch_s, create_s = time_plan(S.PLAN_GRAPH | S.PLAN_AUTOTUNE, p)
     info = plan.info()
     same = 0
     for k, R in enumerate(regs):
@@ -184,16 +371,35 @@ def run_batched(args, S, synth, torch, p, dev):
     for (spec, _, _), L, nb in zip(work, info["fft_side"], info["blocks"]):
         classes[f"m{spec['m']}_r{spec['r']}"] = f"L{L}x{nb * nb}"
     plan.close()
+    # the same plan describing the sensed images whole, as the per-pair calls
+    # do: the gain of batching alone
+    plan_d, dense_s, _ = time_plan(S.PLAN_GRAPH | S.PLAN_AUTOTUNE | S.PLAN_DENSE_SEN, p)
+    info_d = plan_d.info()
+    plan_d.close()
+    # bfloat16 descriptor storage in the plan, against the plain float32 calls
+    pb = S.preset("baseline", dtype=S.DTYPE_BF16)
+    plan_b, bf16_s, _ = time_plan(S.PLAN_GRAPH | S.PLAN_AUTOTUNE, pb)
+    same_b = 0
+    for k, c in enumerate(plain_cps):
+        a, b = plan_b.cps[k].cpu().numpy(), c.cpu().numpy()
+        same_b += int(((a[:, 2] == b[:, 2]) & (a[:, 3] == b[:, 3])).sum())
+    acc_b = correct(plan_b.cps)
+    plan_b.close()
     return {"workload": f"{len(work)} seeded pairs, square sides U{{512..4096}} ({mpx:.0f} Mpx per image set), "
                         f"{n_ips} uniform IPs (50..500 per pair), m in {{48,64,96}}, r in {{16,32,64}}, "
                         f"every second sensed image speckled; one autotuned plan replayed as a hipGraph",
             "value": n_ips / batch_s, "unit": "CPs/s", "ms_per_step": 1e3 * batch_s,
             "plain_value": n_ips / plain_s, "plain_ms_per_step": 1e3 * plain_s, "gain": plain_s / batch_s,
+            "dense_sensed": {"value": n_ips / dense_s, "ms_per_step": 1e3 * dense_s, "gain": plain_s / dense_s,
+                             "describe_tiles": info_d["describe_tiles"]},
             "identical_cps": same, "ips": n_ips, "steps": args.batched_steps,
+            "accuracy_plain": correct(plain_cps),
             "sides": classes, "persistent": info["persistent"], "describe_tiles": info["describe_tiles"],
             "match_items": info["match_items"],
             "tuned_classes": info["tuned_classes"], "plan_create_s": create_s, "generate_s": gen_s,
-            "device_gb": info["device_bytes"] / 2 ** 30}
+            "device_gb": info["device_bytes"] / 2 ** 30,
+            "bf16": {"value": n_ips / bf16_s, "ms_per_step": 1e3 * bf16_s, "gain_vs_plain_f32": plain_s / bf16_s,
+                     "integer_cps_equal_to_plain_f32": same_b, "accuracy": acc_b}}
 
 
 def run_learned(args, S, synth, torch, p, dev, ref, sen, dips, m, r):
@@ -429,6 +635,9 @@ def main():
     ap.add_argument("--rectify", type=int, default=1, help="10000^2 rectification (0: skip)")
     ap.add_argument("--fast", type=int, default=1, help="block-based FAST detection (0: skip)")
     ap.add_argument("--sweep-pairs", type=int, default=4, help="pairs of the noise-sensitivity sweep (0: skip)")
+    ap.add_argument("--precision", type=int, default=1, help="bfloat16 / float16 storage sections (0: skip)")
+    ap.add_argument("--large", type=int, default=1, help="the 10000^2 precision workload (0: skip)")
+    ap.add_argument("--large-steps", type=int, default=3)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -476,16 +685,14 @@ def main():
 
     z = p.z
     avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kt.items()}   # ms per launch
-    d_ms, m_ms = avg["describe"], avg["match"]
+    d_ms = avg["describe"]
     px = H * W
     sfoc_mpix = px / (d_ms * 1e-3) / 1e6 if d_ms > 0 else None
-    flops_px = sfoc_flops_per_px(p)
-    flops_ip = fastncc_flops_per_ip(m + 2 * r, z)
     per_step = {k: kt[k][0] / args.steps for k in kt}
-    if m_ms * kt["match"][1] >= d_ms * kt["describe"][1]:
-        dom, ach = "match", flops_ip * n / (m_ms * 1e-3)
-    else:
-        dom, ach = "describe", flops_px * px / (d_ms * 1e-3)
+    kernels = kernel_table(kt, args.steps, p, H, W, n, m, r)
+    # the dominant kernel: the largest share of a step's kernel time
+    dom = max(("describe", "match"), key=lambda k: per_step[k])
+    ke = kernels[dom]
     out = {
         "metric": "matched CPs/s + SFOC Mpixel/s",
         "value": cps_s,
@@ -508,11 +715,18 @@ def main():
         "sfoc_mpixel_per_s_step": 2 * px * args.steps / elapsed / 1e6,
         "kernel_ms_per_launch": avg,
         "kernel_ms_per_step": per_step,
-        "roofline": {"kernel": dom, "bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-                     "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU, "traffic": stored_traffic(dom),
-                     "algorithmic": {"sfoc_flop_per_px": flops_px, "fastncc_flop_per_ip": flops_ip}},
+        "roofline": {"kernel": dom, "bound": "alu", "achieved": ke["achieved_tflops"],
+                     "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s", "frac": ke["frac_valu_peak"],
+                     "traffic": stored_traffic(dom),
+                     "algorithmic": {"sfoc_flop_per_px": sfoc_flops_per_px(p),
+                                     "fastncc_flop_per_ip": fastncc_flops_per_ip(m + 2 * r, z, 2 * r + 1),
+                                     "units_per_launch": px if dom == "describe" else n,
+                                     "flop_per_launch": ke["algorithmic_flop"]},
+                     "frac_binding_roof": ke["frac_binding_roof"]},
+        "kernels": kernels,
         "accuracy": {"valid": int(valid.sum()), "correct_1p5px": int((err[valid] <= 1.5).sum()),
                      "rmse_valid_px": float(np.sqrt(np.mean(err[valid] ** 2))) if valid.any() else None},
+        "parity": parity_vs_stored_oracle(S, "scene", R.cps),
     }
     if args.ransac:
         out["ransac"] = run_ransac(args, S, synth, torch, p, dev)
@@ -524,6 +738,8 @@ def main():
         out["noise_sweep"] = run_sweep(args, S, torch)
     if args.learned_pairs > 0:
         out["learned"] = run_learned(args, S, synth, torch, p, dev, ref, sen, dips, m, r)
+    if args.precision:
+        out["precision"] = run_precision(args, S, synth, torch, dev, (pr, ips, m, r))
     if args.batched_steps > 0:
         del R
         torch.cuda.empty_cache()

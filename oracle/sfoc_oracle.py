@@ -534,6 +534,29 @@ def match_one_region(ref: np.ndarray, sen: np.ndarray, ip, m: int, r: int, p: Pa
     return decide(ncc, flatT, nonfin, r), ncc
 
 
+def match_one_region_variants(ref: np.ndarray, sen: np.ndarray, ip, m: int, r: int, p: Params | None = None,
+                              prior=None, quantise=(None,)):
+    """match_one_region for several storage roundings of the same CP: the
+    template and search-window descriptors (Section 2.1) are computed once,
+    then each rounding in `quantise` (None, "bf16", "f16") is applied to
+    both and Eq. 9-16 plus the peak decision run on the rounded values.
+    Returns a list of (record, surface), one per entry of `quantise`, each
+    equal to what match_one_region returns for that rounding."""
+    p = p or Params()
+    (ty, tx), (sy, sx) = window_origins(ip, prior, m, r)
+    M = m + 2 * r
+    if not (in_bounds(ty, tx, m, m, *sen.shape) and in_bounds(sy, sx, M, M, *ref.shape)):
+        return [((0, 0, 0.0, 0.0, 0.0, OOB), np.zeros((2 * r + 1, 2 * r + 1))) for _ in quantise]
+    T0 = sfoc_region(sen, ty, tx, m, m, p)
+    S0 = sfoc_region(ref, sy, sx, M, M, p)
+    out = []
+    for kind in quantise:
+        q = quantiser(kind)
+        ncc, flatT, nonfin = ncc_fast(q(S0), q(T0))
+        out.append((decide(ncc, flatT, nonfin, r), ncc))
+    return out
+
+
 def register_cps(ref: np.ndarray, sen: np.ndarray, ips, m: int, r: int,
                  p: Params | None = None, prior=None, method: str = "fast",
                  quantise=None, want_surfaces: bool = False):

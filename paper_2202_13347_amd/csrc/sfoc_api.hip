@@ -153,10 +153,11 @@ int sfoc_describe(const float* img, int64_t H, int64_t W, int64_t ld, const sfoc
     DescribeConsts c;
     build_describe_consts(p, &c);
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = launch_describe(img, (int)H, (int)W, ld, desc, integ1, integ2, c, st);
+    double* agg = integ1 ? (double*)ws : nullptr;
+    hipError_t e = launch_describe(img, (int)H, (int)W, ld, desc, integ1, integ2, agg, c, st);
     if (e != hipSuccess) return hip_status(e);
     if (integ1) {
-        e = launch_integral(integ1, integ2, (int)H, (int)W, (double*)ws, st);
+        e = launch_integral(integ1, integ2, (int)H, (int)W, agg, st);
         if (e != hipSuccess) return hip_status(e);
     }
     return SFOC_OK;
@@ -230,12 +231,13 @@ int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr, con
     // while the sensed image is described; the match waits for both.
     SideStream* side = nullptr;
     hipError_t e = side_stream(&side);
-    if (e == hipSuccess) e = launch_describe(ref, (int)Hr, (int)Wr, ldr, dref, i1, i2, c, st);
+    double* agg = (double*)(base + L.scan);
+    if (e == hipSuccess) e = launch_describe(ref, (int)Hr, (int)Wr, ldr, dref, i1, i2, agg, c, st);
     if (e == hipSuccess) e = hipEventRecord(side->fork, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->fork, 0);
-    if (e == hipSuccess) e = launch_integral(i1, i2, (int)Hr, (int)Wr, (double*)(base + L.scan), side->s);
+    if (e == hipSuccess) e = launch_integral(i1, i2, (int)Hr, (int)Wr, agg, side->s);
     if (e == hipSuccess) e = hipEventRecord(side->join, side->s);
-    if (e == hipSuccess) e = launch_describe(sen, (int)Hs, (int)Ws, lds, dsen, nullptr, nullptr, c, st);
+    if (e == hipSuccess) e = launch_describe(sen, (int)Hs, (int)Ws, lds, dsen, nullptr, nullptr, nullptr, c, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(st, side->join, 0);
     if (e != hipSuccess) return hip_status(e);
     if (n == 0) return SFOC_OK;

@@ -32,9 +32,9 @@ struct sfoc_plan {
     int4* dtiles = nullptr;
     int ndt = 0, ndt_ref = 0;   // all tiles; reference tiles (first)
     IntegJob* ijobs = nullptr;
-    int4* irows = nullptr;
-    int4* icols = nullptr;
-    int nir = 0, nic = 0;
+    int4* ipre = nullptr;     // integral prefix items (integral_prefix_items)
+    int4* itiles = nullptr;   // integral tiles {job, tile row, tile column}
+    int npre = 0, nitiles = 0;
     MatchArgs* margs = nullptr;
     int4* items[2] = {nullptr, nullptr};   // L = 64, L = 128
     int nitems[2] = {0, 0};
@@ -101,9 +101,7 @@ void append_items(std::vector<int4>& out, int pair, int n, int nb) {
         for (int b = 0; b < nblk; ++b) out.push_back(make_int4(pair, i, b, 0));
 }
 
-// Tune cache: one line per (device, z, dtype, m, r) -> L.
-using TuneKey = std::tuple<std::string, int, int, int, int>;
-
+// Autotuner cache key of a device: architecture and CU count.
 std::string device_key(int dev) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
@@ -112,31 +110,6 @@ std::string device_key(int dev) {
     for (char* c = buf; *c; ++c)
         if (*c == ' ') *c = '_';
     return buf;
-}
-
-std::map<TuneKey, int> read_cache(const char* path) {
-    std::map<TuneKey, int> m;
-    if (!path) return m;
-    FILE* f = fopen(path, "r");
-    if (!f) return m;
-    char dev[160];
-    int z, dt, mm, r, L;
-    while (fscanf(f, "%159s %d %d %d %d %d", dev, &z, &dt, &mm, &r, &L) == 6)
-        if (L == 64 || L == 128) m[TuneKey(dev, z, dt, mm, r)] = L;
-    fclose(f);
-    return m;
-}
-
-void write_cache(const char* path, const std::map<TuneKey, int>& m) {
-    if (!path) return;
-    const std::string tmp = std::string(path) + ".tmp";
-    FILE* f = fopen(tmp.c_str(), "w");
-    if (!f) return;
-    for (const auto& kv : m)
-        fprintf(f, "%s %d %d %d %d %d\n", std::get<0>(kv.first).c_str(), std::get<1>(kv.first),
-                std::get<2>(kv.first), std::get<3>(kv.first), std::get<4>(kv.first), kv.second);
-    fclose(f);
-    rename(tmp.c_str(), path);
 }
 
 // Everything after the describe / integral stage for the plan's current
@@ -173,7 +146,7 @@ hipError_t enqueue_all(sfoc_plan* P, hipStream_t st) {
     if (e == hipSuccess) e = hipEventRecord(P->ev_fork2, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(P->side_stream, P->ev_fork2, 0);
     if (e == hipSuccess)
-        e = launch_integral_batched(P->ijobs, P->irows, P->nir, P->icols, P->nic, P->side_stream);
+        e = launch_integral_batched(P->ijobs, P->ipre, P->npre, P->itiles, P->nitiles, P->side_stream);
     if (e == hipSuccess) e = hipEventRecord(P->ev_join2, P->side_stream);
     if (e == hipSuccess)
         e = launch_describe_batched(P->djobs, P->dtiles + P->ndt_ref, P->ndt - P->ndt_ref, P->c, st);
@@ -336,17 +309,16 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
         pm[k].scan = cur.take(describe_ws_bytes(q.Hr, q.Wr));
         pm[k].ws = cur.take(ws);
     }
-    // integral-scan work lists
+    // integral-image work lists: prefix items, then every tile of each reference
     std::vector<IntegJob> ijobs(n_pairs);
-    std::vector<int4> irows, icols;
+    std::vector<int4> ipre, itiles;
     size_t max_items[2] = {0, 0}, max_peak = 0;
     for (int k = 0; k < n_pairs; ++k) {
         const sfoc_pair& q = pairs[k];
-        for (int y = 0; y <= q.Hr; ++y) irows.push_back(make_int4(k, y, 0, 0));
-        const int nbr = (int)((q.Hr + kScanRows - 1) / kScanRows);
-        const int ncb = (int)((q.Wr + 1 + 255) / 256);
-        for (int b = 0; b < nbr; ++b)
-            for (int x = 0; x < ncb; ++x) icols.push_back(make_int4(k, x, b, 0));
+        integral_prefix_items(k, (int)q.Hr, (int)q.Wr, ipre);
+        const IntegAgg ag = integ_agg(q.Hr, q.Wr);
+        for (int a = 0; a < ag.nty; ++a)
+            for (int b = 0; b < ag.ntx; ++b) itiles.push_back(make_int4(k, a, b, 0));
         for (int L : cands[k]) {
             const MatchPlan m = match_plan_L(q.n, q.m, q.r, L);
             max_items[bucket_of(L)] += (size_t)q.n * m.nb * m.nb;
@@ -356,8 +328,8 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     const size_t o_djobs = cur.take(djobs.size() * sizeof(DescribeJob));
     const size_t o_dtiles = cur.take(dtiles.size() * sizeof(int4));
     const size_t o_ijobs = cur.take(ijobs.size() * sizeof(IntegJob));
-    const size_t o_irows = cur.take(irows.size() * sizeof(int4));
-    const size_t o_icols = cur.take(icols.size() * sizeof(int4));
+    const size_t o_ipre = cur.take(ipre.size() * sizeof(int4));
+    const size_t o_itiles = cur.take(itiles.size() * sizeof(int4));
     const size_t o_margs = cur.take((size_t)n_pairs * sizeof(MatchArgs));
     const size_t o_items0 = cur.take(max_items[0] * sizeof(int4));
     const size_t o_items1 = cur.take(max_items[1] * sizeof(int4));
@@ -378,23 +350,21 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     char* mem = P->mem;
     for (int k = 0; k < n_pairs; ++k) {
         const sfoc_pair& q = pairs[k];
+        double* agg = (double*)(mem + pm[k].scan);
         djobs[2 * k] = DescribeJob{q.ref, mem + pm[k].dref, (double*)(mem + pm[k].i1), (double*)(mem + pm[k].i2),
-                                   q.ldr, (int)q.Hr, (int)q.Wr};
-        djobs[2 * k + 1] = DescribeJob{q.sen, mem + pm[k].dsen, nullptr, nullptr, q.lds, (int)q.Hs, (int)q.Ws};
-        const int nbr = (int)((q.Hr + kScanRows - 1) / kScanRows);
-        double* bs = (double*)(mem + pm[k].scan);
-        ijobs[k] = IntegJob{(double*)(mem + pm[k].i1), (double*)(mem + pm[k].i2), bs, bs + (size_t)nbr * (q.Wr + 1),
-                            (int)q.Hr, (int)q.Wr};
+                                   agg, q.ldr, (int)q.Hr, (int)q.Wr};
+        djobs[2 * k + 1] = DescribeJob{q.sen, mem + pm[k].dsen, nullptr, nullptr, nullptr, q.lds, (int)q.Hs, (int)q.Ws};
+        ijobs[k] = IntegJob{(double*)(mem + pm[k].i1), (double*)(mem + pm[k].i2), agg, (int)q.Hr, (int)q.Wr};
     }
     P->djobs = (DescribeJob*)(mem + o_djobs);
     P->dtiles = (int4*)(mem + o_dtiles);
     P->ndt = (int)dtiles.size();
     P->ndt_ref = nref_tiles;
     P->ijobs = (IntegJob*)(mem + o_ijobs);
-    P->irows = (int4*)(mem + o_irows);
-    P->icols = (int4*)(mem + o_icols);
-    P->nir = (int)irows.size();
-    P->nic = (int)icols.size();
+    P->ipre = (int4*)(mem + o_ipre);
+    P->itiles = (int4*)(mem + o_itiles);
+    P->npre = (int)ipre.size();
+    P->nitiles = (int)itiles.size();
     P->margs = (MatchArgs*)(mem + o_margs);
     P->items[0] = (int4*)(mem + o_items0);
     P->items[1] = (int4*)(mem + o_items1);
@@ -411,8 +381,8 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     up(P->djobs, djobs.data(), djobs.size() * sizeof(DescribeJob));
     up(P->dtiles, dtiles.data(), dtiles.size() * sizeof(int4));
     up(P->ijobs, ijobs.data(), ijobs.size() * sizeof(IntegJob));
-    up(P->irows, irows.data(), irows.size() * sizeof(int4));
-    up(P->icols, icols.data(), icols.size() * sizeof(int4));
+    up(P->ipre, ipre.data(), ipre.size() * sizeof(int4));
+    up(P->itiles, itiles.data(), itiles.size() * sizeof(int4));
     if (e != hipSuccess) {
         free_plan(P);
         return hip_status(e);
@@ -427,22 +397,20 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     }
     if (!classes.empty()) {
         const std::string dev = device_key(P->device);
-        std::map<TuneKey, int> cache = read_cache(tune_cache);
+        TuneCache cache = tune_cache_read(tune_cache);
         bool wrote = false;
         bool described = false;
         for (auto& cl : classes) {
             const int m = cl.first.first, r = cl.first.second;
             const TuneKey key(dev, z, P->dtype, m, r);
-            auto hit = cache.find(key);
-            int best = 0;
-            if (hit != cache.end()) {
-                best = hit->second;
+            int best = tune_cache_lookup(cache, dev, z, P->dtype, m, r);
+            if (best != 0) {
                 ++P->cached;
             } else {
                 if (!described) {   // the candidates are timed on this plan's own descriptors
                     e = launch_describe_batched(P->djobs, P->dtiles, P->ndt, P->c, st);
                     if (e == hipSuccess)
-                        e = launch_integral_batched(P->ijobs, P->irows, P->nir, P->icols, P->nic, st);
+                        e = launch_integral_batched(P->ijobs, P->ipre, P->npre, P->itiles, P->nitiles, st);
                     described = true;
                 }
                 // at most ~2048 IPs of the class are timed
@@ -487,7 +455,7 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
             free_plan(P);
             return hip_status(e);
         }
-        if (wrote) write_cache(tune_cache, cache);
+        if (wrote) (void)tune_cache_write(tune_cache, cache);
     }
 
     // ---- match work lists; costlier items first ----

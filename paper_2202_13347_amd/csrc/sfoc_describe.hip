@@ -516,202 +516,247 @@ __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const De
         emit(0, N);
         emit(N, Z);
     }
-    if (integ1 && gy < H) {
-        const int64_t io = (int64_t)(gy + 1) * (W + 1) + gx0 + 1;
+    if (integ1) {
+        // Per-pixel channel sums of the stored values (zero outside the
+        // image) into the integral-image buffers, and this tile's aggregates
+        // for the prefix pass: row sums (the 8 lanes of a row, butterfly),
+        // column sums (the 8 rows of a wave, butterfly, then the 4 waves in
+        // order) and the total (the 32 column sums in order).  Every sum is
+        // taken in a fixed order, so the integral images are reproducible.
 #pragma unroll
         for (int j = 0; j < kRun; ++j)
-            if (gx0 + j < W) {
-                integ1[io + j] = d1[j];
-                integ2[io + j] = d2[j];
+            if (gy >= H || gx0 + j >= W) d1[j] = d2[j] = 0.0;
+        if (gy < H) {
+            const int64_t io = (int64_t)(gy + 1) * (W + 1) + gx0 + 1;
+#pragma unroll
+            for (int j = 0; j < kRun; ++j)
+                if (gx0 + j < W) {
+                    integ1[io + j] = d1[j];
+                    integ2[io + j] = d2[j];
+                }
+        }
+        const IntegAgg ag = integ_agg(H, W);
+        double* __restrict__ agg = J.agg;
+        const int tb = tx0 / kTS, ta = ty0 / kTS;
+        double r1 = ((d1[0] + d1[1]) + d1[2]) + d1[3];
+        double r2 = ((d2[0] + d2[1]) + d2[2]) + d2[3];
+#pragma unroll
+        for (int d = 1; d < kTS / kRun; d <<= 1) {
+            r1 += __shfl_xor(r1, d, 64);
+            r2 += __shfl_xor(r2, d, 64);
+        }
+        if ((t & (kTS / kRun - 1)) == 0 && gy < H) {
+            agg[ag.rs1 + tb * (int64_t)H + gy] = r1;
+            agg[ag.rs2 + tb * (int64_t)H + gy] = r2;
+        }
+#pragma unroll
+        for (int j = 0; j < kRun; ++j)
+#pragma unroll
+            for (int d = kTS / kRun; d < 64; d <<= 1) {
+                d1[j] += __shfl_xor(d1[j], d, 64);
+                d2[j] += __shfl_xor(d2[j], d, 64);
             }
+        double* cs = reinterpret_cast<double*>(lds);   // [map][wave][column], then [map][column]
+        const int lane = t & 63, wv = t >> 6;
+        if (lane < kTS / kRun) {
+#pragma unroll
+            for (int j = 0; j < kRun; ++j) {
+                cs[(0 * (kNT / 64) + wv) * kTS + lane * kRun + j] = d1[j];
+                cs[(1 * (kNT / 64) + wv) * kTS + lane * kRun + j] = d2[j];
+            }
+        }
+        __syncthreads();
+        double* ct = cs + 2 * (kNT / 64) * kTS;
+        if (t < 2 * kTS) {
+            const int q = t / kTS, x = t % kTS;
+            double c = 0.0;
+#pragma unroll
+            for (int w = 0; w < kNT / 64; ++w) c += cs[(q * (kNT / 64) + w) * kTS + x];
+            ct[q * kTS + x] = c;
+            if (tx0 + x < W) agg[(q ? ag.cs2 : ag.cs1) + ta * (int64_t)W + tx0 + x] = c;
+        }
+        __syncthreads();
+        if (t < 2) {
+            double c = 0.0;
+            for (int x = 0; x < kTS; ++x) c += ct[t * kTS + x];
+            agg[(t ? ag.tt2 : ag.tt1) + ta * ag.ntx + tb] = c;
+        }
     }
 }
 
 
-// ---- integral images (Eq. 15 as two scans) -----------------------------
-// Row pass: in place, inclusive prefix along each row 1..H of the
-// (H+1) x (W+1) image, column 0 and row 0 set to zero.
-constexpr int kScanNT = 256;
-constexpr int kScanPer = 8;
+// ---- integral images (Eq. 14-16) ------------------------------------------
+// The inclusive 2-D prefix sum (Eq. 15) of a per-pixel map s, at a pixel
+// (y0 + i, x0 + j) of the tile (a, b) with origin (y0, x0), splits into
+//   Corner(a, b)                  the tiles above and to the left,
+// + sum_{j' <= j} Above(x0 + j')  the rows above the tile, per column,
+// + sum_{i' <= i} [Left(y0 + i') + sum_{j' <= j} s(y0 + i', x0 + j')]
+// with Left(y) the sum of row y left of the tile and Above(x) the sum of
+// column x above it.  The describe kernel wrote s into the integral buffers
+// and each tile's row sums, column sums and total; integral_prefix turns
+// these into Left (exclusive prefixes of the row sums over tile columns),
+// Above (of the column sums over tile rows) and Corner (the 2-D exclusive
+// prefix of the tile totals); integral_tiles then reads s once and writes
+// the prefix sums in place.  All sums are in a fixed order.
+
+// In place: v[0], v[step], ... (n entries) -> their exclusive prefix sums.
+SFOC_DEV void exclusive_prefix(double* __restrict__ v, int64_t n, int64_t step) {
+    double run = 0.0;
+    int64_t k = 0;
+    for (; k + 8 <= n; k += 8) {   // eight loads in flight, then the sums in order
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = v[(k + u) * step];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            v[(k + u) * step] = run;
+            run += a[u];
+        }
+    }
+    for (; k < n; ++k) {
+        const double a = v[k * step];
+        v[k * step] = run;
+        run += a;
+    }
+}
+
+void integral_prefix_items(int job, int H, int W, std::vector<int4>& out) {
+    for (int k = 0; k < (H + kScanNT - 1) / kScanNT; ++k) out.push_back(make_int4(job, 0, k, 0));
+    for (int k = 0; k < (W + kScanNT - 1) / kScanNT; ++k) out.push_back(make_int4(job, 1, k, 0));
+    out.push_back(make_int4(job, 2, 0, 0));
+}
 
 template <bool BATCH>
-__global__ __launch_bounds__(kScanNT) void integral_row_scan(const IntegJob single, const IntegJob* __restrict__ jobs,
-                                                              const int4* __restrict__ rows) {
-    __shared__ double wsum[2][kScanNT / 64];
-    const IntegJob J = BATCH ? load_table(jobs, rows[blockIdx.x].x) : single;
-    const int y = BATCH ? rows[blockIdx.x].y : (int)blockIdx.x;   // 0..H
-    double* __restrict__ g1 = J.g1;
-    double* __restrict__ g2 = J.g2;
-    const int W = J.W;
-    const int t = threadIdx.x;
-    const int64_t rowoff = (int64_t)y * (W + 1);
-    if (y == 0) {
-        for (int x = t; x <= W; x += kScanNT) {
-            g1[x] = 0.0;
-            g2[x] = 0.0;
-        }
-        return;
+__global__ __launch_bounds__(kScanNT) void integral_prefix(const IntegJob single, const IntegJob* __restrict__ jobs,
+                                                           const int4* __restrict__ items) {
+    IntegJob J;
+    int kind, blk;
+    if (BATCH) {
+        const int4 it = items[blockIdx.x];
+        J = load_table(jobs, it.x);
+        kind = it.y;
+        blk = it.z;
+    } else {
+        J = single;
+        const int nbr = (J.H + kScanNT - 1) / kScanNT, nbc = (J.W + kScanNT - 1) / kScanNT;
+        const int k = blockIdx.x;
+        kind = k < nbr ? 0 : (k < nbr + nbc ? 1 : 2);
+        blk = kind == 0 ? k : (kind == 1 ? k - nbr : 0);
     }
-    double carry[2] = {0.0, 0.0};
-    if (t == 0) {
-        g1[rowoff] = 0.0;
-        g2[rowoff] = 0.0;
-    }
-    const int seg = kScanNT * kScanPer;
-    for (int x0 = 1; x0 <= W; x0 += seg) {
-        // thread t owns the kScanPer consecutive elements from x0 + t kScanPer,
-        // held in registers: serial sums, then a wave scan of the thread
-        // totals and the workgroup's wave offsets
-        const int xb = x0 + t * kScanPer;
-        double v[2][kScanPer];
-        for (int q = 0; q < 2; ++q) {
-            const double* g = q ? g2 : g1;
-#pragma unroll
-            for (int i = 0; i < kScanPer; ++i) v[q][i] = xb + i <= W ? g[rowoff + xb + i] : 0.0;
+    const int H = J.H, W = J.W, t = threadIdx.x;
+    const IntegAgg ag = integ_agg(H, W);
+    double* __restrict__ agg = J.agg;
+    if (kind == 0) {          // Left: per row y, over the tile columns
+        const int y = blk * kScanNT + t;
+        if (y < H) {
+            exclusive_prefix(agg + ag.rs1 + y, ag.ntx, H);
+            exclusive_prefix(agg + ag.rs2 + y, ag.ntx, H);
         }
-        double tot[2];
-        for (int q = 0; q < 2; ++q) {
-            double s = 0.0;
-#pragma unroll
-            for (int i = 0; i < kScanPer; ++i) {
-                s += v[q][i];
-                v[q][i] = s;
-            }
-            tot[q] = s;
+    } else if (kind == 1) {   // Above: per column x, over the tile rows
+        const int x = blk * kScanNT + t;
+        if (x < W) {
+            exclusive_prefix(agg + ag.cs1 + x, ag.nty, W);
+            exclusive_prefix(agg + ag.cs2 + x, ag.nty, W);
         }
-        // inclusive scan of per-thread totals within the wave
-        const int lane = t & 63, wv = t >> 6;
+    } else {                  // Corner: tile totals, over tile columns, then over tile rows
         for (int q = 0; q < 2; ++q) {
-            double x = tot[q];
-            for (int d = 1; d < 64; d <<= 1) {
-                const double u = __shfl_up(x, d, 64);
-                if (lane >= d) x += u;
-            }
-            if (lane == 63) wsum[q][wv] = x;
-            const double ex = __shfl_up(x, 1, 64);
-            tot[q] = lane == 0 ? 0.0 : ex;   // exclusive within wave
+            double* tt = agg + (q ? ag.tt2 : ag.tt1);
+            for (int64_t a = t; a < ag.nty; a += kScanNT) exclusive_prefix(tt + a * ag.ntx, ag.ntx, 1);
         }
         __syncthreads();
         for (int q = 0; q < 2; ++q) {
-            double pre = carry[q];
-            for (int w = 0; w < wv; ++w) pre += wsum[q][w];
-            const double add = pre + tot[q];
-#pragma unroll
-            for (int i = 0; i < kScanPer; ++i) v[q][i] += add;
-            double all = carry[q];
-            for (int w = 0; w < kScanNT / 64; ++w) all += wsum[q][w];
-            carry[q] = all;
+            double* tt = agg + (q ? ag.tt2 : ag.tt1);
+            for (int64_t b = t; b < ag.ntx; b += kScanNT) exclusive_prefix(tt + b, ag.nty, ag.ntx);
         }
-        for (int q = 0; q < 2; ++q) {
-            double* g = q ? g2 : g1;
-#pragma unroll
-            for (int i = 0; i < kScanPer; ++i)
-                if (xb + i <= W) g[rowoff + xb + i] = v[q][i];
-        }
-        __syncthreads();   // wsum is rewritten by the next segment
     }
 }
 
-// Column pass, phase 1: per block of kScanRows rows, the column totals.
+// One 32 x 32 tile per workgroup: thread t holds a run of 4 pixels of row
+// t / 8.  Row 0 and column 0 of the integral images are set to zero by the
+// tiles that border them.
 template <bool BATCH>
-__global__ __launch_bounds__(kScanNT) void integral_col_blocksum(const IntegJob single,
-                                                                  const IntegJob* __restrict__ jobs,
-                                                                  const int4* __restrict__ cols) {
-    const IntegJob J = BATCH ? load_table(jobs, cols[blockIdx.x].x) : single;
-    const int bx = BATCH ? cols[blockIdx.x].y : (int)blockIdx.x;
-    const int b = BATCH ? cols[blockIdx.x].z : (int)blockIdx.y;
-    const int H = J.H, W = J.W;
-    const double* __restrict__ g1 = J.g1;
-    const double* __restrict__ g2 = J.g2;
-    double* __restrict__ bs1 = J.bs1;
-    double* __restrict__ bs2 = J.bs2;
-    const int x = bx * kScanNT + threadIdx.x;
-    if (x > W) return;
-    const int y0 = 1 + b * kScanRows, y1 = min(H, y0 + kScanRows - 1);
+__global__ __launch_bounds__(kScanNT) void integral_tiles(const IntegJob single, const IntegJob* __restrict__ jobs,
+                                                          const int4* __restrict__ tiles) {
+    static_assert(kScanNT == kTS * kTS / kRun, "one run of 4 pixels per thread");
+    IntegJob J;
+    int ta, tb;
+    if (BATCH) {
+        const int4 e = tiles[blockIdx.x];
+        J = load_table(jobs, e.x);
+        ta = e.y;
+        tb = e.z;
+    } else {
+        J = single;
+        ta = blockIdx.y;
+        tb = blockIdx.x;
+    }
+    __shared__ double above[2][kTS];
+    __shared__ double wtot[2][kScanNT / 64][kTS];
+    const int H = J.H, W = J.W, t = threadIdx.x;
+    const IntegAgg ag = integ_agg(H, W);
+    const double* __restrict__ agg = J.agg;
     const int64_t P = W + 1;
-    double s1 = 0.0, s2 = 0.0;
-    int y = y0;
-    // eight rows' loads in flight, then the sums in row order
-    for (; y + 7 <= y1; y += 8) {
-        double a1[8], a2[8];
+    const int y0 = ta * kTS, x0 = tb * kTS;
+    const int i = t / (kTS / kRun), j0 = (t % (kTS / kRun)) * kRun, rl = t % (kTS / kRun);
+    const int lane = t & 63, wv = t >> 6;
+    const int y = y0 + i;
+    // Corner + prefix over the tile's columns of Above (wave 0: map 1 in
+    // lanes 0..31, map 2 in lanes 32..63)
+    if (t < 2 * kTS) {
+        const int q = t / kTS, jj = t % kTS;
+        double v = x0 + jj < W ? agg[(q ? ag.cs2 : ag.cs1) + ta * (int64_t)W + x0 + jj] : 0.0;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            a1[k] = g1[(int64_t)(y + k) * P + x];
-            a2[k] = g2[(int64_t)(y + k) * P + x];
+        for (int d = 1; d < kTS; d <<= 1) {
+            const double u = __shfl_up(v, d, kTS);
+            if (jj >= d) v += u;
         }
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            s1 += a1[k];
-            s2 += a2[k];
-        }
+        above[q][jj] = agg[(q ? ag.tt2 : ag.tt1) + ta * ag.ntx + tb] + v;
     }
-    for (; y <= y1; ++y) {
-        s1 += g1[(int64_t)y * P + x];
-        s2 += g2[(int64_t)y * P + x];
-    }
-    bs1[(int64_t)b * (W + 1) + x] = s1;
-    bs2[(int64_t)b * (W + 1) + x] = s2;
-}
-
-// Column pass, phase 2: carry from the blocks above, then the in-block scan.
-template <bool BATCH>
-__global__ __launch_bounds__(kScanNT) void integral_col_apply(const IntegJob single, const IntegJob* __restrict__ jobs,
-                                                               const int4* __restrict__ cols) {
-    const IntegJob J = BATCH ? load_table(jobs, cols[blockIdx.x].x) : single;
-    const int bx = BATCH ? cols[blockIdx.x].y : (int)blockIdx.x;
-    const int b = BATCH ? cols[blockIdx.x].z : (int)blockIdx.y;
-    const int H = J.H, W = J.W;
-    double* __restrict__ g1 = J.g1;
-    double* __restrict__ g2 = J.g2;
-    const double* __restrict__ bs1 = J.bs1;
-    const double* __restrict__ bs2 = J.bs2;
-    const int x = bx * kScanNT + threadIdx.x;
-    if (x > W) return;
-    const int64_t P = W + 1;
-    double c1 = 0.0, c2 = 0.0;
-    // eight loads in flight per step; sums in block and row order
-    int q = 0;
-    for (; q + 7 < b; q += 8) {
-        double a1[8], a2[8];
+    double r[2][kRun];
+    for (int q = 0; q < 2; ++q) {
+        double* __restrict__ g = q ? J.g2 : J.g1;
+        double v[kRun];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            a1[k] = bs1[(int64_t)(q + k) * P + x];
-            a2[k] = bs2[(int64_t)(q + k) * P + x];
-        }
+        for (int k = 0; k < kRun; ++k) v[k] = (y < H && x0 + j0 + k < W) ? g[(int64_t)(y + 1) * P + x0 + j0 + 1 + k] : 0.0;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            c1 += a1[k];
-            c2 += a2[k];
-        }
-    }
-    for (; q < b; ++q) {
-        c1 += bs1[(int64_t)q * P + x];
-        c2 += bs2[(int64_t)q * P + x];
-    }
-    const int y0 = 1 + b * kScanRows, y1 = min(H, y0 + kScanRows - 1);
-    int y = y0;
-    for (; y + 7 <= y1; y += 8) {
-        double a1[8], a2[8];
+        for (int k = 1; k < kRun; ++k) v[k] += v[k - 1];
+        // exclusive prefix of the run totals over the 8 lanes of the row
+        double inc = v[kRun - 1];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            a1[k] = g1[(int64_t)(y + k) * P + x];
-            a2[k] = g2[(int64_t)(y + k) * P + x];
+        for (int d = 1; d < kTS / kRun; d <<= 1) {
+            const double u = __shfl_up(inc, d, kTS / kRun);
+            if (rl >= d) inc += u;
         }
+        double ex = __shfl_up(inc, 1, kTS / kRun);
+        if (rl == 0) ex = 0.0;
+        const double left = y < H ? agg[(q ? ag.rs2 : ag.rs1) + tb * (int64_t)H + y] : 0.0;
+        const double base = left + ex;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int64_t o = (int64_t)(y + k) * P + x;
-            c1 += a1[k];
-            c2 += a2[k];
-            g1[o] = c1;
-            g2[o] = c2;
-        }
+        for (int k = 0; k < kRun; ++k) r[q][k] = base + v[k];
+        // prefix over the 8 rows of the wave, column by column
+#pragma unroll
+        for (int d = kTS / kRun; d < 64; d <<= 1)
+#pragma unroll
+            for (int k = 0; k < kRun; ++k) {
+                const double u = __shfl_up(r[q][k], d, 64);
+                if (lane >= d) r[q][k] += u;
+            }
+        if (lane >= 64 - kTS / kRun)
+#pragma unroll
+            for (int k = 0; k < kRun; ++k) wtot[q][wv][j0 + k] = r[q][k];
     }
-    for (; y <= y1; ++y) {
-        const int64_t o = (int64_t)y * P + x;
-        c1 += g1[o];
-        c2 += g2[o];
-        g1[o] = c1;
-        g2[o] = c2;
+    __syncthreads();
+    for (int q = 0; q < 2; ++q) {
+        double* __restrict__ g = q ? J.g2 : J.g1;
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+            double acc = above[q][j0 + k];
+            for (int w = 0; w < wv; ++w) acc += wtot[q][w][j0 + k];
+            if (y < H && x0 + j0 + k < W) g[(int64_t)(y + 1) * P + x0 + j0 + 1 + k] = acc + r[q][k];
+        }
+        if (ta == 0 && t < kTS && x0 + t < W) g[x0 + t + 1] = 0.0;
+        if (ta == 0 && tb == 0 && t == 0) g[0] = 0.0;
+        if (tb == 0 && rl == 0 && y < H) g[(int64_t)(y + 1) * P] = 0.0;
     }
 }
 
@@ -765,33 +810,31 @@ hipError_t launch_describe_batched(const DescribeJob* jobs, const int4* tiles, i
 }
 
 hipError_t launch_describe(const float* img, int H, int W, int64_t ld, void* desc, double* i1, double* i2,
-                           const DescribeConsts& c, hipStream_t st) {
-    DescribeJob job{img, desc, i1, i2, ld, H, W};
+                           double* agg, const DescribeConsts& c, hipStream_t st) {
+    DescribeJob job{img, desc, i1, i2, agg, ld, H, W};
     return launch_describe_any(job, nullptr, nullptr, 0, c, st);
 }
 
-hipError_t launch_integral(double* i1, double* i2, int H, int W, double* ws, hipStream_t st) {
-    const int nb = (H + kScanRows - 1) / kScanRows;
-    const IntegJob J{i1, i2, ws, ws + (size_t)nb * (W + 1), H, W};
+hipError_t launch_integral(double* i1, double* i2, int H, int W, double* agg, hipStream_t st) {
+    const IntegJob J{i1, i2, agg, H, W};
     const IntegJob* none = nullptr;
     const int4* nit = nullptr;
+    const int npre = (H + kScanNT - 1) / kScanNT + (W + kScanNT - 1) / kScanNT + 1;
     trace_begin(st, SFOC_K_INTEGRAL);
-    hipLaunchKernelGGL(integral_row_scan<false>, dim3(H + 1), dim3(kScanNT), 0, st, J, none, nit);
-    dim3 grid((W + 1 + kScanNT - 1) / kScanNT, nb);
-    hipLaunchKernelGGL(integral_col_blocksum<false>, grid, dim3(kScanNT), 0, st, J, none, nit);
-    hipLaunchKernelGGL(integral_col_apply<false>, grid, dim3(kScanNT), 0, st, J, none, nit);
+    hipLaunchKernelGGL(integral_prefix<false>, dim3(npre), dim3(kScanNT), 0, st, J, none, nit);
+    hipLaunchKernelGGL(integral_tiles<false>, dim3((W + kTS - 1) / kTS, (H + kTS - 1) / kTS), dim3(kScanNT), 0, st,
+                       J, none, nit);
     trace_end(st, SFOC_K_INTEGRAL);
     return hipGetLastError();
 }
 
-hipError_t launch_integral_batched(const IntegJob* jobs, const int4* rows, int nrows, const int4* cols, int ncols,
+hipError_t launch_integral_batched(const IntegJob* jobs, const int4* pre, int npre, const int4* tiles, int ntiles,
                                    hipStream_t st) {
-    if (nrows == 0) return hipSuccess;
+    if (npre == 0) return hipSuccess;
     const IntegJob none{};
     trace_begin(st, SFOC_K_INTEGRAL);
-    hipLaunchKernelGGL(integral_row_scan<true>, dim3(nrows), dim3(kScanNT), 0, st, none, jobs, rows);
-    hipLaunchKernelGGL(integral_col_blocksum<true>, dim3(ncols), dim3(kScanNT), 0, st, none, jobs, cols);
-    hipLaunchKernelGGL(integral_col_apply<true>, dim3(ncols), dim3(kScanNT), 0, st, none, jobs, cols);
+    hipLaunchKernelGGL(integral_prefix<true>, dim3(npre), dim3(kScanNT), 0, st, none, jobs, pre);
+    hipLaunchKernelGGL(integral_tiles<true>, dim3(ntiles), dim3(kScanNT), 0, st, none, jobs, tiles);
     trace_end(st, SFOC_K_INTEGRAL);
     return hipGetLastError();
 }

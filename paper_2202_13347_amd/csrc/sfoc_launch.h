@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "sfoc_plan.h"
 
 namespace sfoc {
@@ -17,17 +19,17 @@ struct DescribeJob {
     void* desc;
     double* integ1;   // (H+1) x (W+1) per-pixel sum / sum of squares, or null
     double* integ2;
+    double* agg;      // per-tile aggregates (layout integ_agg(H, W)) when integ1 is set
     int64_t ld;
     int H, W;
 };
 
-// The float64 integral images of one reference image and the scratch of
-// the column pass (ceil(H / kScanRows) x (W + 1) doubles per image).
+// The float64 integral images of one reference image and the per-tile
+// aggregates its describe launch wrote (layout integ_agg(H, W)).
 struct IntegJob {
     double* g1;
     double* g2;
-    double* bs1;
-    double* bs2;
+    double* agg;
     int H, W;
 };
 
@@ -48,9 +50,6 @@ struct MatchArgs {
     int32_t nbu, nbv, Vb;   // offset blocks per axis and offsets per block
 };
 
-// Side of the square describe tile.
-constexpr int kDescribeTile = 32;
-
 // SFOC_OK for hipSuccess, else SFOC_E_HIP (the HIP error is kept for
 // sfoc_status_string).
 int hip_status(hipError_t e);
@@ -61,9 +60,12 @@ int hip_status(hipError_t e);
 hipError_t ensure_dynamic_lds(const void* kern, int bytes);
 
 // ---- one image / one pair ------------------------------------------------
+// i1, i2 and agg (the aggregates, describe_ws_bytes) all null, or all set.
 hipError_t launch_describe(const float* img, int H, int W, int64_t ld, void* desc, double* i1, double* i2,
-                           const DescribeConsts& c, hipStream_t st);
-hipError_t launch_integral(double* i1, double* i2, int H, int W, double* ws, hipStream_t st);
+                           double* agg, const DescribeConsts& c, hipStream_t st);
+// Completes the integral images from what launch_describe left in i1, i2
+// and agg (the same buffers).
+hipError_t launch_integral(double* i1, double* i2, int H, int W, double* agg, hipStream_t st);
 hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void* desc_ref, int64_t Hr, int64_t Wr,
                         const double* i1, const double* i2, int z, int dtype, const int32_t* ips,
                         const int32_t* prior, int n, int m, int r, float* ncc, sfoc_cp* cps, void* ws,
@@ -76,9 +78,16 @@ void match_args_layout(MatchArgs& a, const MatchPlan& mp, void* ws);
 // tiles[k] = {job, tile row origin, tile column origin, 0}
 hipError_t launch_describe_batched(const DescribeJob* jobs, const int4* tiles, int ntiles, const DescribeConsts& c,
                                    hipStream_t st);
-// rows[k] = {job, row 0..H, 0, 0};  cols[k] = {job, column block, row block, 0}
-hipError_t launch_integral_batched(const IntegJob* jobs, const int4* rows, int nrows, const int4* cols, int ncols,
+// pre[k] = {job, kind, block, 0}: kind 0 a block of kScanNT rows of the
+// row sums, 1 a block of kScanNT columns of the column sums, 2 the tile
+// totals (integral_prefix_items lists them); tiles[k] = {job, tile row,
+// tile column, 0} over every tile of every image
+hipError_t launch_integral_batched(const IntegJob* jobs, const int4* pre, int npre, const int4* tiles, int ntiles,
                                    hipStream_t st);
+// Threads per workgroup of the integral kernels, and the prefix work items
+// of one image.
+constexpr int kScanNT = 256;
+void integral_prefix_items(int job, int H, int W, std::vector<int4>& out);
 // items[k] = {pair, IP, offset block, 0}, all with transform side L; one
 // workgroup per item, or (counter != null) a persistent grid of `grid`
 // workgroups taking items from *counter (zeroed by the launch)

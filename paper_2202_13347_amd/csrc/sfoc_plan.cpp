@@ -1,7 +1,10 @@
 // Host-side parameter checks, constant synthesis and workspace sizing.
 #include "sfoc_plan.h"
 
+#include <errno.h>
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 namespace sfoc {
@@ -143,13 +146,12 @@ int build_describe_consts(const sfoc_params* p, DescribeConsts* c) {
 }
 
 size_t describe_ws_bytes(int64_t H, int64_t W) {
-    const int64_t nb = (H + kScanRows - 1) / kScanRows;
-    return align_up((size_t)(nb * (W + 1)) * sizeof(double) * 2, 256);
+    return align_up((size_t)integ_agg(H, W).total * sizeof(double), 256);
 }
 
 MatchPlan match_plan_L(int32_t n, int32_t m, int32_t r, int L) {
     MatchPlan p{0, 1, 0, 0};
-    if (m < 3 || r < 1 || r > kMaxRadiusMatch || n < 0 || (L != 64 && L != 128)) return p;
+    if (m < 3 || m > 128 || r < 1 || r > kMaxRadiusMatch || n < 0 || (L != 64 && L != 128)) return p;
     const int M = m + 2 * r, V = 2 * r + 1;
     if (M <= L) {
         p.L = L;
@@ -166,7 +168,9 @@ MatchPlan match_plan_L(int32_t n, int32_t m, int32_t r, int L) {
 }
 
 MatchPlan match_plan(int32_t n, int32_t m, int32_t r) {
-    if (m < 3 || r < 1) return MatchPlan{0, 1, 0, 0};
+    // (templates beyond 128 never fit a transform; the bounds also keep
+    // m + 2r far from int overflow)
+    if (m < 3 || r < 1 || m > 128 || r > kMaxRadiusMatch) return MatchPlan{0, 1, 0, 0};
     const int M = m + 2 * r;
     if (M <= 64) return match_plan_L(n, m, r, 64);
     if (m > 126) return MatchPlan{0, 1, 0, 0};
@@ -182,6 +186,73 @@ int match_candidates(int32_t m, int32_t r, int* Ls) {
     const MatchPlan o = match_plan_L(1, m, r, other);
     if (o.L != 0 && o.nb <= kMaxTuneBlocks && o.Vb >= 2) Ls[k++] = other;
     return k;
+}
+
+static bool is_candidate(int m, int r, int L) {
+    int Ls[2];
+    const int n = match_candidates(m, r, Ls);
+    for (int k = 0; k < n; ++k)
+        if (Ls[k] == L) return true;
+    return false;
+}
+
+// One integer field of a cache line: optional sign and decimal digits,
+// within [-2^30, 2^30]; false on anything else.
+static bool parse_field(const char* tok, int* out) {
+    if (!tok) return false;
+    char* end = nullptr;
+    errno = 0;
+    const long v = strtol(tok, &end, 10);
+    if (errno != 0 || end == tok || *end != '\0' || v < -(1L << 30) || v > (1L << 30)) return false;
+    *out = (int)v;
+    return true;
+}
+
+TuneCache tune_cache_read(const char* path) {
+    TuneCache cache;
+    if (!path) return cache;
+    FILE* f = fopen(path, "r");
+    if (!f) return cache;
+    char line[512];
+    while (fgets(line, sizeof line, f)) {
+        // exactly six whitespace-separated fields: device z dtype m r L
+        char* save = nullptr;
+        const char* tok[7];
+        int nt = 0;
+        for (char* t = strtok_r(line, " \t\r\n", &save); t && nt < 7; t = strtok_r(nullptr, " \t\r\n", &save))
+            tok[nt++] = t;
+        if (nt != 6 || strlen(tok[0]) >= 160) continue;
+        int v[5];
+        bool ok = true;
+        for (int k = 0; k < 5 && ok; ++k) ok = parse_field(tok[k + 1], &v[k]);
+        if (!ok) continue;
+        const int z = v[0], dt = v[1], m = v[2], r = v[3], L = v[4];
+        if (z < 1 || dtype_size(dt) == 0 || !is_candidate(m, r, L)) continue;
+        cache[TuneKey(tok[0], z, dt, m, r)] = L;
+    }
+    fclose(f);
+    return cache;
+}
+
+bool tune_cache_write(const char* path, const TuneCache& cache) {
+    if (!path) return false;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    bool ok = true;
+    for (const auto& kv : cache)
+        ok = ok && fprintf(f, "%s %d %d %d %d %d\n", std::get<0>(kv.first).c_str(), std::get<1>(kv.first),
+                           std::get<2>(kv.first), std::get<3>(kv.first), std::get<4>(kv.first), kv.second) > 0;
+    ok = (fclose(f) == 0) && ok;
+    if (ok) ok = rename(tmp.c_str(), path) == 0;
+    else remove(tmp.c_str());
+    return ok;
+}
+
+int tune_cache_lookup(const TuneCache& cache, const std::string& dev, int z, int dtype, int m, int r) {
+    const auto it = cache.find(TuneKey(dev, z, dtype, m, r));
+    if (it == cache.end() || !is_candidate(m, r, it->second)) return 0;
+    return it->second;
 }
 
 void sensed_tile_mask(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m, int32_t r, int64_t Hs,

@@ -5,7 +5,19 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <map>
+#include <string>
+#include <tuple>
+
 #include "sfoc.h"
+
+// Layout helpers below are also called by device code when this header is
+// compiled for the GPU.
+#ifdef __HIPCC__
+#define SFOC_HOST_DEVICE __host__ __device__
+#else
+#define SFOC_HOST_DEVICE
+#endif
 
 namespace sfoc {
 
@@ -41,8 +53,33 @@ int build_describe_consts(const sfoc_params* p, DescribeConsts* c);
 // Element size of a descriptor dtype (0 on a bad dtype).
 size_t dtype_size(int32_t dtype);
 
-// Integral-image column scan: rows per block.
-constexpr int kScanRows = 64;
+// Side of the square describe tile.
+constexpr int kDescribeTile = 32;
+
+// Integral images (Eq. 14-16) are assembled per describe tile from
+// aggregates the describe kernel writes for each tile (a, b) and each of the
+// two maps (sum_c g and sum_c g^2): the tile's row sums RS[b][y] (global row
+// y), column sums CS[a][x] (global column x) and total TT[a][b].  Offsets in
+// doubles inside the describe workspace; ntx, nty are the tile counts.
+struct IntegAgg {
+    int64_t ntx, nty;
+    int64_t rs1, rs2, cs1, cs2, tt1, tt2, total;
+};
+inline SFOC_HOST_DEVICE IntegAgg integ_agg(int64_t H, int64_t W) {
+    IntegAgg g;
+    g.ntx = (W + kDescribeTile - 1) / kDescribeTile;
+    g.nty = (H + kDescribeTile - 1) / kDescribeTile;
+    g.rs1 = 0;
+    g.rs2 = g.rs1 + g.ntx * H;
+    g.cs1 = g.rs2 + g.ntx * H;
+    g.cs2 = g.cs1 + g.nty * W;
+    g.tt1 = g.cs2 + g.nty * W;
+    g.tt2 = g.tt1 + g.nty * g.ntx;
+    g.total = g.tt2 + g.nty * g.ntx;
+    return g;
+}
+// Bytes of the aggregates (the describe workspace when integral images are
+// asked for): 2 (ntx H + nty W + nty ntx) doubles, about 1 byte per pixel.
 size_t describe_ws_bytes(int64_t H, int64_t W);
 
 // How a match is laid out: FFT side L and the split of the (2r+1)^2 offsets
@@ -63,6 +100,20 @@ constexpr int kMaxRadiusMatch = 511;
 // default first.  Returns the count written to Ls (at most 2).
 constexpr int kMaxTuneBlocks = 8;
 int match_candidates(int32_t m, int32_t r, int* Ls);
+
+// Autotuner cache: one text line "device z dtype m r L" per (m, r) class
+// timed before.  Reading keeps only lines that parse completely and whose
+// side L is one of match_candidates(m, r) for a positive z and a known
+// dtype; anything else in the file (a corrupt or hand-edited line) is
+// skipped, so a cached side is always one the match launches accept.
+using TuneKey = std::tuple<std::string, int, int, int, int>;   // device, z, dtype, m, r
+using TuneCache = std::map<TuneKey, int>;
+TuneCache tune_cache_read(const char* path);
+// Writes every entry (to path.tmp, then renamed); false on an I/O error.
+bool tune_cache_write(const char* path, const TuneCache& cache);
+// The cached side for the class, or 0 when there is none or it is not a
+// candidate for (m, r) (the caller then times the class or takes the default).
+int tune_cache_lookup(const TuneCache& cache, const std::string& dev, int z, int dtype, int m, int r);
 
 // Sensed-image describe tiles (side kTile) that the templates of in-bounds
 // interest points read: mask[ty * ceil(Ws / kTile) + tx] = 1.  An IP whose

@@ -36,6 +36,15 @@ def cmr(cps: np.ndarray, shift, prior=None) -> tuple[int, int]:
     return int((ok & peak).sum()), int(peak.sum())
 
 
+NOISE = {"gaussian": synth.gaussian_noise, "speckle": synth.speckle_noise}
+
+
+def noisy_sensed(sen: np.ndarray, kind: str, v: float, pair_index: int) -> np.ndarray:
+    """The sensed image of pair `pair_index` with noise of type `kind` and
+    variance v, seeded per pair and level (v = 0: unchanged)."""
+    return NOISE[kind](sen, v, 1000 * pair_index + int(round(v * 1e4))) if v > 0 else sen
+
+
 def run(n_pairs: int | None = None, recipe: dict = synth.SWEEP, preset: str = "paper", device="cuda", log=None):
     """CMR (averaged over pairs, and pooled) per noise type and level, for
     SFOC and F-SFOC.  Returns a dict of tables and the GPU time spent."""
@@ -55,15 +64,14 @@ def run(n_pairs: int | None = None, recipe: dict = synth.SWEEP, preset: str = "p
     out = {"levels": {"gaussian": recipe["gaussian"], "speckle": recipe["speckle"]}, "pairs": n_pairs,
            "template": m, "radius": r, "size": size, "ips_per_pair": nby * nbx, "preset": preset}
     gpu_s = 0.0
-    for kind, levels, noise in (("gaussian", recipe["gaussian"], synth.gaussian_noise),
-                                ("speckle", recipe["speckle"], synth.speckle_noise)):
+    for kind, levels in (("gaussian", recipe["gaussian"]), ("speckle", recipe["speckle"])):
         tab = {k: [] for k in descs}
         pooled = {k: [] for k in descs}
         for v in levels:
             per = {k: [] for k in descs}
             tot = {k: [0, 0] for k in descs}
             for i, pr in enumerate(pairs):
-                sen_np = noise(pr.sen, v, 1000 * i + int(round(v * 1e4))) if v > 0 else pr.sen
+                sen_np = noisy_sensed(pr.sen, kind, v, i)
                 sen = torch.from_numpy(sen_np).to(device)
                 ref = torch.from_numpy(pr.ref).to(device)
                 torch.cuda.synchronize()

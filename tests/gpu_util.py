@@ -10,6 +10,7 @@ NCC_TOL = 1e-4          # NCC scores: |gpu - oracle| <= 1e-4 (NCC lies in [-1, 1
 SUBPX_TOL = 0.05        # sub-pixel offsets, px
 DESC_TOL = 1e-5         # float32 descriptors: |gpu - oracle| <= 1e-5 (values in [0, 1])
 AMBIG_REL = 2e-4        # a second index within this fraction of the peak is a tie
+KAPPA_CAP_ABS = 32.0    # largest conditioning factor accepted under |.| rectification (measured <= 23.3)
 CONSIST_BAND = 0.1      # |deviation - 1.5| below this may flip INCONSISTENT / VALID
 
 
@@ -17,29 +18,118 @@ def to_chw(F):
     return np.ascontiguousarray(np.asarray(F).transpose(2, 0, 1))
 
 
+def near_peak(surf, idx):
+    """Row-major indices of the surface whose value lies within AMBIG_REL *
+    |peak| of the peak at `idx` (the tie set of the G13 reading; it always
+    holds idx itself)."""
+    s = np.asarray(surf, np.float64).ravel()
+    pk = s[idx]
+    return np.nonzero(s >= pk - AMBIG_REL * abs(pk))[0]
+
+
+def total_offset_err(a, b):
+    """Largest per-axis difference of the refined displacements dy + sub_dy,
+    dx + sub_dx of two records."""
+    return max(abs(float(a["dy"]) + float(a["sub_dy"]) - float(b["dy"]) - float(b["sub_dy"])),
+               abs(float(a["dx"]) + float(a["sub_dx"]) - float(b["dx"]) - float(b["sub_dx"])))
+
+
+def load_golden(name):
+    """Stored oracle CPs of a full-size workload (tests/golden/make_oracle_cps.py)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"oracle_cps_{name}.npz")
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def golden_records(gold, kind):
+    """(records, ties) of one storage kind of a golden file: records in the
+    oracle's CP layout, ties a dict cp -> set of (dy, dx) also correct."""
+    rec = gold[kind + "_rec"]
+    o = np.zeros(len(rec), dtype=O.CP_DTYPE)
+    o["dy"], o["dx"] = rec[:, 0].astype(np.int32), rec[:, 1].astype(np.int32)
+    o["sub_dy"], o["sub_dx"], o["score"] = rec[:, 2], rec[:, 3], rec[:, 4]
+    o["flags"] = gold[kind + "_flags"]
+    ties = {}
+    for i, dy, dx in gold[kind + "_ties"]:
+        ties.setdefault(int(i), set()).add((int(dy), int(dx)))
+    return o, ties
+
+
+def compare_to_golden(g, o, ties, ref=None):
+    """GPU records g against stored oracle records o (flags before the
+    consistency check) with the same tie rule as compare_cps.  `ref`: the
+    unrounded oracle's records, against which per-CP score and displacement
+    errors are reported (not asserted).  Returns statistics and per-CP
+    error arrays."""
+    n = len(o)
+    base_mask = int(~np.uint32(O.VALID | O.INCONSISTENT))
+    st = dict(n=n, compared=0, equal=0, ambiguous=len(ties), ambiguous_taken=0, max_score_err=0.0,
+              max_sub_err=0.0)
+    score_err = np.full(n, np.nan)
+    off_err = np.full(n, np.nan)
+    for i in range(n):
+        fo, fg = int(o["flags"][i]), int(g["flags"][i]) & base_mask
+        if fo & (O.OOB | O.FLAT_T | O.FLAT_S | O.NONFINITE):
+            assert fo == fg, (i, fo, fg)
+            continue
+        st["compared"] += 1
+        same = (int(g["dy"][i]), int(g["dx"][i])) == (int(o["dy"][i]), int(o["dx"][i]))
+        if not same:
+            assert (int(g["dy"][i]), int(g["dx"][i])) in ties.get(i, ()), (i, o[i], g[i])
+            assert total_offset_err(g[i], o[i]) <= SUBPX_TOL, (i, o[i], g[i])
+            st["ambiguous_taken"] += 1
+        else:
+            st["equal"] += 1
+            assert fo == fg, (i, fo, fg)
+            e = abs(float(g["score"][i]) - float(o["score"][i]))
+            st["max_score_err"] = max(st["max_score_err"], e)
+            assert e <= NCC_TOL, (i, o[i], g[i])
+            e = max(abs(float(g["sub_dy"][i]) - o["sub_dy"][i]), abs(float(g["sub_dx"][i]) - o["sub_dx"][i]))
+            st["max_sub_err"] = max(st["max_sub_err"], e)
+            assert e <= SUBPX_TOL, (i, o[i], g[i])
+        if ref is not None:
+            if (int(g["dy"][i]), int(g["dx"][i])) == (int(ref["dy"][i]), int(ref["dx"][i])):
+                score_err[i] = abs(float(g["score"][i]) - float(ref["score"][i]))
+            off_err[i] = total_offset_err(g[i], ref[i])
+    return st, score_err, off_err
+
+
 def compare_cps(g, o, surf_o, r, surf_g=None, check_consistency=True):
     """g: GPU records (structured), o: oracle records, surf_o: oracle surfaces.
 
-    Integer CPs must agree exactly unless the oracle's surface holds the
-    GPU's location within AMBIG_REL of its peak (several correct answers).
-    Returns a dict of statistics."""
+    A CP is ambiguous when the oracle surface holds a second index within
+    AMBIG_REL * |peak| of its peak (the top-2 gap is below that); then any
+    index of that tie set is a correct answer.  Every other CP must agree on
+    the integer location exactly.  Returns statistics, among them
+    `ambiguous` (oracle CPs with such a tie, whatever the GPU chose) and
+    `ambiguous_taken` (those where the GPU took another index of the set)."""
     V = 2 * r + 1
     n = len(o)
-    stats = dict(n=n, ambiguous=0, max_score_err=0.0, max_sub_err=0.0, max_ncc_err=0.0, flips=0)
+    stats = dict(n=n, compared=0, ambiguous=0, ambiguous_taken=0, max_score_err=0.0, max_sub_err=0.0,
+                 max_ncc_err=0.0, flips=0)
     base_mask = ~np.uint32(O.VALID | O.INCONSISTENT)
     for i in range(n):
         fo, fg = int(o["flags"][i]), int(g["flags"][i])
-        assert (fo & int(base_mask)) == (fg & int(base_mask)), (i, fo, fg)
         if fo & (O.OOB | O.FLAT_T | O.FLAT_S | O.NONFINITE):
+            assert (fo & int(base_mask)) == (fg & int(base_mask)), (i, fo, fg)
             assert g["dy"][i] == 0 and g["dx"][i] == 0 and g["score"][i] == 0
             continue
-        if (g["dy"][i], g["dx"][i]) != (o["dy"][i], o["dx"][i]):
-            ui, vi = o["dy"][i] + r, o["dx"][i] + r
-            ug, vg = g["dy"][i] + r, g["dx"][i] + r
-            pk = surf_o[i][ui, vi]
-            assert abs(surf_o[i][ug, vg] - pk) <= AMBIG_REL * abs(pk) + NCC_TOL, (i, o[i], g[i])
+        stats["compared"] += 1
+        io = (int(o["dy"][i]) + r) * V + int(o["dx"][i]) + r
+        ig = (int(g["dy"][i]) + r) * V + int(g["dx"][i]) + r
+        ties = near_peak(surf_o[i], io)
+        if len(ties) > 1:
             stats["ambiguous"] += 1
-            continue
+            assert ig in ties, (i, o[i], g[i])
+            if ig != io:
+                # another correct integer answer: the refined displacement
+                # must still agree
+                stats["ambiguous_taken"] += 1
+                assert total_offset_err(g[i], o[i]) <= SUBPX_TOL, (i, o[i], g[i])
+                continue
+        assert ig == io, (i, o[i], g[i])
+        assert (fo & int(base_mask)) == (fg & int(base_mask)), (i, fo, fg)
         stats["max_score_err"] = max(stats["max_score_err"], abs(float(g["score"][i]) - float(o["score"][i])))
         assert abs(float(g["score"][i]) - float(o["score"][i])) <= NCC_TOL * max(1.0, abs(float(o["score"][i])))
         e = max(abs(float(g["sub_dy"][i]) - o["sub_dy"][i]), abs(float(g["sub_dx"][i]) - o["sub_dx"][i]))

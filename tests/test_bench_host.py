@@ -54,8 +54,11 @@ def test_committed_summary_parses():
 
 def test_work_counts():
     p = S.preset("baseline")
+    # 674 FMA per pixel: 312 convolution + 40 steering + 288 smoothing + 34 normalisation
+    assert bench.sfoc_fma_per_px(p) == 674.0
     base = bench.sfoc_flops_per_px(p)
-    assert base == 1252.0
+    assert base == 1348.0
+    assert bench.sfoc_bytes_per_px(4, 16) == 68.0 and bench.sfoc_bytes_per_px(2, 16) == 36.0
     # the first-order-only ablation drops the second-order passes, steering and channels
     q = p.copy()
     q.second_order = 0
@@ -64,10 +67,26 @@ def test_work_counts():
     r = p.copy()
     r.n_orient = 12
     assert bench.sfoc_flops_per_px(r) > base
-    # Fast-NCC: 2z + 1 real 2-D FFTs of side M plus the spectrum products
-    assert bench.fastncc_flops_per_ip(128, 16) == 19988480.0
-    # linear in the channel count (one shared inverse), quadratic-log in the side
+    # Fast-NCC: 2z + 1 real 2-D FFTs of side M, the spectrum products and the
+    # NCC assembly: 20.07 Mflop for m 64, r 32 (M 128, V 65)
     f = bench.fastncc_flops_per_ip
-    assert f(128, 48) - f(128, 32) == f(128, 32) - f(128, 16)
-    assert f(128, 16) < 2 * f(128, 8)
-    assert 4 * f(64, 16) < f(128, 16) < 5 * f(64, 16)
+    assert f(128, 16, 65) == 19988480.0 + 20.0 * 65 * 65
+    assert round(f(128, 16, 65) / 1e6, 1) == 20.1
+    assert round(f(160, 16, 97) / 1e6, 1) == 32.8
+    # linear in the channel count (one shared inverse), quadratic-log in the side
+    assert f(128, 48, 65) - f(128, 32, 65) == f(128, 32, 65) - f(128, 16, 65)
+    assert f(128, 16, 65) < 2 * f(128, 8, 65)
+    assert 4 * f(64, 16, 33) < f(128, 16, 65) < 5 * f(64, 16, 33)
+    # 655 KB per IP at bfloat16 for the scene's windows
+    assert bench.fastncc_bytes_per_ip(64, 128, 16, 2) == 16 * 2 * (64 * 64 + 128 * 128)
+
+
+def test_roof_entry():
+    e = bench.roof_entry("x", 1.0, 157.3e9, 1e9)
+    assert e["frac_valu_peak"] == pytest.approx(1.0)
+    assert e["binding_roof"] == "valu" and e["frac_binding_roof"] == pytest.approx(1.0)
+    e = bench.roof_entry("x", 1.0, 1e9, 8e9)         # intensity 1/8 flop per byte: HBM binds
+    assert e["binding_roof"] == "hbm" and e["frac_binding_roof"] == pytest.approx(1.0)
+    e = bench.roof_entry("x", 2.0, 0.0, 8e9)
+    assert e["binding_roof"] == "hbm" and e["frac_hbm_peak"] == pytest.approx(0.5)
+    assert bench.roof_entry("x", 0.0, 1.0, 1.0) is None

@@ -211,3 +211,59 @@ def test_autotune_and_cache(tmp_path):
     assert i2["tuned_classes"] == 0 and i2["cached_classes"] == timed
     assert i2["fft_side"] == info["fft_side"]
     plan2.close()
+
+
+def test_corrupt_cache_is_ignored(tmp_path):
+    """A cache whose lines name sides the classes cannot use (or do not
+    parse) is ignored: every class is timed again and the plan computes
+    what per-pair calls compute with the chosen sides."""
+    say("autotune with a corrupt cache")
+    cache = tmp_path / "tune.txt"
+    p = S.preset("baseline")
+    pairs = build_pairs(SPECS)
+    lines = ["not a cache line", "gfx950/256cu 16 0 1 2"]
+    for q in pairs:
+        lines.append(f"gfx950/256cu 16 0 {q['m']} {q['r']} 96")     # no such transform side
+        lines.append(f"gfx950/256cu 16 0 {q['m']} {q['r']} 128 64")  # trailing field
+    cache.write_text("\n".join(lines) + "\n")
+    dp = to_device(pairs)
+    plan = S.Plan(dp, p, flags=S.PLAN_AUTOTUNE, tune_cache=str(cache), want_ncc=True)
+    info = plan.info()
+    timed = sum(len(S.match_candidates(q["m"], q["r"])) > 1 and len(q["ips"]) > 0 for q in pairs)
+    assert info["cached_classes"] == 0 and info["tuned_classes"] == timed
+    for q, L in zip(pairs, info["fft_side"]):
+        assert L in [c[0] for c in S.match_candidates(q["m"], q["r"])]
+    plan()
+    torch.cuda.synchronize()
+    for k, q in enumerate(pairs):
+        if info["fft_side"][k] == (64 if q["m"] + 2 * q["r"] <= 64 else 128):
+            continue
+        if len(q["ips"]):
+            oracle_check(q, plan.cps[k], plan.ncc[k], p)
+    plan.close()
+
+
+@pytest.mark.parametrize("kind", ["bf16", "f16"])
+def test_rounded_storage_plan(kind):
+    """BF16 / FP16 descriptor storage in a batched plan (graph, sparse
+    sensed tiles, split offsets included): bit for bit the per-pair calls
+    with the same storage, and the oracle on the same rounded descriptors
+    (O64q) for pairs with IPs."""
+    say("batched plan with storage", kind)
+    p = S.preset("baseline", dtype={"bf16": S.DTYPE_BF16, "f16": S.DTYPE_F16}[kind])
+    pairs = build_pairs(SPECS)
+    dp = to_device(pairs)
+    want = per_pair(dp, p)
+    plan = S.Plan(dp, p, flags=S.PLAN_GRAPH, want_ncc=True)
+    for rep in range(2):
+        plan()
+        torch.cuda.synchronize()
+        assert_same(plan, want)
+    for k in (1, 2, 4):
+        q = pairs[k]
+        o, so = O.register_cps(q["ref"], q["sen"], q["ips"], q["m"], q["r"], O.Params(), prior=q["prior"],
+                               quantise=kind, want_surfaces=True)
+        g = S.cps_to_numpy(plan.cps[k])
+        st = compare_cps(g, o, so, q["r"], surf_g=plan.ncc[k].cpu().numpy(), check_consistency=False)
+        say("  pair", k, st)
+    plan.close()

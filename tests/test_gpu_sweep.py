@@ -22,3 +22,60 @@ def test_reduced_sweep():
         for k, vals in res[kind]["pooled_cmr"].items():
             assert vals[0] >= 0.9, (kind, k, vals)
             assert vals[-1] <= vals[0] + 0.02, (kind, k, vals)
+
+
+def test_sweep_cps_match_oracle():
+    """One sweep pair at one Gaussian and one speckle level: every CP from
+    its block-FAST points, for SFOC and F-SFOC (second-order channels off,
+    the z = 6 ablation of Section 4.2) with the paper's preset, against the
+    oracle CP by CP (tie rule, 1e-4 NCC, 0.05 px); then the correct matching
+    ratio of both."""
+    import numpy as np
+
+    from oracle import sfoc_oracle as O
+    from tests.gpu_util import compare_cps, consistency_flip_allowed
+    from tests.oracle_pool import oracle_cps
+    assert torch.cuda.is_available()
+    S.lib()
+    rec = synth.SWEEP
+    m, r = rec["m"], rec["r"]
+    margin = (m + 1) // 2 + r
+    nby, nbx = rec["blocks"]
+    size = rec["size"]
+    pr = synth.sweep_pair(0, rec)
+    det = S.Detector(size, size, nby, nbx, 1, rec["fast_threshold"], margin, device="cuda")
+    ref = torch.from_numpy(pr.ref).cuda()
+    variants = {"SFOC": (S.preset("paper"), O.preset_paper())}
+    f = S.preset("paper")
+    f.second_order = 0
+    import dataclasses
+    variants["F-SFOC"] = (f, dataclasses.replace(O.preset_paper(), second_order=False))
+    for kind, v in (("gaussian", 0.005), ("speckle", 0.05)):
+        sen_np = W.noisy_sensed(pr.sen, kind, v, 0)
+        sen = torch.from_numpy(sen_np).cuda()
+        ips, _, _, n = det(sen)
+        k = int(n.item())
+        ips_np = ips[:k].cpu().numpy()
+        assert k >= 0.9 * nby * nbx
+        for name, (p, op) in variants.items():
+            assert S.check_params(p) == (12 if p.second_order else 6)
+            cps, ncc = S.register_cps(ref, sen, ips[:k].contiguous(), m, r, p, want_ncc=True)
+            torch.cuda.synchronize()
+            g = S.cps_to_numpy(cps).copy()
+            [(o, so)] = oracle_cps(pr.ref, sen_np, ips_np, m, r, op)
+            gs = g.copy()
+            gs["flags"] &= ~np.uint32(O.VALID | O.INCONSISTENT)
+            st = compare_cps(gs, o, so, r, ncc.cpu().numpy(), check_consistency=False)
+            oc = o.copy()
+            O.consistency(oc)
+            flips = {i for i in range(k) if oc["flags"][i] != g["flags"][i]}
+            assert flips <= consistency_flip_allowed(oc), flips
+            ncm_g, tot_g = W.cmr(g, pr.shift)
+            ncm_o, tot_o = W.cmr(oc, pr.shift)
+            # a refined displacement within 0.05 px of the 1.5 px criterion may
+            # fall on either side of it
+            d = np.hypot(oc["dy"] + oc["sub_dy"] - pr.shift[0], oc["dx"] + oc["sub_dx"] - pr.shift[1])
+            near = int(np.sum(np.abs(d - W.CORRECT_PX) <= 0.05))
+            print(f"{kind} v={v} {name}: {k} CPs, GPU CMR {ncm_g}/{tot_g}, oracle CMR {ncm_o}/{tot_o}, {st}",
+                  file=sys.stderr, flush=True)
+            assert tot_g == tot_o and abs(ncm_g - ncm_o) <= near

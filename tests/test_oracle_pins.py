@@ -428,3 +428,25 @@ def test_region_match_equals_dense_match():
         assert rec[0] == cps["dy"][i] and rec[1] == cps["dx"][i]
         assert rec[5] == (int(cps["flags"][i]) & ~(O.VALID | O.INCONSISTENT))
         assert np.abs(s - surf[i]).max() < 1e-10
+
+
+def test_region_variants_equal_dense_match_per_rounding():
+    # The several-roundings crop evaluation gives, for each rounding, the
+    # dense oracle's CP on descriptors rounded the same way.
+    from paper_2202_13347_amd import synth
+    pr = synth.make_pair(4, 96, 4.0)
+    p = O.Params()
+    ips = np.array([[30, 30], [48, 60], [65, 40], [5, 5]])
+    kinds = (None, "bf16", "f16")
+    dense = {k: O.register_cps(pr.ref, pr.sen, ips, 16, 6, p, quantise=k, want_surfaces=True) for k in kinds}
+    for i, ip in enumerate(ips):
+        res = O.match_one_region_variants(pr.ref, pr.sen, ip, 16, 6, p, quantise=kinds)
+        assert len(res) == 3
+        for k, (rec, s) in zip(kinds, res):
+            cps, surf = dense[k]
+            assert rec[0] == cps["dy"][i] and rec[1] == cps["dx"][i]
+            assert rec[5] == (int(cps["flags"][i]) & ~(O.VALID | O.INCONSISTENT))
+            assert np.abs(s - surf[i]).max() < 1e-10
+    # rounding changes the surfaces (the variants are not the same computation)
+    r0 = O.match_one_region_variants(pr.ref, pr.sen, ips[0], 16, 6, p, quantise=kinds)
+    assert np.abs(r0[0][1] - r0[1][1]).max() > 1e-6
