@@ -163,6 +163,25 @@ int sfoc_describe(const float* img, int64_t H, int64_t W, int64_t ld,
                   void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * sfoc_describe with integral images, allocating nothing: for callers that
+ * cannot allocate device memory (code under HIP stream capture, serving
+ * loops, harnesses that forbid allocation).  Arguments, results and errors
+ * are sfoc_describe's with integ1 and integ2 required (non-NULL) and no
+ * workspace: the per-tile aggregates the integral images are assembled from
+ * live in a library-owned device array of SFOC_NOALLOC_SCRATCH_BYTES (one
+ * per GPU, held until the process ends).  Images whose aggregates
+ * (sfoc_describe_workspace) exceed it are rejected with SFOC_E_UNSUPPORTED
+ * (about 8000 x 8000 pixels is the largest square image).  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (different
+ * streams, or host threads) race and must be serialised by the caller.  The
+ * results equal sfoc_describe's bit for bit.  Errors: SFOC_E_INVALID_ARG
+ * (as sfoc_describe, or integ1 / integ2 NULL), SFOC_E_UNSUPPORTED, SFOC_E_HIP.
+ */
+#define SFOC_NOALLOC_SCRATCH_BYTES (64u << 20)
+int sfoc_describe_noalloc(const float* img, int64_t H, int64_t W, int64_t ld, const sfoc_params* p,
+                          void* desc, double* integ1, double* integ2, void* stream);
+
+/*
  * Fast-NCC_SFOC CP detection for n interest points of one image pair
  * (Section 2.2, Eq. 9-16; Section 3.2.2).  For IP i at (row, col) in the
  * sensed image, the template is the m x m x z window with top-left

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsfoc.so")
 
-HIP_SOURCES = ["sfoc_describe.hip", "sfoc_match.hip", "sfoc_api.hip", "sfoc_batch.hip", "sfoc_head.hip", "sfoc_ransac.hip", "sfoc_rectify.hip", "sfoc_fast.hip", "sfoc_trace.hip"]
+HIP_SOURCES = ["sfoc_describe.hip", "sfoc_match.hip", "sfoc_api.hip", "sfoc_batch.hip", "sfoc_head.hip", "sfoc_ransac.hip", "sfoc_rectify.hip", "sfoc_fast.hip", "sfoc_trace.hip", "sfoc_noalloc.hip"]
 CPP_SOURCES = ["sfoc_plan.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

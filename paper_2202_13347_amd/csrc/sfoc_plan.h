@@ -81,6 +81,8 @@ inline SFOC_HOST_DEVICE IntegAgg integ_agg(int64_t H, int64_t W) {
 // Bytes of the aggregates (the describe workspace when integral images are
 // asked for): 2 (ntx H + nty W + nty ntx) doubles, about 1 byte per pixel.
 size_t describe_ws_bytes(int64_t H, int64_t W);
+// Size of the library-owned aggregate array of sfoc_describe_noalloc.
+constexpr size_t kNoAllocScratchBytes = SFOC_NOALLOC_SCRATCH_BYTES;
 
 // How a match is laid out: FFT side L and the split of the (2r+1)^2 offsets
 // into nb x nb blocks of at most Vb offsets per axis, each with a search

@@ -105,6 +105,7 @@ def lib() -> ctypes.CDLL:
         L.sfoc_params_check.argtypes = [P, ctypes.POINTER(i32)]
         L.sfoc_describe_workspace.argtypes = [i64, i64, P, ctypes.POINTER(sz)]
         L.sfoc_describe.argtypes = [vp, i64, i64, i64, P, vp, vp, vp, vp, sz, vp]
+        L.sfoc_describe_noalloc.argtypes = [vp, i64, i64, i64, P, vp, vp, vp, vp]
         L.sfoc_match_workspace.argtypes = [i32, i32, i32, i32, ctypes.POINTER(sz)]
         L.sfoc_fastncc_match.argtypes = [vp, i64, i64, vp, i64, i64, vp, vp, i32, i32, vp, vp, i32, i32, i32,
                                          vp, vp, vp, sz, vp]
@@ -252,6 +253,20 @@ def describe(img, p: Params, integrals: bool = True, stream=None, out=None):
                              _ptr(ws), wsb, _stream(stream))
     _check(rc, "sfoc_describe")
     return desc, i1, i2
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # SFOC_NOALLOC_SCRATCH_BYTES
+
+
+def describe_noalloc(img, p: Params, desc, integ1, integ2, stream=None):
+    """sfoc_describe_noalloc into caller-provided outputs (desc (z, H, W),
+    integ1 and integ2 (H+1, W+1) float64 CUDA tensors): the library
+    allocates nothing for it."""
+    H, W = img.shape
+    rc = lib().sfoc_describe_noalloc(_ptr(img), H, W, img.stride(0), ctypes.byref(p), _ptr(desc), _ptr(integ1),
+                                     _ptr(integ2), _stream(stream))
+    _check(rc, "sfoc_describe_noalloc")
+    return desc, integ1, integ2
 
 
 def fastncc_match(desc_sen, desc_ref, integ1, integ2, ips, m: int, r: int, prior=None, want_ncc=False,
