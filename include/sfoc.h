@@ -201,12 +201,14 @@ int sfoc_describe_noalloc(const float* img, int64_t H, int64_t W, int64_t ld, co
  *  prior               n x 2 int32 (dy, dx) search-window offsets, or NULL.
  *  ncc                 n x (2r+1) x (2r+1) float32 surfaces, or NULL.  (output)
  *  cps                 n records.                                      (output)
- * Search windows up to 128 x 128 (m + 2r <= 128) are one transform; larger
- * ones split the offsets into blocks whose windows fit 128 x 128 and need
- * the workspace sfoc_match_workspace reports (per-CP surfaces and block
- * records; 0 bytes otherwise).
- * Limits: 3 <= m, 1 <= r <= 511, m <= 126 when m + 2r > 128, each image
- * below 2^30 pixels (SFOC_E_UNSUPPORTED beyond).
+ * The transform side L is the smallest of 64, 128, 160 and 192 (radices
+ * 8 x 8, 16 x 8, 16 x 10, 16 x 12) that holds the search window, so windows
+ * up to 192 x 192 (m + 2r <= 192) are one transform.  Larger ones split the
+ * offsets into blocks whose windows fit L x L, with the side of least
+ * transform work, and need the workspace sfoc_match_workspace reports
+ * (per-CP surfaces and block records; 0 bytes otherwise).
+ * Limits: 3 <= m <= 191, 1 <= r <= 511, each image below 2^30 pixels
+ * (SFOC_E_UNSUPPORTED beyond).
  * n == 0 is valid and enqueues nothing.
  */
 int sfoc_match_workspace(int32_t n, int32_t m, int32_t r, int32_t z, size_t* bytes);
@@ -251,10 +253,11 @@ int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr,
  *    SFOC_PLAN_DENSE_SEN is set (then they are described whole);
  *  - integral images: three launches over all reference images;
  *  - match: one launch per transform side over (pair, IP, offset block)
- *    items, the two sides on two graph branches; a peak launch over pairs
+ *    items, side 64 on a second graph branch beside the larger sides; a
+ *    peak launch over pairs
  *    whose offsets are split; one consistency launch, a workgroup per pair.
- * The transform side of a pair is pair.fft_side when that is 64 or 128
- * (SFOC_E_UNSUPPORTED if the template does not fit it), else the default of
+ * The transform side of a pair is pair.fft_side when that is 64, 128, 160
+ * or 192 (SFOC_E_UNSUPPORTED if the template does not fit it), else the default of
  * sfoc_match_workspace, or with SFOC_PLAN_AUTOTUNE the faster of the
  * candidates sfoc_match_candidates lists, timed on the plan's own work at
  * creation (the images should hold data by then) and remembered per
@@ -287,7 +290,7 @@ typedef struct sfoc_pair {
     const int32_t* ips;         /* n x 2 (row, col) in the sensed image */
     const int32_t* prior;       /* n x 2 (dy, dx) or NULL */
     int32_t n, m, r;
-    int32_t fft_side;           /* 0: default / autotuned; 64 or 128: forced */
+    int32_t fft_side;           /* 0: default / autotuned; 64, 128, 160, 192: forced */
     float* ncc;                 /* n x (2r+1)^2 float32 surfaces or NULL (output) */
     sfoc_cp* cps;               /* n records (output) */
 } sfoc_pair;
@@ -311,12 +314,12 @@ int sfoc_plan_destroy(sfoc_plan* plan);
 typedef struct sfoc_plan_info {
     int32_t n_pairs;
     int32_t describe_tiles;     /* entries of the describe launch */
-    int32_t match_items[2];     /* items of the L = 64 and L = 128 launches */
+    int32_t match_items[4];     /* items of the L = 64, 128, 160, 192 launches */
     int32_t peak_items;
     int32_t tuned_classes;      /* (m, r) classes timed at creation */
     int32_t cached_classes;     /* (m, r) classes taken from tune_cache */
     int32_t graph;              /* 1 once a graph is captured */
-    int32_t persistent[2];      /* L = 64 / L = 128 match launches persistent */
+    int32_t persistent[4];      /* those launches persistent (1) or one workgroup per item */
     int32_t reserved;
     int64_t device_bytes;
 } sfoc_plan_info;
@@ -325,9 +328,10 @@ int sfoc_plan_get_info(const sfoc_plan* plan, sfoc_plan_info* info, int32_t* fft
 
 /*
  * Planning queries (host only, no device work).
- * sfoc_match_candidates: the transform sides (64 / 128) usable for template
- * m and radius r with at most 8 offset blocks per axis, the default first,
- * and the offset blocks per axis of each; returns the count (0: none).
+ * sfoc_match_candidates: the transform sides (64 / 128 / 160 / 192) usable
+ * for template m and radius r with at most 8 offset blocks per axis, the
+ * default first and the others by increasing side, and the offset blocks per
+ * axis of each; returns the count (0: none; at most 4).
  * sfoc_sensed_tiles: the 32 x 32 sensed-image tiles that the templates of
  * in-bounds IPs read (host arrays; mask has ceil(Hs/32) * ceil(Ws/32) bytes,
  * row-major over tiles); returns the number of marked tiles, or a negative

@@ -248,7 +248,7 @@ int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr, con
 
 int sfoc_match_candidates(int32_t m, int32_t r, int32_t* fft_side, int32_t* blocks, int32_t cap) {
     if (cap < 0 || (cap > 0 && !fft_side)) return SFOC_E_INVALID_ARG;
-    int Ls[2];
+    int Ls[kNumSides];
     const int n = match_candidates(m, r, Ls);
     for (int k = 0; k < n && k < cap; ++k) {
         fft_side[k] = Ls[k];

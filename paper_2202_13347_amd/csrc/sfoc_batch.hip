@@ -36,13 +36,13 @@ struct sfoc_plan {
     int4* itiles = nullptr;   // integral tiles {job, tile row, tile column}
     int npre = 0, nitiles = 0;
     MatchArgs* margs = nullptr;
-    int4* items[2] = {nullptr, nullptr};   // L = 64, L = 128
-    int nitems[2] = {0, 0};
+    int4* items[kNumSides] = {};        // per transform side kSides[b]
+    int nitems[kNumSides] = {};
     int4* peak = nullptr;
     int npeak = 0;
     int* counters = nullptr;            // work counters of the persistent launches (one per side)
-    bool persist[2] = {false, false};   // persistent match launch per transform side
-    int grid = 0;                       // persistent grid: two workgroups per CU
+    bool persist[kNumSides] = {};       // persistent match launch per transform side
+    int grid = 0;                       // CUs (a persistent grid has MINB workgroups per CU)
     hipStream_t side_stream = nullptr;   // second graph branch
     hipStream_t cap_stream = nullptr;    // capture happens here (the caller's may be the null stream)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;     // match sides
@@ -68,7 +68,7 @@ struct Cursor {
     }
 };
 
-int bucket_of(int L) { return L == 64 ? 0 : 1; }
+int bucket_of(int L) { return side_index(L); }
 
 MatchArgs make_args(const sfoc_pair& q, const char* mem, const PairMem& pm, int32_t z, int32_t dtype,
                     const MatchPlan& mp) {
@@ -113,28 +113,24 @@ std::string device_key(int dev) {
 }
 
 // Everything after the describe / integral stage for the plan's current
-// tables.  The two transform sides run on two streams (two graph branches).
+// tables.  The side-64 launch runs on a second stream (a second graph
+// branch) beside the larger sides, which run in turn on the caller's.
 hipError_t enqueue_match(sfoc_plan* P, hipStream_t st) {
     hipError_t e = hipSuccess;
-    const bool both = P->nitems[0] > 0 && P->nitems[1] > 0;
-    if (both) {
+    bool big = false;
+    for (int b = 1; b < kNumSides; ++b) big = big || P->nitems[b] > 0;
+    const bool fork = P->nitems[0] > 0 && big;
+    if (fork) {
         if ((e = hipEventRecord(P->ev_fork, st)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(P->side_stream, P->ev_fork, 0)) != hipSuccess) return e;
-        e = launch_match_items(64, P->dtype, P->margs, P->items[0], P->nitems[0], P->persist[0] ? P->counters : nullptr,
-                               P->grid, P->side_stream);
-        if (e != hipSuccess) return e;
-        if ((e = hipEventRecord(P->ev_join, P->side_stream)) != hipSuccess) return e;
-        e = launch_match_items(128, P->dtype, P->margs, P->items[1], P->nitems[1],
-                               P->persist[1] ? P->counters + 1 : nullptr, P->grid, st);
-        if (e != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(st, P->ev_join, 0)) != hipSuccess) return e;
-    } else {
-        for (int b = 0; b < 2; ++b) {
-            e = launch_match_items(b ? 128 : 64, P->dtype, P->margs, P->items[b], P->nitems[b],
-                                   P->persist[b] ? P->counters + b : nullptr, P->grid, st);
-            if (e != hipSuccess) return e;
-        }
     }
+    for (int b = 0; b < kNumSides; ++b) {
+        e = launch_match_items(kSides[b], P->dtype, P->margs, P->items[b], P->nitems[b],
+                               P->persist[b] ? P->counters + b : nullptr, P->grid, b == 0 && fork ? P->side_stream : st);
+        if (e != hipSuccess) return e;
+        if (b == 0 && fork && (e = hipEventRecord(P->ev_join, P->side_stream)) != hipSuccess) return e;
+    }
+    if (fork && (e = hipStreamWaitEvent(st, P->ev_join, 0)) != hipSuccess) return e;
     if ((e = launch_peak_batched(P->margs, P->peak, P->npeak, st)) != hipSuccess) return e;
     return launch_consistency_batched(P->margs, (int)P->pairs.size(), st);
 }
@@ -221,7 +217,7 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
         if ((rc = check_match_shape(q.n, q.m, q.r))) return rc;
         if (q.Hs * q.Ws >= kMaxPlane || q.Hr * q.Wr >= kMaxPlane) return SFOC_E_UNSUPPORTED;
         if (q.n > 0 && (!q.ips || !q.cps)) return SFOC_E_INVALID_ARG;
-        if (q.fft_side != 0 && q.fft_side != 64 && q.fft_side != 128) return SFOC_E_INVALID_ARG;
+        if (q.fft_side != 0 && side_index(q.fft_side) < 0) return SFOC_E_INVALID_ARG;
         if (q.fft_side != 0 && match_plan_L(q.n, q.m, q.r, q.fft_side).L == 0) return SFOC_E_UNSUPPORTED;
     }
     hipStream_t st = (hipStream_t)stream;
@@ -290,7 +286,7 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     std::vector<std::vector<int>> cands(n_pairs);
     for (int k = 0; k < n_pairs; ++k) {
         const sfoc_pair& q = pairs[k];
-        int Ls[2];
+        int Ls[kNumSides];
         int nc = 0;
         if (q.fft_side) {
             Ls[nc++] = q.fft_side;
@@ -312,7 +308,7 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     // integral-image work lists: prefix items, then every tile of each reference
     std::vector<IntegJob> ijobs(n_pairs);
     std::vector<int4> ipre, itiles;
-    size_t max_items[2] = {0, 0}, max_peak = 0;
+    size_t max_items[kNumSides] = {}, max_peak = 0;
     for (int k = 0; k < n_pairs; ++k) {
         const sfoc_pair& q = pairs[k];
         integral_prefix_items(k, (int)q.Hr, (int)q.Wr, ipre);
@@ -331,10 +327,10 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     const size_t o_ipre = cur.take(ipre.size() * sizeof(int4));
     const size_t o_itiles = cur.take(itiles.size() * sizeof(int4));
     const size_t o_margs = cur.take((size_t)n_pairs * sizeof(MatchArgs));
-    const size_t o_items0 = cur.take(max_items[0] * sizeof(int4));
-    const size_t o_items1 = cur.take(max_items[1] * sizeof(int4));
+    size_t o_items[kNumSides];
+    for (int b = 0; b < kNumSides; ++b) o_items[b] = cur.take(max_items[b] * sizeof(int4));
     const size_t o_peak = cur.take(max_peak * sizeof(int4));
-    const size_t o_counters = cur.take(2 * sizeof(int));
+    const size_t o_counters = cur.take(kNumSides * sizeof(int));
     P->bytes = cur.off;
     e = hipMalloc((void**)&P->mem, P->bytes);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->side_stream, hipStreamNonBlocking);
@@ -366,14 +362,13 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     P->npre = (int)ipre.size();
     P->nitiles = (int)itiles.size();
     P->margs = (MatchArgs*)(mem + o_margs);
-    P->items[0] = (int4*)(mem + o_items0);
-    P->items[1] = (int4*)(mem + o_items1);
+    for (int b = 0; b < kNumSides; ++b) P->items[b] = (int4*)(mem + o_items[b]);
     P->peak = (int4*)(mem + o_peak);
     P->counters = (int*)(mem + o_counters);
     {
         int cus = 0;
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device);
-        P->grid = 2 * (cus > 0 ? cus : 1);
+        P->grid = cus > 0 ? cus : 1;
     }
     auto up = [&](void* dst, const void* src, size_t n) {
         if (e == hipSuccess && n) e = hipMemcpy(dst, src, n, hipMemcpyHostToDevice);
@@ -415,7 +410,7 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
                 }
                 // at most ~2048 IPs of the class are timed
                 float tbest = 0.f;
-                int Ls[2];
+                int Ls[kNumSides];
                 const int nc = match_candidates(m, r, Ls);
                 for (int c = 0; c < nc && e == hipSuccess; ++c) {
                     const int L = Ls[c];
@@ -472,14 +467,14 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
         return pairs[k].m + std::min(m.Vb, 2 * pairs[k].r + 1) - 1 + pairs[k].m;
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
-    std::vector<int4> items[2], peak;
+    std::vector<int4> items[kNumSides], peak;
     for (int k : order) {
         append_items(items[bucket_of(P->side[k])], k, pairs[k].n, P->mp[k].nb);
         if (P->mp[k].nb > 1)
             for (int i = 0; i < pairs[k].n; i += 256) peak.push_back(make_int4(k, i, 0, 0));
     }
     up(P->margs, margs.data(), margs.size() * sizeof(MatchArgs));
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < kNumSides; ++b) {
         up(P->items[b], items[b].data(), items[b].size() * sizeof(int4));
         P->nitems[b] = (int)items[b].size();
     }
@@ -487,10 +482,10 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     P->npeak = (int)peak.size();
     // launch form per side: persistent when asked; with autotuning the
     // faster of the two on this plan's items
-    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+    for (int b = 0; b < kNumSides && e == hipSuccess; ++b) {
         P->persist[b] = (flags & SFOC_PLAN_PERSISTENT) != 0;
         if (tune && P->nitems[b] > 0) {
-            const int L = b ? 128 : 64;
+            const int L = kSides[b];
             const float tg = time_items(L, P->dtype, P->margs, P->items[b], P->nitems[b], nullptr, 0, st, 3, &e);
             if (e != hipSuccess) break;
             const float tp = time_items(L, P->dtype, P->margs, P->items[b], P->nitems[b], P->counters + b, P->grid, st,
@@ -550,14 +545,14 @@ int sfoc_plan_get_info(const sfoc_plan* P, sfoc_plan_info* info, int32_t* fft_si
     if (!P || !info || cap < 0) return SFOC_E_INVALID_ARG;
     info->n_pairs = (int32_t)P->pairs.size();
     info->describe_tiles = P->ndt;
-    info->match_items[0] = P->nitems[0];
-    info->match_items[1] = P->nitems[1];
+    for (int b = 0; b < kNumSides; ++b) {
+        info->match_items[b] = P->nitems[b];
+        info->persistent[b] = P->persist[b];
+    }
     info->peak_items = P->npeak;
     info->tuned_classes = P->tuned;
     info->cached_classes = P->cached;
     info->graph = P->exec != nullptr;
-    info->persistent[0] = P->persist[0];
-    info->persistent[1] = P->persist[1];
     info->reserved = 0;
     info->device_bytes = (int64_t)P->bytes;
     const int n = std::min<int>(cap, (int)P->pairs.size());

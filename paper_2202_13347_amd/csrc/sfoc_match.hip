@@ -79,6 +79,17 @@ SFOC_DEV void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Orders the reads of a row pair's tasks before their in-place writes.  A
+// pair's TPP tasks are consecutive task indices; when TPP divides the wave
+// size they are lanes of one wave and wave_sync suffices, otherwise a pair
+// can straddle two waves and the whole workgroup synchronises (every
+// thread runs the same number of rounds, so all of them reach it).
+template <int TPP>
+SFOC_DEV void pair_sync() {
+    if constexpr (64 % TPP == 0) wave_sync();
+    else __syncthreads();
+}
+
 // ---- small DFTs in registers -------------------------------------------
 template <bool INV>
 SFOC_DEV void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
@@ -146,42 +157,166 @@ SFOC_DEV void dft16(float2 (&x)[16]) {
     }
 }
 
+// 3-point DFT: with W = exp(-+2 pi i / 3) = -1/2 -+ i sqrt(3)/2,
+// X1, X2 = a0 - (a1 + a2)/2 +- i s (a1 - a2), s = -+sqrt(3)/2.
+template <bool INV>
+SFOC_DEV void dft3(float2& a0, float2& a1, float2& a2) {
+    const float s = (INV ? 1.f : -1.f) * 0.86602540378443865f;
+    const float2 t1 = cadd(a1, a2), t2 = csub(a1, a2);
+    const float2 m = make_float2(a0.x - 0.5f * t1.x, a0.y - 0.5f * t1.y);
+    const float2 q = make_float2(-s * t2.y, s * t2.x);   // i s t2
+    a0 = cadd(a0, t1);
+    a1 = cadd(m, q);
+    a2 = csub(m, q);
+}
+
+// 5-point DFT from the conjugate-symmetric pairs (a1, a4) and (a2, a3):
+// with c_k = cos(2 pi k / 5), s_k = sin(2 pi k / 5) and sigma = -+1,
+// X1,4 = a0 + c1 t1 + c2 t2 +- sigma i (s1 d1 + s2 d2),
+// X2,3 = a0 + c2 t1 + c1 t2 +- sigma i (s2 d1 - s1 d2),
+// t1 = a1 + a4, t2 = a2 + a3, d1 = a1 - a4, d2 = a2 - a3.
+template <bool INV>
+SFOC_DEV void dft5(float2 (&a)[5]) {
+    const float sg = INV ? 1.f : -1.f;
+    const float c1 = 0.30901699437494742f, c2 = -0.80901699437494742f;
+    const float s1 = 0.95105651629515357f, s2 = 0.58778525229247313f;
+    const float2 t1 = cadd(a[1], a[4]), t2 = cadd(a[2], a[3]);
+    const float2 d1 = csub(a[1], a[4]), d2 = csub(a[2], a[3]);
+    const float2 p1 = make_float2(a[0].x + c1 * t1.x + c2 * t2.x, a[0].y + c1 * t1.y + c2 * t2.y);
+    const float2 p2 = make_float2(a[0].x + c2 * t1.x + c1 * t2.x, a[0].y + c2 * t1.y + c1 * t2.y);
+    const float2 e1 = make_float2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y);
+    const float2 e2 = make_float2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y);
+    const float2 q1 = make_float2(-sg * e1.y, sg * e1.x);   // sigma i e1
+    const float2 q2 = make_float2(-sg * e2.y, sg * e2.x);
+    a[0] = cadd(a[0], cadd(t1, t2));
+    a[1] = cadd(p1, q1);
+    a[4] = csub(p1, q1);
+    a[2] = cadd(p2, q2);
+    a[3] = csub(p2, q2);
+}
+
+// 10-point DFT, 2 x 5: the even and odd samples each get a 5-point DFT,
+// the odd ones then W_10^k, and X[k], X[k+5] = E[k] +- W_10^k O[k].
+template <bool INV>
+SFOC_DEV void dft10(float2 (&x)[10]) {
+    const float sg = INV ? 1.f : -1.f;
+    float2 e[5], o[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        e[k] = x[2 * k];
+        o[k] = x[2 * k + 1];
+    }
+    dft5<INV>(e);
+    dft5<INV>(o);
+    // W_10^k = cos(pi k / 5) + sigma i sin(pi k / 5), k = 1..4
+    const float ca = 0.80901699437494742f, sa = 0.58778525229247313f;   // 36 degrees
+    const float cb = 0.30901699437494742f, sb = 0.95105651629515357f;   // 72 degrees
+    o[1] = cmul(o[1], make_float2(ca, sg * sa));
+    o[2] = cmul(o[2], make_float2(cb, sg * sb));
+    o[3] = cmul(o[3], make_float2(-cb, sg * sb));
+    o[4] = cmul(o[4], make_float2(-ca, sg * sa));
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        x[k] = cadd(e[k], o[k]);
+        x[k + 5] = csub(e[k], o[k]);
+    }
+}
+
+// 12-point DFT, 3 x 4: n = n1 + 3 n2, k = 4 k1 + k2; 4-point DFTs over n2,
+// twiddles W_12^(n1 k2), 3-point DFTs over n1.
+template <bool INV>
+SFOC_DEV void dft12(float2 (&x)[12]) {
+    const float sg = INV ? 1.f : -1.f;
+    const float h = 0.86602540378443865f;   // cos 30 degrees
+    float2 y[3][4];
+#pragma unroll
+    for (int n1 = 0; n1 < 3; ++n1) {
+        float2 a0 = x[n1], a1 = x[n1 + 3], a2 = x[n1 + 6], a3 = x[n1 + 9];
+        dft4<INV>(a0, a1, a2, a3);
+        y[n1][0] = a0;
+        y[n1][1] = a1;
+        y[n1][2] = a2;
+        y[n1][3] = a3;
+    }
+    // W_12^e, e = n1 k2 in 1..6: angles 30 e degrees
+    const float2 w[7] = {make_float2(1.f, 0.f),     make_float2(h, sg * 0.5f), make_float2(0.5f, sg * h),
+                         make_float2(0.f, sg * 1.f), make_float2(-0.5f, sg * h), make_float2(-h, sg * 0.5f),
+                         make_float2(-1.f, 0.f)};
+#pragma unroll
+    for (int n1 = 1; n1 < 3; ++n1)
+#pragma unroll
+        for (int k2 = 1; k2 < 4; ++k2) y[n1][k2] = cmul(y[n1][k2], w[n1 * k2]);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+        float2 a0 = y[0][k2], a1 = y[1][k2], a2 = y[2][k2];
+        dft3<INV>(a0, a1, a2);
+        x[k2] = a0;
+        x[4 + k2] = a1;
+        x[8 + k2] = a2;
+    }
+}
+
 template <int N, bool INV>
 SFOC_DEV void dftn(float2 (&x)[N]) {
     if constexpr (N == 8) dft8<INV>(x);
+    else if constexpr (N == 10) dft10<INV>(x);
+    else if constexpr (N == 12) dft12<INV>(x);
     else dft16<INV>(x);
 }
 
 // ---- geometry ----------------------------------------------------------
+// A side L = NA * NB transform: pass A are NA-point DFTs, pass B NB-point
+// ones.  NT threads per workgroup and MINB workgroups per CU (the LDS
+// buffer of the larger sides leaves room for one).
 template <int L>
 struct Fft;
-// LDS layout of the transform buffer: row r starts at r * PITCH + (r / 8) *
-// SKEW complex values.  The column passes read rows n1 + 8 k (k across the
+// LDS layout of the transform buffer: row r starts at r * PITCH + (r / NB) *
+// SKEW complex values.  The column passes read rows n1 + NB k (k across the
 // lanes of a wave, or across the loop), whose starts would otherwise fall on
-// the same LDS banks; the pitch and the per-8-rows skew spread both kinds of
+// the same LDS banks; the pitch and the per-group skew spread both kinds of
 // access over all banks, and keep each row (and each row pair) contiguous.
 template <>
 struct Fft<128> {
-    static constexpr int NA = 16, NB = 8, NT = 256, PITCH = 68, SKEW = 8;
+    static constexpr int NA = 16, NB = 8, NT = 256, PITCH = 68, SKEW = 8, MINB = 2;
 };
 template <>
 struct Fft<64> {
-    static constexpr int NA = 8, NB = 8, NT = 128, PITCH = 40, SKEW = 8;
+    static constexpr int NA = 8, NB = 8, NT = 128, PITCH = 40, SKEW = 8, MINB = 2;
+};
+template <>
+struct Fft<160> {
+    static constexpr int NA = 16, NB = 10, NT = 640, PITCH = 84, SKEW = 8, MINB = 1;
+};
+template <>
+struct Fft<192> {
+    static constexpr int NA = 16, NB = 12, NT = 768, PITCH = 100, SKEW = 8, MINB = 1;
 };
 
 template <int L>
 struct MatchCfg {
     using F = Fft<L>;
-    static constexpr int NA = F::NA, NB = F::NB, NT = F::NT, P = F::PITCH, SKEW = F::SKEW;
+    static constexpr int NA = F::NA, NB = F::NB, NT = F::NT, P = F::PITCH, SKEW = F::SKEW, MINB = F::MINB;
     static constexpr int HA = NA / 2;
     static constexpr int COLS = L / 2;                     // column transforms (DC+Nyquist packed)
     static constexpr int RB = COLS * HA / NT;              // pass-B tasks per thread
     static constexpr int BINS = 2 * NB;                    // bins per pass-B task
-    static_assert(COLS * HA % NT == 0 && COLS * NB % NT == 0, "balanced column passes");
-    static constexpr size_t buf_elems = (size_t)L * P + (size_t)(L / 8) * SKEW;   // complex
-    static SFOC_DEV int row(int r) { return r * P + (r >> 3) * SKEW; }
-    // row n1 + NB * k with n1 < NB (= 8): its 8-row group is k
+    // Two tasks' loads in flight in the search window's stages: only where
+    // the registers allow (the larger sides run more waves per CU and keep
+    // more of the spectra in registers).
+    static constexpr bool PIPE = L <= 128;
+    static_assert(L == NA * NB && NB % 2 == 0 && NA % 2 == 0, "even radices");
+    static_assert(COLS * HA % NT == 0, "whole pass-B rounds");
+    static_assert(2 * P >= L, "a row pair holds one real row of L values per row");
+    static constexpr size_t buf_elems = (size_t)L * P + (size_t)(L / NB) * SKEW;   // complex
+    static SFOC_DEV int row(int r) { return r * P + (r / NB) * SKEW; }
+    // row n1 + NB * k with n1 < NB: its NB-row group is k
     static SFOC_DEV int rowg(int n1, int k) { return n1 * P + k * (NB * P + SKEW); }
+    // Slot of element n1 of pass-A output column k2 inside a row pair: a
+    // permutation of n1 that differs between columns (bank spreading).
+    static SFOC_DEV int swz(int n1, int k2) {
+        if constexpr ((NB & (NB - 1)) == 0) return n1 ^ (k2 & (NB - 1));
+        else return (n1 + k2) % NB;
+    }
     static constexpr size_t lds_bytes = sizeof(float2) * (buf_elems + L) + 1024;
 };
 
@@ -294,7 +429,7 @@ SFOC_DEV void row_stage(const void* plane, int pitch, int y0, int x0, int nrows,
         float2* reg = buf + C::row(2 * p);
 #pragma unroll
         for (int k2 = 0; k2 < C::NA; ++k2)
-            reg[k2 * C::NB + (n1 ^ (k2 & (C::NB - 1)))] = k2 == 0 ? x[0] : cmul(x[k2], tw[n1 * k2]);
+            reg[k2 * C::NB + C::swz(n1, k2)] = k2 == 0 ? x[0] : cmul(x[k2], tw[n1 * k2]);
     };
     if (PIPE) {
         // Two tasks per iteration with both tasks' loads issued first.
@@ -329,13 +464,13 @@ SFOC_DEV void row_stage(const void* plane, int pitch, int y0, int x0, int nrows,
             const int ka = j, kb = j == 0 ? C::HA : C::NA - j;
 #pragma unroll
             for (int n1 = 0; n1 < C::NB; ++n1) {
-                u[n1] = reg[ka * C::NB + (n1 ^ (ka & (C::NB - 1)))];
-                v[n1] = reg[kb * C::NB + (n1 ^ (kb & (C::NB - 1)))];
+                u[n1] = reg[ka * C::NB + C::swz(n1, ka)];
+                v[n1] = reg[kb * C::NB + C::swz(n1, kb)];
             }
             dftn<C::NB, false>(u);
             dftn<C::NB, false>(v);
         }
-        wave_sync();   // this pair's reads before its in-place writes
+        pair_sync<C::HA>();   // this pair's reads before its in-place writes
         if (act) {
             // half spectra of the two real rows: A = (X + conj X~)/2, B = -i (X - conj X~)/2
             float2* ra = buf + C::row(2 * p);
@@ -508,10 +643,10 @@ SFOC_DEV void match_item(const MatchArgs& A, int i, int bq, int slot, const floa
     float2 xsp[C::RB][C::BINS];   // search-window spectrum of the current channel
     for (int h = 0; h < A.z; ++h) {
         stage_fence();
-        row_stage<L, DT, true>(elem_ptr<DT>(A.desc_ref, h * plane_r), (int)A.Wr, (int)(sy + u0), (int)(sx + v0), Mu, Mv,
+        row_stage<L, DT, C::PIPE>(elem_ptr<DT>(A.desc_ref, h * plane_r), (int)A.Wr, (int)(sy + u0), (int)(sx + v0), Mu, Mv,
                          buf, tw, nullptr, nullptr);
         stage_fence();
-        col_stage<L, false, true>(buf, tw, Mpair2, [&](int rd, int cc, int j, float2(&u)[C::NB], float2(&v)[C::NB]) {
+        col_stage<L, false, C::PIPE>(buf, tw, Mpair2, [&](int rd, int cc, int j, float2(&u)[C::NB], float2(&v)[C::NB]) {
             if (cc == 0) separate_packed<C::NB>(u, v, j);
 #pragma unroll
             for (int q = 0; q < C::NB; ++q) {
@@ -593,7 +728,7 @@ SFOC_DEV void match_item(const MatchArgs& A, int i, int bq, int slot, const floa
     __syncthreads();
     {
         float2 zc[C::RB][C::BINS];
-        col_stage<L, true, true>(buf, tw, L, [&](int rd, int, int, float2(&u)[C::NB], float2(&v)[C::NB]) {
+        col_stage<L, true, C::PIPE>(buf, tw, L, [&](int rd, int, int, float2(&u)[C::NB], float2(&v)[C::NB]) {
 #pragma unroll
             for (int q = 0; q < C::NB; ++q) {
                 zc[rd][q] = u[q];
@@ -648,12 +783,12 @@ SFOC_DEV void match_item(const MatchArgs& A, int i, int bq, int slot, const floa
                 }
                 dftn<C::NA, true>(x);
             }
-            wave_sync();   // this pair's reads before its in-place writes
+            pair_sync<C::NB>();   // this pair's reads before its in-place writes
             if (act) {
                 float2* reg = buf + C::row(2 * p);
 #pragma unroll
                 for (int k2 = 0; k2 < C::NA; ++k2)
-                    reg[k2 * C::NB + (n1 ^ (k2 & (C::NB - 1)))] = k2 == 0 ? x[0] : cmul(x[k2], cconj(tw[n1 * k2]));
+                    reg[k2 * C::NB + C::swz(n1, k2)] = k2 == 0 ? x[0] : cmul(x[k2], cconj(tw[n1 * k2]));
             }
         }
         __syncthreads();
@@ -670,13 +805,13 @@ SFOC_DEV void match_item(const MatchArgs& A, int i, int bq, int slot, const floa
             if (act) {
 #pragma unroll
                 for (int n1 = 0; n1 < C::NB; ++n1) {
-                    u[n1] = reg[ka * C::NB + (n1 ^ (ka & (C::NB - 1)))];
-                    v[n1] = reg[kb * C::NB + (n1 ^ (kb & (C::NB - 1)))];
+                    u[n1] = reg[ka * C::NB + C::swz(n1, ka)];
+                    v[n1] = reg[kb * C::NB + C::swz(n1, kb)];
                 }
                 dftn<C::NB, true>(u);
                 dftn<C::NB, true>(v);
             }
-            wave_sync();   // this pair's reads before its in-place writes
+            pair_sync<C::HA>();   // this pair's reads before its in-place writes
             if (act) {
                 float* rr = reinterpret_cast<float*>(reg);   // R[2p][v] at rr[v], R[2p+1][v] at rr[L + v]
 #pragma unroll
@@ -813,7 +948,7 @@ SFOC_DEV void match_item(const MatchArgs& A, int i, int bq, int slot, const floa
 }
 
 template <int L, int DT, bool BATCH>
-__global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchArgs single,
+__global__ __launch_bounds__(MatchCfg<L>::NT, MatchCfg<L>::MINB) void match_kernel(const MatchArgs single,
                                                                    const MatchArgs* __restrict__ pairs,
                                                                    const int4* __restrict__ items) {
     using C = MatchCfg<L>;
@@ -840,7 +975,7 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_kernel(const MatchAr
 // takes items in order from a counter (zeroed before the launch) until the
 // table is exhausted; every workgroup then exits.
 template <int L, int DT>
-__global__ __launch_bounds__(MatchCfg<L>::NT, 2) void match_persistent_kernel(const MatchArgs* __restrict__ pairs,
+__global__ __launch_bounds__(MatchCfg<L>::NT, MatchCfg<L>::MINB) void match_persistent_kernel(const MatchArgs* __restrict__ pairs,
                                                                               const int4* __restrict__ items,
                                                                               int nitems, int* __restrict__ counter) {
     using C = MatchCfg<L>;
@@ -1082,6 +1217,12 @@ static hipError_t launch_match_L(const MatchArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <int L>
+static hipError_t launch_match_side(const MatchArgs& a, int dtype, hipStream_t st) {
+    return dtype == 0 ? launch_match_L<L, 0>(a, st) : dtype == 1 ? launch_match_L<L, 1>(a, st)
+                                                                 : launch_match_L<L, 2>(a, st);
+}
+
 hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void* desc_ref, int64_t Hr, int64_t Wr,
                         const double* i1, const double* i2, int z, int dtype, const int32_t* ips,
                         const int32_t* prior, int n, int m, int r, float* ncc, sfoc_cp* cps, void* ws,
@@ -1108,11 +1249,13 @@ hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void
     const int L = mp.L;
     match_args_layout(a, mp, ws);
     hipError_t e;
-    if (L == 64) e = dtype == 0 ? launch_match_L<64, 0>(a, st)
-                   : dtype == 1 ? launch_match_L<64, 1>(a, st) : launch_match_L<64, 2>(a, st);
-    else if (L == 128) e = dtype == 0 ? launch_match_L<128, 0>(a, st)
-                        : dtype == 1 ? launch_match_L<128, 1>(a, st) : launch_match_L<128, 2>(a, st);
-    else return hipErrorInvalidValue;
+    switch (L) {
+        case 64: e = launch_match_side<64>(a, dtype, st); break;
+        case 128: e = launch_match_side<128>(a, dtype, st); break;
+        case 160: e = launch_match_side<160>(a, dtype, st); break;
+        case 192: e = launch_match_side<192>(a, dtype, st); break;
+        default: return hipErrorInvalidValue;
+    }
     if (e != hipSuccess) return e;
     if (mp.nb > 1) {
         trace_begin(st, SFOC_K_PEAK);
@@ -1138,7 +1281,8 @@ static hipError_t launch_match_items_L(const MatchArgs* pairs, const int4* items
         if ((e = ensure_dynamic_lds((const void*)kern, (int)C::lds_bytes)) != hipSuccess) return e;
         trace_begin(st, SFOC_K_MATCH);
         hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, st, counter);
-        hipLaunchKernelGGL(kern, dim3(grid < nitems ? grid : nitems), dim3(C::NT), C::lds_bytes, st, pairs, items,
+        const int g = grid * C::MINB;   // `grid` counts CUs
+        hipLaunchKernelGGL(kern, dim3(g < nitems ? g : nitems), dim3(C::NT), C::lds_bytes, st, pairs, items,
                            nitems, counter);
         trace_end(st, SFOC_K_MATCH);
     } else {
@@ -1151,21 +1295,27 @@ static hipError_t launch_match_items_L(const MatchArgs* pairs, const int4* items
     return hipGetLastError();
 }
 
+template <int L>
+static hipError_t launch_match_items_side(int dtype, const MatchArgs* pairs, const int4* items, int nitems,
+                                          int* counter, int grid, hipStream_t st) {
+    return dtype == 0 ? launch_match_items_L<L, 0>(pairs, items, nitems, counter, grid, st)
+         : dtype == 1 ? launch_match_items_L<L, 1>(pairs, items, nitems, counter, grid, st)
+                      : launch_match_items_L<L, 2>(pairs, items, nitems, counter, grid, st);
+}
+
 // One launch over (pair, IP, block) items that share the transform side L:
 // one workgroup per item, or (counter != null) a persistent grid of `grid`
 // workgroups taking items from *counter.
 hipError_t launch_match_items(int L, int dtype, const MatchArgs* pairs, const int4* items, int nitems, int* counter,
                               int grid, hipStream_t st) {
     if (nitems == 0) return hipSuccess;
-    if (L == 64)
-        return dtype == 0 ? launch_match_items_L<64, 0>(pairs, items, nitems, counter, grid, st)
-             : dtype == 1 ? launch_match_items_L<64, 1>(pairs, items, nitems, counter, grid, st)
-                          : launch_match_items_L<64, 2>(pairs, items, nitems, counter, grid, st);
-    if (L == 128)
-        return dtype == 0 ? launch_match_items_L<128, 0>(pairs, items, nitems, counter, grid, st)
-             : dtype == 1 ? launch_match_items_L<128, 1>(pairs, items, nitems, counter, grid, st)
-                          : launch_match_items_L<128, 2>(pairs, items, nitems, counter, grid, st);
-    return hipErrorInvalidValue;
+    switch (L) {
+        case 64: return launch_match_items_side<64>(dtype, pairs, items, nitems, counter, grid, st);
+        case 128: return launch_match_items_side<128>(dtype, pairs, items, nitems, counter, grid, st);
+        case 160: return launch_match_items_side<160>(dtype, pairs, items, nitems, counter, grid, st);
+        case 192: return launch_match_items_side<192>(dtype, pairs, items, nitems, counter, grid, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 // Peak of split pairs: items {pair, first IP of a run of 256}.

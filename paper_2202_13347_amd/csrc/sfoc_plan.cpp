@@ -151,7 +151,7 @@ size_t describe_ws_bytes(int64_t H, int64_t W) {
 
 MatchPlan match_plan_L(int32_t n, int32_t m, int32_t r, int L) {
     MatchPlan p{0, 1, 0, 0};
-    if (m < 3 || m > 128 || r < 1 || r > kMaxRadiusMatch || n < 0 || (L != 64 && L != 128)) return p;
+    if (m < 3 || m > kMaxTemplate || r < 1 || r > kMaxRadiusMatch || n < 0 || side_index(L) < 0) return p;
     const int M = m + 2 * r, V = 2 * r + 1;
     if (M <= L) {
         p.L = L;
@@ -167,14 +167,24 @@ MatchPlan match_plan_L(int32_t n, int32_t m, int32_t r, int L) {
     return p;
 }
 
+// Transform work of one IP under a plan, in units of L^2 log2(L^2).
+static double plan_cost(const MatchPlan& p) {
+    const double L2 = (double)p.L * p.L;
+    return (double)p.nb * p.nb * L2 * log2(L2);
+}
+
 MatchPlan match_plan(int32_t n, int32_t m, int32_t r) {
-    // (templates beyond 128 never fit a transform; the bounds also keep
-    // m + 2r far from int overflow)
-    if (m < 3 || r < 1 || m > 128 || r > kMaxRadiusMatch) return MatchPlan{0, 1, 0, 0};
+    // (the bounds also keep m + 2r far from int overflow)
+    if (m < 3 || r < 1 || m > kMaxTemplate || r > kMaxRadiusMatch) return MatchPlan{0, 1, 0, 0};
     const int M = m + 2 * r;
-    if (M <= 64) return match_plan_L(n, m, r, 64);
-    if (m > 126) return MatchPlan{0, 1, 0, 0};
-    return match_plan_L(n, m, r, 128);
+    for (int k = 0; k < kNumSides; ++k)
+        if (M <= kSides[k]) return match_plan_L(n, m, r, kSides[k]);
+    MatchPlan best{0, 1, 0, 0};
+    for (int k = 0; k < kNumSides; ++k) {
+        const MatchPlan q = match_plan_L(n, m, r, kSides[k]);
+        if (q.L != 0 && (best.L == 0 || plan_cost(q) < plan_cost(best))) best = q;
+    }
+    return best;
 }
 
 int match_candidates(int32_t m, int32_t r, int* Ls) {
@@ -182,14 +192,16 @@ int match_candidates(int32_t m, int32_t r, int* Ls) {
     if (d.L == 0) return 0;
     int k = 0;
     Ls[k++] = d.L;
-    const int other = d.L == 64 ? 128 : 64;
-    const MatchPlan o = match_plan_L(1, m, r, other);
-    if (o.L != 0 && o.nb <= kMaxTuneBlocks && o.Vb >= 2) Ls[k++] = other;
+    for (int j = 0; j < kNumSides; ++j) {
+        if (kSides[j] == d.L) continue;
+        const MatchPlan o = match_plan_L(1, m, r, kSides[j]);
+        if (o.L != 0 && o.nb <= kMaxTuneBlocks && o.Vb >= 2) Ls[k++] = kSides[j];
+    }
     return k;
 }
 
 static bool is_candidate(int m, int r, int L) {
-    int Ls[2];
+    int Ls[kNumSides];
     const int n = match_candidates(m, r, Ls);
     for (int k = 0; k < n; ++k)
         if (Ls[k] == L) return true;

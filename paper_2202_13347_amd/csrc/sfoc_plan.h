@@ -84,6 +84,19 @@ size_t describe_ws_bytes(int64_t H, int64_t W);
 // Size of the library-owned aggregate array of sfoc_describe_noalloc.
 constexpr size_t kNoAllocScratchBytes = SFOC_NOALLOC_SCRATCH_BYTES;
 
+// Transform sides of the match kernels: L = 16 x NB with NB = 4 (L = 64,
+// radices 8 x 8), 8, 10, 12.
+constexpr int kNumSides = 4;
+constexpr int kSides[kNumSides] = {64, 128, 160, 192};
+inline int side_index(int L) {
+    for (int k = 0; k < kNumSides; ++k)
+        if (kSides[k] == L) return k;
+    return -1;
+}
+// Largest template side: a search window of m + Vb - 1 rows with Vb >= 2
+// offsets per block must fit the largest transform.
+constexpr int kMaxTemplate = 191;
+
 // How a match is laid out: FFT side L and the split of the (2r+1)^2 offsets
 // into nb x nb blocks of at most Vb offsets per axis, each with a search
 // window of at most L x L.  L = 0 means unsupported.
@@ -91,15 +104,19 @@ struct MatchPlan {
     int L, nb, Vb;
     size_t ws_bytes;   // surfaces + per-block records when nb > 1
 };
+// The default layout: one transform of the smallest side L >= M = m + 2r
+// when M <= 192; beyond, offset blocks of the side with the least transform
+// work nb^2 L^2 log2 L^2.
 MatchPlan match_plan(int32_t n, int32_t m, int32_t r);
-// The same for a given transform side L (64 or 128); L = 0 in the result if
-// the template does not fit (a block needs m + Vb - 1 <= L with Vb >= 2).
+// The same for a given side L (one of kSides); L = 0 in the result if the
+// template does not fit it (a block needs m + Vb - 1 <= L with Vb >= 2).
 MatchPlan match_plan_L(int32_t n, int32_t m, int32_t r, int L);
 constexpr int kMaxRadiusMatch = 511;
 
-// Transform sides an autotuner may time for (m, r): every L in {64, 128}
-// whose plan exists with at most kMaxTuneBlocks offset blocks per axis, the
-// default first.  Returns the count written to Ls (at most 2).
+// Transform sides an autotuner may time for (m, r): the default first, then
+// every other side whose plan exists with at most kMaxTuneBlocks offset
+// blocks per axis, in increasing L.  Returns the count written to Ls (at
+// most kNumSides).
 constexpr int kMaxTuneBlocks = 8;
 int match_candidates(int32_t m, int32_t r, int* Ls);
 

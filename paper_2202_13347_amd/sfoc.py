@@ -67,9 +67,9 @@ class PlanInfo(ctypes.Structure):
     """sfoc_plan_info: what a batched plan decided (work items, tuned and
     cached shape classes, graph and persistent launches, device bytes)."""
     _fields_ = [("n_pairs", ctypes.c_int32), ("describe_tiles", ctypes.c_int32),
-                ("match_items", ctypes.c_int32 * 2), ("peak_items", ctypes.c_int32),
+                ("match_items", ctypes.c_int32 * 4), ("peak_items", ctypes.c_int32),
                 ("tuned_classes", ctypes.c_int32), ("cached_classes", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("persistent", ctypes.c_int32 * 2), ("reserved", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+                ("persistent", ctypes.c_int32 * 4), ("reserved", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
 
 
 PLAN_GRAPH, PLAN_AUTOTUNE, PLAN_DENSE_SEN, PLAN_PERSISTENT = 1, 2, 4, 8
@@ -338,7 +338,7 @@ class Plan:
 
     pairs: sequence of dicts with CUDA tensors ref (Hr, Wr) float32, sen
     (Hs, Ws) float32, ips (n, 2) int32, optional prior (n, 2) int32, and ints
-    m, r, optional fft_side (0 / 64 / 128).  The plan owns per-pair outputs
+    m, r, optional fft_side (0 / 64 / 128 / 160 / 192).  The plan owns per-pair outputs
     cps (n, 8) int32 and, with want_ncc, ncc (n, 2r+1, 2r+1); it keeps
     references to every input tensor for its lifetime.  Calling the plan
     runs sfoc_register_cps_batched on the current stream."""
@@ -389,9 +389,9 @@ class Plan:
         nb = (ctypes.c_int32 * n)()
         _check(lib().sfoc_plan_get_info(self.handle, ctypes.byref(inf), L, nb, n), "sfoc_plan_get_info")
         return {"n_pairs": inf.n_pairs, "describe_tiles": inf.describe_tiles,
-                "match_items": (inf.match_items[0], inf.match_items[1]), "peak_items": inf.peak_items,
+                "match_items": tuple(inf.match_items), "peak_items": inf.peak_items,
                 "tuned_classes": inf.tuned_classes, "cached_classes": inf.cached_classes, "graph": inf.graph,
-                "persistent": (inf.persistent[0], inf.persistent[1]),
+                "persistent": tuple(inf.persistent),
                 "device_bytes": inf.device_bytes, "fft_side": list(L), "blocks": list(nb)}
 
     def close(self):
@@ -408,9 +408,9 @@ class Plan:
 
 def match_candidates(m: int, r: int) -> list[tuple[int, int]]:
     """[(transform side, offset blocks per axis)] an autotuner may time."""
-    L = (ctypes.c_int32 * 2)()
-    nb = (ctypes.c_int32 * 2)()
-    k = lib().sfoc_match_candidates(m, r, L, nb, 2)
+    L = (ctypes.c_int32 * 4)()
+    nb = (ctypes.c_int32 * 4)()
+    k = lib().sfoc_match_candidates(m, r, L, nb, 4)
     if k < 0:
         raise SfocError(k, "sfoc_match_candidates")
     return [(L[i], nb[i]) for i in range(k)]

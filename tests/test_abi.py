@@ -91,10 +91,13 @@ def test_workspace_queries():
     assert w >= 2 * 16 * 2048 * 2048 * 4 + 2 * 2049 * 2049 * 8
     b = ctypes.c_size_t()
     assert S.lib().sfoc_match_workspace(10, 64, 32, 16, ctypes.byref(b)) == 0 and b.value == 0
-    # windows beyond 128 x 128 split the offsets: per-CP surfaces + block records
-    assert S.lib().sfoc_match_workspace(10, 64, 48, 16, ctypes.byref(b)) == 0
-    assert b.value >= 10 * 97 * 97 * 4 + 10 * 4 * 16
-    assert S.lib().sfoc_match_workspace(10, 127, 2, 16, ctypes.byref(b)) == S.SFOC_E_UNSUPPORTED
+    # windows up to 192 x 192 are one transform: no workspace
+    assert S.lib().sfoc_match_workspace(10, 64, 48, 16, ctypes.byref(b)) == 0 and b.value == 0
+    assert S.lib().sfoc_match_workspace(10, 127, 30, 16, ctypes.byref(b)) == 0 and b.value == 0
+    # windows beyond 192 x 192 split the offsets: per-CP surfaces + block records
+    assert S.lib().sfoc_match_workspace(10, 96, 64, 16, ctypes.byref(b)) == 0
+    assert b.value >= 10 * 129 * 129 * 4 + 10 * 4 * 16
+    assert S.lib().sfoc_match_workspace(10, 192, 2, 16, ctypes.byref(b)) == S.SFOC_E_UNSUPPORTED
     assert S.lib().sfoc_match_workspace(10, 16, 600, 16, ctypes.byref(b)) == S.SFOC_E_UNSUPPORTED
     assert S.lib().sfoc_match_workspace(10, 2, 3, 16, ctypes.byref(b)) == S.SFOC_E_INVALID_ARG
 
@@ -125,8 +128,8 @@ def test_match_and_register_reject_bad_arguments_before_launch():
         return m_(*a.values())
     assert call(m=2) == S.SFOC_E_INVALID_ARG
     assert call(r=0) == S.SFOC_E_INVALID_ARG
-    assert call(m=127, r=20) == S.SFOC_E_UNSUPPORTED
-    assert call(m=100, r=20) == S.SFOC_E_WORKSPACE        # split offsets need a workspace
+    assert call(m=192, r=20) == S.SFOC_E_UNSUPPORTED
+    assert call(m=100, r=50) == S.SFOC_E_WORKSPACE        # split offsets (window beyond 192) need a workspace
     assert call(dt=5) == S.SFOC_E_INVALID_ARG
     assert call(i1=None) == S.SFOC_E_INVALID_ARG
     assert call(cps=None) == S.SFOC_E_INVALID_ARG

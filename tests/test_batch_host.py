@@ -42,6 +42,9 @@ int main(void) {
     assert int(got["info.size"]) == ctypes.sizeof(S.PlanInfo)
 
 
+SIDES = (64, 128, 160, 192)
+
+
 def _split(m, r, L):
     """Offset blocks per axis for transform side L, written from the
     condition that a block of Vb offsets needs a search window of
@@ -57,25 +60,41 @@ def _split(m, r, L):
     return math.ceil(V / best)
 
 
+def _default(m, r):
+    """The smallest side holding the whole window; beyond 192 the side of
+    least transform work nb^2 L^2 log2(L^2)."""
+    M = m + 2 * r
+    for L in SIDES:
+        if M <= L:
+            return L
+    cost = {L: _split(m, r, L) ** 2 * L * L * math.log2(L * L) for L in SIDES if _split(m, r, L)}
+    return min(cost, key=cost.get) if cost else None
+
+
 @pytest.mark.parametrize("m,r", [(32, 10), (48, 16), (64, 32), (96, 64), (48, 64), (30, 100), (64, 16),
-                                 (96, 16), (3, 1), (126, 200), (60, 2), (62, 40)])
+                                 (96, 16), (3, 1), (126, 200), (60, 2), (62, 40), (64, 48), (150, 20),
+                                 (191, 1), (100, 46), (16, 100), (190, 300)])
 def test_match_candidates(m, r):
     got = S.match_candidates(m, r)
-    M = m + 2 * r
-    default = 64 if M <= 64 else 128
-    assert got[0][0] == default
-    assert got[0][1] == _split(m, r, default)
-    other = 128 if default == 64 else 64
-    nb = _split(m, r, other)
-    want_other = nb is not None and nb <= 8
-    assert (len(got) == 2) == want_other, got
-    if want_other:
-        assert got[1] == (other, nb)
+    d = _default(m, r)
+    assert got[0] == (d, _split(m, r, d))
+    want = [(L, _split(m, r, L)) for L in SIDES if L != d and _split(m, r, L) is not None and _split(m, r, L) <= 8]
+    assert got[1:] == want, (got, want)
+
+
+def test_large_windows_are_one_transform():
+    # every search window up to 192 x 192 is a single transform
+    for m, r in ((64, 48), (32, 60), (100, 46), (150, 20), (126, 2)):
+        L, nb = S.match_candidates(m, r)[0]
+        assert nb == 1 and L >= m + 2 * r and L in (160, 192)
+    # 224: 2 x 2 blocks of the 160 side (4 x 160^2 transforms, less work than 4 x 192^2 or 16 x 128^2)
+    assert S.match_candidates(96, 64)[0] == (160, 2)
 
 
 def test_match_candidates_unsupported():
     assert S.match_candidates(2, 4) == []      # m < 3
-    assert S.match_candidates(127, 10) == []   # m > 126 with M > 128
+    assert S.match_candidates(192, 10) == []   # m > 191
+    assert S.match_candidates(30, 512) == []   # r > 511
 
 
 def _brute_tiles(ips, prior, m, r, Hs, Ws, Hr, Wr):
@@ -127,7 +146,7 @@ def _pair(**kw):
     ({"m": 2}, 0, S.SFOC_E_INVALID_ARG),
     ({"fft_side": 96}, 0, S.SFOC_E_INVALID_ARG),
     ({"m": 70, "r": 4, "fft_side": 64}, 0, S.SFOC_E_UNSUPPORTED),   # template wider than the transform
-    ({"m": 127, "r": 10}, 0, S.SFOC_E_UNSUPPORTED),
+    ({"m": 192, "r": 10}, 0, S.SFOC_E_UNSUPPORTED),
     ({"cps": None}, 0, S.SFOC_E_INVALID_ARG),
     ({"Hs": 1 << 17}, 0, S.SFOC_E_UNSUPPORTED),
 ])

@@ -32,11 +32,18 @@ def gpu():
 SPECS = [
     (0, (200, 240), (180, 240), 24, 6, 9, False, False),
     (1, (256, 256), None, 32, 10, 16, True, True),
-    (2, (300, 220), (300, 200), 48, 48, 6, False, False),   # 144-px window: offsets split (L = 128)
+    (2, (300, 220), (300, 200), 48, 48, 6, False, False),   # 144-px window: one L = 160 transform
     (3, (160, 160), None, 16, 4, 0, False, False),          # no IPs
     (4, (240, 260), None, 32, 20, 12, False, False),
-    (5, (220, 220), None, 20, 60, 5, False, True),          # 140-px window, split
+    (5, (220, 220), None, 20, 60, 5, False, True),          # 140-px window (L = 160)
+    (6, (340, 330), None, 48, 80, 5, False, False),         # 208-px window: offsets split (2 x 2 blocks, L = 128)
+    (7, (300, 300), None, 96, 64, 4, True, False),          # 224-px window: 2 x 2 blocks of L = 160
 ]
+SIDES = (64, 128, 160, 192)
+
+
+def default_side(m, r):
+    return S.match_candidates(m, r)[0]
 
 
 def build_pairs(specs, seed_shift=0):
@@ -96,15 +103,16 @@ def test_batched_equals_per_pair(flags):
     want = per_pair(dp, p)
     plan = S.Plan(dp, p, flags=flags, want_ncc=True)
     info = plan.info()
-    assert info["fft_side"] == [64 if q["m"] + 2 * q["r"] <= 64 else 128 for q in dp]
-    assert info["blocks"][2] == 2 and info["blocks"][5] == 2
+    assert info["fft_side"] == [default_side(q["m"], q["r"])[0] for q in dp]
+    assert info["fft_side"][2] == 160 and info["blocks"][2] == 1
+    assert (info["fft_side"][6], info["blocks"][6]) == (128, 2) and (info["fft_side"][7], info["blocks"][7]) == (160, 2)
     for rep in range(2):
         plan()
         torch.cuda.synchronize()
         assert_same(plan, want)
     if flags & S.PLAN_GRAPH:
         assert plan.info()["graph"] == 1
-    assert plan.info()["persistent"] == ((1, 1) if flags & S.PLAN_PERSISTENT else (0, 0))
+    assert plan.info()["persistent"] == ((1,) * 4 if flags & S.PLAN_PERSISTENT else (0,) * 4)
     plan.close()
 
 
@@ -161,9 +169,10 @@ def oracle_check(q, cps, ncc, p):
     return st
 
 
-@pytest.mark.parametrize("sides", [(64, 128), (128, 64)])
+@pytest.mark.parametrize("sides", [(64, 128), (128, 64), (160, 192), (192, 160)])
 def test_forced_sides_match_oracle(sides):
-    # pair 0: 36-px window (default 64); pair 4: 72-px window (default 128, or 64 in two blocks per axis)
+    # pair 0: 36-px window (default 64); pair 4: 72-px window (default 128, or 64 in two blocks per
+    # axis); the 160 and 192 sides with windows narrower than the transform
     say(f"forced transform sides {sides}")
     specs = [SPECS[0], SPECS[4]]
     pairs = build_pairs(specs)
@@ -193,7 +202,7 @@ def test_autotune_and_cache(tmp_path):
     info = plan.info()
     # every class with IPs and two candidate sides is timed once
     timed = sum(len(S.match_candidates(q["m"], q["r"])) > 1 and len(q["ips"]) > 0 for q in pairs)
-    assert timed == 5
+    assert timed >= 5
     assert info["tuned_classes"] == timed
     for q, L in zip(pairs, info["fft_side"]):
         assert L in [c[0] for c in S.match_candidates(q["m"], q["r"])]
@@ -201,7 +210,7 @@ def test_autotune_and_cache(tmp_path):
     torch.cuda.synchronize()
     for k, q in enumerate(pairs):
         g = plan.cps[k].cpu().numpy()
-        if info["fft_side"][k] == (64 if q["m"] + 2 * q["r"] <= 64 else 128):
+        if info["fft_side"][k] == default_side(q["m"], q["r"])[0]:
             np.testing.assert_array_equal(g, want[k][0])
         elif len(q["ips"]):
             oracle_check(q, plan.cps[k], plan.ncc[k], p)
@@ -236,7 +245,7 @@ def test_corrupt_cache_is_ignored(tmp_path):
     plan()
     torch.cuda.synchronize()
     for k, q in enumerate(pairs):
-        if info["fft_side"][k] == (64 if q["m"] + 2 * q["r"] <= 64 else 128):
+        if info["fft_side"][k] == default_side(q["m"], q["r"])[0]:
             continue
         if len(q["ips"]):
             oracle_check(q, plan.cps[k], plan.ncc[k], p)

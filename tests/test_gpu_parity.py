@@ -193,9 +193,12 @@ def test_register_small_pairs(seed):
 
 @pytest.mark.parametrize("m,r,size", [(3, 62, 200), (126, 1, 200), (60, 2, 120), (64, 1, 150), (5, 3, 40),
                                       (31, 16, 150), (17, 9, 90),
-                                      # search windows beyond 128: offsets split into blocks
-                                      (64, 48, 300), (32, 60, 300), (100, 20, 260), (16, 100, 330),
-                                      (126, 2, 200)])
+                                      # one transform of side 160 (16 x 10) or 192 (16 x 12)
+                                      (64, 48, 300), (32, 60, 300), (100, 20, 260), (126, 2, 200),
+                                      (64, 60, 320), (150, 20, 330), (190, 1, 260),
+                                      # windows beyond 192: offsets split into blocks (of side 128,
+                                      # 160 and 192 respectively)
+                                      (16, 100, 330), (96, 64, 360), (180, 10, 300)])
 def test_template_and_radius_extremes(m, r, size):
     say("extremes", m, r, size)
     pr = synth.make_pair(21 + m, size, min(3.0, r - 0.5) if r > 1 else 0.4)
@@ -321,5 +324,5 @@ def test_scene_all_cps_match_oracle(scene):
     assert np.array_equal(go["dy"], o["dy"]) and np.array_equal(go["dx"], o["dx"])
     assert np.array_equal(go["flags"], o["flags"])
     assert np.abs(go["score"] - o["score"]).max() <= 1e-12
-    st2, _, _ = compare_to_golden(gs, go, ties)
+    st2, _, _ = compare_to_golden(gs, go, ties, r)
     assert st2["ambiguous"] == st["ambiguous"] and st2["ambiguous_taken"] == st["ambiguous_taken"]

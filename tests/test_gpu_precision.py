@@ -98,7 +98,7 @@ def test_large_all_cps_match_stored_oracle(large):
         oq, ties = golden_records(gold, kind)
         gk = g.copy()
         gk["flags"] &= ~np.uint32(O.VALID | O.INCONSISTENT)
-        st, score_err, off_err = compare_to_golden(gk, oq, ties, ref=o64)
+        st, score_err, off_err = compare_to_golden(gk, oq, ties, r, ref=o64)
         same64 = np.isfinite(score_err)
         summ = dict(st, vs_o64={
             "integer_equal": int(same64.sum()),

@@ -27,7 +27,7 @@ using namespace sfoc;
 
 static void show_plan(int m, int r) {
     const MatchPlan p = match_plan(7, m, r);
-    int Ls[2];
+    int Ls[kNumSides];
     const int n = match_candidates(m, r, Ls);
     printf("plan %d %d %d %d %d %zu cand", m, r, p.L, p.nb, p.Vb, p.ws_bytes);
     for (int k = 0; k < n; ++k) printf(" %d", Ls[k]);
@@ -177,7 +177,8 @@ def test_planner_host_code(tmp_path, sanitize):
     assert got["params_null"] == [["-1"]]
     plans = {(int(e[0]), int(e[1])): e[2:] for e in got["plan"]}
     assert plans[(64, 32)][:3] == ["128", "1", "65"]
-    assert plans[(96, 64)][:3] == ["128", "4", "33"] and plans[(96, 64)][4:] == ["cand", "128"]
-    assert plans[(2, 5)][0] == "0" and plans[(127, 1)][0] == "0" and plans[(30, 512)][0] == "0"
+    assert plans[(96, 64)][:3] == ["160", "2", "65"] and plans[(96, 64)][4:] == ["cand", "160", "128", "192"]
+    assert plans[(64, 48)][:3] == ["160", "1", "97"]
+    assert plans[(2, 5)][0] == "0" and plans[(127, 1)][0] == "160" and plans[(30, 512)][0] == "0"
     assert plans[(1 << 30, 1 << 30)][0] == "0" and plans[(2000000000, 5)][0] == "0"
     assert got["tiles"] == [["ok"]]
