@@ -249,6 +249,35 @@ def kernel_table(kt, steps, p, H, W, n, m, r):
     }
 
 
+def run_integral_alone(args, S, torch, p, ref):
+    """sfoc_describe with integral images on the scene's reference image:
+    the describe launch, then the integral-image kernels on the same stream
+    with nothing beside them (in the register step they share the GPU with
+    the sensed image's describe)."""
+    H, W = ref.shape
+    z = p.z
+    desc = torch.empty((z, H, W), dtype=torch.float32, device=ref.device)
+    i1 = torch.empty((H + 1, W + 1), dtype=torch.float64, device=ref.device)
+    i2 = torch.empty_like(i1)
+    wsb = S.describe_workspace(H, W, p)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=ref.device)
+    fn = S.lib().sfoc_describe
+    import ctypes
+
+    def step():
+        rc = fn(ref.data_ptr(), H, W, ref.stride(0), ctypes.byref(p), desc.data_ptr(), i1.data_ptr(),
+                i2.data_ptr(), ws.data_ptr(), wsb, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert rc == 0, rc
+
+    for _ in range(args.warmup):
+        step()
+    _, _, kt, _ = timed_and_traced(S, torch, step, args.steps)
+    ms = kt["integral"][0] / max(1, kt["integral"][1])
+    return {"workload": f"sfoc_describe with integral images of the {H}x{W} reference image",
+            "integral_ms_per_call": ms, "describe_ms_per_call": kt["describe"][0] / max(1, kt["describe"][1]),
+            "kernels": {"integral": roof_entry("integral", ms, 0.0, INTEGRAL_BYTES_PER_PX * H * W, 1)}}
+
+
 def run_precision(args, S, synth, torch, dev, scene):
     """Descriptor storage in bfloat16 and float16 (FFT in float32, integral
     images and variance in float64): the scene step and the 10000 x 10000
@@ -728,6 +757,7 @@ def main():
                      "rmse_valid_px": float(np.sqrt(np.mean(err[valid] ** 2))) if valid.any() else None},
         "parity": parity_vs_stored_oracle(S, "scene", R.cps),
     }
+    out["integral_standalone"] = run_integral_alone(args, S, torch, p, ref)
     if args.ransac:
         out["ransac"] = run_ransac(args, S, synth, torch, p, dev)
     if args.rectify:

@@ -196,7 +196,12 @@ int sfoc_describe_noalloc(const float* img, int64_t H, int64_t W, int64_t ld, co
  * parabola; then a median-displacement consistency check at 1.5 px sets
  * INCONSISTENT / VALID.
  *  desc_sen, desc_ref  descriptors (layout above), z channels, element type dtype.
- *  integ1, integ2      integral images of desc_ref ((Hr+1) x (Wr+1) float64).
+ *  integ1, integ2      integral images of desc_ref ((Hr+1) x (Wr+1) float64),
+ *                      or both NULL: then each IP's pair of integral images
+ *                      is built over its own search window ((M+1) x (M+1)
+ *                      float64, the per-pixel channel sums of the stored
+ *                      values, Eq. 14-15) inside ws, which must then hold
+ *                      sfoc_match_window_workspace bytes.
  *  ips                 n x 2 int32 (row, col) in the sensed image.
  *  prior               n x 2 int32 (dy, dx) search-window offsets, or NULL.
  *  ncc                 n x (2r+1) x (2r+1) float32 surfaces, or NULL.  (output)
@@ -210,8 +215,13 @@ int sfoc_describe_noalloc(const float* img, int64_t H, int64_t W, int64_t ld, co
  * Limits: 3 <= m <= 191, 1 <= r <= 511, each image below 2^30 pixels
  * (SFOC_E_UNSUPPORTED beyond).
  * n == 0 is valid and enqueues nothing.
+ * Errors: SFOC_E_INVALID_ARG (null descriptors, ips or cps, only one of
+ * integ1 / integ2 NULL, m < 3, r < 1, z < 1, unknown dtype, sizes < 1),
+ * SFOC_E_UNSUPPORTED, SFOC_E_WORKSPACE (ws smaller than the query for the
+ * chosen integral mode), SFOC_E_HIP.
  */
 int sfoc_match_workspace(int32_t n, int32_t m, int32_t r, int32_t z, size_t* bytes);
+int sfoc_match_window_workspace(int32_t n, int32_t m, int32_t r, int32_t z, size_t* bytes);
 int sfoc_fastncc_match(const void* desc_sen, int64_t Hs, int64_t Ws,
                        const void* desc_ref, int64_t Hr, int64_t Wr,
                        const double* integ1, const double* integ2,

@@ -171,6 +171,14 @@ int sfoc_match_workspace(int32_t n, int32_t m, int32_t r, int32_t z, size_t* byt
     return SFOC_OK;
 }
 
+int sfoc_match_window_workspace(int32_t n, int32_t m, int32_t r, int32_t z, size_t* bytes) {
+    if (!bytes || z < 1) return SFOC_E_INVALID_ARG;
+    int rc = check_match_shape(n, m, r);
+    if (rc) return rc;
+    *bytes = match_plan(n, m, r).ws_bytes + match_window_ws_bytes(n, m, r);
+    return SFOC_OK;
+}
+
 int sfoc_fastncc_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void* desc_ref, int64_t Hr, int64_t Wr,
                        const double* integ1, const double* integ2, int32_t z, int32_t dtype, const int32_t* ips,
                        const int32_t* prior, int32_t n, int32_t m, int32_t r, float* ncc, sfoc_cp* cps, void* ws,
@@ -182,8 +190,9 @@ int sfoc_fastncc_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void*
     if (Hs > kMaxSide || Ws > kMaxSide || Hr > kMaxSide || Wr > kMaxSide) return SFOC_E_UNSUPPORTED;
     if (Hs * Ws >= kMaxPlane || Hr * Wr >= kMaxPlane) return SFOC_E_UNSUPPORTED;
     if (n == 0) return SFOC_OK;
-    if (!desc_sen || !desc_ref || !integ1 || !integ2 || !ips || !cps) return SFOC_E_INVALID_ARG;
-    const size_t need = match_plan(n, m, r).ws_bytes;
+    if (!desc_sen || !desc_ref || !ips || !cps || ((integ1 == nullptr) != (integ2 == nullptr)))
+        return SFOC_E_INVALID_ARG;
+    const size_t need = match_plan(n, m, r).ws_bytes + (integ1 ? 0 : match_window_ws_bytes(n, m, r));
     if (need > 0 && (!ws || ws_bytes < need)) return SFOC_E_WORKSPACE;
     hipError_t e = launch_match(desc_sen, Hs, Ws, desc_ref, Hr, Wr, integ1, integ2, z, dtype, ips, prior, n, m, r,
                                 ncc, cps, ws, (hipStream_t)stream);

@@ -216,15 +216,21 @@ __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const De
     const int t = threadIdx.x;
     DescribeJob J;
     int ty0, tx0;
+    // Workgroups are dealt to the eight XCDs in turn; renumbered so that each
+    // XCD takes a contiguous run of tiles, whose overlapping input halos then
+    // meet in one L2.
+    const int nblk = (int)(gridDim.x * gridDim.y), q8 = nblk / 8 * 8;
+    const int id = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    const int k = id < q8 ? (id % 8) * (q8 / 8) + id / 8 : id;
     if (tiles) {
-        const int4 e = tiles[blockIdx.x];
+        const int4 e = tiles[k];
         J = load_table(jobs, e.x);
         ty0 = e.y;
         tx0 = e.z;
     } else {
         J = single;
-        ty0 = blockIdx.y * kTS;
-        tx0 = blockIdx.x * kTS;
+        ty0 = (k / gridDim.x) * kTS;
+        tx0 = (k % gridDim.x) * kTS;
     }
     const float* __restrict__ img = J.img;
     void* __restrict__ desc = J.desc;
@@ -599,24 +605,34 @@ __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const De
 // prefix of the tile totals); integral_tiles then reads s once and writes
 // the prefix sums in place.  All sums are in a fixed order.
 
-// In place: v[0], v[step], ... (n entries) -> their exclusive prefix sums.
-SFOC_DEV void exclusive_prefix(double* __restrict__ v, int64_t n, int64_t step) {
-    double run = 0.0;
+// In place, for two sequences at once: a[0], a[step], ... and b[0],
+// b[step], ... (n entries each) -> their exclusive prefix sums.  Sixteen
+// loads of each are in flight before their sums, which run in order.
+SFOC_DEV void exclusive_prefix2(double* __restrict__ a, double* __restrict__ b, int64_t n, int64_t step) {
+    constexpr int kB = 16;
+    double ra = 0.0, rb = 0.0;
     int64_t k = 0;
-    for (; k + 8 <= n; k += 8) {   // eight loads in flight, then the sums in order
-        double a[8];
+    for (; k + kB <= n; k += kB) {
+        double x[kB], y[kB];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = v[(k + u) * step];
+        for (int u = 0; u < kB; ++u) {
+            x[u] = a[(k + u) * step];
+            y[u] = b[(k + u) * step];
+        }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            v[(k + u) * step] = run;
-            run += a[u];
+        for (int u = 0; u < kB; ++u) {
+            a[(k + u) * step] = ra;
+            b[(k + u) * step] = rb;
+            ra += x[u];
+            rb += y[u];
         }
     }
     for (; k < n; ++k) {
-        const double a = v[k * step];
-        v[k * step] = run;
-        run += a;
+        const double x = a[k * step], y = b[k * step];
+        a[k * step] = ra;
+        b[k * step] = rb;
+        ra += x;
+        rb += y;
     }
 }
 
@@ -648,26 +664,16 @@ __global__ __launch_bounds__(kScanNT) void integral_prefix(const IntegJob single
     double* __restrict__ agg = J.agg;
     if (kind == 0) {          // Left: per row y, over the tile columns
         const int y = blk * kScanNT + t;
-        if (y < H) {
-            exclusive_prefix(agg + ag.rs1 + y, ag.ntx, H);
-            exclusive_prefix(agg + ag.rs2 + y, ag.ntx, H);
-        }
+        if (y < H) exclusive_prefix2(agg + ag.rs1 + y, agg + ag.rs2 + y, ag.ntx, H);
     } else if (kind == 1) {   // Above: per column x, over the tile rows
         const int x = blk * kScanNT + t;
-        if (x < W) {
-            exclusive_prefix(agg + ag.cs1 + x, ag.nty, W);
-            exclusive_prefix(agg + ag.cs2 + x, ag.nty, W);
-        }
+        if (x < W) exclusive_prefix2(agg + ag.cs1 + x, agg + ag.cs2 + x, ag.nty, W);
     } else {                  // Corner: tile totals, over tile columns, then over tile rows
-        for (int q = 0; q < 2; ++q) {
-            double* tt = agg + (q ? ag.tt2 : ag.tt1);
-            for (int64_t a = t; a < ag.nty; a += kScanNT) exclusive_prefix(tt + a * ag.ntx, ag.ntx, 1);
-        }
+        for (int64_t a = t; a < ag.nty; a += kScanNT)
+            exclusive_prefix2(agg + ag.tt1 + a * ag.ntx, agg + ag.tt2 + a * ag.ntx, ag.ntx, 1);
         __syncthreads();
-        for (int q = 0; q < 2; ++q) {
-            double* tt = agg + (q ? ag.tt2 : ag.tt1);
-            for (int64_t b = t; b < ag.ntx; b += kScanNT) exclusive_prefix(tt + b, ag.nty, ag.ntx);
-        }
+        for (int64_t b = t; b < ag.ntx; b += kScanNT)
+            exclusive_prefix2(agg + ag.tt1 + b, agg + ag.tt2 + b, ag.nty, ag.ntx);
     }
 }
 
@@ -680,15 +686,23 @@ __global__ __launch_bounds__(kScanNT) void integral_tiles(const IntegJob single,
     static_assert(kScanNT == kTS * kTS / kRun, "one run of 4 pixels per thread");
     IntegJob J;
     int ta, tb;
+    // Workgroups are dealt to the eight XCDs in turn; renumbered so that each
+    // XCD takes one contiguous run of tiles (row-major), neighbouring tiles
+    // share an L2 and the cache lines on their borders (the images' row
+    // pitch W + 1 is not a multiple of a line) are fetched once.
+    const int nblk = BATCH ? (int)gridDim.x : (int)(gridDim.x * gridDim.y);
+    const int id = BATCH ? (int)blockIdx.x : (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    const int q8 = nblk / 8 * 8;
+    const int k = id < q8 ? (id % 8) * (q8 / 8) + id / 8 : id;
     if (BATCH) {
-        const int4 e = tiles[blockIdx.x];
+        const int4 e = tiles[k];
         J = load_table(jobs, e.x);
         ta = e.y;
         tb = e.z;
     } else {
         J = single;
-        ta = blockIdx.y;
-        tb = blockIdx.x;
+        ta = k / gridDim.x;
+        tb = k - ta * gridDim.x;
     }
     __shared__ double above[2][kTS];
     __shared__ double wtot[2][kScanNT / 64][kTS];

@@ -48,6 +48,9 @@ struct MatchArgs {
     int64_t Hs, Ws, Hr, Wr;
     int32_t z, dtype, n, m, r;
     int32_t nbu, nbv, Vb;   // offset blocks per axis and offsets per block
+    // 0: integ1 / integ2 are the reference image's integral images; 1: they
+    // hold one (M+1) x (M+1) pair per IP, built over its own search window
+    int32_t integ_win;
 };
 
 // SFOC_OK for hipSuccess, else SFOC_E_HIP (the HIP error is kept for
@@ -66,6 +69,8 @@ hipError_t launch_describe(const float* img, int H, int W, int64_t ld, void* des
 // Completes the integral images from what launch_describe left in i1, i2
 // and agg (the same buffers).
 hipError_t launch_integral(double* i1, double* i2, int H, int W, double* agg, hipStream_t st);
+// i1 == i2 == null: per-window integral images, built into ws after the
+// split-offset scratch (match_window_ws_bytes).
 hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void* desc_ref, int64_t Hr, int64_t Wr,
                         const double* i1, const double* i2, int z, int dtype, const int32_t* ips,
                         const int32_t* prior, int n, int m, int r, float* ncc, sfoc_cp* cps, void* ws,

@@ -50,6 +50,10 @@ SFOC_DEV float2 cmulc(float2 a, float2 b) {  // a * conj(b)
     return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
 SFOC_DEV float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+// c ? a : b per component (a select of two array elements written this way
+// stays in registers; as one conditional expression the compiler may turn
+// it into a select of the arrays' addresses, which puts both in scratch).
+SFOC_DEV float2 pick(bool c, float2 a, float2 b) { return make_float2(c ? a.x : b.x, c ? a.y : b.y); }
 SFOC_DEV float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 SFOC_DEV float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 SFOC_DEV float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
@@ -480,7 +484,7 @@ SFOC_DEV void row_stage(const void* plane, int pitch, int y0, int x0, int nrows,
             for (int k1 = 0; k1 <= C::NB / 2; ++k1) {
                 if (k1 < C::NB / 2 || j == 0) {
                     const float2 za = u[k1];
-                    const float2 zb = cconj(j == 0 ? u[(C::NB - k1) % C::NB] : v[C::NB - 1 - k1]);
+                    const float2 zb = cconj(pick(j == 0, u[(C::NB - k1) % C::NB], v[C::NB - 1 - k1]));
                     const int k = C::NA * k1 + ka;
                     ra[k] = cscale(cadd(za, zb), 0.5f);
                     rb[k] = cscale(mul_mi<false>(csub(za, zb)), 0.5f);
@@ -489,7 +493,7 @@ SFOC_DEV void row_stage(const void* plane, int pitch, int y0, int x0, int nrows,
 #pragma unroll
             for (int k1 = 0; k1 < C::NB / 2; ++k1) {
                 const float2 za = v[k1];
-                const float2 zb = cconj(j == 0 ? v[C::NB - 1 - k1] : u[C::NB - 1 - k1]);
+                const float2 zb = cconj(pick(j == 0, v[C::NB - 1 - k1], u[C::NB - 1 - k1]));
                 const int k = C::NA * k1 + kb;
                 ra[k] = cscale(cadd(za, zb), 0.5f);
                 rb[k] = cscale(mul_mi<false>(csub(za, zb)), 0.5f);
@@ -828,7 +832,12 @@ SFOC_DEV void match_item(const MatchArgs& A, int i, int bq, int slot, const floa
     }
 
     // NCC (Eq. 9) with integral-image box sums (Eq. 16), float64 variance.
-    const int64_t IW = A.Wr + 1;
+    // The integral images are the reference image's, or this IP's own over
+    // its search window (origin (sy, sx), side M + 1).
+    const int64_t IW = A.integ_win ? (int64_t)M + 1 : A.Wr + 1;
+    const double* __restrict__ I1 = A.integ_win ? A.integ1 + (int64_t)i * IW * IW : A.integ1;
+    const double* __restrict__ I2 = A.integ_win ? A.integ2 + (int64_t)i * IW * IW : A.integ2;
+    const int64_t oy = A.integ_win ? 0 : sy, ox = A.integ_win ? 0 : sx;
     const bool flatT = !(varT > tau);
     const bool badT = !isfinite(RT) || !isfinite(RTT);
     // NCC at offset (u, v); flags: bit 0 non-flat search window, bit 1 non-finite.
@@ -836,10 +845,10 @@ SFOC_DEV void match_item(const MatchArgs& A, int i, int bq, int slot, const floa
     auto ncc_at = [&](int u, int v, int& fl) -> float {
         const float* rr = reinterpret_cast<const float*>(buf + C::row((u >> 1) * 2));
         const float rst = rr[(u & 1) * L + v];
-        const int64_t y = sy + u0 + u, x = sx + v0 + v;
+        const int64_t y = oy + u0 + u, x = ox + v0 + v;
         const int64_t a00 = y * IW + x, a01 = a00 + m, a10 = a00 + (int64_t)m * IW, a11 = a10 + m;
-        const double RS = A.integ1[a11] - A.integ1[a10] - A.integ1[a01] + A.integ1[a00];
-        const double RSS = A.integ2[a11] - A.integ2[a10] - A.integ2[a01] + A.integ2[a00];
+        const double RS = I1[a11] - I1[a10] - I1[a01] + I1[a00];
+        const double RSS = I2[a11] - I2[a10] - I2[a01] + I2[a00];
         const double varS = RSS - RS * RS / mnz;
         float val = 0.f;
         fl = 0;
@@ -965,9 +974,14 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, MatchCfg<L>::MINB) void match_kern
         const MatchArgs A = load_table(pairs, it.x);
         match_item<L, DT>(A, it.y, it.z, it.y * A.nbu * A.nbv + it.z, tw, buf, red);
     } else {
+        // Workgroups are dealt to the eight XCDs in turn; renumbered so that
+        // each XCD takes a contiguous run of IPs, whose overlapping search
+        // windows then meet in one L2.
+        const int n = (int)gridDim.x, q8 = n / 8 * 8, id = (int)blockIdx.x;
+        const int k = id < q8 ? (id % 8) * (q8 / 8) + id / 8 : id;
         const int nblk = single.nbu * single.nbv;
-        const int i = blockIdx.x / nblk;
-        match_item<L, DT>(single, i, blockIdx.x - i * nblk, blockIdx.x, tw, buf, red);
+        const int i = k / nblk;
+        match_item<L, DT>(single, i, k - i * nblk, k, tw, buf, red);
     }
 }
 
@@ -1191,6 +1205,62 @@ __global__ __launch_bounds__(kConsNT) void consistency_kernel(sfoc_cp* cps, cons
     }
 }
 
+// ---- per-window integral images (Eq. 14-16 over one search window) --------
+// One workgroup per IP: G1 / G2 are the (M+1) x (M+1) exclusive prefix sums
+// of sum_c g and sum_c g^2 (float64, of the stored values) over the IP's
+// M x M search window, zero first row and column.  The per-pixel sums run
+// over the channels in order, then each row is summed left to right and
+// each column top to bottom: a fixed order, so results are reproducible.
+// An IP whose windows leave the images is skipped (the match flags it and
+// reads nothing).
+template <int DT>
+__global__ __launch_bounds__(256) void window_integral_kernel(const MatchArgs A) {
+    const int i = blockIdx.x, t = threadIdx.x;
+    const int m = A.m, r = A.r, M = m + 2 * r, P = M + 1;
+    const int py = A.ips[2 * i], px = A.ips[2 * i + 1];
+    const int pry = A.prior ? A.prior[2 * i] : 0, prx = A.prior ? A.prior[2 * i + 1] : 0;
+    const int64_t ty = (int64_t)py - m / 2, tx = (int64_t)px - m / 2;
+    const int64_t sy = ty - r + pry, sx = tx - r + prx;
+    if (!in_image(ty, tx, m, m, A.Hs, A.Ws) || !in_image(sy, sx, M, M, A.Hr, A.Wr)) return;
+    double* __restrict__ G1 = const_cast<double*>(A.integ1) + (int64_t)i * P * P;
+    double* __restrict__ G2 = const_cast<double*>(A.integ2) + (int64_t)i * P * P;
+    const int64_t plane = A.Hr * A.Wr;
+    for (int e = t; e < P * P; e += 256) {
+        const int y = e / P, x = e - y * P;
+        double s1 = 0.0, s2 = 0.0;
+        if (y > 0 && x > 0) {
+            const int o = (int)((sy + y - 1) * A.Wr + sx + x - 1);   // within one plane (< 2^30)
+            for (int h = 0; h < A.z; ++h) {
+                const double g = (double)ldd<DT>(elem_ptr<DT>(A.desc_ref, h * plane), o);
+                s1 += g;
+                s2 = fma(g, g, s2);
+            }
+        }
+        G1[e] = s1;
+        G2[e] = s2;
+    }
+    __syncthreads();
+    for (int y = 1 + t; y < P; y += 256) {   // rows, left to right
+        double a = 0.0, b = 0.0;
+        for (int x = 1; x < P; ++x) {
+            a += G1[(int64_t)y * P + x];
+            b += G2[(int64_t)y * P + x];
+            G1[(int64_t)y * P + x] = a;
+            G2[(int64_t)y * P + x] = b;
+        }
+    }
+    __syncthreads();
+    for (int x = 1 + t; x < P; x += 256) {   // columns, top to bottom
+        double a = 0.0, b = 0.0;
+        for (int y = 1; y < P; ++y) {
+            a += G1[(int64_t)y * P + x];
+            b += G2[(int64_t)y * P + x];
+            G1[(int64_t)y * P + x] = a;
+            G2[(int64_t)y * P + x] = b;
+        }
+    }
+}
+
 // ---- launch -------------------------------------------------------------
 void match_args_layout(MatchArgs& a, const MatchPlan& mp, void* ws) {
     a.nbu = a.nbv = mp.nb;
@@ -1248,7 +1318,21 @@ hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void
     const MatchPlan mp = match_plan(n, m, r);
     const int L = mp.L;
     match_args_layout(a, mp, ws);
+    a.integ_win = 0;
     hipError_t e;
+    if (!i1) {   // per-window integral images, after the split-offset scratch
+        double* g = (double*)((char*)ws + mp.ws_bytes);
+        const size_t per = (size_t)(m + 2 * r + 1) * (m + 2 * r + 1);
+        a.integ1 = g;
+        a.integ2 = g + (size_t)n * per;
+        a.integ_win = 1;
+        trace_begin(st, SFOC_K_INTEGRAL);
+        if (dtype == 0) hipLaunchKernelGGL(window_integral_kernel<0>, dim3(n), dim3(256), 0, st, a);
+        else if (dtype == 1) hipLaunchKernelGGL(window_integral_kernel<1>, dim3(n), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL(window_integral_kernel<2>, dim3(n), dim3(256), 0, st, a);
+        trace_end(st, SFOC_K_INTEGRAL);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     switch (L) {
         case 64: e = launch_match_side<64>(a, dtype, st); break;
         case 128: e = launch_match_side<128>(a, dtype, st); break;

@@ -167,6 +167,11 @@ MatchPlan match_plan_L(int32_t n, int32_t m, int32_t r, int L) {
     return p;
 }
 
+size_t match_window_ws_bytes(int32_t n, int32_t m, int32_t r) {
+    const size_t W1 = (size_t)(m + 2 * r + 1);
+    return align_up((size_t)n * 2 * W1 * W1 * sizeof(double), 256);
+}
+
 // Transform work of one IP under a plan, in units of L^2 log2(L^2).
 static double plan_cost(const MatchPlan& p) {
     const double L2 = (double)p.L * p.L;

@@ -112,6 +112,9 @@ MatchPlan match_plan(int32_t n, int32_t m, int32_t r);
 // template does not fit it (a block needs m + Vb - 1 <= L with Vb >= 2).
 MatchPlan match_plan_L(int32_t n, int32_t m, int32_t r, int L);
 constexpr int kMaxRadiusMatch = 511;
+// Bytes of the per-window integral images (two (M+1)^2 float64 images per
+// IP) that the match builds when it is given no integral images.
+size_t match_window_ws_bytes(int32_t n, int32_t m, int32_t r);
 
 // Transform sides an autotuner may time for (m, r): the default first, then
 // every other side whose plan exists with at most kMaxTuneBlocks offset

@@ -107,6 +107,7 @@ def lib() -> ctypes.CDLL:
         L.sfoc_describe.argtypes = [vp, i64, i64, i64, P, vp, vp, vp, vp, sz, vp]
         L.sfoc_describe_noalloc.argtypes = [vp, i64, i64, i64, P, vp, vp, vp, vp]
         L.sfoc_match_workspace.argtypes = [i32, i32, i32, i32, ctypes.POINTER(sz)]
+        L.sfoc_match_window_workspace.argtypes = [i32, i32, i32, i32, ctypes.POINTER(sz)]
         L.sfoc_fastncc_match.argtypes = [vp, i64, i64, vp, i64, i64, vp, vp, i32, i32, vp, vp, i32, i32, i32,
                                          vp, vp, vp, sz, vp]
         L.sfoc_register_workspace.argtypes = [i64, i64, i64, i64, i32, i32, i32, P, ctypes.POINTER(sz)]
@@ -272,7 +273,8 @@ def describe_noalloc(img, p: Params, desc, integ1, integ2, stream=None):
 def fastncc_match(desc_sen, desc_ref, integ1, integ2, ips, m: int, r: int, prior=None, want_ncc=False,
                   stream=None):
     """CPs (an (n, 8) int32 CUDA tensor of 32-byte records) and optionally
-    the NCC surfaces (n, 2r+1, 2r+1)."""
+    the NCC surfaces (n, 2r+1, 2r+1).  integ1 = integ2 = None: the integral
+    images are built per search window (in the workspace)."""
     torch = _torch()
     z, Hs, Ws = desc_sen.shape
     _, Hr, Wr = desc_ref.shape
@@ -282,7 +284,8 @@ def fastncc_match(desc_sen, desc_ref, integ1, integ2, ips, m: int, r: int, prior
     cps = torch.empty((n, 8), dtype=torch.int32, device=desc_sen.device)
     ncc = torch.empty((n, V, V), dtype=torch.float32, device=desc_sen.device) if want_ncc else None
     b = ctypes.c_size_t(0)
-    _check(lib().sfoc_match_workspace(n, m, r, z, ctypes.byref(b)), "sfoc_match_workspace")
+    query = lib().sfoc_match_workspace if integ1 is not None else lib().sfoc_match_window_workspace
+    _check(query(n, m, r, z, ctypes.byref(b)), "match workspace query")
     ws = torch.empty(b.value, dtype=torch.uint8, device=desc_sen.device) if b.value else None
     rc = lib().sfoc_fastncc_match(_ptr(desc_sen), Hs, Ws, _ptr(desc_ref), Hr, Wr, _ptr(integ1), _ptr(integ2),
                                   z, dt, _ptr(ips), _ptr(prior), n, m, r, _ptr(ncc), _ptr(cps), _ptr(ws), b.value,

@@ -100,6 +100,12 @@ def test_workspace_queries():
     assert S.lib().sfoc_match_workspace(10, 192, 2, 16, ctypes.byref(b)) == S.SFOC_E_UNSUPPORTED
     assert S.lib().sfoc_match_workspace(10, 16, 600, 16, ctypes.byref(b)) == S.SFOC_E_UNSUPPORTED
     assert S.lib().sfoc_match_workspace(10, 2, 3, 16, ctypes.byref(b)) == S.SFOC_E_INVALID_ARG
+    # per-window integral images: two (M+1)^2 float64 images per IP on top
+    assert S.lib().sfoc_match_window_workspace(10, 64, 32, 16, ctypes.byref(b)) == 0
+    assert b.value >= 10 * 2 * 129 * 129 * 8
+    assert S.lib().sfoc_match_window_workspace(10, 96, 64, 16, ctypes.byref(b)) == 0
+    assert b.value >= 10 * 2 * 225 * 225 * 8 + 10 * 129 * 129 * 4
+    assert S.lib().sfoc_match_window_workspace(10, 2, 3, 16, ctypes.byref(b)) == S.SFOC_E_INVALID_ARG
 
 
 def test_describe_rejects_bad_arguments_before_launch():
@@ -131,7 +137,9 @@ def test_match_and_register_reject_bad_arguments_before_launch():
     assert call(m=192, r=20) == S.SFOC_E_UNSUPPORTED
     assert call(m=100, r=50) == S.SFOC_E_WORKSPACE        # split offsets (window beyond 192) need a workspace
     assert call(dt=5) == S.SFOC_E_INVALID_ARG
-    assert call(i1=None) == S.SFOC_E_INVALID_ARG
+    assert call(i1=None) == S.SFOC_E_INVALID_ARG                # only one integral image
+    assert call(i2=None) == S.SFOC_E_INVALID_ARG
+    assert call(i1=None, i2=None) == S.SFOC_E_WORKSPACE         # per-window images need a workspace
     assert call(cps=None) == S.SFOC_E_INVALID_ARG
     assert call(n=-1) == S.SFOC_E_INVALID_ARG
     assert call(n=0, desc_sen=None) == S.SFOC_OK           # empty input enqueues nothing

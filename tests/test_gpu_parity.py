@@ -176,6 +176,35 @@ def test_match_kernel_on_oracle_descriptors(seed):
     assert flips <= consistency_flip_allowed(o)
 
 
+@pytest.mark.parametrize("seed,m,r,size", [(0, 32, 10, 256), (1, 32, 10, 256), (2, 64, 48, 300),
+                                           (3, 96, 64, 360)])
+def test_match_per_window_integral_images(seed, m, r, size):
+    """No integral images given: each IP's are built over its own search
+    window (Eq. 14-16 per window).  Against the oracle, and against the
+    reference image's integral images on the same descriptors (the box sums
+    differ only by float64 rounding)."""
+    say("per-window integrals", seed, m, r, size)
+    pr = synth.make_pair(40 + seed, size, min(8.0, r - 2.0))
+    b = (m + 1) // 2 + r
+    ips = synth.grid_ips(size, size, 4, b)
+    ips = np.concatenate([ips, np.array([[1, 1]], np.int32)])   # one out of bounds
+    Fr = O.sfoc(pr.ref).astype(np.float32).astype(np.float64)
+    Fs = O.sfoc(pr.sen).astype(np.float32).astype(np.float64)
+    G1, G2 = O.integral_feature_images(Fr)
+    o, so = O.match(Fs, Fr, ips, m, r, integ=(G1, G2), want_surfaces=True)
+    ds, dr = dev(to_chw(Fs), torch.float32), dev(to_chw(Fr), torch.float32)
+    cw, nw = S.fastncc_match(ds, dr, None, None, dev(ips), m, r, want_ncc=True)
+    cg, ng = S.fastncc_match(ds, dr, dev(G1), dev(G2), dev(ips), m, r, want_ncc=True)
+    torch.cuda.synchronize()
+    gw, gg = S.cps_to_numpy(cw), S.cps_to_numpy(cg)
+    st = compare_cps(gw, o, so, r, nw.cpu().numpy())
+    say("  ", st)
+    assert np.abs(nw.cpu().numpy() - ng.cpu().numpy()).max() <= 1e-6
+    assert np.array_equal(gw["flags"], gg["flags"]) and gw["flags"][-1] & O.OOB
+    flips = {i for i in range(len(o)) if o["flags"][i] != gw["flags"][i]}
+    assert flips <= consistency_flip_allowed(o)
+
+
 @pytest.mark.parametrize("seed", list(range(10)))
 def test_register_small_pairs(seed):
     say("register small seed", seed)
