@@ -27,7 +27,8 @@ PEAK_HBM = 8.0e12
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_scene2048_rectify10000.md")
-KERNEL_SOURCES = {"describe": "sfoc_describe.hip", "match": "sfoc_match.hip", "rectify": "sfoc_rectify.hip"}
+KERNEL_SOURCES = {"describe": "sfoc_describe.hip", "integral": "sfoc_describe.hip", "match": "sfoc_match.hip",
+                  "rectify": "sfoc_rectify.hip"}
 
 
 def stored_traffic(kernel: str):
@@ -719,6 +720,9 @@ def main():
     sfoc_mpix = px / (d_ms * 1e-3) / 1e6 if d_ms > 0 else None
     per_step = {k: kt[k][0] / args.steps for k in kt}
     kernels = kernel_table(kt, args.steps, p, H, W, n, m, r)
+    for k in kernels:   # measured HBM bytes per launch (counters of this configuration)
+        if kernels[k] is not None:
+            kernels[k]["traffic"] = stored_traffic(k)
     # the dominant kernel: the largest share of a step's kernel time
     dom = max(("describe", "match"), key=lambda k: per_step[k])
     ke = kernels[dom]
