@@ -232,10 +232,13 @@ int sfoc_fastncc_match(const void* desc_sen, int64_t Hs, int64_t Ws,
                        void* ws, size_t ws_bytes, void* stream);
 
 /*
- * Whole fine-registration hot path for one pair: sfoc_describe of both
- * images into the workspace, integral images of the reference, then
- * sfoc_fastncc_match.  Arguments as above; the descriptors and integral
- * images live inside ws (see sfoc_register_workspace).
+ * Whole fine-registration hot path for one pair: sfoc_describe of the
+ * reference image and of the sensed image's tiles that the templates read
+ * (an m x m template at each IP, Section 2.2), integral images of the
+ * reference, then sfoc_fastncc_match.  Arguments as above; the descriptors,
+ * integral images and the sensed tile mask live inside ws (see
+ * sfoc_register_workspace).  The CPs equal those of sfoc_describe of both
+ * whole images followed by sfoc_fastncc_match.
  */
 int sfoc_register_workspace(int64_t Hr, int64_t Wr, int64_t Hs, int64_t Ws,
                             int32_t n, int32_t m, int32_t r,

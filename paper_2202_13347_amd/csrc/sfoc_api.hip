@@ -59,7 +59,7 @@ static hipError_t side_stream(SideStream** out) {
 }
 
 struct RegisterLayout {
-    size_t desc_ref, desc_sen, integ1, integ2, scan, match, total;
+    size_t desc_ref, desc_sen, integ1, integ2, scan, mask, match, total;
 };
 
 static RegisterLayout register_layout(int64_t Hr, int64_t Wr, int64_t Hs, int64_t Ws, int32_t z, size_t es,
@@ -76,6 +76,8 @@ static RegisterLayout register_layout(int64_t Hr, int64_t Wr, int64_t Hs, int64_
     off = align_up(off + (size_t)(Hr + 1) * (Wr + 1) * sizeof(double), 256);
     L.scan = off;
     off = align_up(off + describe_ws_bytes(Hr, Wr), 256);
+    L.mask = off;
+    off = align_up(off + tile_mask_bytes(Hs, Ws), 256);
     L.match = off;
     off = align_up(off + match_ws, 256);
     L.total = off;
@@ -237,16 +239,19 @@ int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr, con
     DescribeConsts c;
     build_describe_consts(p, &c);
     // The reference's integral scans (memory-bound) run on a second stream
-    // while the sensed image is described; the match waits for both.
+    // while the sensed image is described; the match waits for both.  Of
+    // the sensed image only the tiles under the templates are described.
     SideStream* side = nullptr;
     hipError_t e = side_stream(&side);
     double* agg = (double*)(base + L.scan);
+    uint8_t* tmask = (uint8_t*)(base + L.mask);
+    if (e == hipSuccess) e = launch_tile_mask(ips, n, m, (int)Hs, (int)Ws, tmask, st);
     if (e == hipSuccess) e = launch_describe(ref, (int)Hr, (int)Wr, ldr, dref, i1, i2, agg, c, st);
     if (e == hipSuccess) e = hipEventRecord(side->fork, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->fork, 0);
     if (e == hipSuccess) e = launch_integral(i1, i2, (int)Hr, (int)Wr, agg, side->s);
     if (e == hipSuccess) e = hipEventRecord(side->join, side->s);
-    if (e == hipSuccess) e = launch_describe(sen, (int)Hs, (int)Ws, lds, dsen, nullptr, nullptr, nullptr, c, st);
+    if (e == hipSuccess) e = launch_describe(sen, (int)Hs, (int)Ws, lds, dsen, nullptr, nullptr, nullptr, c, st, tmask);
     if (e == hipSuccess) e = hipStreamWaitEvent(st, side->join, 0);
     if (e != hipSuccess) return hip_status(e);
     if (n == 0) return SFOC_OK;

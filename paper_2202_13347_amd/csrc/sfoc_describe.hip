@@ -210,7 +210,8 @@ SFOC_DEV void col_run_any(const float* p, int P, int rho, const float* te, const
 template <int Z, int CG, bool FAST>
 __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const DescribeJob single,
                                                           const DescribeJob* __restrict__ jobs,
-                                                          const int4* __restrict__ tiles, const DescribeConsts C,
+                                                          const int4* __restrict__ tiles,
+                                                          const uint8_t* __restrict__ tmask, const DescribeConsts C,
                                                           int BSP_, int ISX, int BPP_, int IPP) {
     extern __shared__ float lds[];
     const int t = threadIdx.x;
@@ -228,6 +229,8 @@ __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const De
         ty0 = e.y;
         tx0 = e.z;
     } else {
+        // a tile that nothing reads is skipped by the whole workgroup
+        if (tmask && !tmask[k]) return;
         J = single;
         ty0 = (k / gridDim.x) * kTS;
         tx0 = (k % gridDim.x) * kTS;
@@ -777,7 +780,7 @@ __global__ __launch_bounds__(kScanNT) void integral_tiles(const IntegJob single,
 // ---- launch -------------------------------------------------------------
 template <int Z, bool FAST>
 static hipError_t launch_describe_zf(const DescribeJob& job, const DescribeJob* jobs, const int4* tiles, int ntiles,
-                                     const DescribeConsts& c, hipStream_t st) {
+                                     const uint8_t* tmask, const DescribeConsts& c, hipStream_t st) {
     constexpr int CG = FAST ? 2 : (Z >= 4 ? 4 : Z);
     const DescribeGeom g = describe_geom(c, CG);
     dim3 grid = tiles ? dim3(ntiles) : dim3((job.W + kTS - 1) / kTS, (job.H + kTS - 1) / kTS);
@@ -786,32 +789,32 @@ static hipError_t launch_describe_zf(const DescribeJob& job, const DescribeJob* 
     hipError_t e = ensure_dynamic_lds((const void*)kern, (int)g.bytes);
     if (e != hipSuccess) return e;
     trace_begin(st, SFOC_K_DESCRIBE);
-    hipLaunchKernelGGL(kern, grid, dim3(kNT), g.bytes, st, job, jobs, tiles, c, g.BSP, g.ISX, g.BPP, g.IPP);
+    hipLaunchKernelGGL(kern, grid, dim3(kNT), g.bytes, st, job, jobs, tiles, tmask, c, g.BSP, g.ISX, g.BPP, g.IPP);
     trace_end(st, SFOC_K_DESCRIBE);
     return hipGetLastError();
 }
 
 template <int Z>
 static hipError_t launch_describe_z(const DescribeJob& job, const DescribeJob* jobs, const int4* tiles, int ntiles,
-                                    const DescribeConsts& c, hipStream_t st) {
+                                    const uint8_t* tmask, const DescribeConsts& c, hipStream_t st) {
     const bool fast = c.K == 1 && c.ndil == 3 && c.dil[0] == 1 && c.dil[1] == 2 && c.dil[2] == 3 && c.second &&
                       c.N * 2 == Z;
-    return fast ? launch_describe_zf<Z, true>(job, jobs, tiles, ntiles, c, st)
-                : launch_describe_zf<Z, false>(job, jobs, tiles, ntiles, c, st);
+    return fast ? launch_describe_zf<Z, true>(job, jobs, tiles, ntiles, tmask, c, st)
+                : launch_describe_zf<Z, false>(job, jobs, tiles, ntiles, tmask, c, st);
 }
 
 static hipError_t launch_describe_any(const DescribeJob& job, const DescribeJob* jobs, const int4* tiles, int ntiles,
-                                      const DescribeConsts& c, hipStream_t st) {
+                                      const uint8_t* tmask, const DescribeConsts& c, hipStream_t st) {
     switch (c.z) {
-        case 2: return launch_describe_z<2>(job, jobs, tiles, ntiles, c, st);
-        case 3: return launch_describe_z<3>(job, jobs, tiles, ntiles, c, st);
-        case 4: return launch_describe_z<4>(job, jobs, tiles, ntiles, c, st);
-        case 6: return launch_describe_z<6>(job, jobs, tiles, ntiles, c, st);
-        case 8: return launch_describe_z<8>(job, jobs, tiles, ntiles, c, st);
-        case 12: return launch_describe_z<12>(job, jobs, tiles, ntiles, c, st);
-        case 16: return launch_describe_z<16>(job, jobs, tiles, ntiles, c, st);
-        case 24: return launch_describe_z<24>(job, jobs, tiles, ntiles, c, st);
-        case 32: return launch_describe_z<32>(job, jobs, tiles, ntiles, c, st);
+        case 2: return launch_describe_z<2>(job, jobs, tiles, ntiles, tmask, c, st);
+        case 3: return launch_describe_z<3>(job, jobs, tiles, ntiles, tmask, c, st);
+        case 4: return launch_describe_z<4>(job, jobs, tiles, ntiles, tmask, c, st);
+        case 6: return launch_describe_z<6>(job, jobs, tiles, ntiles, tmask, c, st);
+        case 8: return launch_describe_z<8>(job, jobs, tiles, ntiles, tmask, c, st);
+        case 12: return launch_describe_z<12>(job, jobs, tiles, ntiles, tmask, c, st);
+        case 16: return launch_describe_z<16>(job, jobs, tiles, ntiles, tmask, c, st);
+        case 24: return launch_describe_z<24>(job, jobs, tiles, ntiles, tmask, c, st);
+        case 32: return launch_describe_z<32>(job, jobs, tiles, ntiles, tmask, c, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -820,13 +823,45 @@ static hipError_t launch_describe_any(const DescribeJob& job, const DescribeJob*
 hipError_t launch_describe_batched(const DescribeJob* jobs, const int4* tiles, int ntiles, const DescribeConsts& c,
                                    hipStream_t st) {
     DescribeJob none{};
-    return launch_describe_any(none, jobs, tiles, ntiles, c, st);
+    return launch_describe_any(none, jobs, tiles, ntiles, nullptr, c, st);
 }
 
 hipError_t launch_describe(const float* img, int H, int W, int64_t ld, void* desc, double* i1, double* i2,
-                           double* agg, const DescribeConsts& c, hipStream_t st) {
+                           double* agg, const DescribeConsts& c, hipStream_t st, const uint8_t* tmask) {
     DescribeJob job{img, desc, i1, i2, agg, ld, H, W};
-    return launch_describe_any(job, nullptr, nullptr, 0, c, st);
+    return launch_describe_any(job, nullptr, nullptr, 0, tmask, c, st);
+}
+
+// ---- the sensed tiles that templates read ----------------------------------
+// One byte per describe tile of an H x W sensed image (row-major over the
+// tile grid): 1 where some IP's m x m template (top-left at the IP minus
+// m / 2, clipped to the image) meets the tile.  A first launch clears the
+// mask, a second marks every IP's tiles; concurrent marks write the same
+// value.  Marking also the tiles of IPs whose search window leaves the
+// reference only describes tiles that no one reads.
+__global__ __launch_bounds__(256) void tile_mask_clear(uint8_t* __restrict__ mask, int nt) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k < nt) mask[k] = 0;
+}
+
+__global__ __launch_bounds__(256) void tile_mask_mark(const int32_t* __restrict__ ips, int n, int m, int H, int W,
+                                                      uint8_t* __restrict__ mask) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int ntx = (W + kTS - 1) / kTS;
+    const int64_t ty = (int64_t)ips[2 * i] - m / 2, tx = (int64_t)ips[2 * i + 1] - m / 2;
+    const int64_t y0 = ty < 0 ? 0 : ty, x0 = tx < 0 ? 0 : tx;
+    const int64_t y1 = ty + m - 1 < H - 1 ? ty + m - 1 : H - 1, x1 = tx + m - 1 < W - 1 ? tx + m - 1 : W - 1;
+    if (y0 > y1 || x0 > x1) return;
+    for (int64_t a = y0 / kTS; a <= y1 / kTS; ++a)
+        for (int64_t b = x0 / kTS; b <= x1 / kTS; ++b) mask[a * ntx + b] = 1;
+}
+
+hipError_t launch_tile_mask(const int32_t* ips, int n, int m, int H, int W, uint8_t* mask, hipStream_t st) {
+    const int nt = ((H + kTS - 1) / kTS) * ((W + kTS - 1) / kTS);
+    hipLaunchKernelGGL(tile_mask_clear, dim3((nt + 255) / 256), dim3(256), 0, st, mask, nt);
+    if (n > 0) hipLaunchKernelGGL(tile_mask_mark, dim3((n + 255) / 256), dim3(256), 0, st, ips, n, m, H, W, mask);
+    return hipGetLastError();
 }
 
 hipError_t launch_integral(double* i1, double* i2, int H, int W, double* agg, hipStream_t st) {

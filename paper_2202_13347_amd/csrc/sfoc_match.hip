@@ -271,7 +271,9 @@ SFOC_DEV void dftn(float2 (&x)[N]) {
 // ---- geometry ----------------------------------------------------------
 // A side L = NA * NB transform: pass A are NA-point DFTs, pass B NB-point
 // ones.  NT threads per workgroup and MINB workgroups per CU (the LDS
-// buffer of the larger sides leaves room for one).
+// buffer of the larger sides leaves room for one); the kernels' launch
+// bounds ask for the waves per SIMD that MINB workgroups need, which caps
+// their registers accordingly.
 template <int L>
 struct Fft;
 // LDS layout of the transform buffer: row r starts at r * PITCH + (r / NB) *
@@ -281,11 +283,11 @@ struct Fft;
 // access over all banks, and keep each row (and each row pair) contiguous.
 template <>
 struct Fft<128> {
-    static constexpr int NA = 16, NB = 8, NT = 256, PITCH = 68, SKEW = 8, MINB = 2;
+    static constexpr int NA = 16, NB = 8, NT = 512, PITCH = 68, SKEW = 8, MINB = 2;
 };
 template <>
 struct Fft<64> {
-    static constexpr int NA = 8, NB = 8, NT = 128, PITCH = 40, SKEW = 8, MINB = 2;
+    static constexpr int NA = 8, NB = 8, NT = 128, PITCH = 40, SKEW = 8, MINB = 7;
 };
 template <>
 struct Fft<160> {
@@ -300,14 +302,15 @@ template <int L>
 struct MatchCfg {
     using F = Fft<L>;
     static constexpr int NA = F::NA, NB = F::NB, NT = F::NT, P = F::PITCH, SKEW = F::SKEW, MINB = F::MINB;
+    static constexpr int WAVES_PER_SIMD = (MINB * NT + 255) / 256;   // 4 SIMDs of 64 lanes per CU
     static constexpr int HA = NA / 2;
     static constexpr int COLS = L / 2;                     // column transforms (DC+Nyquist packed)
     static constexpr int RB = COLS * HA / NT;              // pass-B tasks per thread
     static constexpr int BINS = 2 * NB;                    // bins per pass-B task
-    // Two tasks' loads in flight in the search window's stages: only where
-    // the registers allow (the larger sides run more waves per CU and keep
-    // more of the spectra in registers).
-    static constexpr bool PIPE = L <= 128;
+    // Two tasks' loads in flight in the search window's stages where a
+    // thread has at least two tasks per stage (L / 2 row pairs or columns
+    // of NB tasks each) and the registers allow it (side 64).
+    static constexpr bool PIPE = L * NB / 2 >= 2 * NT && L <= 128;
     static_assert(L == NA * NB && NB % 2 == 0 && NA % 2 == 0, "even radices");
     static_assert(COLS * HA % NT == 0, "whole pass-B rounds");
     static_assert(2 * P >= L, "a row pair holds one real row of L values per row");
@@ -957,7 +960,7 @@ SFOC_DEV void match_item(const MatchArgs& A, int i, int bq, int slot, const floa
 }
 
 template <int L, int DT, bool BATCH>
-__global__ __launch_bounds__(MatchCfg<L>::NT, MatchCfg<L>::MINB) void match_kernel(const MatchArgs single,
+__global__ __launch_bounds__(MatchCfg<L>::NT, MatchCfg<L>::WAVES_PER_SIMD) void match_kernel(const MatchArgs single,
                                                                    const MatchArgs* __restrict__ pairs,
                                                                    const int4* __restrict__ items) {
     using C = MatchCfg<L>;
@@ -989,7 +992,7 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, MatchCfg<L>::MINB) void match_kern
 // takes items in order from a counter (zeroed before the launch) until the
 // table is exhausted; every workgroup then exits.
 template <int L, int DT>
-__global__ __launch_bounds__(MatchCfg<L>::NT, MatchCfg<L>::MINB) void match_persistent_kernel(const MatchArgs* __restrict__ pairs,
+__global__ __launch_bounds__(MatchCfg<L>::NT, MatchCfg<L>::WAVES_PER_SIMD) void match_persistent_kernel(const MatchArgs* __restrict__ pairs,
                                                                               const int4* __restrict__ items,
                                                                               int nitems, int* __restrict__ counter) {
     using C = MatchCfg<L>;

@@ -149,6 +149,11 @@ size_t describe_ws_bytes(int64_t H, int64_t W) {
     return align_up((size_t)integ_agg(H, W).total * sizeof(double), 256);
 }
 
+size_t tile_mask_bytes(int64_t H, int64_t W) {
+    const IntegAgg g = integ_agg(H, W);
+    return align_up((size_t)(g.ntx * g.nty), 256);
+}
+
 MatchPlan match_plan_L(int32_t n, int32_t m, int32_t r, int L) {
     MatchPlan p{0, 1, 0, 0};
     if (m < 3 || m > kMaxTemplate || r < 1 || r > kMaxRadiusMatch || n < 0 || side_index(L) < 0) return p;

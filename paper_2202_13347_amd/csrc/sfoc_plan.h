@@ -81,6 +81,8 @@ inline SFOC_HOST_DEVICE IntegAgg integ_agg(int64_t H, int64_t W) {
 // Bytes of the aggregates (the describe workspace when integral images are
 // asked for): 2 (ntx H + nty W + nty ntx) doubles, about 1 byte per pixel.
 size_t describe_ws_bytes(int64_t H, int64_t W);
+// Bytes of a describe tile mask of an H x W image: one per tile.
+size_t tile_mask_bytes(int64_t H, int64_t W);
 // Size of the library-owned aggregate array of sfoc_describe_noalloc.
 constexpr size_t kNoAllocScratchBytes = SFOC_NOALLOC_SCRATCH_BYTES;
 

@@ -5,6 +5,7 @@ the benchmark's launch configuration and every one of its 400 CPs (record
 and whole NCC surface) is compared with the oracle, which recomputes them
 from crops over a pool of host processes; properties that hold at any size
 are checked too."""
+import ctypes
 import sys
 
 import numpy as np
@@ -279,6 +280,44 @@ def test_empty_ip_list_and_prior():
     compare_cps(g, o, so, 6, ncc.cpu().numpy())
     flips = {i for i in range(len(o)) if o["flags"][i] != g["flags"][i]}
     assert flips <= consistency_flip_allowed(o, prior)
+
+
+@pytest.mark.parametrize("dtype", [S.DTYPE_F32, S.DTYPE_BF16])
+def test_register_describes_sensed_tiles_under_templates(dtype):
+    """The pair call describes only the sensed tiles its templates read; its
+    CPs and surfaces equal those of describing both images whole and
+    matching, bit for bit.  IPs whose templates are clipped by the image
+    border or whose search windows leave the reference, a prior, an image of
+    another shape, and a second call with fewer IPs on the same workspace
+    (the tile mask of the first call must not carry over)."""
+    pr = synth.make_pair(77, (230, 300), 6.0)
+    ref = pr.ref
+    sen = np.ascontiguousarray(pr.sen[:190, :260])
+    m, r = 40, 12
+    ips = synth.random_ips(5, 190, 260, 40, 0)
+    ips = np.concatenate([ips, np.array([[0, 0], [189, 259], [5, 130], [100, 2]], np.int32)])
+    prior = np.random.default_rng(3).integers(-20, 21, size=ips.shape).astype(np.int32)
+    p = S.preset("baseline", dtype)
+    dr, ds, dips, dprior = dev(ref), dev(sen), dev(ips), dev(prior)
+    Fr, i1, i2 = S.describe(dr, p)
+    Fs, _, _ = S.describe(ds, p, integrals=False)
+    R = S.Registrar(230, 300, 190, 260, len(ips), m, r, p, want_ncc=True)
+    for k, n in enumerate((len(ips), 7)):
+        say("sparse sensed", dtype, "call", k, "n", n)
+        cw, nw = S.fastncc_match(Fs, Fr, i1, i2, dips[:n], m, r, prior=dprior[:n], want_ncc=True)
+        # the first call's workspace, with the first n IPs (the later ones'
+        # tiles are no longer marked)
+        cs = torch.empty((n, 8), dtype=torch.int32, device="cuda")
+        ns = torch.empty((n, 2 * r + 1, 2 * r + 1), dtype=torch.float32, device="cuda")
+        rc = S.lib().sfoc_register_cps(S._ptr(dr), 230, 300, 300, S._ptr(ds), 190, 260, 260, S._ptr(dips),
+                                       S._ptr(dprior), n, m, r, ctypes.byref(R.p), S._ptr(ns), S._ptr(cs),
+                                       S._ptr(R.ws), R.wsb, None)
+        assert rc == 0
+        torch.cuda.synchronize()
+        assert torch.equal(cs.cpu(), cw.cpu())
+        assert torch.equal(ns.cpu(), nw.cpu())
+    g = S.cps_to_numpy(cs)
+    assert (g["flags"] & O.OOB).any() and not (g["flags"] & O.OOB).all()
 
 
 def test_paper_preset_end_to_end():
