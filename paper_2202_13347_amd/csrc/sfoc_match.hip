@@ -1101,33 +1101,43 @@ SFOC_DEV float cp_disp(const sfoc_cp& c, const int32_t* prior, int i, int axis) 
 // CPs (both axes); larger pairs read them from the records on every pass.
 constexpr int kConsCache = 4096;
 
-// k-th smallest (0-based) key among the eligible CPs along one axis: four
-// 8-bit radix passes; each histogram is scanned by the first wave (four
-// bins per lane) to find the bin holding rank k.
-SFOC_DEV uint32_t select_kth(const sfoc_cp* cps, const int32_t* prior, int n, int axis, int k,
-                             const uint32_t* cache, int ncache, uint32_t* hist, uint32_t* shared_sel) {
-    uint32_t prefix = 0, mask = 0;
+// The k-th smallest (0-based) key among the eligible CPs for four (axis,
+// rank) targets at once: four 8-bit radix passes, each building the four
+// targets' histograms in one sweep over the keys; wave q then scans
+// histogram q (four bins per lane) for the bin holding its rank.
+static_assert(kConsNT == 256, "one scanning wave per target");
+SFOC_DEV void select_kth4(const sfoc_cp* cps, const int32_t* prior, int n, const int (&axis)[4], int (&k)[4],
+                          const uint32_t* const (&cache)[2], int ncache, uint32_t (*hist)[256], uint32_t* sel,
+                          uint32_t (&prefix)[4]) {
+    uint32_t mask = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) prefix[q] = 0;
     for (int shift = 24; shift >= 0; shift -= 8) {
-        for (int b = threadIdx.x; b < 256; b += kConsNT) hist[b] = 0;
+        for (int b = threadIdx.x; b < 4 * 256; b += kConsNT) hist[b >> 8][b & 255] = 0;
         __syncthreads();
-        if (cache) {
-            for (int i = threadIdx.x; i < ncache; i += kConsNT) {
-                const uint32_t key = cache[i];
-                if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
-            }
-        } else {
-            for (int i = threadIdx.x; i < n; i += kConsNT) {
+        const int cnt = cache[0] ? ncache : n;
+        for (int i = threadIdx.x; i < cnt; i += kConsNT) {
+            uint32_t key[2];
+            if (cache[0]) {
+                key[0] = cache[0][i];
+                key[1] = cache[1][i];
+            } else {
                 const sfoc_cp c = cps[i];
                 if (c.flags & kBad) continue;
-                const uint32_t key = fkey(cp_disp(c, prior, i, axis));
-                if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+                key[0] = fkey(cp_disp(c, prior, i, 0));
+                key[1] = fkey(cp_disp(c, prior, i, 1));
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t kq = key[axis[q]];
+                if ((kq & mask) == prefix[q]) atomicAdd(&hist[q][(kq >> shift) & 255u], 1u);
             }
         }
         __syncthreads();
-        if (threadIdx.x < 64) {
-            const int lane = threadIdx.x;
-            const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2],
-                           h3 = hist[4 * lane + 3];
+        {
+            const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
+            const uint32_t* h = hist[q];
+            const uint32_t h0 = h[4 * lane], h1 = h[4 * lane + 1], h2 = h[4 * lane + 2], h3 = h[4 * lane + 3];
             const uint32_t own = h0 + h1 + h2 + h3;
             uint32_t incl = own;   // inclusive prefix over lanes
             for (int d = 1; d < 64; d <<= 1) {
@@ -1135,26 +1145,31 @@ SFOC_DEV uint32_t select_kth(const sfoc_cp* cps, const int32_t* prior, int n, in
                 if (lane >= d) incl += u;
             }
             const uint32_t before = incl - own;   // keys in bins below this lane's four
-            if (before <= (uint32_t)k && (uint32_t)k < incl) {   // exactly one lane
+            uint32_t kq = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (j == q) kq = (uint32_t)k[j];
+            if (before <= kq && kq < incl) {   // exactly one lane per target
                 uint32_t cum = before;
                 int b = 4 * lane;
                 const uint32_t hs[4] = {h0, h1, h2, h3};
-                for (int q = 0; q < 4; ++q, ++b) {
-                    if (cum + hs[q] > (uint32_t)k) break;
-                    cum += hs[q];
+                for (int j = 0; j < 4; ++j, ++b) {
+                    if (cum + hs[j] > kq) break;
+                    cum += hs[j];
                 }
-                shared_sel[0] = (uint32_t)b;
-                shared_sel[1] = cum;
+                sel[2 * q] = (uint32_t)b;
+                sel[2 * q + 1] = cum;
             }
         }
         __syncthreads();
-        const uint32_t b = shared_sel[0];
-        k -= (int)shared_sel[1];
-        prefix |= b << shift;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            prefix[q] |= sel[2 * q] << shift;
+            k[q] -= (int)sel[2 * q + 1];
+        }
         mask |= 255u << shift;
         __syncthreads();
     }
-    return prefix;
 }
 
 __global__ __launch_bounds__(kConsNT) void consistency_kernel(sfoc_cp* cps, const int32_t* prior, int n,
@@ -1165,8 +1180,8 @@ __global__ __launch_bounds__(kConsNT) void consistency_kernel(sfoc_cp* cps, cons
         prior = P.prior;
         n = P.n;
     }
-    __shared__ uint32_t hist[256];
-    __shared__ uint32_t sel[2];
+    __shared__ uint32_t hist[4][256];
+    __shared__ uint32_t sel[8];
     __shared__ int cnt;
     __shared__ uint32_t keys[2][kConsCache];
     if (threadIdx.x == 0) cnt = 0;
@@ -1186,17 +1201,17 @@ __global__ __launch_bounds__(kConsNT) void consistency_kernel(sfoc_cp* cps, cons
     __syncthreads();
     const int ne = cnt;
     if (ne == 0) return;
+    // the median per axis: the middle key, or the mean of the two middle
+    // ones (ranks ne/2 - 1 and ne/2) when ne is even
+    const int axis[4] = {0, 0, 1, 1};
+    int k[4] = {(ne - 1) / 2, ne / 2, (ne - 1) / 2, ne / 2};
+    const uint32_t* const cache[2] = {cached ? keys[0] : nullptr, cached ? keys[1] : nullptr};
+    uint32_t sk[4];
+    select_kth4(cps, prior, n, axis, k, cache, ne, hist, sel, sk);
     float med[2];
-    for (int axis = 0; axis < 2; ++axis) {
-        const uint32_t* cache = cached ? keys[axis] : nullptr;
-        if (ne & 1) {
-            med[axis] = fkey_inv(select_kth(cps, prior, n, axis, ne / 2, cache, ne, hist, sel));
-        } else {
-            const float a = fkey_inv(select_kth(cps, prior, n, axis, ne / 2 - 1, cache, ne, hist, sel));
-            const float b = fkey_inv(select_kth(cps, prior, n, axis, ne / 2, cache, ne, hist, sel));
-            med[axis] = 0.5f * (a + b);
-        }
-    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+        med[a] = (ne & 1) ? fkey_inv(sk[2 * a + 1]) : 0.5f * (fkey_inv(sk[2 * a]) + fkey_inv(sk[2 * a + 1]));
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += kConsNT) {
         sfoc_cp c = cps[i];
