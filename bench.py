@@ -22,7 +22,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_VALU = 157.3e12       # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+PEAK_FP32_VALU = 157.3e12       # published FP32 vector rate: 256 CU x 4 SIMD x 32 lanes/cycle x 2 (FMA) x 2.4 GHz
 PEAK_HBM = 8.0e12
 
 
@@ -598,7 +598,9 @@ def run_rectify(args, S, torch, dev):
 
 
 FAST_OPS_PER_PX = 176.0   # 16 differences, 3 x 32 pairwise min / max, 16 x 4 to close the arcs
-PEAK_FP32_OPS = 39.3e12   # single-issue FP32 lane operations: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
+# The published FP32 vector rate (157.3 TFLOP/s) counts an FMA as two flops:
+# non-fused lane operations (add, min, max) at the same issue rate.
+PEAK_FP32_OPS = PEAK_FP32_VALU / 2
 
 
 def run_fast(args, S, synth, torch, dev):

@@ -530,7 +530,7 @@ __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const De
         // image) into the integral-image buffers, and this tile's aggregates
         // for the prefix pass: row sums (the 8 lanes of a row, butterfly),
         // column sums (the 8 rows of a wave, butterfly, then the 4 waves in
-        // order) and the total (the 32 column sums in order).  Every sum is
+        // order) and the total (the 32 column sums, butterfly).  Every sum is
         // taken in a fixed order, so the integral images are reproducible.
 #pragma unroll
         for (int j = 0; j < kRun; ++j)
@@ -575,20 +575,19 @@ __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const De
             }
         }
         __syncthreads();
-        double* ct = cs + 2 * (kNT / 64) * kTS;
+        static_assert(2 * kTS == 64, "the column sums of both maps fill one wave");
         if (t < 2 * kTS) {
+            // wave 0: lane q * 32 + x sums column x of map q over the four
+            // waves in order, then the 32 columns of each map are summed by
+            // a butterfly within its half-wave (a fixed order)
             const int q = t / kTS, x = t % kTS;
             double c = 0.0;
 #pragma unroll
             for (int w = 0; w < kNT / 64; ++w) c += cs[(q * (kNT / 64) + w) * kTS + x];
-            ct[q * kTS + x] = c;
             if (tx0 + x < W) agg[(q ? ag.cs2 : ag.cs1) + ta * (int64_t)W + tx0 + x] = c;
-        }
-        __syncthreads();
-        if (t < 2) {
-            double c = 0.0;
-            for (int x = 0; x < kTS; ++x) c += ct[t * kTS + x];
-            agg[(t ? ag.tt2 : ag.tt1) + ta * ag.ntx + tb] = c;
+#pragma unroll
+            for (int d = 1; d < kTS; d <<= 1) c += __shfl_xor(c, d, 64);
+            if (x == 0) agg[(q ? ag.tt2 : ag.tt1) + ta * ag.ntx + tb] = c;
         }
     }
 }
