@@ -37,7 +37,7 @@ hipError_t ensure_dynamic_lds(const void* kern, int bytes) {
 // for the life of the process; default priority, non-blocking.
 struct SideStream {
     hipStream_t s = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+    hipEvent_t start = nullptr, mask = nullptr, fork = nullptr, join = nullptr;
 };
 
 static hipError_t side_stream(SideStream** out) {
@@ -49,6 +49,8 @@ static hipError_t side_stream(SideStream** out) {
     if (!ss.s) {
         SideStream t;
         e = hipStreamCreateWithFlags(&t.s, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&t.start, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&t.mask, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&t.fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&t.join, hipEventDisableTiming);
         if (e != hipSuccess) return e;
@@ -238,19 +240,25 @@ int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr, con
     hipStream_t st = (hipStream_t)stream;
     DescribeConsts c;
     build_describe_consts(p, &c);
-    // The reference's integral scans (memory-bound) run on a second stream
-    // while the sensed image is described; the match waits for both.  Of
-    // the sensed image only the tiles under the templates are described.
+    // Of the sensed image only the tiles under the templates are described;
+    // their mask is built on a second stream while the reference image is
+    // described.  The reference's integral scans (memory-bound) then run on
+    // that stream while the sensed image is described; the match waits for
+    // both.
     SideStream* side = nullptr;
     hipError_t e = side_stream(&side);
     double* agg = (double*)(base + L.scan);
     uint8_t* tmask = (uint8_t*)(base + L.mask);
-    if (e == hipSuccess) e = launch_tile_mask(ips, n, m, (int)Hs, (int)Ws, tmask, st);
+    if (e == hipSuccess) e = hipEventRecord(side->start, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->start, 0);
+    if (e == hipSuccess) e = launch_tile_mask(ips, n, m, (int)Hs, (int)Ws, tmask, side->s);
+    if (e == hipSuccess) e = hipEventRecord(side->mask, side->s);
     if (e == hipSuccess) e = launch_describe(ref, (int)Hr, (int)Wr, ldr, dref, i1, i2, agg, c, st);
     if (e == hipSuccess) e = hipEventRecord(side->fork, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->fork, 0);
     if (e == hipSuccess) e = launch_integral(i1, i2, (int)Hr, (int)Wr, agg, side->s);
     if (e == hipSuccess) e = hipEventRecord(side->join, side->s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, side->mask, 0);
     if (e == hipSuccess) e = launch_describe(sen, (int)Hs, (int)Ws, lds, dsen, nullptr, nullptr, nullptr, c, st, tmask);
     if (e == hipSuccess) e = hipStreamWaitEvent(st, side->join, 0);
     if (e != hipSuccess) return hip_status(e);

@@ -1099,7 +1099,7 @@ SFOC_DEV float cp_disp(const sfoc_cp& c, const int32_t* prior, int i, int axis) 
 
 // Keys of the eligible CPs' displacements are cached in LDS up to this many
 // CPs (both axes); larger pairs read them from the records on every pass.
-constexpr int kConsCache = 4096;
+constexpr int kConsCache = 6144;
 
 // The k-th smallest (0-based) key among the eligible CPs for four (axis,
 // rank) targets at once: four 8-bit radix passes, each building the four

@@ -320,6 +320,48 @@ def test_register_describes_sensed_tiles_under_templates(dtype):
     assert (g["flags"] & O.OOB).any() and not (g["flags"] & O.OOB).all()
 
 
+@pytest.mark.parametrize("n", [6000, 7000])
+def test_consistency_median_many_cps(n):
+    """The median-translation check (Section 3.2.3, the 1.5 px rule of
+    Section 4.1) over thousands of CPs: with the keys cached in LDS (n up to
+    6144) and read from the records on every radix pass (beyond).  The
+    median is that of the float32 displacements prior + d + sub-pixel
+    offset, the mean of the two middle ones for an even count; VALID and
+    INCONSISTENT must follow it exactly."""
+    say("consistency n", n)
+    pr = synth.make_pair(90, 512, 6.0)
+    m, r = 16, 8
+    ips = synth.random_ips(9, 512, 512, n, m // 2 + r + 1)
+    ips[:5] = [[0, 0], [511, 511], [3, 200], [200, 3], [510, 100]]   # out of bounds
+    prior = np.zeros_like(ips)
+    prior[::3] = np.random.default_rng(4).integers(-2, 3, size=prior[::3].shape)
+    p = S.preset("baseline")
+    Fr, i1, i2 = S.describe(dev(pr.ref), p)
+    Fs, _, _ = S.describe(dev(pr.sen), p, integrals=False)
+    cps = S.fastncc_match(Fs, Fr, i1, i2, dev(ips), m, r, prior=dev(prior))
+    torch.cuda.synchronize()
+    g = S.cps_to_numpy(cps)
+    bad = O.OOB | O.FLAT_T | O.FLAT_S | O.EDGE_PEAK | O.NONFINITE
+    elig = (g["flags"] & bad) == 0
+    assert 0 < elig.sum() < n
+    ty = (prior[:, 0] + g["dy"]).astype(np.float32) + g["sub_dy"].astype(np.float32)
+    tx = (prior[:, 1] + g["dx"]).astype(np.float32) + g["sub_dx"].astype(np.float32)
+
+    def med(v):
+        s = np.sort(v[elig])
+        k = len(s)
+        return s[k // 2] if k % 2 else np.float32(0.5) * (s[k // 2 - 1] + s[k // 2])
+    ey, ex = ty - med(ty), tx - med(tx)
+    d = np.sqrt(ey * ey + ex * ex)
+    want = np.where(elig, np.where(d > np.float32(1.5), O.INCONSISTENT, O.VALID), 0)
+    got = g["flags"] & (O.VALID | O.INCONSISTENT)
+    # a deviation within a few float32 ulps of 1.5 may round either way
+    # (fused multiply-add, the device square root)
+    sure = np.abs(d - 1.5) > 1e-5
+    assert np.array_equal(got[sure], want[sure]), np.nonzero((got != want) & sure)[0][:10]
+    assert (want == O.INCONSISTENT).any() or (want == O.VALID).all()
+
+
 def test_paper_preset_end_to_end():
     pr, ips, m, r = synth.workload(synth.SMALL, 7)
     p = S.preset("paper")
