@@ -445,6 +445,7 @@ def run_batched(args, S, synth, torch, p, dev):
             "ips": n_ips, "steps": args.batched_steps,
             "accuracy_plain": correct(plain_cps),
             "sides": classes, "persistent": info["persistent"], "describe_tiles": info["describe_tiles"],
+            "describe_config": info["describe_config"],
             "match_items": info["match_items"],
             "tuned_classes": info["tuned_classes"], "plan_create_s": create_s, "generate_s": gen_s,
             "device_gb": info["device_bytes"] / 2 ** 30,

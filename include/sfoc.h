@@ -282,6 +282,13 @@ int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr,
  * workgroups per CU taking items from a counter) with SFOC_PLAN_PERSISTENT;
  * with SFOC_PLAN_AUTOTUNE each transform side's launch form is also timed
  * at creation and the faster kept.
+ * The describe launch has two configurations of its 32 x 32 tile where the
+ * parameters allow (K = 1, dilation rates 1, 2, 3, both orders, z <= 16):
+ * 0, three workgroups per CU; 1, four workgroups per CU with half-width
+ * row-pass maps and one steered channel map at a time.  Both give the same
+ * descriptors bit for bit.  SFOC_PLAN_DESCRIBE_ALT selects configuration 1;
+ * with SFOC_PLAN_AUTOTUNE both are timed on the plan's tiles at creation
+ * and the faster kept (not remembered in tune_cache).
  *
  * Ownership and lifetime: the caller owns every pair buffer (device
  * pointers) and keeps them allocated for the plan's lifetime; the plan
@@ -314,6 +321,7 @@ typedef struct sfoc_plan sfoc_plan;
 #define SFOC_PLAN_AUTOTUNE    2
 #define SFOC_PLAN_DENSE_SEN   4
 #define SFOC_PLAN_PERSISTENT  8
+#define SFOC_PLAN_DESCRIBE_ALT 16
 
 int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params* p, int32_t flags,
                      const char* tune_cache, void* stream, sfoc_plan** plan);
@@ -333,7 +341,7 @@ typedef struct sfoc_plan_info {
     int32_t cached_classes;     /* (m, r) classes taken from tune_cache */
     int32_t graph;              /* 1 once a graph is captured */
     int32_t persistent[4];      /* those launches persistent (1) or one workgroup per item */
-    int32_t reserved;
+    int32_t describe_config;    /* describe launch configuration: 0, or 1 (four workgroups per CU) */
     int64_t device_bytes;
 } sfoc_plan_info;
 int sfoc_plan_get_info(const sfoc_plan* plan, sfoc_plan_info* info, int32_t* fft_side, int32_t* blocks,

@@ -31,6 +31,7 @@ struct sfoc_plan {
     DescribeJob* djobs = nullptr;
     int4* dtiles = nullptr;
     int ndt = 0, ndt_ref = 0;   // all tiles; reference tiles (first)
+    int dvar = 0;               // describe launch configuration (describe_configs)
     IntegJob* ijobs = nullptr;
     int4* ipre = nullptr;     // integral prefix items (integral_prefix_items)
     int4* itiles = nullptr;   // integral tiles {job, tile row, tile column}
@@ -138,14 +139,14 @@ hipError_t enqueue_match(sfoc_plan* P, hipStream_t st) {
 // Reference descriptors, then the integral scans on the second branch while
 // the sensed tiles are described, then the match.
 hipError_t enqueue_all(sfoc_plan* P, hipStream_t st) {
-    hipError_t e = launch_describe_batched(P->djobs, P->dtiles, P->ndt_ref, P->c, st);
+    hipError_t e = launch_describe_batched(P->djobs, P->dtiles, P->ndt_ref, P->c, st, P->dvar);
     if (e == hipSuccess) e = hipEventRecord(P->ev_fork2, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(P->side_stream, P->ev_fork2, 0);
     if (e == hipSuccess)
         e = launch_integral_batched(P->ijobs, P->ipre, P->npre, P->itiles, P->nitiles, P->side_stream);
     if (e == hipSuccess) e = hipEventRecord(P->ev_join2, P->side_stream);
     if (e == hipSuccess)
-        e = launch_describe_batched(P->djobs, P->dtiles + P->ndt_ref, P->ndt - P->ndt_ref, P->c, st);
+        e = launch_describe_batched(P->djobs, P->dtiles + P->ndt_ref, P->ndt - P->ndt_ref, P->c, st, P->dvar);
     if (e == hipSuccess) e = hipStreamWaitEvent(st, P->ev_join2, 0);
     if (e == hipSuccess) e = enqueue_match(P, st);
     return e;
@@ -193,6 +194,34 @@ float time_items(int L, int dtype, const MatchArgs* margs, const int4* items, in
     return t[t.size() / 2];
 }
 
+// Median time of the plan's whole describe launch in configuration var.
+float time_describe(const sfoc_plan* P, int var, hipStream_t st, int reps, hipError_t* err) {
+    hipEvent_t a, b;
+    *err = hipEventCreate(&a);
+    if (*err != hipSuccess) return 0.f;
+    *err = hipEventCreate(&b);
+    if (*err != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return 0.f;
+    }
+    std::vector<float> t;
+    *err = launch_describe_batched(P->djobs, P->dtiles, P->ndt, P->c, st, var);   // warm-up
+    for (int k = 0; k < reps && *err == hipSuccess; ++k) {
+        *err = hipEventRecord(a, st);
+        if (*err == hipSuccess) *err = launch_describe_batched(P->djobs, P->dtiles, P->ndt, P->c, st, var);
+        if (*err == hipSuccess) *err = hipEventRecord(b, st);
+        if (*err == hipSuccess) *err = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (*err == hipSuccess) *err = hipEventElapsedTime(&ms, a, b);
+        t.push_back(ms);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (t.empty()) return 0.f;
+    std::sort(t.begin(), t.end());
+    return t[t.size() / 2];
+}
+
 }  // namespace
 
 extern "C" {
@@ -201,7 +230,8 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
                      const char* tune_cache, void* stream, sfoc_plan** plan) {
     if (!plan || !pairs || n_pairs < 1) return SFOC_E_INVALID_ARG;
     *plan = nullptr;
-    if (flags & ~(SFOC_PLAN_GRAPH | SFOC_PLAN_AUTOTUNE | SFOC_PLAN_DENSE_SEN | SFOC_PLAN_PERSISTENT))
+    if (flags & ~(SFOC_PLAN_GRAPH | SFOC_PLAN_AUTOTUNE | SFOC_PLAN_DENSE_SEN | SFOC_PLAN_PERSISTENT |
+                  SFOC_PLAN_DESCRIBE_ALT))
         return SFOC_E_INVALID_ARG;
     int32_t z = 0;
     int rc = check_params(p, &z);
@@ -383,6 +413,20 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
         return hip_status(e);
     }
 
+    // ---- describe launch configuration: asked for, or the faster of the
+    //      two on this plan's tiles (both give the same descriptors) ----
+    const bool two_configs = describe_configs(P->c) == 2;
+    P->dvar = two_configs && (flags & SFOC_PLAN_DESCRIBE_ALT) ? 1 : 0;
+    if (tune && two_configs && P->ndt > 0) {
+        const float t0 = time_describe(P, 0, st, 3, &e);
+        const float t1 = e == hipSuccess ? time_describe(P, 1, st, 3, &e) : 0.f;
+        if (e != hipSuccess) {
+            free_plan(P);
+            return hip_status(e);
+        }
+        P->dvar = t1 < t0 ? 1 : 0;
+    }
+
     // ---- transform side per pair ----
     P->side.assign(n_pairs, 0);
     std::map<std::pair<int, int>, std::vector<int>> classes;   // (m, r) -> pairs still open
@@ -403,7 +447,7 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
                 ++P->cached;
             } else {
                 if (!described) {   // the candidates are timed on this plan's own descriptors
-                    e = launch_describe_batched(P->djobs, P->dtiles, P->ndt, P->c, st);
+                    e = launch_describe_batched(P->djobs, P->dtiles, P->ndt, P->c, st, P->dvar);
                     if (e == hipSuccess)
                         e = launch_integral_batched(P->ijobs, P->ipre, P->npre, P->itiles, P->nitiles, st);
                     described = true;
@@ -553,7 +597,7 @@ int sfoc_plan_get_info(const sfoc_plan* P, sfoc_plan_info* info, int32_t* fft_si
     info->tuned_classes = P->tuned;
     info->cached_classes = P->cached;
     info->graph = P->exec != nullptr;
-    info->reserved = 0;
+    info->describe_config = P->dvar;
     info->device_bytes = (int64_t)P->bytes;
     const int n = std::min<int>(cap, (int)P->pairs.size());
     for (int k = 0; k < n; ++k) {

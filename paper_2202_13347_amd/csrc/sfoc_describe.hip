@@ -39,7 +39,11 @@ struct DescribeGeom {
     size_t bytes;
 };
 
-static DescribeGeom describe_geom(const DescribeConsts& c, int CG) {
+// Pitch of the half-width row-pass maps of the four-workgroup configuration
+// (20 columns, odd).
+constexpr int kHalfPitch = 21;
+
+static DescribeGeom describe_geom(const DescribeConsts& c, int CG, bool halves) {
     DescribeGeom g;
     g.BSP = (kTS + 2 * c.Q + kRun - 1) / kRun * kRun;
     g.ISX = g.BSP + 2 * c.R;
@@ -50,7 +54,7 @@ static DescribeGeom describe_geom(const DescribeConsts& c, int CG) {
     // Phase 2 holds the image region and the row-pass maps; phase 3 the five
     // basis maps (over the same memory) and CG steered channels.
     const size_t img = (size_t)g.ISX * g.IPP;
-    const size_t row = 3 * (size_t)g.ISX * g.BPP;
+    const size_t row = 3 * (size_t)g.ISX * (halves ? kHalfPitch : g.BPP);
     const size_t bb = (size_t)g.BSP * g.BPP;
     const size_t p2 = img + row, p3 = (5 + (size_t)CG) * bb;
     g.bytes = (p2 > p3 ? p2 : p3) * sizeof(float);
@@ -207,8 +211,19 @@ SFOC_DEV void col_run_any(const float* p, int P, int rho, const float* te, const
         default: CALL_ANY; break;                 \
     }
 
-template <int Z, int CG, bool FAST>
-__global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const DescribeJob single,
+// Two launch configurations of the 32 x 32 tile.  Configuration 0: three
+// workgroups per CU, two steered channel maps per group.  Configuration 1
+// (K = 1, rates 1-3, up to 16 channels): four workgroups per CU in at most
+// 40 KB of LDS and 128 VGPRs each: the basis columns in two halves (half-width
+// row-pass maps), one steered channel map per group, and the accumulators of
+// one order at a time.  Both give the same descriptors bit for bit.
+template <int Z, bool FAST, int VAR>
+constexpr int describe_wpc() { return VAR ? 4 : (Z >= 32 ? 2 : 3); }
+template <int Z, bool FAST, int VAR>
+constexpr int describe_cg() { return VAR ? 1 : (FAST ? 2 : (Z >= 4 ? 4 : Z)); }
+
+template <int Z, int CG, bool FAST, int VAR>
+__global__ __launch_bounds__(kNT, (describe_wpc<Z, FAST, VAR>())) void describe_kernel(const DescribeJob single,
                                                           const DescribeJob* __restrict__ jobs,
                                                           const int4* __restrict__ tiles,
                                                           const uint8_t* __restrict__ tmask, const DescribeConsts C,
@@ -299,89 +314,174 @@ __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const De
             for (int j = 0; j < kRun; ++j) bas[o][m][j] = 0.f;
     const int BSr = kTS + 2 * Q;      // rows / columns of the basis maps that steering reads
     const int ncolrun = nrun * BSr;   // (row-run, column) pairs
-    for (int s = 0; s < C.nsig; ++s) {
-        const int rho = C.rad[s];
-        const float* tg = C.taps + C.off[s];
-        const float* td = tg + (rho + 1);
-        const float* tdd = td + (rho + 1);
-        const float cn = C.cnorm[s];
-        const int rows = BSP + 2 * rho;
-        // row pass on rows [0, rows) x cols [0, BSP): horizontal runs.  Row a
-        // of this pass is image-region row a + R - rho.
-        for (int e = t; e < rows * nrun; e += kNT) {
-            const int a = e / nrun, b0 = (e - a * nrun) * kRun;
-            const float* p = simg + (a + R - rho) * IPP + (b0 + R);
-            float og[kRun], od[kRun], odd[kRun];
-#define ROW_T(RR) row_run<RR>(p, tg, td, tdd, og, od, odd)
-            SFOC_RADIUS_SWITCH(rho, ROW_T, row_run_any(p, rho, tg, td, tdd, og, od, odd))
-#undef ROW_T
-            float* w = srow + a * BPP + b0;
+    if constexpr (VAR == 1) {
+        // The basis columns in two halves, [0, 20) and [20, 38): per sigma
+        // and half, a row pass over the half's 20 columns (five runs per
+        // row) into half-width maps, then the column pass of that half.
+        // Thread t owns run t of each half (10 row runs x the half's
+        // columns), so bas[h] holds its half-h run for the whole sigma sum.
+        constexpr int kHW = kFastBSP / 2, kHR = kHW / kRun;
+        static_assert(kMaxOwn == 2 && kFastBSP == 40 && kNT >= kHW * (kFastBSP / kRun), "two halves of 40 columns");
+        for (int s = 0; s < C.nsig; ++s) {
+            const int rho = C.rad[s];
+            const float* tg = C.taps + C.off[s];
+            const float* td = tg + (rho + 1);
+            const float* tdd = td + (rho + 1);
+            const float cn = C.cnorm[s];
+            const int use = C.use[s];
+            const int rows = BSP + 2 * rho;
+            const int ig = ISX * IPP, id = ig + rows * kHalfPitch, idd = ig + 2 * rows * kHalfPitch;
 #pragma unroll
-            for (int j = 0; j < kRun; ++j) {
-                w[j] = og[j];
-                w[rows * BPP + j] = od[j];
-                w[2 * rows * BPP + j] = odd[j];
+            for (int h = 0; h < 2; ++h) {
+                for (int e = t; e < rows * kHR; e += kNT) {
+                    const int a = e / kHR, b0 = (e - a * kHR) * kRun;
+                    const float* p = simg + (a + R - rho) * IPP + (h * kHW + b0 + R);
+                    float og[kRun], od[kRun], odd[kRun];
+#define ROW_T(RR) row_run<RR>(p, tg, td, tdd, og, od, odd)
+                    SFOC_RADIUS_SWITCH(rho, ROW_T, row_run_any(p, rho, tg, td, tdd, og, od, odd))
+#undef ROW_T
+                    float* w = srow + a * kHalfPitch + b0;
+#pragma unroll
+                    for (int j = 0; j < kRun; ++j) {
+                        w[j] = og[j];
+                        w[rows * kHalfPitch + j] = od[j];
+                        w[2 * rows * kHalfPitch + j] = odd[j];
+                    }
+                }
+                __syncthreads();
+                const int wh = h ? BSr - kHW : kHW;   // basis columns of this half
+                if (t < wh * nrun) {
+                    const int b = t % wh, a0 = (t / wh) * kRun;
+                    float bx[kRun], by[kRun], bxx[kRun], byy[kRun], bxy[kRun], dummy[kRun];
+                    const int c0 = (a0 + rho) * kHalfPitch + b;
+#define COL_T(RR)                                                       \
+    do {                                                                \
+        col_run<RR>(lds, ig + c0, kHalfPitch, tdd, td, byy, by);        \
+        col_run<RR>(lds, id + c0, kHalfPitch, tg, td, bx, bxy);         \
+        col_run<RR>(lds, idd + c0, kHalfPitch, tg, nullptr, bxx, dummy); \
+    } while (0)
+#define COL_ANY                                                         \
+    do {                                                                \
+        col_run_any(lds + ig + c0, kHalfPitch, rho, tdd, td, byy, by);  \
+        col_run_any(lds + id + c0, kHalfPitch, rho, tg, td, bx, bxy);   \
+        col_run_any(lds + idd + c0, kHalfPitch, rho, tg, nullptr, bxx, dummy); \
+    } while (0)
+                    SFOC_RADIUS_SWITCH(rho, COL_T, COL_ANY)
+#undef COL_T
+#undef COL_ANY
+                    (void)dummy;
+#pragma unroll
+                    for (int j = 0; j < kRun; ++j) {
+                        if (use & 1) {
+                            bas[h][0][j] = fmaf(cn, bx[j], bas[h][0][j]);
+                            bas[h][1][j] = fmaf(cn, by[j], bas[h][1][j]);
+                        }
+                        if (use & 2) {
+                            bas[h][2][j] = fmaf(cn, bxx[j], bas[h][2][j]);
+                            bas[h][3][j] = fmaf(cn, byy[j], bas[h][3][j]);
+                            bas[h][4][j] = fmaf(cn, bxy[j], bas[h][4][j]);
+                        }
+                    }
+                }
+                __syncthreads();
             }
         }
-        __syncthreads();
-        // column pass on vertical runs; output row a reads pass rows a + rho + k.
-        const float* rg = srow;
-        const float* rd = srow + rows * BPP;
-        const float* rdd = srow + 2 * rows * BPP;
-        const int ig = ISX * IPP, id = ig + rows * BPP, idd = ig + 2 * rows * BPP;   // the same, as lds indices
-        const int use = C.use[s];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int wh = h ? BSr - kHW : kHW;
+            if (t < wh * nrun) {
+                const int b = h * kHW + t % wh, a0 = (t / wh) * kRun;
+#pragma unroll
+                for (int m = 0; m < 5; ++m)
+#pragma unroll
+                    for (int j = 0; j < kRun; ++j) sbas[m * BB + (a0 + j) * BPP + b] = bas[h][m][j];
+            }
+        }
+    } else {
+        for (int s = 0; s < C.nsig; ++s) {
+            const int rho = C.rad[s];
+            const float* tg = C.taps + C.off[s];
+            const float* td = tg + (rho + 1);
+            const float* tdd = td + (rho + 1);
+            const float cn = C.cnorm[s];
+            const int rows = BSP + 2 * rho;
+            // row pass on rows [0, rows) x cols [0, BSP): horizontal runs.  Row a
+            // of this pass is image-region row a + R - rho.
+            for (int e = t; e < rows * nrun; e += kNT) {
+                const int a = e / nrun, b0 = (e - a * nrun) * kRun;
+                const float* p = simg + (a + R - rho) * IPP + (b0 + R);
+                float og[kRun], od[kRun], odd[kRun];
+#define ROW_T(RR) row_run<RR>(p, tg, td, tdd, og, od, odd)
+                SFOC_RADIUS_SWITCH(rho, ROW_T, row_run_any(p, rho, tg, td, tdd, og, od, odd))
+#undef ROW_T
+                float* w = srow + a * BPP + b0;
+#pragma unroll
+                for (int j = 0; j < kRun; ++j) {
+                    w[j] = og[j];
+                    w[rows * BPP + j] = od[j];
+                    w[2 * rows * BPP + j] = odd[j];
+                }
+            }
+            __syncthreads();
+            // column pass on vertical runs; output row a reads pass rows a + rho + k.
+            const float* rg = srow;
+            const float* rd = srow + rows * BPP;
+            const float* rdd = srow + 2 * rows * BPP;
+            const int ig = ISX * IPP, id = ig + rows * BPP, idd = ig + 2 * rows * BPP;   // the same, as lds indices
+            const int use = C.use[s];
+#pragma unroll
+            for (int o = 0; o < kMaxOwn; ++o) {
+                const int e = t + o * kNT;
+                if (e < ncolrun) {
+                    const int b = e % BSr, a0 = (e / BSr) * kRun;
+                    float bx[kRun], by[kRun], bxx[kRun], byy[kRun], bxy[kRun], dummy[kRun];
+                    const int c0 = (a0 + rho) * BPP + b;
+                    // rg -> By (odd d), Byy (even dd); rd -> Bx (even g), Bxy (odd d);
+                    // rdd -> Bxx (even g).
+#define COL_T(RR)                                                \
+        do {                                                         \
+            col_run<RR>(lds, ig + c0, BPP, tdd, td, byy, by);        \
+            col_run<RR>(lds, id + c0, BPP, tg, td, bx, bxy);         \
+            col_run<RR>(lds, idd + c0, BPP, tg, nullptr, bxx, dummy); \
+        } while (0)
+#define COL_ANY                                                  \
+        do {                                                         \
+            col_run_any(rg + c0, BPP, rho, tdd, td, byy, by);        \
+            col_run_any(rd + c0, BPP, rho, tg, td, bx, bxy);         \
+            col_run_any(rdd + c0, BPP, rho, tg, nullptr, bxx, dummy); \
+        } while (0)
+                    SFOC_RADIUS_SWITCH(rho, COL_T, COL_ANY)
+#undef COL_T
+#undef COL_ANY
+                    (void)dummy;
+#pragma unroll
+                    for (int j = 0; j < kRun; ++j) {
+                        // the 2-D normalisation cn of this sigma, applied as the
+                        // response joins the sum over sigma
+                        if (use & 1) {
+                            bas[o][0][j] = fmaf(cn, bx[j], bas[o][0][j]);
+                            bas[o][1][j] = fmaf(cn, by[j], bas[o][1][j]);
+                        }
+                        if (use & 2) {
+                            bas[o][2][j] = fmaf(cn, bxx[j], bas[o][2][j]);
+                            bas[o][3][j] = fmaf(cn, byy[j], bas[o][3][j]);
+                            bas[o][4][j] = fmaf(cn, bxy[j], bas[o][4][j]);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
 #pragma unroll
         for (int o = 0; o < kMaxOwn; ++o) {
             const int e = t + o * kNT;
             if (e < ncolrun) {
                 const int b = e % BSr, a0 = (e / BSr) * kRun;
-                float bx[kRun], by[kRun], bxx[kRun], byy[kRun], bxy[kRun], dummy[kRun];
-                const int c0 = (a0 + rho) * BPP + b;
-                // rg -> By (odd d), Byy (even dd); rd -> Bx (even g), Bxy (odd d);
-                // rdd -> Bxx (even g).
-#define COL_T(RR)                                                \
-    do {                                                         \
-        col_run<RR>(lds, ig + c0, BPP, tdd, td, byy, by);        \
-        col_run<RR>(lds, id + c0, BPP, tg, td, bx, bxy);         \
-        col_run<RR>(lds, idd + c0, BPP, tg, nullptr, bxx, dummy); \
-    } while (0)
-#define COL_ANY                                                  \
-    do {                                                         \
-        col_run_any(rg + c0, BPP, rho, tdd, td, byy, by);        \
-        col_run_any(rd + c0, BPP, rho, tg, td, bx, bxy);         \
-        col_run_any(rdd + c0, BPP, rho, tg, nullptr, bxx, dummy); \
-    } while (0)
-                SFOC_RADIUS_SWITCH(rho, COL_T, COL_ANY)
-#undef COL_T
-#undef COL_ANY
-                (void)dummy;
 #pragma unroll
-                for (int j = 0; j < kRun; ++j) {
-                    // the 2-D normalisation cn of this sigma, applied as the
-                    // response joins the sum over sigma
-                    if (use & 1) {
-                        bas[o][0][j] = fmaf(cn, bx[j], bas[o][0][j]);
-                        bas[o][1][j] = fmaf(cn, by[j], bas[o][1][j]);
-                    }
-                    if (use & 2) {
-                        bas[o][2][j] = fmaf(cn, bxx[j], bas[o][2][j]);
-                        bas[o][3][j] = fmaf(cn, byy[j], bas[o][3][j]);
-                        bas[o][4][j] = fmaf(cn, bxy[j], bas[o][4][j]);
-                    }
-                }
+                for (int m = 0; m < 5; ++m)
+#pragma unroll
+                    for (int j = 0; j < kRun; ++j) sbas[m * BB + (a0 + j) * BPP + b] = bas[o][m][j];
             }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int o = 0; o < kMaxOwn; ++o) {
-        const int e = t + o * kNT;
-        if (e < ncolrun) {
-            const int b = e % BSr, a0 = (e / BSr) * kRun;
-#pragma unroll
-            for (int m = 0; m < 5; ++m)
-#pragma unroll
-                for (int j = 0; j < kRun; ++j) sbas[m * BB + (a0 + j) * BPP + b] = bas[o][m][j];
         }
     }
     __syncthreads();
@@ -461,8 +561,10 @@ __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const De
             }
         }
     };
+    // channels [lo, hi) in groups of CG: steer into LDS, then smooth
+    auto steer_smooth = [&](int lo, int hi) {
 #pragma unroll
-    for (int c0 = 0; c0 < Z; c0 += CG) {
+    for (int c0 = lo; c0 < hi; c0 += CG) {
         // thread index laundered per group: keeps the group's LDS addresses
         // from being hoisted (and kept live) across the whole channel loop.
         int tl = t;
@@ -518,10 +620,15 @@ __global__ __launch_bounds__(kNT, Z >= 32 ? 2 : 3) void describe_kernel(const De
         }
         __syncthreads();
     }
-    if (FAST) {
+    };
+    if constexpr (VAR == 1) {
+        // one order at a time: its accumulators die at its emit
+        steer_smooth(0, Z / 2);
         emit(0, Z / 2);
+        steer_smooth(Z / 2, Z);
         emit(Z / 2, Z);
     } else {
+        steer_smooth(0, Z);
         emit(0, N);
         emit(N, Z);
     }
@@ -777,14 +884,14 @@ __global__ __launch_bounds__(kScanNT) void integral_tiles(const IntegJob single,
 }
 
 // ---- launch -------------------------------------------------------------
-template <int Z, bool FAST>
+template <int Z, bool FAST, int VAR>
 static hipError_t launch_describe_zf(const DescribeJob& job, const DescribeJob* jobs, const int4* tiles, int ntiles,
                                      const uint8_t* tmask, const DescribeConsts& c, hipStream_t st) {
-    constexpr int CG = FAST ? 2 : (Z >= 4 ? 4 : Z);
-    const DescribeGeom g = describe_geom(c, CG);
+    constexpr int CG = describe_cg<Z, FAST, VAR>();
+    const DescribeGeom g = describe_geom(c, CG, VAR == 1);
     dim3 grid = tiles ? dim3(ntiles) : dim3((job.W + kTS - 1) / kTS, (job.H + kTS - 1) / kTS);
     if (grid.x == 0) return hipSuccess;
-    auto kern = describe_kernel<Z, CG, FAST>;
+    auto kern = describe_kernel<Z, CG, FAST, VAR>;
     hipError_t e = ensure_dynamic_lds((const void*)kern, (int)g.bytes);
     if (e != hipSuccess) return e;
     trace_begin(st, SFOC_K_DESCRIBE);
@@ -793,42 +900,50 @@ static hipError_t launch_describe_zf(const DescribeJob& job, const DescribeJob* 
     return hipGetLastError();
 }
 
+// The K = 1, rates 1-3 path with both orders: compile-time geometry.
+static bool describe_fast(const DescribeConsts& c) {
+    return c.K == 1 && c.ndil == 3 && c.dil[0] == 1 && c.dil[1] == 2 && c.dil[2] == 3 && c.second &&
+           c.N * 2 == c.z;
+}
+
+int describe_configs(const DescribeConsts& c) { return describe_fast(c) && c.z <= 16 && c.z % 2 == 0 ? 2 : 1; }
+
 template <int Z>
 static hipError_t launch_describe_z(const DescribeJob& job, const DescribeJob* jobs, const int4* tiles, int ntiles,
-                                    const uint8_t* tmask, const DescribeConsts& c, hipStream_t st) {
-    const bool fast = c.K == 1 && c.ndil == 3 && c.dil[0] == 1 && c.dil[1] == 2 && c.dil[2] == 3 && c.second &&
-                      c.N * 2 == Z;
-    return fast ? launch_describe_zf<Z, true>(job, jobs, tiles, ntiles, tmask, c, st)
-                : launch_describe_zf<Z, false>(job, jobs, tiles, ntiles, tmask, c, st);
+                                    const uint8_t* tmask, const DescribeConsts& c, hipStream_t st, int var) {
+    if (!describe_fast(c)) return launch_describe_zf<Z, false, 0>(job, jobs, tiles, ntiles, tmask, c, st);
+    if constexpr (Z <= 16 && Z % 2 == 0)
+        if (var == 1) return launch_describe_zf<Z, true, 1>(job, jobs, tiles, ntiles, tmask, c, st);
+    return launch_describe_zf<Z, true, 0>(job, jobs, tiles, ntiles, tmask, c, st);
 }
 
 static hipError_t launch_describe_any(const DescribeJob& job, const DescribeJob* jobs, const int4* tiles, int ntiles,
-                                      const uint8_t* tmask, const DescribeConsts& c, hipStream_t st) {
+                                      const uint8_t* tmask, const DescribeConsts& c, hipStream_t st, int var) {
     switch (c.z) {
-        case 2: return launch_describe_z<2>(job, jobs, tiles, ntiles, tmask, c, st);
-        case 3: return launch_describe_z<3>(job, jobs, tiles, ntiles, tmask, c, st);
-        case 4: return launch_describe_z<4>(job, jobs, tiles, ntiles, tmask, c, st);
-        case 6: return launch_describe_z<6>(job, jobs, tiles, ntiles, tmask, c, st);
-        case 8: return launch_describe_z<8>(job, jobs, tiles, ntiles, tmask, c, st);
-        case 12: return launch_describe_z<12>(job, jobs, tiles, ntiles, tmask, c, st);
-        case 16: return launch_describe_z<16>(job, jobs, tiles, ntiles, tmask, c, st);
-        case 24: return launch_describe_z<24>(job, jobs, tiles, ntiles, tmask, c, st);
-        case 32: return launch_describe_z<32>(job, jobs, tiles, ntiles, tmask, c, st);
+        case 2: return launch_describe_z<2>(job, jobs, tiles, ntiles, tmask, c, st, var);
+        case 3: return launch_describe_z<3>(job, jobs, tiles, ntiles, tmask, c, st, var);
+        case 4: return launch_describe_z<4>(job, jobs, tiles, ntiles, tmask, c, st, var);
+        case 6: return launch_describe_z<6>(job, jobs, tiles, ntiles, tmask, c, st, var);
+        case 8: return launch_describe_z<8>(job, jobs, tiles, ntiles, tmask, c, st, var);
+        case 12: return launch_describe_z<12>(job, jobs, tiles, ntiles, tmask, c, st, var);
+        case 16: return launch_describe_z<16>(job, jobs, tiles, ntiles, tmask, c, st, var);
+        case 24: return launch_describe_z<24>(job, jobs, tiles, ntiles, tmask, c, st, var);
+        case 32: return launch_describe_z<32>(job, jobs, tiles, ntiles, tmask, c, st, var);
         default: return hipErrorInvalidValue;
     }
 }
 
 // Several images in one launch: jobs and tiles are device tables.
 hipError_t launch_describe_batched(const DescribeJob* jobs, const int4* tiles, int ntiles, const DescribeConsts& c,
-                                   hipStream_t st) {
+                                   hipStream_t st, int var) {
     DescribeJob none{};
-    return launch_describe_any(none, jobs, tiles, ntiles, nullptr, c, st);
+    return launch_describe_any(none, jobs, tiles, ntiles, nullptr, c, st, var);
 }
 
 hipError_t launch_describe(const float* img, int H, int W, int64_t ld, void* desc, double* i1, double* i2,
                            double* agg, const DescribeConsts& c, hipStream_t st, const uint8_t* tmask) {
     DescribeJob job{img, desc, i1, i2, agg, ld, H, W};
-    return launch_describe_any(job, nullptr, nullptr, 0, tmask, c, st);
+    return launch_describe_any(job, nullptr, nullptr, 0, tmask, c, st, 0);
 }
 
 // ---- the sensed tiles that templates read ----------------------------------

@@ -86,9 +86,13 @@ hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void
 void match_args_layout(MatchArgs& a, const MatchPlan& mp, void* ws);
 
 // ---- tables (device pointers) --------------------------------------------
-// tiles[k] = {job, tile row origin, tile column origin, 0}
+// tiles[k] = {job, tile row origin, tile column origin, 0}; var picks the
+// launch configuration (0, or 1 where describe_configs() is 2): the same
+// descriptors either way.
 hipError_t launch_describe_batched(const DescribeJob* jobs, const int4* tiles, int ntiles, const DescribeConsts& c,
-                                   hipStream_t st);
+                                   hipStream_t st, int var = 0);
+// Launch configurations of the describe kernel for these constants (1 or 2).
+int describe_configs(const DescribeConsts& c);
 // pre[k] = {job, kind, block, 0}: kind 0 a block of kScanNT rows of the
 // row sums, 1 a block of kScanNT columns of the column sums, 2 the tile
 // totals (integral_prefix_items lists them); tiles[k] = {job, tile row,

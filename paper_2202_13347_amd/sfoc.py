@@ -65,14 +65,16 @@ class Pair(ctypes.Structure):
 
 class PlanInfo(ctypes.Structure):
     """sfoc_plan_info: what a batched plan decided (work items, tuned and
-    cached shape classes, graph and persistent launches, device bytes)."""
+    cached shape classes, graph and persistent launches, the describe launch
+    configuration, device bytes)."""
     _fields_ = [("n_pairs", ctypes.c_int32), ("describe_tiles", ctypes.c_int32),
                 ("match_items", ctypes.c_int32 * 4), ("peak_items", ctypes.c_int32),
                 ("tuned_classes", ctypes.c_int32), ("cached_classes", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("persistent", ctypes.c_int32 * 4), ("reserved", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+                ("persistent", ctypes.c_int32 * 4), ("describe_config", ctypes.c_int32),
+                ("device_bytes", ctypes.c_int64)]
 
 
-PLAN_GRAPH, PLAN_AUTOTUNE, PLAN_DENSE_SEN, PLAN_PERSISTENT = 1, 2, 4, 8
+PLAN_GRAPH, PLAN_AUTOTUNE, PLAN_DENSE_SEN, PLAN_PERSISTENT, PLAN_DESCRIBE_ALT = 1, 2, 4, 8, 16
 
 
 class RansacParams(ctypes.Structure):
@@ -394,7 +396,7 @@ class Plan:
         return {"n_pairs": inf.n_pairs, "describe_tiles": inf.describe_tiles,
                 "match_items": tuple(inf.match_items), "peak_items": inf.peak_items,
                 "tuned_classes": inf.tuned_classes, "cached_classes": inf.cached_classes, "graph": inf.graph,
-                "persistent": tuple(inf.persistent),
+                "persistent": tuple(inf.persistent), "describe_config": inf.describe_config,
                 "device_bytes": inf.device_bytes, "fft_side": list(L), "blocks": list(nb)}
 
     def close(self):

@@ -26,7 +26,7 @@ def test_pair_and_info_layout_match_header(tmp_path):
 int main(void) {
   P(ref) P(Hr) P(Wr) P(ldr) P(sen) P(Hs) P(Ws) P(lds) P(ips) P(prior) P(n) P(m) P(r) P(fft_side) P(ncc) P(cps)
   I(n_pairs) I(describe_tiles) I(match_items) I(peak_items) I(tuned_classes) I(cached_classes) I(graph)
-  I(persistent) I(reserved)
+  I(persistent) I(describe_config)
   I(device_bytes)
   printf("pair.size %zu\ninfo.size %zu\n", sizeof(sfoc_pair), sizeof(sfoc_plan_info));
   return 0;
@@ -140,7 +140,7 @@ def _pair(**kw):
 
 
 @pytest.mark.parametrize("kw,flags,code", [
-    ({}, 16, S.SFOC_E_INVALID_ARG),                                # unknown flag
+    ({}, 32, S.SFOC_E_INVALID_ARG),                                # unknown flag
     ({"ref": None}, 0, S.SFOC_E_INVALID_ARG),
     ({"ldr": 10}, 0, S.SFOC_E_INVALID_ARG),
     ({"m": 2}, 0, S.SFOC_E_INVALID_ARG),

@@ -95,7 +95,9 @@ def assert_same(plan, ref_res):
 
 
 @pytest.mark.parametrize("flags", [0, S.PLAN_GRAPH, S.PLAN_DENSE_SEN, S.PLAN_PERSISTENT,
-                                   S.PLAN_PERSISTENT | S.PLAN_GRAPH])
+                                   S.PLAN_PERSISTENT | S.PLAN_GRAPH,
+                                   # the four-workgroup describe configuration: the same descriptors
+                                   S.PLAN_DESCRIBE_ALT, S.PLAN_DESCRIBE_ALT | S.PLAN_GRAPH | S.PLAN_DENSE_SEN])
 def test_batched_equals_per_pair(flags):
     say(f"batched vs per-pair, flags {flags}")
     p = S.preset("baseline")
@@ -113,6 +115,7 @@ def test_batched_equals_per_pair(flags):
     if flags & S.PLAN_GRAPH:
         assert plan.info()["graph"] == 1
     assert plan.info()["persistent"] == ((1,) * 4 if flags & S.PLAN_PERSISTENT else (0,) * 4)
+    assert plan.info()["describe_config"] == (1 if flags & S.PLAN_DESCRIBE_ALT else 0)
     plan.close()
 
 
@@ -204,6 +207,7 @@ def test_autotune_and_cache(tmp_path):
     timed = sum(len(S.match_candidates(q["m"], q["r"])) > 1 and len(q["ips"]) > 0 for q in pairs)
     assert timed >= 5
     assert info["tuned_classes"] == timed
+    assert info["describe_config"] in (0, 1)   # the faster of the two, timed at creation
     for q, L in zip(pairs, info["fft_side"]):
         assert L in [c[0] for c in S.match_candidates(q["m"], q["r"])]
     plan()
