@@ -320,11 +320,12 @@ def test_register_describes_sensed_tiles_under_templates(dtype):
     assert (g["flags"] & O.OOB).any() and not (g["flags"] & O.OOB).all()
 
 
-@pytest.mark.parametrize("n", [6000, 7000])
+@pytest.mark.parametrize("n", [300, 901, 6000, 7000])
 def test_consistency_median_many_cps(n):
     """The median-translation check (Section 3.2.3, the 1.5 px rule of
-    Section 4.1) over thousands of CPs: with the keys cached in LDS (n up to
-    6144) and read from the records on every radix pass (beyond).  The
+    Section 4.1) over hundreds to thousands of CPs: by radix passes over
+    keys cached in LDS (up to 6144 CPs) and read from the records on every
+    pass (beyond).  The
     median is that of the float32 displacements prior + d + sub-pixel
     offset, the mean of the two middle ones for an even count; VALID and
     INCONSISTENT must follow it exactly."""
