@@ -236,13 +236,14 @@ def parity_vs_stored_oracle(S, name, cps, kind="o64", ref_kind=None):
 def described_px(S, ips, m, r, H, W):
     """Pixels the two describe launches of a register step cover, on
     average: the whole reference image, and the sensed image's tiles under
-    the templates (every IP of these workloads is in bounds, so the tile
-    rule of sfoc_sensed_tiles is the one the pair call applies)."""
+    the templates.  The pair call describes each IP's own template tiles
+    (a tile two IPs share is described twice), so the tiles are counted per
+    IP, each clipped to the image."""
     import numpy as np
-    mask = S.sensed_tiles(ips, m, r, H, W, H, W).astype(bool)
-    th = np.minimum(32, H - 32 * np.arange(mask.shape[0]))
-    tw = np.minimum(32, W - 32 * np.arange(mask.shape[1]))
-    sen_px = float((np.outer(th, tw) * mask).sum())
+    sen_px = 0.0
+    for k in range(len(ips)):
+        t = S.sensed_tiles(ips[k:k + 1], m, r, H, W, H, W)
+        sen_px += float((np.minimum(32, H - t[:, 0]) * np.minimum(32, W - t[:, 1])).sum())
     return (H * W + sen_px) / 2.0, sen_px
 
 

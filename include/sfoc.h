@@ -262,8 +262,9 @@ int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr,
  * (descriptors, integral images, scratch and the launch tables; it is the
  * only call of this library that allocates) and builds the work lists:
  *  - describe: one launch over (image, 32 x 32 tile) entries of all images;
- *    the sensed images get only the tiles that their templates read unless
- *    SFOC_PLAN_DENSE_SEN is set (then they are described whole);
+ *    a sensed image gets only the tiles over its templates, the shorter of
+ *    the two lists of sfoc_sensed_tiles (SFOC_COVER_SMALLER), unless
+ *    SFOC_PLAN_DENSE_SEN is set (then it is described whole);
  *  - integral images: three launches over all reference images;
  *  - match: one launch per transform side over (pair, IP, offset block)
  *    items, side 64 on a second graph branch beside the larger sides; a
@@ -353,14 +354,28 @@ int sfoc_plan_get_info(const sfoc_plan* plan, sfoc_plan_info* info, int32_t* fft
  * for template m and radius r with at most 8 offset blocks per axis, the
  * default first and the others by increasing side, and the offset blocks per
  * axis of each; returns the count (0: none; at most 4).
- * sfoc_sensed_tiles: the 32 x 32 sensed-image tiles that the templates of
- * in-bounds IPs read (host arrays; mask has ceil(Hs/32) * ceil(Ws/32) bytes,
- * row-major over tiles); returns the number of marked tiles, or a negative
- * status.
+ * sfoc_sensed_tiles: 32 x 32 sensed-image tiles that cover the m x m
+ * templates of the in-bounds IPs (template and search window inside their
+ * images; host arrays, no device work).  Tiles start on multiples of 32 in
+ * the column and may run past a template; they are clipped to the image.
+ *   SFOC_COVER_TEMPLATE: per IP, ceil(m/32) tile rows from the template's
+ *     first row by the tile columns it spans, in IP order (what
+ *     sfoc_register_cps describes, which also repeats a tile two IPs share);
+ *   SFOC_COVER_GRID: the tiles of the image's 32-grid that templates touch,
+ *     row-major;
+ *   SFOC_COVER_SMALLER: the shorter of the two (the template list on a
+ *     tie), what a sparse plan describes.
+ * The distinct tiles go to origins as (row, column) pairs, at most cap of
+ * them (origins may be null when cap is 0); returns the number of distinct
+ * tiles, or a negative status (SFOC_E_INVALID_ARG for an unknown cover).
  */
+#define SFOC_COVER_TEMPLATE 0
+#define SFOC_COVER_GRID     1
+#define SFOC_COVER_SMALLER  2
 int sfoc_match_candidates(int32_t m, int32_t r, int32_t* fft_side, int32_t* blocks, int32_t cap);
 int64_t sfoc_sensed_tiles(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m, int32_t r,
-                          int64_t Hs, int64_t Ws, int64_t Hr, int64_t Wr, uint8_t* mask);
+                          int64_t Hs, int64_t Ws, int64_t Hr, int64_t Wr, int32_t cover, int32_t* origins,
+                          int64_t cap);
 
 /*
  * Learned CP-validity and sub-pixel head (not part of the paper).  It reads

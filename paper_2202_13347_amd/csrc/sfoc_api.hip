@@ -5,6 +5,7 @@
 #include <map>
 #include <mutex>
 #include <utility>
+#include <vector>
 
 #include "sfoc_launch.h"
 
@@ -37,7 +38,7 @@ hipError_t ensure_dynamic_lds(const void* kern, int bytes) {
 // for the life of the process; default priority, non-blocking.
 struct SideStream {
     hipStream_t s = nullptr;
-    hipEvent_t start = nullptr, mask = nullptr, fork = nullptr, join = nullptr;
+    hipEvent_t start = nullptr, tiles = nullptr, fork = nullptr, join = nullptr;
 };
 
 static hipError_t side_stream(SideStream** out) {
@@ -50,7 +51,7 @@ static hipError_t side_stream(SideStream** out) {
         SideStream t;
         e = hipStreamCreateWithFlags(&t.s, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&t.start, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&t.mask, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&t.tiles, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&t.fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&t.join, hipEventDisableTiming);
         if (e != hipSuccess) return e;
@@ -61,11 +62,11 @@ static hipError_t side_stream(SideStream** out) {
 }
 
 struct RegisterLayout {
-    size_t desc_ref, desc_sen, integ1, integ2, scan, mask, match, total;
+    size_t desc_ref, desc_sen, integ1, integ2, scan, tiles, match, total;
 };
 
-static RegisterLayout register_layout(int64_t Hr, int64_t Wr, int64_t Hs, int64_t Ws, int32_t z, size_t es,
-                                      size_t match_ws) {
+static RegisterLayout register_layout(int64_t Hr, int64_t Wr, int64_t Hs, int64_t Ws, int32_t n, int32_t m,
+                                      int32_t z, size_t es, size_t match_ws) {
     RegisterLayout L;
     size_t off = 0;
     L.desc_ref = off;
@@ -78,8 +79,8 @@ static RegisterLayout register_layout(int64_t Hr, int64_t Wr, int64_t Hs, int64_
     off = align_up(off + (size_t)(Hr + 1) * (Wr + 1) * sizeof(double), 256);
     L.scan = off;
     off = align_up(off + describe_ws_bytes(Hr, Wr), 256);
-    L.mask = off;
-    off = align_up(off + tile_mask_bytes(Hs, Ws), 256);
+    L.tiles = off;
+    off = align_up(off + (size_t)n * template_tile_slots(m, kDescribeTile) * 16, 256);
     L.match = off;
     off = align_up(off + match_ws, 256);
     L.total = off;
@@ -211,7 +212,7 @@ int sfoc_register_workspace(int64_t Hr, int64_t Wr, int64_t Hs, int64_t Ws, int3
     if (rc) return rc;
     rc = check_match_shape(n, m, r);
     if (rc) return rc;
-    *bytes = register_layout(Hr, Wr, Hs, Ws, z, dtype_size(p->desc_dtype), match_plan(n, m, r).ws_bytes).total;
+    *bytes = register_layout(Hr, Wr, Hs, Ws, n, m, z, dtype_size(p->desc_dtype), match_plan(n, m, r).ws_bytes).total;
     return SFOC_OK;
 }
 
@@ -230,7 +231,10 @@ int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr, con
     if (rc) return rc;
     if (Hs * Ws >= kMaxPlane || Hr * Wr >= kMaxPlane) return SFOC_E_UNSUPPORTED;
     if (n > 0 && (!ips || !cps)) return SFOC_E_INVALID_ARG;
-    const RegisterLayout L = register_layout(Hr, Wr, Hs, Ws, z, dtype_size(p->desc_dtype), match_plan(n, m, r).ws_bytes);
+    const int64_t ntiles = (int64_t)n * template_tile_slots(m, kDescribeTile);
+    if (ntiles > INT32_MAX) return SFOC_E_UNSUPPORTED;
+    const RegisterLayout L =
+        register_layout(Hr, Wr, Hs, Ws, n, m, z, dtype_size(p->desc_dtype), match_plan(n, m, r).ws_bytes);
     if (!ws || ws_bytes < L.total) return SFOC_E_WORKSPACE;
     char* base = (char*)ws;
     void* dref = base + L.desc_ref;
@@ -240,26 +244,27 @@ int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr, con
     hipStream_t st = (hipStream_t)stream;
     DescribeConsts c;
     build_describe_consts(p, &c);
-    // Of the sensed image only the tiles under the templates are described;
-    // their mask is built on a second stream while the reference image is
-    // described.  The reference's integral scans (memory-bound) then run on
-    // that stream while the sensed image is described; the match waits for
-    // both.
+    // Of the sensed image only the tiles under the templates of in-bounds
+    // IPs are described, one table entry per template tile; the table is
+    // written on a second stream while the reference image is described.
+    // The reference's integral scans (memory-bound) then run on that stream
+    // while the sensed image is described; the match waits for both.
     SideStream* side = nullptr;
     hipError_t e = side_stream(&side);
     double* agg = (double*)(base + L.scan);
-    uint8_t* tmask = (uint8_t*)(base + L.mask);
+    int4* tiles = (int4*)(base + L.tiles);
     if (e == hipSuccess) e = hipEventRecord(side->start, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->start, 0);
-    if (e == hipSuccess) e = launch_tile_mask(ips, n, m, (int)Hs, (int)Ws, tmask, side->s);
-    if (e == hipSuccess) e = hipEventRecord(side->mask, side->s);
+    if (e == hipSuccess)
+        e = launch_template_tiles(ips, prior, n, m, r, (int)Hs, (int)Ws, (int)Hr, (int)Wr, tiles, side->s);
+    if (e == hipSuccess) e = hipEventRecord(side->tiles, side->s);
     if (e == hipSuccess) e = launch_describe(ref, (int)Hr, (int)Wr, ldr, dref, i1, i2, agg, c, st);
     if (e == hipSuccess) e = hipEventRecord(side->fork, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->fork, 0);
     if (e == hipSuccess) e = launch_integral(i1, i2, (int)Hr, (int)Wr, agg, side->s);
     if (e == hipSuccess) e = hipEventRecord(side->join, side->s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, side->mask, 0);
-    if (e == hipSuccess) e = launch_describe(sen, (int)Hs, (int)Ws, lds, dsen, nullptr, nullptr, nullptr, c, st, tmask);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, side->tiles, 0);
+    if (e == hipSuccess) e = launch_describe_tiles(sen, (int)Hs, (int)Ws, lds, dsen, tiles, (int)ntiles, c, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(st, side->join, 0);
     if (e != hipSuccess) return hip_status(e);
     if (n == 0) return SFOC_OK;
@@ -280,15 +285,18 @@ int sfoc_match_candidates(int32_t m, int32_t r, int32_t* fft_side, int32_t* bloc
 }
 
 int64_t sfoc_sensed_tiles(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m, int32_t r, int64_t Hs,
-                          int64_t Ws, int64_t Hr, int64_t Wr, uint8_t* mask) {
-    if (n < 0 || m < 3 || r < 1 || Hs < 1 || Ws < 1 || Hr < 1 || Wr < 1 || !mask || (n > 0 && !ips))
+                          int64_t Ws, int64_t Hr, int64_t Wr, int32_t cover, int32_t* origins, int64_t cap) {
+    if (n < 0 || m < 3 || r < 1 || Hs < 1 || Ws < 1 || Hr < 1 || Wr < 1 || cap < 0 || (cap > 0 && !origins) ||
+        (n > 0 && !ips) || cover < kCoverTemplate || cover > kCoverSmaller)
         return SFOC_E_INVALID_ARG;
     if (Hs > kMaxSide || Ws > kMaxSide) return SFOC_E_UNSUPPORTED;
-    sensed_tile_mask(ips, prior, n, m, r, Hs, Ws, Hr, Wr, kDescribeTile, mask);
-    const int64_t nt = ((Hs + kDescribeTile - 1) / kDescribeTile) * ((Ws + kDescribeTile - 1) / kDescribeTile);
-    int64_t c = 0;
-    for (int64_t k = 0; k < nt; ++k) c += mask[k];
-    return c;
+    std::vector<std::pair<int, int>> t;
+    sensed_tiles(ips, prior, n, m, r, Hs, Ws, Hr, Wr, kDescribeTile, cover, t);
+    for (size_t k = 0; k < t.size() && (int64_t)k < cap; ++k) {
+        origins[2 * k] = t[k].first;
+        origins[2 * k + 1] = t[k].second;
+    }
+    return (int64_t)t.size();
 }
 
 }  // extern "C"

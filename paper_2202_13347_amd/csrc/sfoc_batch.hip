@@ -288,7 +288,7 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     const int T = kDescribeTile;
     std::vector<DescribeJob> djobs(2 * (size_t)n_pairs);
     std::vector<int4> dtiles;
-    std::vector<uint8_t> mask;
+    std::vector<std::pair<int, int>> sens;
     for (int k = 0; k < n_pairs; ++k) {   // reference tiles first
         const sfoc_pair& q = pairs[k];
         const int ntyr = (int)((q.Hr + T - 1) / T), ntxr = (int)((q.Wr + T - 1) / T);
@@ -298,16 +298,18 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     const int nref_tiles = (int)dtiles.size();
     for (int k = 0; k < n_pairs; ++k) {
         const sfoc_pair& q = pairs[k];
-        const int ntys = (int)((q.Hs + T - 1) / T), ntxs = (int)((q.Ws + T - 1) / T);
-        if (sparse) {
-            mask.assign((size_t)ntys * ntxs, 0);
+        if (sparse) {   // the tiles over the templates of in-bounds IPs
             if (q.n > 0)
-                sensed_tile_mask(hips[k].data(), q.prior ? hprior[k].data() : nullptr, q.n, q.m, q.r, q.Hs, q.Ws,
-                                 q.Hr, q.Wr, T, mask.data());
+                sensed_tiles(hips[k].data(), q.prior ? hprior[k].data() : nullptr, q.n, q.m, q.r, q.Hs, q.Ws, q.Hr,
+                             q.Wr, T, kCoverSmaller, sens);
+            else
+                sens.clear();
+            for (const auto& o : sens) dtiles.push_back(make_int4(2 * k + 1, o.first, o.second, 0));
+            continue;
         }
+        const int ntys = (int)((q.Hs + T - 1) / T), ntxs = (int)((q.Ws + T - 1) / T);
         for (int a = 0; a < ntys; ++a)
-            for (int b = 0; b < ntxs; ++b)
-                if (!sparse || mask[(size_t)a * ntxs + b]) dtiles.push_back(make_int4(2 * k + 1, a * T, b * T, 0));
+            for (int b = 0; b < ntxs; ++b) dtiles.push_back(make_int4(2 * k + 1, a * T, b * T, 0));
     }
 
     // ---- memory: per pair descriptors, integrals, scan scratch, match scratch ----

@@ -225,8 +225,7 @@ constexpr int describe_cg() { return VAR ? 1 : (FAST ? 2 : (Z >= 4 ? 4 : Z)); }
 template <int Z, int CG, bool FAST, int VAR>
 __global__ __launch_bounds__(kNT, (describe_wpc<Z, FAST, VAR>())) void describe_kernel(const DescribeJob single,
                                                           const DescribeJob* __restrict__ jobs,
-                                                          const int4* __restrict__ tiles,
-                                                          const uint8_t* __restrict__ tmask, const DescribeConsts C,
+                                                          const int4* __restrict__ tiles, const DescribeConsts C,
                                                           int BSP_, int ISX, int BPP_, int IPP) {
     extern __shared__ float lds[];
     const int t = threadIdx.x;
@@ -239,13 +238,15 @@ __global__ __launch_bounds__(kNT, (describe_wpc<Z, FAST, VAR>())) void describe_
     const int id = (int)(blockIdx.y * gridDim.x + blockIdx.x);
     const int k = id < q8 ? (id % 8) * (q8 / 8) + id / 8 : id;
     if (tiles) {
+        // entries: {job, tile row origin, tile column origin}; without a job
+        // table every entry is of `single`, and a negative job is an empty
+        // slot that the whole workgroup skips
         const int4 e = tiles[k];
-        J = load_table(jobs, e.x);
+        if (e.x < 0) return;
+        J = jobs ? load_table(jobs, e.x) : single;
         ty0 = e.y;
         tx0 = e.z;
     } else {
-        // a tile that nothing reads is skipped by the whole workgroup
-        if (tmask && !tmask[k]) return;
         J = single;
         ty0 = (k / gridDim.x) * kTS;
         tx0 = (k % gridDim.x) * kTS;
@@ -886,7 +887,7 @@ __global__ __launch_bounds__(kScanNT) void integral_tiles(const IntegJob single,
 // ---- launch -------------------------------------------------------------
 template <int Z, bool FAST, int VAR>
 static hipError_t launch_describe_zf(const DescribeJob& job, const DescribeJob* jobs, const int4* tiles, int ntiles,
-                                     const uint8_t* tmask, const DescribeConsts& c, hipStream_t st) {
+                                     const DescribeConsts& c, hipStream_t st) {
     constexpr int CG = describe_cg<Z, FAST, VAR>();
     const DescribeGeom g = describe_geom(c, CG, VAR == 1);
     dim3 grid = tiles ? dim3(ntiles) : dim3((job.W + kTS - 1) / kTS, (job.H + kTS - 1) / kTS);
@@ -895,7 +896,7 @@ static hipError_t launch_describe_zf(const DescribeJob& job, const DescribeJob* 
     hipError_t e = ensure_dynamic_lds((const void*)kern, (int)g.bytes);
     if (e != hipSuccess) return e;
     trace_begin(st, SFOC_K_DESCRIBE);
-    hipLaunchKernelGGL(kern, grid, dim3(kNT), g.bytes, st, job, jobs, tiles, tmask, c, g.BSP, g.ISX, g.BPP, g.IPP);
+    hipLaunchKernelGGL(kern, grid, dim3(kNT), g.bytes, st, job, jobs, tiles, c, g.BSP, g.ISX, g.BPP, g.IPP);
     trace_end(st, SFOC_K_DESCRIBE);
     return hipGetLastError();
 }
@@ -910,25 +911,25 @@ int describe_configs(const DescribeConsts& c) { return describe_fast(c) && c.z <
 
 template <int Z>
 static hipError_t launch_describe_z(const DescribeJob& job, const DescribeJob* jobs, const int4* tiles, int ntiles,
-                                    const uint8_t* tmask, const DescribeConsts& c, hipStream_t st, int var) {
-    if (!describe_fast(c)) return launch_describe_zf<Z, false, 0>(job, jobs, tiles, ntiles, tmask, c, st);
+                                    const DescribeConsts& c, hipStream_t st, int var) {
+    if (!describe_fast(c)) return launch_describe_zf<Z, false, 0>(job, jobs, tiles, ntiles, c, st);
     if constexpr (Z <= 16 && Z % 2 == 0)
-        if (var == 1) return launch_describe_zf<Z, true, 1>(job, jobs, tiles, ntiles, tmask, c, st);
-    return launch_describe_zf<Z, true, 0>(job, jobs, tiles, ntiles, tmask, c, st);
+        if (var == 1) return launch_describe_zf<Z, true, 1>(job, jobs, tiles, ntiles, c, st);
+    return launch_describe_zf<Z, true, 0>(job, jobs, tiles, ntiles, c, st);
 }
 
 static hipError_t launch_describe_any(const DescribeJob& job, const DescribeJob* jobs, const int4* tiles, int ntiles,
-                                      const uint8_t* tmask, const DescribeConsts& c, hipStream_t st, int var) {
+                                      const DescribeConsts& c, hipStream_t st, int var) {
     switch (c.z) {
-        case 2: return launch_describe_z<2>(job, jobs, tiles, ntiles, tmask, c, st, var);
-        case 3: return launch_describe_z<3>(job, jobs, tiles, ntiles, tmask, c, st, var);
-        case 4: return launch_describe_z<4>(job, jobs, tiles, ntiles, tmask, c, st, var);
-        case 6: return launch_describe_z<6>(job, jobs, tiles, ntiles, tmask, c, st, var);
-        case 8: return launch_describe_z<8>(job, jobs, tiles, ntiles, tmask, c, st, var);
-        case 12: return launch_describe_z<12>(job, jobs, tiles, ntiles, tmask, c, st, var);
-        case 16: return launch_describe_z<16>(job, jobs, tiles, ntiles, tmask, c, st, var);
-        case 24: return launch_describe_z<24>(job, jobs, tiles, ntiles, tmask, c, st, var);
-        case 32: return launch_describe_z<32>(job, jobs, tiles, ntiles, tmask, c, st, var);
+        case 2: return launch_describe_z<2>(job, jobs, tiles, ntiles, c, st, var);
+        case 3: return launch_describe_z<3>(job, jobs, tiles, ntiles, c, st, var);
+        case 4: return launch_describe_z<4>(job, jobs, tiles, ntiles, c, st, var);
+        case 6: return launch_describe_z<6>(job, jobs, tiles, ntiles, c, st, var);
+        case 8: return launch_describe_z<8>(job, jobs, tiles, ntiles, c, st, var);
+        case 12: return launch_describe_z<12>(job, jobs, tiles, ntiles, c, st, var);
+        case 16: return launch_describe_z<16>(job, jobs, tiles, ntiles, c, st, var);
+        case 24: return launch_describe_z<24>(job, jobs, tiles, ntiles, c, st, var);
+        case 32: return launch_describe_z<32>(job, jobs, tiles, ntiles, c, st, var);
         default: return hipErrorInvalidValue;
     }
 }
@@ -937,44 +938,48 @@ static hipError_t launch_describe_any(const DescribeJob& job, const DescribeJob*
 hipError_t launch_describe_batched(const DescribeJob* jobs, const int4* tiles, int ntiles, const DescribeConsts& c,
                                    hipStream_t st, int var) {
     DescribeJob none{};
-    return launch_describe_any(none, jobs, tiles, ntiles, nullptr, c, st, var);
+    return launch_describe_any(none, jobs, tiles, ntiles, c, st, var);
 }
 
 hipError_t launch_describe(const float* img, int H, int W, int64_t ld, void* desc, double* i1, double* i2,
-                           double* agg, const DescribeConsts& c, hipStream_t st, const uint8_t* tmask) {
+                           double* agg, const DescribeConsts& c, hipStream_t st) {
     DescribeJob job{img, desc, i1, i2, agg, ld, H, W};
-    return launch_describe_any(job, nullptr, nullptr, 0, tmask, c, st, 0);
+    return launch_describe_any(job, nullptr, nullptr, 0, c, st, 0);
 }
 
-// ---- the sensed tiles that templates read ----------------------------------
-// One byte per describe tile of an H x W sensed image (row-major over the
-// tile grid): 1 where some IP's m x m template (top-left at the IP minus
-// m / 2, clipped to the image) meets the tile.  A first launch clears the
-// mask, a second marks every IP's tiles; concurrent marks write the same
-// value.  Marking also the tiles of IPs whose search window leaves the
-// reference only describes tiles that no one reads.
-__global__ __launch_bounds__(256) void tile_mask_clear(uint8_t* __restrict__ mask, int nt) {
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    if (k < nt) mask[k] = 0;
+hipError_t launch_describe_tiles(const float* img, int H, int W, int64_t ld, void* desc, const int4* tiles,
+                                 int ntiles, const DescribeConsts& c, hipStream_t st) {
+    if (ntiles == 0) return hipSuccess;
+    DescribeJob job{img, desc, nullptr, nullptr, nullptr, ld, H, W};
+    return launch_describe_any(job, nullptr, tiles, ntiles, c, st, 0);
 }
 
-__global__ __launch_bounds__(256) void tile_mask_mark(const int32_t* __restrict__ ips, int n, int m, int H, int W,
-                                                      uint8_t* __restrict__ mask) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const int ntx = (W + kTS - 1) / kTS;
-    const int64_t ty = (int64_t)ips[2 * i] - m / 2, tx = (int64_t)ips[2 * i + 1] - m / 2;
-    const int64_t y0 = ty < 0 ? 0 : ty, x0 = tx < 0 ? 0 : tx;
-    const int64_t y1 = ty + m - 1 < H - 1 ? ty + m - 1 : H - 1, x1 = tx + m - 1 < W - 1 ? tx + m - 1 : W - 1;
-    if (y0 > y1 || x0 > x1) return;
-    for (int64_t a = y0 / kTS; a <= y1 / kTS; ++a)
-        for (int64_t b = x0 / kTS; b <= x1 / kTS; ++b) mask[a * ntx + b] = 1;
+// ---- template-aligned sensed tiles ------------------------------------------
+// Slot (i, a, c) of the table, i < n, a < ceil(m / T), c < ceil(m / T) + 1:
+// the tile of IP i's template with rows from the template's row a * T and
+// columns of grid tile c0 + c, or an empty slot (job -1) where the IP reads
+// nothing or its template spans fewer tile columns (template_tile_range).
+// Two IPs may name the same tile: both describe it, with equal results.
+__global__ __launch_bounds__(256) void template_tiles_kernel(const int32_t* __restrict__ ips,
+                                                             const int32_t* __restrict__ prior, int n, int m, int r,
+                                                             int Hs, int Ws, int Hr, int Wr, int4* __restrict__ tiles) {
+    const int S = template_tile_slots(m, kTS), CT = template_tile_rows(m, kTS) + 1;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)n * S) return;
+    const int i = (int)(e / S), s = (int)(e - (int64_t)i * S), a = s / CT, c = s - a * CT;
+    int64_t ty, c0, c1;
+    const bool in = template_tile_range(ips[2 * i], ips[2 * i + 1], prior ? prior[2 * i] : 0,
+                                        prior ? prior[2 * i + 1] : 0, m, r, Hs, Ws, Hr, Wr, kTS, &ty, &c0, &c1);
+    tiles[e] = in && c0 + c <= c1 ? make_int4(0, (int)(ty + (int64_t)a * kTS), (int)((c0 + c) * kTS), 0)
+                                  : make_int4(-1, 0, 0, 0);
 }
 
-hipError_t launch_tile_mask(const int32_t* ips, int n, int m, int H, int W, uint8_t* mask, hipStream_t st) {
-    const int nt = ((H + kTS - 1) / kTS) * ((W + kTS - 1) / kTS);
-    hipLaunchKernelGGL(tile_mask_clear, dim3((nt + 255) / 256), dim3(256), 0, st, mask, nt);
-    if (n > 0) hipLaunchKernelGGL(tile_mask_mark, dim3((n + 255) / 256), dim3(256), 0, st, ips, n, m, H, W, mask);
+hipError_t launch_template_tiles(const int32_t* ips, const int32_t* prior, int n, int m, int r, int Hs, int Ws,
+                                 int Hr, int Wr, int4* tiles, hipStream_t st) {
+    const int64_t cnt = (int64_t)n * template_tile_slots(m, kTS);
+    if (cnt == 0) return hipSuccess;
+    hipLaunchKernelGGL(template_tiles_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, ips, prior, n, m,
+                       r, Hs, Ws, Hr, Wr, tiles);
     return hipGetLastError();
 }
 

@@ -64,14 +64,17 @@ hipError_t ensure_dynamic_lds(const void* kern, int bytes);
 
 // ---- one image / one pair ------------------------------------------------
 // i1, i2 and agg (the aggregates, describe_ws_bytes) all null, or all set.
-// tmask (device, one byte per tile, row-major over the tile grid) limits the
-// launch to the tiles whose byte is nonzero; null describes every tile.
 hipError_t launch_describe(const float* img, int H, int W, int64_t ld, void* desc, double* i1, double* i2,
-                           double* agg, const DescribeConsts& c, hipStream_t st, const uint8_t* tmask = nullptr);
-// Writes into mask (tile_mask_bytes(H, W) device bytes) which describe tiles
-// of an H x W sensed image the m x m templates of the n IPs (device, (row,
-// col) pairs) read.
-hipError_t launch_tile_mask(const int32_t* ips, int n, int m, int H, int W, uint8_t* mask, hipStream_t st);
+                           double* agg, const DescribeConsts& c, hipStream_t st);
+// The tiles of one image that a device table lists ({0, row origin, column
+// origin, 0}; entries with a negative first field are skipped), without
+// integral-image inputs.
+hipError_t launch_describe_tiles(const float* img, int H, int W, int64_t ld, void* desc, const int4* tiles,
+                                 int ntiles, const DescribeConsts& c, hipStream_t st);
+// Writes the template-aligned sensed tiles of n IPs (device arrays) into
+// tiles: n * template_tile_slots(m, kDescribeTile) entries.
+hipError_t launch_template_tiles(const int32_t* ips, const int32_t* prior, int n, int m, int r, int Hs, int Ws,
+                                 int Hr, int Wr, int4* tiles, hipStream_t st);
 // Completes the integral images from what launch_describe left in i1, i2
 // and agg (the same buffers).
 hipError_t launch_integral(double* i1, double* i2, int H, int W, double* agg, hipStream_t st);

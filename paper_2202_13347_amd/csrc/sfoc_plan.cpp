@@ -7,6 +7,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <set>
+
 namespace sfoc {
 
 static int radius_of(double s, double trunc) { return (int)ceil(trunc * s - 1e-9); }
@@ -149,11 +151,6 @@ size_t describe_ws_bytes(int64_t H, int64_t W) {
     return align_up((size_t)integ_agg(H, W).total * sizeof(double), 256);
 }
 
-size_t tile_mask_bytes(int64_t H, int64_t W) {
-    const IntegAgg g = integ_agg(H, W);
-    return align_up((size_t)(g.ntx * g.nty), 256);
-}
-
 MatchPlan match_plan_L(int32_t n, int32_t m, int32_t r, int L) {
     MatchPlan p{0, 1, 0, 0};
     if (m < 3 || m > kMaxTemplate || r < 1 || r > kMaxRadiusMatch || n < 0 || side_index(L) < 0) return p;
@@ -277,19 +274,34 @@ int tune_cache_lookup(const TuneCache& cache, const std::string& dev, int z, int
     return it->second;
 }
 
-void sensed_tile_mask(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m, int32_t r, int64_t Hs,
-                      int64_t Ws, int64_t Hr, int64_t Wr, int kTile, uint8_t* mask) {
-    const int64_t ntx = (Ws + kTile - 1) / kTile, nty = (Hs + kTile - 1) / kTile;
-    memset(mask, 0, (size_t)(ntx * nty));
-    const int64_t M = (int64_t)m + 2 * r;
-    for (int32_t i = 0; i < n; ++i) {
-        const int64_t ty = (int64_t)ips[2 * i] - m / 2, tx = (int64_t)ips[2 * i + 1] - m / 2;
-        const int64_t sy = ty - r + (prior ? prior[2 * i] : 0), sx = tx - r + (prior ? prior[2 * i + 1] : 0);
-        if (ty < 0 || tx < 0 || ty + m > Hs || tx + m > Ws) continue;
-        if (sy < 0 || sx < 0 || sy + M > Hr || sx + M > Wr) continue;
-        for (int64_t a = ty / kTile; a <= (ty + m - 1) / kTile; ++a)
-            for (int64_t b = tx / kTile; b <= (tx + m - 1) / kTile; ++b) mask[a * ntx + b] = 1;
+void sensed_tiles(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m, int32_t r, int64_t Hs,
+                  int64_t Ws, int64_t Hr, int64_t Wr, int T, int cover, std::vector<std::pair<int, int>>& out) {
+    out.clear();
+    if (cover == kCoverSmaller) {
+        std::vector<std::pair<int, int>> g;
+        sensed_tiles(ips, prior, n, m, r, Hs, Ws, Hr, Wr, T, kCoverTemplate, out);
+        sensed_tiles(ips, prior, n, m, r, Hs, Ws, Hr, Wr, T, kCoverGrid, g);
+        if (g.size() < out.size()) out.swap(g);
+        return;
     }
+    std::set<std::pair<int, int>> seen;
+    for (int32_t i = 0; i < n; ++i) {
+        int64_t ty, c0, c1;
+        if (!template_tile_range(ips[2 * i], ips[2 * i + 1], prior ? prior[2 * i] : 0, prior ? prior[2 * i + 1] : 0,
+                                 m, r, Hs, Ws, Hr, Wr, T, &ty, &c0, &c1))
+            continue;
+        if (cover == kCoverGrid) {
+            for (int64_t a = ty / T; a <= (ty + m - 1) / T; ++a)
+                for (int64_t c = c0; c <= c1; ++c) seen.insert(std::pair<int, int>((int)(a * T), (int)(c * T)));
+            continue;
+        }
+        for (int a = 0; a < template_tile_rows(m, T); ++a)
+            for (int64_t c = c0; c <= c1; ++c) {
+                const std::pair<int, int> o((int)(ty + (int64_t)a * T), (int)(c * T));
+                if (seen.insert(o).second) out.push_back(o);
+            }
+    }
+    if (cover == kCoverGrid) out.assign(seen.begin(), seen.end());   // row-major
 }
 
 }  // namespace sfoc

@@ -7,6 +7,8 @@
 
 #include <map>
 #include <string>
+#include <utility>
+#include <vector>
 #include <tuple>
 
 #include "sfoc.h"
@@ -81,8 +83,6 @@ inline SFOC_HOST_DEVICE IntegAgg integ_agg(int64_t H, int64_t W) {
 // Bytes of the aggregates (the describe workspace when integral images are
 // asked for): 2 (ntx H + nty W + nty ntx) doubles, about 1 byte per pixel.
 size_t describe_ws_bytes(int64_t H, int64_t W);
-// Bytes of a describe tile mask of an H x W image: one per tile.
-size_t tile_mask_bytes(int64_t H, int64_t W);
 // Size of the library-owned aggregate array of sfoc_describe_noalloc.
 constexpr size_t kNoAllocScratchBytes = SFOC_NOALLOC_SCRATCH_BYTES;
 
@@ -139,12 +139,38 @@ bool tune_cache_write(const char* path, const TuneCache& cache);
 // candidate for (m, r) (the caller then times the class or takes the default).
 int tune_cache_lookup(const TuneCache& cache, const std::string& dev, int z, int dtype, int m, int r);
 
-// Sensed-image describe tiles (side kTile) that the templates of in-bounds
-// interest points read: mask[ty * ceil(Ws / kTile) + tx] = 1.  An IP whose
-// template or search window leaves its image reads nothing (it is flagged
-// out of bounds).  ips / prior are host arrays (prior may be null).
-void sensed_tile_mask(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m, int32_t r, int64_t Hs,
-                      int64_t Ws, int64_t Hr, int64_t Wr, int kTile, uint8_t* mask);
+// Template-aligned sensed tiles: the describe tiles that cover one IP's
+// m x m template, with tile rows starting at the template's first row and
+// tile columns on the image's tile grid (so every descriptor row segment a
+// tile stores stays aligned).  ceil(m / T) rows of tiles by at most
+// ceil(m / T) + 1 columns.  An IP whose template or search window leaves its
+// image reads nothing (it is flagged out of bounds) and gets no tiles.
+// Returns false then; else the template's first row ty and the first and
+// last tile columns c0, c1 (in tiles).
+inline SFOC_HOST_DEVICE int template_tile_rows(int m, int T) { return (m + T - 1) / T; }
+inline SFOC_HOST_DEVICE int template_tile_slots(int m, int T) { return ((m + T - 1) / T) * ((m + T - 1) / T + 1); }
+inline SFOC_HOST_DEVICE bool template_tile_range(int py, int px, int pry, int prx, int m, int r, int64_t Hs,
+                                                 int64_t Ws, int64_t Hr, int64_t Wr, int T, int64_t* ty, int64_t* c0,
+                                                 int64_t* c1) {
+    const int64_t M = (int64_t)m + 2 * r;
+    const int64_t y = (int64_t)py - m / 2, x = (int64_t)px - m / 2;
+    const int64_t sy = y - r + pry, sx = x - r + prx;
+    if (y < 0 || x < 0 || y + m > Hs || x + m > Ws) return false;
+    if (sy < 0 || sx < 0 || sy + M > Hr || sx + M > Wr) return false;
+    *ty = y;
+    *c0 = x / T;
+    *c1 = (x + m - 1) / T;
+    return true;
+}
+// Sensed tiles of all in-bounds IPs (host arrays; prior may be null) as
+// distinct (first row, first column) origins.  kCoverTemplate: each IP's
+// template-aligned tiles, in IP order (what the pair call describes, but
+// without its repeats); kCoverGrid: the tiles of the image's tile grid that
+// the templates touch, row-major; kCoverSmaller: the shorter of the two lists
+// (the template one on a tie).
+constexpr int kCoverTemplate = SFOC_COVER_TEMPLATE, kCoverGrid = SFOC_COVER_GRID, kCoverSmaller = SFOC_COVER_SMALLER;
+void sensed_tiles(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m, int32_t r, int64_t Hs,
+                  int64_t Ws, int64_t Hr, int64_t Wr, int T, int cover, std::vector<std::pair<int, int>>& out);
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 

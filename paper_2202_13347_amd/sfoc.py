@@ -122,7 +122,7 @@ def lib() -> ctypes.CDLL:
         L.sfoc_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo), ctypes.POINTER(i32), ctypes.POINTER(i32),
                                          i32]
         L.sfoc_match_candidates.argtypes = [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), i32]
-        L.sfoc_sensed_tiles.argtypes = [vp, vp, i32, i32, i32, i64, i64, i64, i64, vp]
+        L.sfoc_sensed_tiles.argtypes = [vp, vp, i32, i32, i32, i64, i64, i64, i64, i32, vp, i64]
         L.sfoc_sensed_tiles.restype = i64
         f32p = ctypes.c_void_p
         L.sfoc_head_features.argtypes = [vp, i64, i64, vp, vp, i64, i64, i32, i32, vp, vp, i32, i32, i32, vp, vp,
@@ -421,17 +421,26 @@ def match_candidates(m: int, r: int) -> list[tuple[int, int]]:
     return [(L[i], nb[i]) for i in range(k)]
 
 
-def sensed_tiles(ips: np.ndarray, m: int, r: int, Hs: int, Ws: int, Hr: int, Wr: int, prior=None) -> np.ndarray:
-    """(ceil(Hs/32), ceil(Ws/32)) uint8 mask of the describe tiles that
-    in-bounds templates read (host arrays, no device work)."""
-    ips = np.ascontiguousarray(ips, dtype=np.int32)
+COVER_TEMPLATE, COVER_GRID, COVER_SMALLER = 0, 1, 2
+
+
+def sensed_tiles(ips: np.ndarray, m: int, r: int, Hs: int, Ws: int, Hr: int, Wr: int, prior=None,
+                 cover: int = COVER_TEMPLATE) -> np.ndarray:
+    """(k, 2) int32 (row, column) origins of the distinct 32 x 32
+    sensed-image tiles over the templates of the in-bounds IPs (host
+    arrays, no device work): COVER_TEMPLATE, each IP's template-aligned
+    tiles (the pair call); COVER_GRID, the image-grid tiles the templates
+    touch; COVER_SMALLER, the shorter list (sparse plans)."""
+    ips = np.ascontiguousarray(ips, dtype=np.int32).reshape(-1, 2)
     pr = None if prior is None else np.ascontiguousarray(prior, dtype=np.int32)
-    mask = np.zeros(((Hs + 31) // 32, (Ws + 31) // 32), dtype=np.uint8)
+    k = (m + 31) // 32
+    cap = len(ips) * max(k * (k + 1), (k + 1) * (k + 1))
+    out = np.zeros((cap, 2), dtype=np.int32)
     c = lib().sfoc_sensed_tiles(ips.ctypes.data, None if pr is None else pr.ctypes.data, len(ips), m, r, Hs, Ws,
-                                Hr, Wr, mask.ctypes.data)
+                                Hr, Wr, cover, out.ctypes.data if cap else None, cap)
     if c < 0:
         raise SfocError(int(c), "sfoc_sensed_tiles")
-    return mask
+    return out[:c]
 
 
 HEAD_PARAMS, HEAD_CROP, HEAD_NSTAT = 54051, 33, 8

@@ -1,5 +1,5 @@
 """Host-side logic of batched plans (no GPU): struct layouts, transform-side
-candidates, the sensed-tile cover and argument rejection in
+candidates, the sensed tiles and argument rejection in
 sfoc_plan_create."""
 import ctypes
 import math
@@ -97,35 +97,100 @@ def test_match_candidates_unsupported():
     assert S.match_candidates(30, 512) == []   # r > 511
 
 
-def _brute_tiles(ips, prior, m, r, Hs, Ws, Hr, Wr):
-    mask = np.zeros(((Hs + 31) // 32, (Ws + 31) // 32), dtype=np.uint8)
+def _in_bounds(ips, prior, m, r, Hs, Ws, Hr, Wr):
+    """Top-left corners of the templates of the IPs whose template and
+    search window stay inside their images."""
     M = m + 2 * r
+    out = []
     for i, (y, x) in enumerate(ips):
-        ty, tx = y - m // 2, x - m // 2
+        ty, tx = int(y) - m // 2, int(x) - m // 2
         py, px = (prior[i] if prior is not None else (0, 0))
-        sy, sx = ty - r + py, tx - r + px
+        sy, sx = ty - r + int(py), tx - r + int(px)
         if ty < 0 or tx < 0 or ty + m > Hs or tx + m > Ws:
             continue
         if sy < 0 or sx < 0 or sy + M > Hr or sx + M > Wr:
             continue
-        for yy in range(ty, ty + m):
-            for xx in range(tx, tx + m):
-                mask[yy // 32, xx // 32] = 1
-    return mask
+        out.append((ty, tx))
+    return out
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2])
-def test_sensed_tiles_match_brute_force(seed):
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_sensed_tiles_cover_the_templates(seed):
     rng = np.random.default_rng(seed)
     Hs, Ws = int(rng.integers(100, 300)), int(rng.integers(100, 300))
     Hr, Wr = int(rng.integers(100, 300)), int(rng.integers(100, 300))
-    m, r = int(rng.integers(3, 40)), int(rng.integers(1, 20))
+    m, r = int(rng.integers(3, 80)), int(rng.integers(1, 20))
     n = 40
     ips = np.stack([rng.integers(-10, Hs + 10, n), rng.integers(-10, Ws + 10, n)], 1).astype(np.int32)
     prior = rng.integers(-15, 16, (n, 2)).astype(np.int32) if seed else None
     got = S.sensed_tiles(ips, m, r, Hs, Ws, Hr, Wr, prior)
-    want = _brute_tiles(ips, prior, m, r, Hs, Ws, Hr, Wr)
-    np.testing.assert_array_equal(got, want)
+    tl = [tuple(map(int, t)) for t in got]
+    assert len(set(tl)) == len(tl)                                     # distinct
+    for (y, x) in tl:                                                   # inside, on the column grid
+        assert 0 <= y < Hs and 0 <= x < Ws and x % 32 == 0
+    # every template pixel of an in-bounds IP is described by some tile ...
+    cov = np.zeros((Hs, Ws), dtype=bool)
+    for (y, x) in tl:
+        cov[y:y + 32, x:x + 32] = True
+    need = np.zeros((Hs, Ws), dtype=bool)
+    tops = _in_bounds(ips, prior, m, r, Hs, Ws, Hr, Wr)
+    for (ty, tx) in tops:
+        need[ty:ty + m, tx:tx + m] = True
+    assert not (need & ~cov).any()
+    # ... and every tile starts on a row of some template's tile rows, over
+    # a tile column that template reads
+    for (y, x) in tl:
+        assert any((y - ty) % 32 == 0 and 0 <= y - ty < m and tx // 32 <= x // 32 <= (tx + m - 1) // 32
+                   for (ty, tx) in tops), (y, x)
+    # at most ceil(m/32) x (ceil(m/32) + 1) tiles per in-bounds IP
+    k = -(-m // 32)
+    assert len(tl) <= len(tops) * k * (k + 1)
+    if not tops:
+        assert len(tl) == 0
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_sensed_grid_tiles_match_brute_force(seed):
+    rng = np.random.default_rng(seed + 10)
+    Hs, Ws = int(rng.integers(100, 300)), int(rng.integers(100, 300))
+    Hr, Wr = int(rng.integers(100, 300)), int(rng.integers(100, 300))
+    m, r = int(rng.integers(3, 80)), int(rng.integers(1, 20))
+    n = 60
+    ips = np.stack([rng.integers(-10, Hs + 10, n), rng.integers(-10, Ws + 10, n)], 1).astype(np.int32)
+    prior = rng.integers(-15, 16, (n, 2)).astype(np.int32) if seed else None
+    # the grid cover: every 32-grid tile holding a template pixel, row-major
+    mask = np.zeros(((Hs + 31) // 32, (Ws + 31) // 32), dtype=bool)
+    for (ty, tx) in _in_bounds(ips, prior, m, r, Hs, Ws, Hr, Wr):
+        for yy in range(ty, ty + m):
+            for xx in range(tx, tx + m):
+                mask[yy // 32, xx // 32] = True
+    want = np.argwhere(mask) * 32
+    grid = S.sensed_tiles(ips, m, r, Hs, Ws, Hr, Wr, prior, S.COVER_GRID)
+    np.testing.assert_array_equal(grid, want)
+    tmpl = S.sensed_tiles(ips, m, r, Hs, Ws, Hr, Wr, prior, S.COVER_TEMPLATE)
+    small = S.sensed_tiles(ips, m, r, Hs, Ws, Hr, Wr, prior, S.COVER_SMALLER)
+    np.testing.assert_array_equal(small, grid if len(grid) < len(tmpl) else tmpl)
+
+
+def test_sensed_tiles_cover_choice():
+    # sparse IPs: each template's own tiles are fewer than the grid tiles it
+    # touches; dense IPs: neighbours share grid tiles
+    sparse = np.array([[100, 100], [300, 300]], np.int32)
+    assert len(S.sensed_tiles(sparse, 64, 8, 512, 512, 512, 512)) == 2 * 2 * 3
+    assert len(S.sensed_tiles(sparse, 64, 8, 512, 512, 512, 512, cover=S.COVER_GRID)) == 2 * 3 * 3
+    dense = np.array([[y, x] for y in range(100, 200, 4) for x in range(100, 200, 4)], np.int32)
+    g = S.sensed_tiles(dense, 64, 8, 512, 512, 512, 512, cover=S.COVER_GRID)
+    t = S.sensed_tiles(dense, 64, 8, 512, 512, 512, 512)
+    assert len(g) < len(t)
+    np.testing.assert_array_equal(S.sensed_tiles(dense, 64, 8, 512, 512, 512, 512, cover=S.COVER_SMALLER), g)
+
+
+def test_sensed_tiles_empty_and_errors():
+    assert S.sensed_tiles(np.zeros((0, 2), np.int32), 16, 4, 64, 64, 64, 64).shape == (0, 2)
+    with pytest.raises(S.SfocError):
+        S.sensed_tiles(np.zeros((1, 2), np.int32), 2, 4, 64, 64, 64, 64)
+    with pytest.raises(S.SfocError):
+        S.sensed_tiles(np.zeros((1, 2), np.int32), 16, 4, 64, 64, 64, 64, cover=3)
 
 
 def _pair(**kw):

@@ -129,7 +129,7 @@ def test_sparse_tiles_count():
         Hr, Wr = q["ref"].shape
         Hs, Ws = q["sen"].shape
         want += ((Hr + 31) // 32) * ((Wr + 31) // 32)
-        want += int(S.sensed_tiles(q["ips"], q["m"], q["r"], Hs, Ws, Hr, Wr, q["prior"]).sum())
+        want += len(S.sensed_tiles(q["ips"], q["m"], q["r"], Hs, Ws, Hr, Wr, q["prior"], S.COVER_SMALLER))
     assert plan.info()["describe_tiles"] == want
     plan.close()
 

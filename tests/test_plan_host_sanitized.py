@@ -93,10 +93,11 @@ int main(int argc, char** argv) {
             ips[i] = (int32_t)(rng() % 700) - 200;
             pri[i] = (int32_t)(rng() % 200) - 100;
         }
-        const int64_t nt = ((Hs + 31) / 32) * ((Ws + 31) / 32);
-        uint8_t* mask = (uint8_t*)malloc(nt);
-        sensed_tile_mask(ips, (t & 1) ? pri : nullptr, n, m, r, Hs, Ws, Hr, Wr, 32, mask);
-        free(mask);
+        std::vector<std::pair<int, int>> tiles;
+        sensed_tiles(ips, (t & 1) ? pri : nullptr, n, m, r, Hs, Ws, Hr, Wr, 32, t % 3, tiles);
+        if ((int64_t)tiles.size() > (int64_t)n * template_tile_slots(m, 32)) printf("too many tiles\n");
+        for (const auto& o : tiles)
+            if (o.first < 0 || o.first >= Hs || o.second < 0 || o.second >= Ws || o.second % 32) printf("bad tile\n");
         free(ips);
         free(pri);
     }
@@ -182,3 +183,4 @@ def test_planner_host_code(tmp_path, sanitize):
     assert plans[(2, 5)][0] == "0" and plans[(127, 1)][0] == "160" and plans[(30, 512)][0] == "0"
     assert plans[(1 << 30, 1 << 30)][0] == "0" and plans[(2000000000, 5)][0] == "0"
     assert got["tiles"] == [["ok"]]
+    assert "too" not in got and "bad" not in got
