@@ -311,12 +311,19 @@ typedef struct sfoc_pair {
     const int32_t* ips;         /* n x 2 (row, col) in the sensed image */
     const int32_t* prior;       /* n x 2 (dy, dx) or NULL */
     int32_t n, m, r;
-    int32_t fft_side;           /* 0: default / autotuned; 64, 128, 160, 192: forced */
+    int32_t fft_side;           /* 0: default / autotuned; 64, 128, 160, 192: forced;
+                                   SFOC_MATCH_DIRECT: the direct form, forced */
     float* ncc;                 /* n x (2r+1)^2 float32 surfaces or NULL (output) */
     sfoc_cp* cps;               /* n records (output) */
 } sfoc_pair;
 
 typedef struct sfoc_plan sfoc_plan;
+
+/* Pseudo transform side naming the direct form of the match: R_ST (Eq. 10)
+ * summed in space on the matrix cores rather than through the FFT.  For
+ * BFLOAT16 / FLOAT16 descriptors (exact operands, float32 accumulation),
+ * 2r + 1 <= 32 and m <= 64; SFOC_E_UNSUPPORTED otherwise. */
+#define SFOC_MATCH_DIRECT 1
 
 #define SFOC_PLAN_GRAPH       1
 #define SFOC_PLAN_AUTOTUNE    2
@@ -343,6 +350,7 @@ typedef struct sfoc_plan_info {
     int32_t graph;              /* 1 once a graph is captured */
     int32_t persistent[4];      /* those launches persistent (1) or one workgroup per item */
     int32_t describe_config;    /* describe launch configuration: 0, or 1 (four workgroups per CU) */
+    int32_t direct_items;       /* items of the direct-form launch (SFOC_MATCH_DIRECT) */
     int64_t device_bytes;
 } sfoc_plan_info;
 int sfoc_plan_get_info(const sfoc_plan* plan, sfoc_plan_info* info, int32_t* fft_side, int32_t* blocks,

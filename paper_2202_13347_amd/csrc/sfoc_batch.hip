@@ -37,12 +37,13 @@ struct sfoc_plan {
     int4* itiles = nullptr;   // integral tiles {job, tile row, tile column}
     int npre = 0, nitiles = 0;
     MatchArgs* margs = nullptr;
-    int4* items[kNumSides] = {};        // per transform side kSides[b]
-    int nitems[kNumSides] = {};
+    int4* items[kNumForms] = {};        // per launch form kForms[b]
+    int nitems[kNumForms] = {};
     int4* peak = nullptr;
     int npeak = 0;
-    int* counters = nullptr;            // work counters of the persistent launches (one per side)
-    bool persist[kNumSides] = {};       // persistent match launch per transform side
+    int* counters = nullptr;            // work counters of the persistent launches (one per form)
+    bool persist[kNumForms] = {};       // persistent match launch per transform side
+    DirLaunch dir{3, 1};                // size of the direct launch (largest over its pairs)
     int grid = 0;                       // CUs (a persistent grid has MINB workgroups per CU)
     hipStream_t side_stream = nullptr;   // second graph branch
     hipStream_t cap_stream = nullptr;    // capture happens here (the caller's may be the null stream)
@@ -69,7 +70,7 @@ struct Cursor {
     }
 };
 
-int bucket_of(int L) { return side_index(L); }
+int bucket_of(int L) { return form_index(L); }
 
 MatchArgs make_args(const sfoc_pair& q, const char* mem, const PairMem& pm, int32_t z, int32_t dtype,
                     const MatchPlan& mp) {
@@ -119,15 +120,16 @@ std::string device_key(int dev) {
 hipError_t enqueue_match(sfoc_plan* P, hipStream_t st) {
     hipError_t e = hipSuccess;
     bool big = false;
-    for (int b = 1; b < kNumSides; ++b) big = big || P->nitems[b] > 0;
+    for (int b = 1; b < kNumForms; ++b) big = big || P->nitems[b] > 0;
     const bool fork = P->nitems[0] > 0 && big;
     if (fork) {
         if ((e = hipEventRecord(P->ev_fork, st)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(P->side_stream, P->ev_fork, 0)) != hipSuccess) return e;
     }
-    for (int b = 0; b < kNumSides; ++b) {
-        e = launch_match_items(kSides[b], P->dtype, P->margs, P->items[b], P->nitems[b],
-                               P->persist[b] ? P->counters + b : nullptr, P->grid, b == 0 && fork ? P->side_stream : st);
+    for (int b = 0; b < kNumForms; ++b) {
+        e = launch_match_items(kForms[b], P->dtype, P->margs, P->items[b], P->nitems[b],
+                               P->persist[b] ? P->counters + b : nullptr, P->grid, P->dir,
+                               b == 0 && fork ? P->side_stream : st);
         if (e != hipSuccess) return e;
         if (b == 0 && fork && (e = hipEventRecord(P->ev_join, P->side_stream)) != hipSuccess) return e;
     }
@@ -167,7 +169,7 @@ void free_plan(sfoc_plan* P) {
 
 // Median time of `reps` launches of one candidate side over `items`.
 float time_items(int L, int dtype, const MatchArgs* margs, const int4* items, int nitems, int* counter, int grid,
-                 hipStream_t st, int reps, hipError_t* err) {
+                 DirLaunch dir, hipStream_t st, int reps, hipError_t* err) {
     hipEvent_t a, b;
     *err = hipEventCreate(&a);
     if (*err != hipSuccess) return 0.f;
@@ -177,10 +179,10 @@ float time_items(int L, int dtype, const MatchArgs* margs, const int4* items, in
         return 0.f;
     }
     std::vector<float> t;
-    *err = launch_match_items(L, dtype, margs, items, nitems, counter, grid, st);   // warm-up
+    *err = launch_match_items(L, dtype, margs, items, nitems, counter, grid, dir, st);   // warm-up
     for (int k = 0; k < reps && *err == hipSuccess; ++k) {
         *err = hipEventRecord(a, st);
-        if (*err == hipSuccess) *err = launch_match_items(L, dtype, margs, items, nitems, counter, grid, st);
+        if (*err == hipSuccess) *err = launch_match_items(L, dtype, margs, items, nitems, counter, grid, dir, st);
         if (*err == hipSuccess) *err = hipEventRecord(b, st);
         if (*err == hipSuccess) *err = hipEventSynchronize(b);
         float ms = 0.f;
@@ -247,8 +249,9 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
         if ((rc = check_match_shape(q.n, q.m, q.r))) return rc;
         if (q.Hs * q.Ws >= kMaxPlane || q.Hr * q.Wr >= kMaxPlane) return SFOC_E_UNSUPPORTED;
         if (q.n > 0 && (!q.ips || !q.cps)) return SFOC_E_INVALID_ARG;
-        if (q.fft_side != 0 && side_index(q.fft_side) < 0) return SFOC_E_INVALID_ARG;
+        if (q.fft_side != 0 && form_index(q.fft_side) < 0) return SFOC_E_INVALID_ARG;
         if (q.fft_side != 0 && match_plan_L(q.n, q.m, q.r, q.fft_side).L == 0) return SFOC_E_UNSUPPORTED;
+        if (q.fft_side == kDirectSide && !direct_ok(q.m, q.r, p->desc_dtype)) return SFOC_E_UNSUPPORTED;
     }
     hipStream_t st = (hipStream_t)stream;
     sfoc_plan* P = new sfoc_plan;
@@ -318,14 +321,14 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     std::vector<std::vector<int>> cands(n_pairs);
     for (int k = 0; k < n_pairs; ++k) {
         const sfoc_pair& q = pairs[k];
-        int Ls[kNumSides];
+        int Ls[kNumForms];
         int nc = 0;
         if (q.fft_side) {
             Ls[nc++] = q.fft_side;
         } else if (tune) {
-            nc = match_candidates(q.m, q.r, Ls);
+            nc = plan_candidates(q.m, q.r, p->desc_dtype, Ls);
         } else {
-            Ls[nc++] = match_plan(q.n, q.m, q.r).L;
+            Ls[nc++] = match_plan_dt(q.n, q.m, q.r, p->desc_dtype).L;
         }
         cands[k].assign(Ls, Ls + nc);
         size_t ws = 0;
@@ -340,7 +343,8 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     // integral-image work lists: prefix items, then every tile of each reference
     std::vector<IntegJob> ijobs(n_pairs);
     std::vector<int4> ipre, itiles;
-    size_t max_items[kNumSides] = {}, max_peak = 0;
+    size_t max_items[kNumForms] = {}, max_peak = 0;
+    DirLaunch dir{3, 1};
     for (int k = 0; k < n_pairs; ++k) {
         const sfoc_pair& q = pairs[k];
         integral_prefix_items(k, (int)q.Hr, (int)q.Wr, ipre);
@@ -350,6 +354,11 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
         for (int L : cands[k]) {
             const MatchPlan m = match_plan_L(q.n, q.m, q.r, L);
             max_items[bucket_of(L)] += (size_t)q.n * m.nb * m.nb;
+            if (L == kDirectSide) {
+                const DirLaunch d = direct_launch_of(q.m, q.r);
+                dir.m = std::max(dir.m, d.m);
+                dir.nkb = std::max(dir.nkb, d.nkb);
+            }
         }
         max_peak += ((size_t)q.n + 255) / 256;
     }
@@ -359,10 +368,10 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     const size_t o_ipre = cur.take(ipre.size() * sizeof(int4));
     const size_t o_itiles = cur.take(itiles.size() * sizeof(int4));
     const size_t o_margs = cur.take((size_t)n_pairs * sizeof(MatchArgs));
-    size_t o_items[kNumSides];
-    for (int b = 0; b < kNumSides; ++b) o_items[b] = cur.take(max_items[b] * sizeof(int4));
+    size_t o_items[kNumForms];
+    for (int b = 0; b < kNumForms; ++b) o_items[b] = cur.take(max_items[b] * sizeof(int4));
     const size_t o_peak = cur.take(max_peak * sizeof(int4));
-    const size_t o_counters = cur.take(kNumSides * sizeof(int));
+    const size_t o_counters = cur.take(kNumForms * sizeof(int));
     P->bytes = cur.off;
     e = hipMalloc((void**)&P->mem, P->bytes);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->side_stream, hipStreamNonBlocking);
@@ -394,7 +403,8 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     P->npre = (int)ipre.size();
     P->nitiles = (int)itiles.size();
     P->margs = (MatchArgs*)(mem + o_margs);
-    for (int b = 0; b < kNumSides; ++b) P->items[b] = (int4*)(mem + o_items[b]);
+    for (int b = 0; b < kNumForms; ++b) P->items[b] = (int4*)(mem + o_items[b]);
+    P->dir = dir;
     P->peak = (int4*)(mem + o_peak);
     P->counters = (int*)(mem + o_counters);
     {
@@ -456,8 +466,8 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
                 }
                 // at most ~2048 IPs of the class are timed
                 float tbest = 0.f;
-                int Ls[kNumSides];
-                const int nc = match_candidates(m, r, Ls);
+                int Ls[kNumForms];
+                const int nc = plan_candidates(m, r, P->dtype, Ls);
                 for (int c = 0; c < nc && e == hipSuccess; ++c) {
                     const int L = Ls[c];
                     std::vector<MatchArgs> margs(n_pairs);
@@ -475,7 +485,8 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
                     int4* dit = P->items[bucket_of(L)];
                     up(dit, items.data(), items.size() * sizeof(int4));
                     if (e != hipSuccess) break;
-                    const float t = time_items(L, P->dtype, P->margs, dit, (int)items.size(), nullptr, 0, st, 3, &e);
+                    const float t = time_items(L, P->dtype, P->margs, dit, (int)items.size(), nullptr, 0, P->dir, st,
+                                               3, &e);
                     if (c == 0 || t < tbest) {
                         tbest = t;
                         best = L;
@@ -513,14 +524,14 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
         return pairs[k].m + std::min(m.Vb, 2 * pairs[k].r + 1) - 1 + pairs[k].m;
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
-    std::vector<int4> items[kNumSides], peak;
+    std::vector<int4> items[kNumForms], peak;
     for (int k : order) {
         append_items(items[bucket_of(P->side[k])], k, pairs[k].n, P->mp[k].nb);
         if (P->mp[k].nb > 1)
             for (int i = 0; i < pairs[k].n; i += 256) peak.push_back(make_int4(k, i, 0, 0));
     }
     up(P->margs, margs.data(), margs.size() * sizeof(MatchArgs));
-    for (int b = 0; b < kNumSides; ++b) {
+    for (int b = 0; b < kNumForms; ++b) {
         up(P->items[b], items[b].data(), items[b].size() * sizeof(int4));
         P->nitems[b] = (int)items[b].size();
     }
@@ -528,14 +539,15 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     P->npeak = (int)peak.size();
     // launch form per side: persistent when asked; with autotuning the
     // faster of the two on this plan's items
-    for (int b = 0; b < kNumSides && e == hipSuccess; ++b) {
+    for (int b = 0; b < kNumSides && e == hipSuccess; ++b) {   // the direct form has one launch form
         P->persist[b] = (flags & SFOC_PLAN_PERSISTENT) != 0;
         if (tune && P->nitems[b] > 0) {
             const int L = kSides[b];
-            const float tg = time_items(L, P->dtype, P->margs, P->items[b], P->nitems[b], nullptr, 0, st, 3, &e);
+            const float tg = time_items(L, P->dtype, P->margs, P->items[b], P->nitems[b], nullptr, 0, P->dir, st, 3,
+                                        &e);
             if (e != hipSuccess) break;
-            const float tp = time_items(L, P->dtype, P->margs, P->items[b], P->nitems[b], P->counters + b, P->grid, st,
-                                        3, &e);
+            const float tp = time_items(L, P->dtype, P->margs, P->items[b], P->nitems[b], P->counters + b, P->grid,
+                                        P->dir, st, 3, &e);
             P->persist[b] = tp < tg;
         }
     }
@@ -600,6 +612,7 @@ int sfoc_plan_get_info(const sfoc_plan* P, sfoc_plan_info* info, int32_t* fft_si
     info->cached_classes = P->cached;
     info->graph = P->exec != nullptr;
     info->describe_config = P->dvar;
+    info->direct_items = P->nitems[form_index(kDirectSide)];
     info->device_bytes = (int64_t)P->bytes;
     const int n = std::min<int>(cap, (int)P->pairs.size());
     for (int k = 0; k < n; ++k) {

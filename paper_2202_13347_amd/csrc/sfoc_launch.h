@@ -106,11 +106,20 @@ hipError_t launch_integral_batched(const IntegJob* jobs, const int4* pre, int np
 // of one image.
 constexpr int kScanNT = 256;
 void integral_prefix_items(int job, int H, int W, std::vector<int4>& out);
+// Size of a direct-form launch: the largest template side and chunk count
+// of the pairs it covers (direct_launch_of for one pair; componentwise
+// maxima for several).
+struct DirLaunch {
+    int m, nkb;
+};
+DirLaunch direct_launch_of(int m, int r);
 // items[k] = {pair, IP, offset block, 0}, all with transform side L; one
 // workgroup per item, or (counter != null) a persistent grid of `grid`
-// workgroups taking items from *counter (zeroed by the launch)
+// workgroups taking items from *counter (zeroed by the launch).  The direct
+// form (L = kDirectSide, 16-bit dtypes) has no persistent grid and is sized
+// by `dir`.
 hipError_t launch_match_items(int L, int dtype, const MatchArgs* pairs, const int4* items, int nitems, int* counter,
-                              int grid, hipStream_t st);
+                              int grid, DirLaunch dir, hipStream_t st);
 // items[k] = {pair, first IP of a run of 256, 0, 0} over pairs with split offsets
 hipError_t launch_peak_batched(const MatchArgs* pairs, const int4* items, int nitems, hipStream_t st);
 // one workgroup per pair

@@ -590,6 +590,183 @@ SFOC_DEV void init_twiddles(float2* tw) {
     }
 }
 
+// Template sums R_T, R_TT (Eq. 12): a block reduction in float64 of every
+// thread's partial sums, left in red[64] and red[65] (red holds at least 66
+// doubles); returns with the workgroup synchronised.
+template <int NT>
+SFOC_DEV void block_sum2(double s1, double s2, double* red) {
+    const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
+    for (int d = 32; d >= 1; d >>= 1) {
+        s1 += __shfl_down(s1, d, 64);
+        s2 += __shfl_down(s2, d, 64);
+    }
+    if (lane == 0) {
+        red[2 * wv] = s1;
+        red[2 * wv + 1] = s2;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double a = 0.0, b = 0.0;
+        for (int w = 0; w < NT / 64; ++w) {
+            a += red[2 * w];
+            b += red[2 * w + 1];
+        }
+        red[64] = a;
+        red[65] = b;
+    }
+    __syncthreads();
+}
+
+// NCC (Eq. 9), the argmax, the parabola refinement and the CP record of one
+// work item, from its correlation surface R_ST: rst_at(u, v) for offsets
+// (u, v) of the block [u0, u0 + Vu) x [v0, v0 + Vv), readable by every
+// thread.  RT, RTT are the template sums; red is workgroup scratch of at
+// least 66 doubles.  Every thread of the workgroup calls it.
+template <int NT, typename Rst>
+SFOC_DEV void ncc_peak(const MatchArgs& A, int i, int slot, int u0, int v0, int Vu, int Vv, double RT, double RTT,
+                       double* red, Rst rst_at) {
+    const int nblk = A.nbu * A.nbv;
+    const int t = threadIdx.x;
+    const int m = A.m, r = A.r, M = m + 2 * r, V = 2 * r + 1;
+    const int py = A.ips[2 * i], px = A.ips[2 * i + 1];
+    const int pry = A.prior ? A.prior[2 * i] : 0, prx = A.prior ? A.prior[2 * i + 1] : 0;
+    const int64_t sy = (int64_t)py - m / 2 - r + pry, sx = (int64_t)px - m / 2 - r + prx;
+    float* nout = A.ncc ? A.ncc + (int64_t)i * V * V : (nblk > 1 ? A.surf + (int64_t)i * V * V : nullptr);
+    sfoc_cp out;
+    out.sen_row = py;
+    out.sen_col = px;
+    out.dy = out.dx = 0;
+    out.sub_dy = out.sub_dx = 0.f;
+    out.score = 0.f;
+    out.flags = 0;
+    const double mnz = (double)m * m * A.z;
+    const double tau = 1e-12 * mnz;
+    const double varT = RTT - RT * RT / mnz;
+    // NCC (Eq. 9) with integral-image box sums (Eq. 16), float64 variance.
+    // The integral images are the reference image's, or this IP's own over
+    // its search window (origin (sy, sx), side M + 1).
+    const int64_t IW = A.integ_win ? (int64_t)M + 1 : A.Wr + 1;
+    const double* __restrict__ I1 = A.integ_win ? A.integ1 + (int64_t)i * IW * IW : A.integ1;
+    const double* __restrict__ I2 = A.integ_win ? A.integ2 + (int64_t)i * IW * IW : A.integ2;
+    const int64_t oy = A.integ_win ? 0 : sy, ox = A.integ_win ? 0 : sx;
+    const bool flatT = !(varT > tau);
+    const bool badT = !isfinite(RT) || !isfinite(RTT);
+    // NCC at offset (u, v); flags: bit 0 non-flat search window, bit 1 non-finite.
+    // (u, v) are offsets within this block; the surface offset is (u0 + u, v0 + v).
+    auto ncc_at = [&](int u, int v, int& fl) -> float {
+        const float rst = rst_at(u, v);
+        const int64_t y = oy + u0 + u, x = ox + v0 + v;
+        const int64_t a00 = y * IW + x, a01 = a00 + m, a10 = a00 + (int64_t)m * IW, a11 = a10 + m;
+        const double RS = I1[a11] - I1[a10] - I1[a01] + I1[a00];
+        const double RSS = I2[a11] - I2[a10] - I2[a01] + I2[a00];
+        const double varS = RSS - RS * RS / mnz;
+        float val = 0.f;
+        fl = 0;
+        if (!isfinite(rst) || !isfinite(RS) || !isfinite(varS)) fl |= 2;
+        if (varS > tau && !flatT) {
+            fl |= 1;
+            const double num = (double)rst - RS * RT / mnz;
+            val = (float)(num / sqrt(varS * varT));
+        }
+        return val;
+    };
+    int nonflat = 0, nonfin = 0;
+    float best = -INFINITY;
+    int bidx = 0x7fffffff;
+    for (int e = t; e < Vu * Vv; e += NT) {
+        const int u = e / Vv, v = e - u * Vv;
+        int fl;
+        const float val = ncc_at(u, v, fl);
+        nonflat |= fl & 1;
+        nonfin |= fl >> 1;
+        const int eg = (u0 + u) * V + v0 + v;   // row-major index on the whole surface
+        if (nout) nout[eg] = val;
+        if (val > best) {   // strictly greater: the first index wins ties
+            best = val;
+            bidx = eg;
+        }
+    }
+    // block reduce (max value, min index), and the flags.
+    {
+        const int lane = t & 63, wv = t >> 6;
+        for (int d = 32; d >= 1; d >>= 1) {
+            const float ob = __shfl_down(best, d, 64);
+            const int oi = __shfl_down(bidx, d, 64);
+            if (ob > best || (ob == best && oi < bidx)) {
+                best = ob;
+                bidx = oi;
+            }
+            nonflat |= __shfl_down(nonflat, d, 64);
+            nonfin |= __shfl_down(nonfin, d, 64);
+        }
+        __syncthreads();
+        float* rf = reinterpret_cast<float*>(red);
+        int* ri = reinterpret_cast<int*>(red) + 64;
+        if (lane == 0) {
+            rf[wv] = best;
+            ri[wv] = bidx;
+            ri[16 + wv] = nonflat;
+            ri[32 + wv] = nonfin;
+        }
+        __syncthreads();
+        if (t == 0) {
+            for (int w = 1; w < NT / 64; ++w) {
+                if (rf[w] > rf[0] || (rf[w] == rf[0] && ri[w] < ri[0])) {
+                    rf[0] = rf[w];
+                    ri[0] = ri[w];
+                }
+                ri[16] |= ri[16 + w];
+                ri[32] |= ri[32 + w];
+            }
+        }
+        __syncthreads();
+        best = rf[0];
+        bidx = ri[0];
+        nonflat = ri[16];
+        nonfin = ri[32];
+    }
+    if (nblk > 1) {
+        if (t == 0) {
+            const int fl = (nonflat ? kBlkNonflat : 0) | (nonfin ? kBlkNonfin : 0) | (flatT ? kBlkFlatT : 0) |
+                           (badT ? kBlkBadT : 0);
+            A.blk[slot] = make_float4(best, __int_as_float(bidx), __int_as_float(fl), 0.f);
+        }
+        return;
+    }
+    if (t == 0) {
+        if (badT || (nonfin && !flatT)) {
+            out.flags = SFOC_CP_NONFINITE;
+        } else if (flatT) {
+            out.flags = SFOC_CP_FLAT_T;
+        } else if (!nonflat || bidx >= V * V) {
+            out.flags = SFOC_CP_FLAT_S;
+        } else {
+            const int u = bidx / V, v = bidx - u * V;
+            out.dy = u - r;
+            out.dx = v - r;
+            out.score = best;
+            if (u == 0 || v == 0 || u == V - 1 || v == V - 1) {
+                out.flags = SFOC_CP_EDGE_PEAK;
+            } else {
+                int fl;
+                const float c0 = best;
+                const float cu = ncc_at(u - 1, v, fl), cd = ncc_at(u + 1, v, fl);
+                const float cl = ncc_at(u, v - 1, fl), cr = ncc_at(u, v + 1, fl);
+                float den = cu - 2.f * c0 + cd;
+                float d = 0.f;
+                if (den < 0.f) d = fminf(0.5f, fmaxf(-0.5f, (cu - cd) / (2.f * den)));
+                out.sub_dy = d;
+                den = cl - 2.f * c0 + cr;
+                d = 0.f;
+                if (den < 0.f) d = fminf(0.5f, fmaxf(-0.5f, (cl - cr) / (2.f * den)));
+                out.sub_dx = d;
+            }
+        }
+        A.cps[i] = out;
+    }
+}
+
 // One work item: interest point i, offset block bq (record slot `slot`).
 // With M <= L there is one block and this workgroup finishes the CP;
 // otherwise each block covers offsets [u0, u0 + Vu) x [v0, v0 + Vv) with a
@@ -681,33 +858,7 @@ SFOC_DEV void match_item(const MatchArgs& A, int i, int bq, int slot, const floa
         __syncthreads();
     }
 
-    // template sums R_T, R_TT (Eq. 12): block reduction in float64.
-    {
-        const int lane = t & 63, wv = t >> 6;
-        for (int d = 32; d >= 1; d >>= 1) {
-            s1 += __shfl_down(s1, d, 64);
-            s2 += __shfl_down(s2, d, 64);
-        }
-        if (lane == 0) {
-            red[2 * wv] = s1;
-            red[2 * wv + 1] = s2;
-        }
-        __syncthreads();
-        if (t == 0) {
-            double a = 0.0, b = 0.0;
-            for (int w = 0; w < C::NT / 64; ++w) {
-                a += red[2 * w];
-                b += red[2 * w + 1];
-            }
-            red[64] = a;
-            red[65] = b;
-        }
-        __syncthreads();
-    }
-    const double RT = red[64], RTT = red[65];
-    const double mnz = (double)m * m * A.z;
-    const double tau = 1e-12 * mnz;
-    const double varT = RTT - RT * RT / mnz;
+    block_sum2<C::NT>(s1, s2, red);
 
     // inverse, columns first: spectrum bins back to LDS (natural order), then
     // column transforms k1 -> u.
@@ -834,129 +985,10 @@ SFOC_DEV void match_item(const MatchArgs& A, int i, int bq, int slot, const floa
         __syncthreads();
     }
 
-    // NCC (Eq. 9) with integral-image box sums (Eq. 16), float64 variance.
-    // The integral images are the reference image's, or this IP's own over
-    // its search window (origin (sy, sx), side M + 1).
-    const int64_t IW = A.integ_win ? (int64_t)M + 1 : A.Wr + 1;
-    const double* __restrict__ I1 = A.integ_win ? A.integ1 + (int64_t)i * IW * IW : A.integ1;
-    const double* __restrict__ I2 = A.integ_win ? A.integ2 + (int64_t)i * IW * IW : A.integ2;
-    const int64_t oy = A.integ_win ? 0 : sy, ox = A.integ_win ? 0 : sx;
-    const bool flatT = !(varT > tau);
-    const bool badT = !isfinite(RT) || !isfinite(RTT);
-    // NCC at offset (u, v); flags: bit 0 non-flat search window, bit 1 non-finite.
-    // (u, v) are offsets within this block; the surface offset is (u0 + u, v0 + v).
-    auto ncc_at = [&](int u, int v, int& fl) -> float {
+    ncc_peak<C::NT>(A, i, slot, u0, v0, Vu, Vv, red[64], red[65], red, [&](int u, int v) {
         const float* rr = reinterpret_cast<const float*>(buf + C::row((u >> 1) * 2));
-        const float rst = rr[(u & 1) * L + v];
-        const int64_t y = oy + u0 + u, x = ox + v0 + v;
-        const int64_t a00 = y * IW + x, a01 = a00 + m, a10 = a00 + (int64_t)m * IW, a11 = a10 + m;
-        const double RS = I1[a11] - I1[a10] - I1[a01] + I1[a00];
-        const double RSS = I2[a11] - I2[a10] - I2[a01] + I2[a00];
-        const double varS = RSS - RS * RS / mnz;
-        float val = 0.f;
-        fl = 0;
-        if (!isfinite(rst) || !isfinite(RS) || !isfinite(varS)) fl |= 2;
-        if (varS > tau && !flatT) {
-            fl |= 1;
-            const double num = (double)rst - RS * RT / mnz;
-            val = (float)(num / sqrt(varS * varT));
-        }
-        return val;
-    };
-    int nonflat = 0, nonfin = 0;
-    float best = -INFINITY;
-    int bidx = 0x7fffffff;
-    for (int e = t; e < Vu * Vv; e += C::NT) {
-        const int u = e / Vv, v = e - u * Vv;
-        int fl;
-        const float val = ncc_at(u, v, fl);
-        nonflat |= fl & 1;
-        nonfin |= fl >> 1;
-        const int eg = (u0 + u) * V + v0 + v;   // row-major index on the whole surface
-        if (nout) nout[eg] = val;
-        if (val > best) {   // strictly greater: the first index wins ties
-            best = val;
-            bidx = eg;
-        }
-    }
-    // block reduce (max value, min index), and the flags.
-    {
-        const int lane = t & 63, wv = t >> 6;
-        for (int d = 32; d >= 1; d >>= 1) {
-            const float ob = __shfl_down(best, d, 64);
-            const int oi = __shfl_down(bidx, d, 64);
-            if (ob > best || (ob == best && oi < bidx)) {
-                best = ob;
-                bidx = oi;
-            }
-            nonflat |= __shfl_down(nonflat, d, 64);
-            nonfin |= __shfl_down(nonfin, d, 64);
-        }
-        __syncthreads();
-        float* rf = reinterpret_cast<float*>(red);
-        int* ri = reinterpret_cast<int*>(red) + 64;
-        if (lane == 0) {
-            rf[wv] = best;
-            ri[wv] = bidx;
-            ri[16 + wv] = nonflat;
-            ri[32 + wv] = nonfin;
-        }
-        __syncthreads();
-        if (t == 0) {
-            for (int w = 1; w < C::NT / 64; ++w) {
-                if (rf[w] > rf[0] || (rf[w] == rf[0] && ri[w] < ri[0])) {
-                    rf[0] = rf[w];
-                    ri[0] = ri[w];
-                }
-                ri[16] |= ri[16 + w];
-                ri[32] |= ri[32 + w];
-            }
-        }
-        __syncthreads();
-        best = rf[0];
-        bidx = ri[0];
-        nonflat = ri[16];
-        nonfin = ri[32];
-    }
-    if (nblk > 1) {
-        if (t == 0) {
-            const int fl = (nonflat ? kBlkNonflat : 0) | (nonfin ? kBlkNonfin : 0) | (flatT ? kBlkFlatT : 0) |
-                           (badT ? kBlkBadT : 0);
-            A.blk[slot] = make_float4(best, __int_as_float(bidx), __int_as_float(fl), 0.f);
-        }
-        return;
-    }
-    if (t == 0) {
-        if (badT || (nonfin && !flatT)) {
-            out.flags = SFOC_CP_NONFINITE;
-        } else if (flatT) {
-            out.flags = SFOC_CP_FLAT_T;
-        } else if (!nonflat || bidx >= V * V) {
-            out.flags = SFOC_CP_FLAT_S;
-        } else {
-            const int u = bidx / V, v = bidx - u * V;
-            out.dy = u - r;
-            out.dx = v - r;
-            out.score = best;
-            if (u == 0 || v == 0 || u == V - 1 || v == V - 1) {
-                out.flags = SFOC_CP_EDGE_PEAK;
-            } else {
-                int fl;
-                const float c0 = best;
-                const float cu = ncc_at(u - 1, v, fl), cd = ncc_at(u + 1, v, fl);
-                const float cl = ncc_at(u, v - 1, fl), cr = ncc_at(u, v + 1, fl);
-                float den = cu - 2.f * c0 + cd;
-                float d = 0.f;
-                if (den < 0.f) d = fminf(0.5f, fmaxf(-0.5f, (cu - cd) / (2.f * den)));
-                out.sub_dy = d;
-                den = cl - 2.f * c0 + cr;
-                d = 0.f;
-                if (den < 0.f) d = fminf(0.5f, fmaxf(-0.5f, (cl - cr) / (2.f * den)));
-                out.sub_dx = d;
-            }
-        }
-        A.cps[i] = out;
-    }
+        return rr[(u & 1) * L + v];
+    });
 }
 
 template <int L, int DT, bool BATCH>
@@ -1016,6 +1048,212 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, MatchCfg<L>::WAVES_PER_SIMD) void 
 }
 
 __global__ void zero_counter_kernel(int* counter) { *counter = 0; }
+
+// ---- direct correlation on the matrix cores -----------------------------
+// R_ST(u, v) = sum_h sum_i sum_k S_h(i + u, k) T_h(i, k - v): Eq. 10 summed in
+// space, with T_h(i, j) = 0 outside 0 <= j < m, for 16-bit descriptors and at
+// most 32 offsets per axis.  For each channel h and template row i this is
+// the product of the 32 window rows i .. i + 31 (32 x K; K = 16 ceil(M / 16)
+// columns, zero beyond M) with the banded Toeplitz matrix of template row i
+// (K x 32, B[k][v] = T_h(i, k - v)): K / 16 MFMAs of 32 x 32 x 16 with
+// float32 accumulation.  The stored 16-bit values are exact operands; only
+// the order of the float32 sums differs from the FFT path.
+//
+// MFMA 32 x 32 x 16 operands (lane l, c = 0..7): A[l % 32][8 (l / 32) + c],
+// B[8 (l / 32) + c][l % 32]; result register q of lane l holds
+// D[8 (q / 4) + 4 (l / 32) + q % 4][l % 32].
+//
+// LDS per channel: the window (m + 31 rows, pitch PW; rows and columns from
+// M on stay zero), then two copies of the zero-padded template rows, with
+// Tz(q) = T_h(i, q - 32): E[q] = Tz(q), O[q] = Tz(q + 1).  Lane (v, g) of
+// chunk kb needs Tz(16 kb + 8 g - v + 32 + c), c = 0..7; it reads E when v is
+// even and O one element earlier when v is odd, so that every read starts on
+// a 4-byte boundary.  Wave w takes the template rows i = w (mod 4); the four
+// partial surfaces are summed in wave order.
+constexpr int kDirNT = 256;
+constexpr int kDirMaxKB = (kDirectMaxM + kDirectMaxV - 1 + 15) / 16;   // chunks of the widest window (94): 6
+
+// Chunks of a window of M = m + 2r columns; a launch runs a fixed chunk
+// count NKB >= that of each of its IPs (further chunks multiply zeros).
+inline SFOC_HOST_DEVICE int dir_nkb(int m, int r) { return (m + 2 * r + 15) / 16; }
+struct DirGeom {
+    int PW;      // window row pitch (elements): 16 NKB + 8
+    int WR;      // window rows staged: m + 31
+    int PT;      // template row pitch (elements): 16 NKB + 40
+    int bytes;   // dynamic LDS: the operands, or the four 32 x 32 float partial surfaces
+};
+inline SFOC_HOST_DEVICE DirGeom dir_geom(int m, int nkb) {
+    DirGeom g;
+    g.PW = 16 * nkb + 8;
+    g.WR = m + 31;
+    g.PT = 16 * nkb + 40;
+    const int b = 2 * (g.WR * g.PW + 2 * m * g.PT);
+    g.bytes = b > 4 * 1024 * 4 ? b : 4 * 1024 * 4;
+    return g;
+}
+
+typedef __bf16 dir_bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 dir_f16x8 __attribute__((ext_vector_type(8)));
+typedef float dir_f32x16 __attribute__((ext_vector_type(16)));
+
+template <int DT>
+SFOC_DEV dir_f32x16 dir_mfma(uint4 a, uint4 b, dir_f32x16 c) {
+    if constexpr (DT == 1)
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(dir_bf16x8, a),
+                                                       __builtin_bit_cast(dir_bf16x8, b), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(dir_f16x8, a),
+                                                      __builtin_bit_cast(dir_f16x8, b), c, 0, 0, 0);
+}
+
+// One interest point of the direct form (A.nbu = A.nbv = 1, V <= 32, m <= 64,
+// dir_nkb(m, r) <= NKB).
+template <int DT, int NKB>
+SFOC_DEV void direct_item(const MatchArgs& A, int i, char* lds, double* red) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, ul = lane & 31, gl = lane >> 5;
+    const int m = A.m, r = A.r, M = m + 2 * r, V = 2 * r + 1;
+    const DirGeom g = dir_geom(m, NKB);
+    const int py = A.ips[2 * i], px = A.ips[2 * i + 1];
+    const int pry = A.prior ? A.prior[2 * i] : 0, prx = A.prior ? A.prior[2 * i + 1] : 0;
+    const int64_t ty = (int64_t)py - m / 2, tx = (int64_t)px - m / 2;
+    const int64_t sy = ty - r + pry, sx = tx - r + prx;
+    if (!in_image(ty, tx, m, m, A.Hs, A.Ws) || !in_image(sy, sx, M, M, A.Hr, A.Wr)) {
+        if (t == 0) {
+            sfoc_cp out;
+            out.sen_row = py;
+            out.sen_col = px;
+            out.dy = out.dx = 0;
+            out.sub_dy = out.sub_dx = 0.f;
+            out.score = 0.f;
+            out.flags = SFOC_CP_OOB;
+            A.cps[i] = out;
+        }
+        if (A.ncc)
+            for (int e = t; e < V * V; e += kDirNT) A.ncc[(int64_t)i * V * V + e] = 0.f;
+        return;
+    }
+    uint16_t* Wl = reinterpret_cast<uint16_t*>(lds);
+    uint16_t* E = Wl + g.WR * g.PW;
+    uint16_t* O = E + m * g.PT;
+    {   // the zero bands of both operands stay zero for every channel
+        uint32_t* zp = reinterpret_cast<uint32_t*>(lds);
+        const int nz = (g.WR * g.PW + 2 * m * g.PT) / 2;
+        for (int e = t; e < nz; e += kDirNT) zp[e] = 0u;
+    }
+    __syncthreads();
+    dir_f32x16 acc0 = {}, acc1 = {};   // even and odd chunks: two independent chains
+    double s1 = 0.0, s2 = 0.0;
+    const int64_t plane_s = A.Hs * A.Ws, plane_r = A.Hr * A.Wr;
+    const uint16_t* refp = static_cast<const uint16_t*>(A.desc_ref) + sy * A.Wr + sx;
+    const uint16_t* senp = static_cast<const uint16_t*>(A.desc_sen) + ty * A.Ws + tx;
+    // Loads go out eight rows at a time (every wave takes rows w, w + 4, ...;
+    // a lane columns lane and lane + 64, as M < 128), then their LDS stores.
+    constexpr int kB = 8;
+    for (int h = 0; h < A.z; ++h) {
+        // (indices below come from a laundered thread index, so that their
+        // arithmetic is redone per channel rather than hoisted and kept live)
+        {
+            const int tl = tid_local(), ln = tl & 63, wl = __builtin_amdgcn_readfirstlane(tl >> 6);
+            const uint16_t* rp = refp + h * plane_r;
+            // rows and columns clamped into the window: every load is in
+            // bounds and unconditional; only the stores are masked
+            const uint32_t xa = (uint32_t)min(ln, M - 1), xb = (uint32_t)min(ln + 64, M - 1);
+            for (int y0 = wl; y0 < M; y0 += 4 * kB) {
+                const uint16_t* row = rp + (int64_t)y0 * A.Wr;   // wave-uniform base
+                uint16_t va[kB], vb[kB];
+#pragma unroll
+                for (int j = 0; j < kB; ++j) {
+                    const uint32_t o = (uint32_t)(min(y0 + 4 * j, M - 1) - y0) * (uint32_t)A.Wr;
+                    va[j] = row[o + xa];
+                    vb[j] = row[o + xb];
+                }
+                uint16_t* wrow = Wl + y0 * g.PW;
+#pragma unroll
+                for (int j = 0; j < kB; ++j)
+                    if (y0 + 4 * j < M) {
+                        if (ln < M) wrow[4 * j * g.PW + ln] = va[j];
+                        if (ln + 64 < M) wrow[4 * j * g.PW + ln + 64] = vb[j];
+                    }
+            }
+        }
+        {
+            const int tl = tid_local(), ln = tl & 63, wl = __builtin_amdgcn_readfirstlane(tl >> 6);
+            const uint16_t* sp = senp + h * plane_s;
+            const uint32_t xt = (uint32_t)min(ln, m - 1);
+            for (int y0 = wl; y0 < m; y0 += 4 * kB) {
+                const uint16_t* row = sp + (int64_t)y0 * A.Ws;
+                uint16_t vt[kB];
+#pragma unroll
+                for (int j = 0; j < kB; ++j)
+                    vt[j] = row[(uint32_t)(min(y0 + 4 * j, m - 1) - y0) * (uint32_t)A.Ws + xt];
+                uint16_t* erow = E + y0 * g.PT + 32 + ln;
+#pragma unroll
+                for (int j = 0; j < kB; ++j)
+                    if (y0 + 4 * j < m && ln < m) {
+                        erow[4 * j * g.PT] = vt[j];
+                        erow[4 * j * g.PT + m * g.PT - 1] = vt[j];   // O[y][31 + x]
+                        const double f = (double)(DT == 1 ? bf16_bits_to_f32(vt[j]) : f16_bits_to_f32(vt[j]));
+                        s1 += f;
+                        s2 += f * f;
+                    }
+            }
+        }
+        __syncthreads();
+        // per template row: every chunk's operands read first, then the MFMAs
+        {
+            const int tl = tid_local(), ln = tl & 63, wl = __builtin_amdgcn_readfirstlane(tl >> 6), u = ln & 31,
+                      gq = ln >> 5;
+            for (int ii = wl; ii < m; ii += 4) {
+                const uint16_t* arow = Wl + (ii + u) * g.PW + 8 * gq;
+                const uint16_t* brow = ((u & 1) ? O : E) + ii * g.PT + 8 * gq + 32 - u - (u & 1);
+                uint4 a[NKB], b[NKB];
+#pragma unroll
+                for (int kb = 0; kb < NKB; ++kb) {
+                    a[kb] = *reinterpret_cast<const uint4*>(arow + 16 * kb);
+                    const uint32_t* bp = reinterpret_cast<const uint32_t*>(brow + 16 * kb);
+                    b[kb] = make_uint4(bp[0], bp[1], bp[2], bp[3]);
+                }
+#pragma unroll
+                for (int kb = 0; kb < NKB; ++kb) {
+                    if (kb & 1)
+                        acc1 = dir_mfma<DT>(a[kb], b[kb], acc1);
+                    else
+                        acc0 = dir_mfma<DT>(a[kb], b[kb], acc0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    float* P = reinterpret_cast<float*>(lds);   // wave w's partial surface at P + 1024 w
+#pragma unroll
+    for (int q = 0; q < 16; ++q) P[1024 * w + (8 * (q >> 2) + 4 * gl + (q & 3)) * 32 + ul] = acc0[q] + acc1[q];
+    __syncthreads();
+    for (int e = t; e < V * V; e += kDirNT) {
+        const int u = e / V, o = u * 32 + (e - u * V);
+        P[o] = ((P[o] + P[1024 + o]) + P[2048 + o]) + P[3072 + o];
+    }
+    block_sum2<kDirNT>(s1, s2, red);
+    ncc_peak<kDirNT>(A, i, i, 0, 0, V, V, red[64], red[65], red, [&](int u, int v) { return P[u * 32 + v]; });
+}
+
+// One pair (blockIdx.x -> IP, dealt to the XCDs in contiguous runs), or
+// (BATCH) a table of (pair, IP) items.
+template <int DT, int NKB, bool BATCH>
+__global__ __launch_bounds__(kDirNT, 4) void match_direct_kernel(const MatchArgs single,
+                                                               const MatchArgs* __restrict__ pairs,
+                                                               const int4* __restrict__ items) {
+    extern __shared__ float4 lds_raw[];
+    __shared__ double red[66];
+    char* lds = reinterpret_cast<char*>(lds_raw);
+    if (BATCH) {
+        const int4 it = items[blockIdx.x];
+        const MatchArgs A = load_table(pairs, it.x);
+        direct_item<DT, NKB>(A, it.y, lds, red);
+    } else {
+        const int n = (int)gridDim.x, q8 = n / 8 * 8, id = (int)blockIdx.x;
+        direct_item<DT, NKB>(single, id < q8 ? (id % 8) * (q8 / 8) + id / 8 : id, lds, red);
+    }
+}
 
 // ---- combining offset blocks --------------------------------------------
 // One thread per interest point: the best score over its blocks (ties: the
@@ -1305,6 +1543,48 @@ static hipError_t launch_match_L(const MatchArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <int DT, int NKB, bool BATCH>
+static hipError_t launch_direct_K(const MatchArgs& a, const MatchArgs* pairs, const int4* items, int nblocks,
+                                  int lds, hipStream_t st) {
+    auto kern = match_direct_kernel<DT, NKB, BATCH>;
+    hipError_t e = ensure_dynamic_lds((const void*)kern, lds);
+    if (e != hipSuccess) return e;
+    trace_begin(st, SFOC_K_MATCH);
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kDirNT), lds, st, a, pairs, items);
+    trace_end(st, SFOC_K_MATCH);
+    return hipGetLastError();
+}
+
+template <int DT, bool BATCH>
+static hipError_t launch_direct_DT(const MatchArgs& a, const MatchArgs* pairs, const int4* items, int nblocks,
+                                   DirLaunch d, hipStream_t st) {
+    const int lds = dir_geom(d.m, d.nkb).bytes;
+    switch (d.nkb) {
+        case 1: return launch_direct_K<DT, 1, BATCH>(a, pairs, items, nblocks, lds, st);
+        case 2: return launch_direct_K<DT, 2, BATCH>(a, pairs, items, nblocks, lds, st);
+        case 3: return launch_direct_K<DT, 3, BATCH>(a, pairs, items, nblocks, lds, st);
+        case 4: return launch_direct_K<DT, 4, BATCH>(a, pairs, items, nblocks, lds, st);
+        case 5: return launch_direct_K<DT, 5, BATCH>(a, pairs, items, nblocks, lds, st);
+        case 6: return launch_direct_K<DT, 6, BATCH>(a, pairs, items, nblocks, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// The direct form: one workgroup per IP of one pair (items null), or per
+// (pair, IP) item; d holds the largest m and chunk count of the IPs' pairs.
+static hipError_t launch_direct(const MatchArgs& a, const MatchArgs* pairs, const int4* items, int nblocks,
+                                DirLaunch d, int dtype, hipStream_t st) {
+    if (dtype == 1)
+        return items ? launch_direct_DT<1, true>(a, pairs, items, nblocks, d, st)
+                     : launch_direct_DT<1, false>(a, pairs, items, nblocks, d, st);
+    if (dtype == 2)
+        return items ? launch_direct_DT<2, true>(a, pairs, items, nblocks, d, st)
+                     : launch_direct_DT<2, false>(a, pairs, items, nblocks, d, st);
+    return hipErrorInvalidValue;
+}
+
+DirLaunch direct_launch_of(int m, int r) { return DirLaunch{m, dir_nkb(m, r)}; }
+
 template <int L>
 static hipError_t launch_match_side(const MatchArgs& a, int dtype, hipStream_t st) {
     return dtype == 0 ? launch_match_L<L, 0>(a, st) : dtype == 1 ? launch_match_L<L, 1>(a, st)
@@ -1333,7 +1613,7 @@ hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void
     a.n = n;
     a.m = m;
     a.r = r;
-    const MatchPlan mp = match_plan(n, m, r);
+    const MatchPlan mp = match_plan_dt(n, m, r, dtype);
     const int L = mp.L;
     match_args_layout(a, mp, ws);
     a.integ_win = 0;
@@ -1356,6 +1636,7 @@ hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void
         case 128: e = launch_match_side<128>(a, dtype, st); break;
         case 160: e = launch_match_side<160>(a, dtype, st); break;
         case 192: e = launch_match_side<192>(a, dtype, st); break;
+        case kDirectSide: e = launch_direct(a, nullptr, nullptr, n, direct_launch_of(m, r), dtype, st); break;
         default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
@@ -1407,10 +1688,16 @@ static hipError_t launch_match_items_side(int dtype, const MatchArgs* pairs, con
 
 // One launch over (pair, IP, block) items that share the transform side L:
 // one workgroup per item, or (counter != null) a persistent grid of `grid`
-// workgroups taking items from *counter.
+// workgroups taking items from *counter.  The direct form (L = kDirectSide)
+// takes one workgroup per item, sized by `dir`.
 hipError_t launch_match_items(int L, int dtype, const MatchArgs* pairs, const int4* items, int nitems, int* counter,
-                              int grid, hipStream_t st) {
+                              int grid, DirLaunch dir, hipStream_t st) {
     if (nitems == 0) return hipSuccess;
+    if (L == kDirectSide) {
+        if (counter) return hipErrorInvalidValue;
+        MatchArgs none{};
+        return launch_direct(none, pairs, items, nitems, dir, dtype, st);
+    }
     switch (L) {
         case 64: return launch_match_items_side<64>(dtype, pairs, items, nitems, counter, grid, st);
         case 128: return launch_match_items_side<128>(dtype, pairs, items, nitems, counter, grid, st);

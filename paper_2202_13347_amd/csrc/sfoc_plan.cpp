@@ -153,6 +153,13 @@ size_t describe_ws_bytes(int64_t H, int64_t W) {
 
 MatchPlan match_plan_L(int32_t n, int32_t m, int32_t r, int L) {
     MatchPlan p{0, 1, 0, 0};
+    if (L == kDirectSide) {
+        if (n >= 0 && direct_ok(m, r, SFOC_DTYPE_BF16)) {
+            p.L = kDirectSide;
+            p.Vb = 2 * r + 1;
+        }
+        return p;
+    }
     if (m < 3 || m > kMaxTemplate || r < 1 || r > kMaxRadiusMatch || n < 0 || side_index(L) < 0) return p;
     const int M = m + 2 * r, V = 2 * r + 1;
     if (M <= L) {
@@ -207,9 +214,19 @@ int match_candidates(int32_t m, int32_t r, int* Ls) {
     return k;
 }
 
-static bool is_candidate(int m, int r, int L) {
-    int Ls[kNumSides];
-    const int n = match_candidates(m, r, Ls);
+MatchPlan match_plan_dt(int32_t n, int32_t m, int32_t r, int32_t dtype) {
+    return direct_ok(m, r, dtype) ? match_plan_L(n, m, r, kDirectSide) : match_plan(n, m, r);
+}
+
+int plan_candidates(int32_t m, int32_t r, int32_t dtype, int* Ls) {
+    if (!direct_ok(m, r, dtype)) return match_candidates(m, r, Ls);
+    Ls[0] = kDirectSide;
+    return 1 + match_candidates(m, r, Ls + 1);
+}
+
+static bool is_candidate(int m, int r, int dtype, int L) {
+    int Ls[kNumForms];
+    const int n = plan_candidates(m, r, dtype, Ls);
     for (int k = 0; k < n; ++k)
         if (Ls[k] == L) return true;
     return false;
@@ -246,7 +263,7 @@ TuneCache tune_cache_read(const char* path) {
         for (int k = 0; k < 5 && ok; ++k) ok = parse_field(tok[k + 1], &v[k]);
         if (!ok) continue;
         const int z = v[0], dt = v[1], m = v[2], r = v[3], L = v[4];
-        if (z < 1 || dtype_size(dt) == 0 || !is_candidate(m, r, L)) continue;
+        if (z < 1 || dtype_size(dt) == 0 || !is_candidate(m, r, dt, L)) continue;
         cache[TuneKey(tok[0], z, dt, m, r)] = L;
     }
     fclose(f);
@@ -270,7 +287,7 @@ bool tune_cache_write(const char* path, const TuneCache& cache) {
 
 int tune_cache_lookup(const TuneCache& cache, const std::string& dev, int z, int dtype, int m, int r) {
     const auto it = cache.find(TuneKey(dev, z, dtype, m, r));
-    if (it == cache.end() || !is_candidate(m, r, it->second)) return 0;
+    if (it == cache.end() || !is_candidate(m, r, dtype, it->second)) return 0;
     return it->second;
 }
 

@@ -99,6 +99,26 @@ inline int side_index(int L) {
 // offsets per block must fit the largest transform.
 constexpr int kMaxTemplate = 191;
 
+// The direct form of the match: R_ST (Eq. 10) summed in space on the
+// matrix cores instead of through the FFT, for 16-bit descriptors (exact
+// MFMA operands), up to 32 offsets per axis (one 32 x 32 output tile) and
+// templates up to 64.  Named by the pseudo side kDirectSide wherever a
+// transform side is named.
+constexpr int kDirectSide = SFOC_MATCH_DIRECT;
+constexpr int kDirectMaxV = 32, kDirectMaxM = 64;
+inline SFOC_HOST_DEVICE bool direct_ok(int m, int r, int dtype) {
+    return (dtype == SFOC_DTYPE_BF16 || dtype == SFOC_DTYPE_F16) && m >= 3 && m <= kDirectMaxM && r >= 1 &&
+           2 * r + 1 <= kDirectMaxV;
+}
+// Launch forms of a batched plan: the transform sides, then the direct form.
+constexpr int kNumForms = 5;
+constexpr int kForms[kNumForms] = {64, 128, 160, 192, kDirectSide};
+inline int form_index(int L) {
+    for (int k = 0; k < kNumForms; ++k)
+        if (kForms[k] == L) return k;
+    return -1;
+}
+
 // How a match is laid out: FFT side L and the split of the (2r+1)^2 offsets
 // into nb x nb blocks of at most Vb offsets per axis, each with a search
 // window of at most L x L.  L = 0 means unsupported.
@@ -112,6 +132,8 @@ struct MatchPlan {
 MatchPlan match_plan(int32_t n, int32_t m, int32_t r);
 // The same for a given side L (one of kSides); L = 0 in the result if the
 // template does not fit it (a block needs m + Vb - 1 <= L with Vb >= 2).
+// L = kDirectSide: one block of all offsets and no scratch when the sizes
+// allow the direct form (its dtype condition is checked by the caller).
 MatchPlan match_plan_L(int32_t n, int32_t m, int32_t r, int L);
 constexpr int kMaxRadiusMatch = 511;
 // Bytes of the per-window integral images (two (M+1)^2 float64 images per
@@ -124,10 +146,18 @@ size_t match_window_ws_bytes(int32_t n, int32_t m, int32_t r);
 // most kNumSides).
 constexpr int kMaxTuneBlocks = 8;
 int match_candidates(int32_t m, int32_t r, int* Ls);
+// The default form for a descriptor dtype: the direct form where direct_ok
+// holds (it is the faster wherever it applies), else match_plan.  Its
+// scratch never exceeds match_plan's.
+MatchPlan match_plan_dt(int32_t n, int32_t m, int32_t r, int32_t dtype);
+// The forms a batched plan's autotuner times for (m, r) and a descriptor
+// dtype: the default of match_plan_dt first, then the other transform sides
+// of match_candidates.  At most kNumForms.
+int plan_candidates(int32_t m, int32_t r, int32_t dtype, int* Ls);
 
 // Autotuner cache: one text line "device z dtype m r L" per (m, r) class
 // timed before.  Reading keeps only lines that parse completely and whose
-// side L is one of match_candidates(m, r) for a positive z and a known
+// form L is one of plan_candidates(m, r, dtype) for a positive z and a known
 // dtype; anything else in the file (a corrupt or hand-edited line) is
 // skipped, so a cached side is always one the match launches accept.
 using TuneKey = std::tuple<std::string, int, int, int, int>;   // device, z, dtype, m, r

@@ -71,10 +71,12 @@ class PlanInfo(ctypes.Structure):
                 ("match_items", ctypes.c_int32 * 4), ("peak_items", ctypes.c_int32),
                 ("tuned_classes", ctypes.c_int32), ("cached_classes", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("persistent", ctypes.c_int32 * 4), ("describe_config", ctypes.c_int32),
+                ("direct_items", ctypes.c_int32),
                 ("device_bytes", ctypes.c_int64)]
 
 
 PLAN_GRAPH, PLAN_AUTOTUNE, PLAN_DENSE_SEN, PLAN_PERSISTENT, PLAN_DESCRIBE_ALT = 1, 2, 4, 8, 16
+MATCH_DIRECT = 1   # fft_side naming the direct form (matrix cores; BF16/FP16, 2r+1 <= 32, m <= 64)
 
 
 class RansacParams(ctypes.Structure):
@@ -343,7 +345,7 @@ class Plan:
 
     pairs: sequence of dicts with CUDA tensors ref (Hr, Wr) float32, sen
     (Hs, Ws) float32, ips (n, 2) int32, optional prior (n, 2) int32, and ints
-    m, r, optional fft_side (0 / 64 / 128 / 160 / 192).  The plan owns per-pair outputs
+    m, r, optional fft_side (0 / 64 / 128 / 160 / 192, or MATCH_DIRECT).  The plan owns per-pair outputs
     cps (n, 8) int32 and, with want_ncc, ncc (n, 2r+1, 2r+1); it keeps
     references to every input tensor for its lifetime.  Calling the plan
     runs sfoc_register_cps_batched on the current stream."""
@@ -397,6 +399,7 @@ class Plan:
                 "match_items": tuple(inf.match_items), "peak_items": inf.peak_items,
                 "tuned_classes": inf.tuned_classes, "cached_classes": inf.cached_classes, "graph": inf.graph,
                 "persistent": tuple(inf.persistent), "describe_config": inf.describe_config,
+                "direct_items": inf.direct_items,
                 "device_bytes": inf.device_bytes, "fft_side": list(L), "blocks": list(nb)}
 
     def close(self):

@@ -26,7 +26,7 @@ def test_pair_and_info_layout_match_header(tmp_path):
 int main(void) {
   P(ref) P(Hr) P(Wr) P(ldr) P(sen) P(Hs) P(Ws) P(lds) P(ips) P(prior) P(n) P(m) P(r) P(fft_side) P(ncc) P(cps)
   I(n_pairs) I(describe_tiles) I(match_items) I(peak_items) I(tuned_classes) I(cached_classes) I(graph)
-  I(persistent) I(describe_config)
+  I(persistent) I(describe_config) I(direct_items)
   I(device_bytes)
   printf("pair.size %zu\ninfo.size %zu\n", sizeof(sfoc_pair), sizeof(sfoc_plan_info));
   return 0;
@@ -214,6 +214,8 @@ def _pair(**kw):
     ({"m": 192, "r": 10}, 0, S.SFOC_E_UNSUPPORTED),
     ({"cps": None}, 0, S.SFOC_E_INVALID_ARG),
     ({"Hs": 1 << 17}, 0, S.SFOC_E_UNSUPPORTED),
+    ({"fft_side": S.MATCH_DIRECT}, 0, S.SFOC_E_UNSUPPORTED),        # the direct form needs 16-bit storage
+    ({"fft_side": 2}, 0, S.SFOC_E_INVALID_ARG),
 ])
 def test_plan_create_rejects_bad_pairs(kw, flags, code):
     arr = (S.Pair * 2)(_pair(), _pair(**kw))
@@ -221,6 +223,17 @@ def test_plan_create_rejects_bad_pairs(kw, flags, code):
     h = ctypes.c_void_p(0)
     rc = S.lib().sfoc_plan_create(arr, 2, ctypes.byref(p), flags, None, None, ctypes.byref(h))
     assert rc == code
+    assert not h.value
+
+
+@pytest.mark.parametrize("kw", [{"r": 16}, {"m": 65, "r": 4}])
+def test_plan_create_direct_form_limits(kw):
+    # the direct form takes 2r + 1 <= 32 offsets per axis and m <= 64
+    arr = (S.Pair * 1)(_pair(fft_side=S.MATCH_DIRECT, **kw))
+    p = S.preset("baseline", dtype=S.DTYPE_BF16)
+    h = ctypes.c_void_p(0)
+    rc = S.lib().sfoc_plan_create(arr, 1, ctypes.byref(p), 0, None, None, ctypes.byref(h))
+    assert rc == S.SFOC_E_UNSUPPORTED
     assert not h.value
 
 

@@ -49,7 +49,7 @@ def default_side(m, r):
 def build_pairs(specs, seed_shift=0):
     out = []
     for seed, hw, crop, m, r, n, use_prior, pitched in specs:
-        pr = synth.make_pair(seed + 100 + seed_shift, hw, max_shift=min(8.0, r - 2.0))
+        pr = synth.make_pair(seed + 100 + seed_shift, hw, max_shift=max(0.0, min(8.0, r - 2.0)))
         sen = pr.sen if crop is None else np.ascontiguousarray(pr.sen[:crop[0], :crop[1]])
         Hs, Ws = sen.shape
         b = (m + 1) // 2 + r
@@ -280,3 +280,68 @@ def test_rounded_storage_plan(kind):
         st = compare_cps(g, o, so, q["r"], surf_g=plan.ncc[k].cpu().numpy(), check_consistency=False)
         say("  pair", k, st)
     plan.close()
+
+
+# pairs the direct form takes (2r + 1 <= 32, m <= 64): small and odd m, r = 1, the largest window
+# (m 64, r 15: 94 columns, six 16-column chunks), a prior and a pitched reference
+DIRECT_SPECS = [
+    SPECS[0], SPECS[1], SPECS[3],
+    (8, (260, 250), None, 64, 15, 10, True, False),
+    (9, (120, 130), None, 5, 1, 8, False, False),
+    (10, (200, 200), (150, 170), 33, 7, 11, False, True),
+]
+
+
+@pytest.mark.parametrize("kind", ["bf16", "f16"])
+def test_direct_form_matches_oracle(kind):
+    """The direct form (R_ST summed in space on the matrix cores) against
+    the oracle on the same rounded descriptors, surfaces included, in a
+    captured plan replayed twice; the autotuner may pick it for 16-bit
+    storage and its choice stays within the oracle's tolerances."""
+    say("direct form", kind)
+    p = S.preset("baseline", dtype={"bf16": S.DTYPE_BF16, "f16": S.DTYPE_F16}[kind])
+    pairs = build_pairs(DIRECT_SPECS)
+    dp = to_device(pairs)
+    for d in dp:
+        d["fft_side"] = S.MATCH_DIRECT
+    plan = S.Plan(dp, p, flags=S.PLAN_GRAPH, want_ncc=True)
+    info = plan.info()
+    assert info["fft_side"] == [S.MATCH_DIRECT] * len(pairs)
+    assert info["direct_items"] == sum(len(q["ips"]) for q in pairs)
+    assert info["match_items"] == (0, 0, 0, 0)
+    first = None
+    for rep in range(2):
+        plan()
+        torch.cuda.synchronize()
+        got = [(plan.cps[k].cpu().numpy(), plan.ncc[k].cpu().numpy()) for k in range(len(pairs))]
+        if first is None:
+            first = got
+        else:
+            for (c0, n0), (c1, n1) in zip(first, got):
+                np.testing.assert_array_equal(c0, c1)
+                np.testing.assert_array_equal(n0, n1)
+    for k, q in enumerate(pairs):
+        if not len(q["ips"]):
+            continue
+        o, so = O.register_cps(q["ref"], q["sen"], q["ips"], q["m"], q["r"], O.Params(), prior=q["prior"],
+                               quantise=kind, want_surfaces=True)
+        g = S.cps_to_numpy(plan.cps[k])
+        st = compare_cps(g, o, so, q["r"], surf_g=plan.ncc[k].cpu().numpy(), check_consistency=False)
+        say("  pair", k, st)
+    plan.close()
+    # autotuned: the direct form is one of the candidates of every class here
+    dp = to_device(pairs)
+    tplan = S.Plan(dp, p, flags=S.PLAN_AUTOTUNE, want_ncc=True)
+    tinfo = tplan.info()
+    for q, L in zip(pairs, tinfo["fft_side"]):
+        assert L in [c[0] for c in S.match_candidates(q["m"], q["r"])] + [S.MATCH_DIRECT]
+    say("  autotuned forms", tinfo["fft_side"])
+    tplan()
+    torch.cuda.synchronize()
+    for k, q in enumerate(pairs):
+        if len(q["ips"]):
+            o, so = O.register_cps(q["ref"], q["sen"], q["ips"], q["m"], q["r"], O.Params(), prior=q["prior"],
+                                   quantise=kind, want_surfaces=True)
+            compare_cps(S.cps_to_numpy(tplan.cps[k]), o, so, q["r"], surf_g=tplan.ncc[k].cpu().numpy(),
+                        check_consistency=False)
+    tplan.close()

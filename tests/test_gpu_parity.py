@@ -289,7 +289,7 @@ def test_register_describes_sensed_tiles_under_templates(dtype):
     matching, bit for bit.  IPs whose templates are clipped by the image
     border or whose search windows leave the reference, a prior, an image of
     another shape, and a second call with fewer IPs on the same workspace
-    (the tile mask of the first call must not carry over)."""
+    (the tile table of the first call must not carry over)."""
     pr = synth.make_pair(77, (230, 300), 6.0)
     ref = pr.ref
     sen = np.ascontiguousarray(pr.sen[:190, :260])

@@ -52,6 +52,30 @@ def test_small_pairs_rounded_storage(kind, seed):
         int(ok.sum())))
 
 
+@pytest.mark.parametrize("kind", ["bf16", "f16"])
+def test_direct_form_per_window_integrals(kind):
+    """Small windows with 16-bit storage take the direct form (R_ST summed
+    in space on the matrix cores) by default: the match call with the
+    reference's integral images and with per-window ones (NULL) against the
+    oracle on the rounded descriptors, prior included."""
+    say("direct form, single pair", kind)
+    pr, ips, m, r = synth.workload(synth.SMALL, 5)
+    prior = np.random.default_rng(4).integers(-2, 3, ips.shape).astype(np.int32)
+    p = S.preset("baseline", dtype=DT[kind])
+    Fr, i1, i2 = S.describe(dev(pr.ref), p)
+    Fs, _, _ = S.describe(dev(pr.sen), p, integrals=False)
+    oq, sq = O.register_cps(pr.ref, pr.sen, ips, m, r, O.Params(), quantise=kind, prior=prior,
+                            want_surfaces=True)
+    for integ in ((i1, i2), (None, None)):
+        cps, ncc = S.fastncc_match(Fs, Fr, integ[0], integ[1], dev(ips), m, r, prior=dev(prior), want_ncc=True)
+        torch.cuda.synchronize()
+        g = S.cps_to_numpy(cps)
+        st = compare_cps(g, oq, sq, r, ncc.cpu().numpy())
+        flips = {i for i in range(len(oq)) if oq["flags"][i] != g["flags"][i]}
+        assert flips <= consistency_flip_allowed(oq, prior)
+        say("  integral images", "reference" if integ[0] is not None else "per window", st)
+
+
 @pytest.fixture(scope="module")
 def large():
     say("generating the 10000 x 10000 pair")

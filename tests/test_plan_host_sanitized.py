@@ -46,7 +46,7 @@ int main(int argc, char** argv) {
         printf("entry %s %d %d %d %d %d\n", std::get<0>(kv.first).c_str(), std::get<1>(kv.first),
                std::get<2>(kv.first), std::get<3>(kv.first), std::get<4>(kv.first), kv.second);
     const int q[][4] = {{16, 0, 96, 64}, {16, 0, 64, 32}, {16, 0, 48, 16}, {16, 1, 64, 32}, {16, 0, 32, 10},
-                        {16, 0, 96, 16}, {12, 0, 64, 32}};
+                        {16, 0, 96, 16}, {12, 0, 64, 32}, {16, 2, 24, 6}, {16, 0, 24, 6}, {16, 1, 48, 16}};
     for (const auto& k : q)
         printf("lookup %d %d %d %d %d\n", k[0], k[1], k[2], k[3], tune_cache_lookup(c, "gfx950/256cu", k[0], k[1], k[2], k[3]));
     // a hand-inserted entry that is not a candidate is refused at lookup too
@@ -123,6 +123,9 @@ gfx950/256cu 16 0 2 1 64
 gfx950/256cu 16 0 1000000000 1000000000 128
 gfx950/256cu 16 0 -1073741824 1073741824 128
 gfx950/256cu 16 0 32 10 64
+gfx950/256cu 16 2 24 6 1
+gfx950/256cu 16 0 24 6 1
+gfx950/256cu 16 1 48 16 1
 """
 
 
@@ -153,12 +156,13 @@ def test_planner_host_code(tmp_path, sanitize):
         f = l.split()
         got.setdefault(f[0], []).append(f[1:])
     # only the lines that parse completely, with a known dtype, z >= 1 and a
-    # side that match_candidates offers, survive
+    # form that plan_candidates offers (the direct form: 16-bit dtypes, 2r + 1 <= 32), survive
     entries = sorted(tuple(e) for e in got["entry"])
     assert entries == sorted([("gfx950/256cu", "16", "0", "64", "32", "128"),
                               ("gfx950/256cu", "16", "0", "48", "16", "64"),
                               ("gfx950/256cu", "16", "1", "64", "32", "128"),
-                              ("gfx950/256cu", "16", "0", "32", "10", "64")]), entries
+                              ("gfx950/256cu", "16", "0", "32", "10", "64"),
+                              ("gfx950/256cu", "16", "2", "24", "6", "1")]), entries
     look = {tuple(map(int, e[:4])): int(e[4]) for e in got["lookup"]}
     assert look[(16, 0, 96, 64)] == 0       # the corrupt L = 64 line for m 96 was dropped
     assert look[(16, 0, 64, 32)] == 128
@@ -167,6 +171,8 @@ def test_planner_host_code(tmp_path, sanitize):
     assert look[(16, 0, 32, 10)] == 64
     assert look[(16, 0, 96, 16)] == 0       # a trailing token and a side of 96: both dropped
     assert look[(12, 0, 64, 32)] == 0
+    assert look[(16, 2, 24, 6)] == 1        # the direct form, for 16-bit storage only
+    assert look[(16, 0, 24, 6)] == 0 and look[(16, 1, 48, 16)] == 0
     assert got["lookup_inserted"] == [["0"]]
     assert got["write"] == [["1"]] and got["roundtrip"] == [["1"]]
     assert got["missing"] == [["0"]] and got["null"] == [["0"]] and got["write_null"] == [["0"]]
