@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_VALU = 157.3e12       # published FP32 vector rate: 256 CU x 4 SIMD x 32 lanes/cycle x 2 (FMA) x 2.4 GHz
 PEAK_HBM = 8.0e12
+PEAK_BF16_MFMA = 2.5e15         # published dense BF16 / FP16 matrix rate
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_scene2048_rectify10000.md")
@@ -675,6 +676,54 @@ def run_sweep(args, S, torch):
     return res
 
 
+def run_small_windows(args, S, synth, torch, dev):
+    """FFT or matrix cores for small windows: the scene pair and its 400 IPs
+    with the small configuration's template (32) and search radius (10) at
+    bfloat16 storage, matched by the FFT of side 64, by the direct form
+    (R_ST summed in space as 32 x 32 x 16 MFMAs), and by an autotuned plan.
+    Plans with one pair each; per-launch match times from the library's
+    events.  The direct form's rates: useful flops 2 V^2 m^2 z per IP and
+    the MFMA flops it issues, 2 x 32 x 32 x 16 per MFMA, ceil(M / 16) m z
+    MFMAs per IP, against the dense BF16 peak."""
+    import numpy as np
+    pr, ips, _, _ = synth.workload(synth.SCENE, args.seed)
+    m, r = 32, 10
+    V, M = 2 * r + 1, m + 2 * r
+    p = S.preset("baseline", dtype=S.DTYPE_BF16)
+    d = dict(ref=torch.from_numpy(pr.ref).to(dev), sen=torch.from_numpy(pr.sen).to(dev),
+             ips=torch.from_numpy(ips).to(dev), prior=None, m=m, r=r)
+    n = len(ips)
+    out = {"workload": f"scene pair ({pr.ref.shape[0]}x{pr.ref.shape[1]}), {n} IPs, template {m}, search +-{r}, "
+                       f"N=8, sigma 1/2/3, bfloat16 descriptors"}
+    got = {}
+    for name, side, flags in (("fft64", 64, 0), ("direct", S.MATCH_DIRECT, 0), ("autotuned", 0, S.PLAN_AUTOTUNE)):
+        d["fft_side"] = side
+        plan = S.Plan([d], p, flags=flags)
+        for _ in range(3):
+            plan()
+        dt, _, kt, _ = timed_and_traced(S, torch, plan, args.steps)
+        ms = kt["match"][0] / max(1, kt["match"][1])
+        got[name] = S.cps_to_numpy(plan.cps[0]).copy()
+        out[name] = {"form": plan.info()["fft_side"][0], "match_us": 1e3 * ms, "ms_per_step": 1e3 * dt,
+                     "cps_per_s": n / dt}
+        plan.close()
+    useful = 2.0 * V * V * m * m * p.z * n
+    issued = 2.0 * 32 * 32 * 16 * ((M + 15) // 16) * m * p.z * n
+    t = out["direct"]["match_us"] * 1e-6
+    out["direct"]["useful_tflops"] = useful / t / 1e12
+    out["direct"]["mfma_tflops"] = issued / t / 1e12
+    out["direct"]["frac_bf16_mfma_peak"] = issued / t / PEAK_BF16_MFMA
+    out["speedup_direct_vs_fft64"] = out["fft64"]["match_us"] / out["direct"]["match_us"]
+    a, b = got["fft64"], got["direct"]
+    bad = S.OOB | S.FLAT_T | S.FLAT_S | S.EDGE_PEAK | S.NONFINITE
+    ok = ((a["flags"] & bad) == 0) & ((b["flags"] & bad) == 0)
+    out["direct_vs_fft64"] = {"integer_cps_equal": int(np.sum((a["dy"] == b["dy"]) & (a["dx"] == b["dx"]) & ok)),
+                              "compared": int(ok.sum()),
+                              "max_score_diff": float(np.abs(a["score"][ok] - b["score"][ok]).max()) if ok.any()
+                              else None}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -692,6 +741,8 @@ def main():
     ap.add_argument("--precision", type=int, default=1, help="bfloat16 / float16 storage sections (0: skip)")
     ap.add_argument("--large", type=int, default=1, help="the 10000^2 precision workload (0: skip)")
     ap.add_argument("--large-steps", type=int, default=3)
+    ap.add_argument("--small-windows", type=int, default=1,
+                    help="FFT vs matrix-core matching for small windows (0: skip)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -799,6 +850,8 @@ def main():
         out["learned"] = run_learned(args, S, synth, torch, p, dev, ref, sen, dips, m, r)
     if args.precision:
         out["precision"] = run_precision(args, S, synth, torch, dev, (pr, ips, m, r))
+    if args.small_windows:
+        out["small_windows"] = run_small_windows(args, S, synth, torch, dev)
     if args.batched_steps > 0:
         del R
         torch.cuda.empty_cache()

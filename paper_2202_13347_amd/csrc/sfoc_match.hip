@@ -1080,14 +1080,21 @@ struct DirGeom {
     int PW;      // window row pitch (elements): 16 NKB + 8
     int WR;      // window rows staged: m + 31
     int PT;      // template row pitch (elements): 16 NKB + 40
+    int OE;      // offset of the O copy from E (elements): m PT, padded to 17 dwords mod 32
     int bytes;   // dynamic LDS: the operands, or the four 32 x 32 float partial surfaces
 };
+// A B-operand read by lanes v = 0..31 of one half-wave touches the E dwords
+// d + 1 .. d + 16 (even v) and the O dwords d .. d + 15 (odd v), d = 8 kb +
+// 4 g plus the row's offset, and one dword later for the second dword read.
+// With O 17 dwords (mod 32) after E the two sets fall on disjoint banks of
+// the 32-bank LDS.
 inline SFOC_HOST_DEVICE DirGeom dir_geom(int m, int nkb) {
     DirGeom g;
     g.PW = 16 * nkb + 8;
     g.WR = m + 31;
     g.PT = 16 * nkb + 40;
-    const int b = 2 * (g.WR * g.PW + 2 * m * g.PT);
+    g.OE = m * g.PT + 2 * ((17 - (m * g.PT / 2) % 32 + 32) % 32);
+    const int b = 2 * (g.WR * g.PW + g.OE + m * g.PT);
     g.bytes = b > 4 * 1024 * 4 ? b : 4 * 1024 * 4;
     return g;
 }
@@ -1134,10 +1141,10 @@ SFOC_DEV void direct_item(const MatchArgs& A, int i, char* lds, double* red) {
     }
     uint16_t* Wl = reinterpret_cast<uint16_t*>(lds);
     uint16_t* E = Wl + g.WR * g.PW;
-    uint16_t* O = E + m * g.PT;
+    uint16_t* O = E + g.OE;
     {   // the zero bands of both operands stay zero for every channel
         uint32_t* zp = reinterpret_cast<uint32_t*>(lds);
-        const int nz = (g.WR * g.PW + 2 * m * g.PT) / 2;
+        const int nz = (g.WR * g.PW + g.OE + m * g.PT) / 2;
         for (int e = t; e < nz; e += kDirNT) zp[e] = 0u;
     }
     __syncthreads();
@@ -1146,83 +1153,93 @@ SFOC_DEV void direct_item(const MatchArgs& A, int i, char* lds, double* red) {
     const int64_t plane_s = A.Hs * A.Ws, plane_r = A.Hr * A.Wr;
     const uint16_t* refp = static_cast<const uint16_t*>(A.desc_ref) + sy * A.Wr + sx;
     const uint16_t* senp = static_cast<const uint16_t*>(A.desc_sen) + ty * A.Ws + tx;
-    // Loads go out eight rows at a time (every wave takes rows w, w + 4, ...;
-    // a lane columns lane and lane + 64, as M < 128), then their LDS stores.
-    constexpr int kB = 8;
-    for (int h = 0; h < A.z; ++h) {
-        // (indices below come from a laundered thread index, so that their
-        // arithmetic is redone per channel rather than hoisted and kept live)
-        {
-            const int tl = tid_local(), ln = tl & 63, wl = __builtin_amdgcn_readfirstlane(tl >> 6);
-            const uint16_t* rp = refp + h * plane_r;
-            // rows and columns clamped into the window: every load is in
-            // bounds and unconditional; only the stores are masked
-            const uint32_t xa = (uint32_t)min(ln, M - 1), xb = (uint32_t)min(ln + 64, M - 1);
-            for (int y0 = wl; y0 < M; y0 += 4 * kB) {
-                const uint16_t* row = rp + (int64_t)y0 * A.Wr;   // wave-uniform base
-                uint16_t va[kB], vb[kB];
+    // A channel's operands go global -> registers -> LDS.  Wave w takes the
+    // rows w, w + 4, ... (at most KR window and KT template rows: M <= 16 NKB,
+    // m <= min(64, 16 NKB)); a lane the columns lane and, when the window is
+    // wider than 64, lane + 64.  Rows and columns are clamped into the window,
+    // so that every load is in bounds and unconditional; only the stores are
+    // masked.  Up to NKB = 4 the next channel's loads are issued before this
+    // channel's MFMAs and land while they run; wider windows (more registers
+    // per lane) load each channel in one batch before its MFMAs.
+    constexpr int KR = 4 * NKB, KC = 16 * NKB > 64 ? 2 : 1, KT = 4 * NKB < 16 ? 4 * NKB : 16;
+    constexpr bool kPrefetch = NKB <= 4;
+    uint16_t wv[KC][KR], tv[KT];
+    auto load = [&](int h) {
+        // (a laundered thread index: the address arithmetic is redone per
+        // channel rather than hoisted out of the loop and kept live)
+        const int tl = tid_local(), ln = tl & 63, wl = __builtin_amdgcn_readfirstlane(tl >> 6);
+        const uint16_t* rp = refp + h * plane_r + (int64_t)wl * A.Wr;   // wave-uniform bases
+        const uint16_t* sp = senp + h * plane_s + (int64_t)wl * A.Ws;
 #pragma unroll
-                for (int j = 0; j < kB; ++j) {
-                    const uint32_t o = (uint32_t)(min(y0 + 4 * j, M - 1) - y0) * (uint32_t)A.Wr;
-                    va[j] = row[o + xa];
-                    vb[j] = row[o + xb];
-                }
-                uint16_t* wrow = Wl + y0 * g.PW;
+        for (int c = 0; c < KC; ++c) {
+            const uint32_t x = (uint32_t)min(ln + 64 * c, M - 1);
 #pragma unroll
-                for (int j = 0; j < kB; ++j)
-                    if (y0 + 4 * j < M) {
-                        if (ln < M) wrow[4 * j * g.PW + ln] = va[j];
-                        if (ln + 64 < M) wrow[4 * j * g.PW + ln + 64] = vb[j];
-                    }
+            for (int j = 0; j < KR; ++j)
+                wv[c][j] = rp[(uint32_t)(min(wl + 4 * j, M - 1) - wl) * (uint32_t)A.Wr + x];
+        }
+        const uint32_t xt = (uint32_t)min(ln, m - 1);
+#pragma unroll
+        for (int j = 0; j < KT; ++j) tv[j] = sp[(uint32_t)(min(wl + 4 * j, m - 1) - wl) * (uint32_t)A.Ws + xt];
+    };
+    auto store = [&]() {
+        const int tl = tid_local(), ln = tl & 63, wl = __builtin_amdgcn_readfirstlane(tl >> 6);
+        uint16_t* wrow = Wl + wl * g.PW + ln;
+#pragma unroll
+        for (int c = 0; c < KC; ++c)
+#pragma unroll
+            for (int j = 0; j < KR; ++j)
+                if (wl + 4 * j < M && ln + 64 * c < M) wrow[4 * j * g.PW + 64 * c] = wv[c][j];
+        uint16_t* erow = E + wl * g.PT + 32 + ln;
+#pragma unroll
+        for (int j = 0; j < KT; ++j)
+            if (wl + 4 * j < m && ln < m) {
+                erow[4 * j * g.PT] = tv[j];
+                erow[4 * j * g.PT + g.OE - 1] = tv[j];   // O[y][31 + x]
+                const double f = (double)(DT == 1 ? bf16_bits_to_f32(tv[j]) : f16_bits_to_f32(tv[j]));
+                s1 += f;
+                s2 += f * f;
+            }
+    };
+    // per template row: every chunk's operands read first, then the MFMAs
+    auto compute = [&]() {
+        const int tl = tid_local(), ln = tl & 63, wl = __builtin_amdgcn_readfirstlane(tl >> 6), u = ln & 31,
+                  gq = ln >> 5;
+        for (int ii = wl; ii < m; ii += 4) {
+            const uint16_t* arow = Wl + (ii + u) * g.PW + 8 * gq;
+            const uint16_t* brow = ((u & 1) ? O : E) + ii * g.PT + 8 * gq + 32 - u - (u & 1);
+            uint4 a[NKB], b[NKB];
+#pragma unroll
+            for (int kb = 0; kb < NKB; ++kb) {
+                a[kb] = *reinterpret_cast<const uint4*>(arow + 16 * kb);
+                const uint32_t* bp = reinterpret_cast<const uint32_t*>(brow + 16 * kb);
+                b[kb] = make_uint4(bp[0], bp[1], bp[2], bp[3]);
+            }
+#pragma unroll
+            for (int kb = 0; kb < NKB; ++kb) {
+                if (kb & 1)
+                    acc1 = dir_mfma<DT>(a[kb], b[kb], acc1);
+                else
+                    acc0 = dir_mfma<DT>(a[kb], b[kb], acc0);
             }
         }
-        {
-            const int tl = tid_local(), ln = tl & 63, wl = __builtin_amdgcn_readfirstlane(tl >> 6);
-            const uint16_t* sp = senp + h * plane_s;
-            const uint32_t xt = (uint32_t)min(ln, m - 1);
-            for (int y0 = wl; y0 < m; y0 += 4 * kB) {
-                const uint16_t* row = sp + (int64_t)y0 * A.Ws;
-                uint16_t vt[kB];
-#pragma unroll
-                for (int j = 0; j < kB; ++j)
-                    vt[j] = row[(uint32_t)(min(y0 + 4 * j, m - 1) - y0) * (uint32_t)A.Ws + xt];
-                uint16_t* erow = E + y0 * g.PT + 32 + ln;
-#pragma unroll
-                for (int j = 0; j < kB; ++j)
-                    if (y0 + 4 * j < m && ln < m) {
-                        erow[4 * j * g.PT] = vt[j];
-                        erow[4 * j * g.PT + m * g.PT - 1] = vt[j];   // O[y][31 + x]
-                        const double f = (double)(DT == 1 ? bf16_bits_to_f32(vt[j]) : f16_bits_to_f32(vt[j]));
-                        s1 += f;
-                        s2 += f * f;
-                    }
-            }
+    };
+    if constexpr (kPrefetch) {
+        load(0);
+        for (int h = 0; h < A.z; ++h) {
+            store();
+            __syncthreads();
+            if (h + 1 < A.z) load(h + 1);
+            compute();
+            __syncthreads();
         }
-        __syncthreads();
-        // per template row: every chunk's operands read first, then the MFMAs
-        {
-            const int tl = tid_local(), ln = tl & 63, wl = __builtin_amdgcn_readfirstlane(tl >> 6), u = ln & 31,
-                      gq = ln >> 5;
-            for (int ii = wl; ii < m; ii += 4) {
-                const uint16_t* arow = Wl + (ii + u) * g.PW + 8 * gq;
-                const uint16_t* brow = ((u & 1) ? O : E) + ii * g.PT + 8 * gq + 32 - u - (u & 1);
-                uint4 a[NKB], b[NKB];
-#pragma unroll
-                for (int kb = 0; kb < NKB; ++kb) {
-                    a[kb] = *reinterpret_cast<const uint4*>(arow + 16 * kb);
-                    const uint32_t* bp = reinterpret_cast<const uint32_t*>(brow + 16 * kb);
-                    b[kb] = make_uint4(bp[0], bp[1], bp[2], bp[3]);
-                }
-#pragma unroll
-                for (int kb = 0; kb < NKB; ++kb) {
-                    if (kb & 1)
-                        acc1 = dir_mfma<DT>(a[kb], b[kb], acc1);
-                    else
-                        acc0 = dir_mfma<DT>(a[kb], b[kb], acc0);
-                }
-            }
+    } else {
+        for (int h = 0; h < A.z; ++h) {
+            load(h);
+            store();
+            __syncthreads();
+            compute();
+            __syncthreads();
         }
-        __syncthreads();
     }
     float* P = reinterpret_cast<float*>(lds);   // wave w's partial surface at P + 1024 w
 #pragma unroll
