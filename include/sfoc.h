@@ -212,6 +212,10 @@ int sfoc_describe_noalloc(const float* img, int64_t H, int64_t W, int64_t ld, co
  * offsets into blocks whose windows fit L x L, with the side of least
  * transform work, and need the workspace sfoc_match_workspace reports
  * (per-CP surfaces and block records; 0 bytes otherwise).
+ * With BFLOAT16 / FLOAT16 descriptors, 2r + 1 <= 32 and m <= 64, R_ST is
+ * instead summed in space on the matrix cores (the direct form,
+ * SFOC_MATCH_DIRECT; exact 16-bit products, float32 sums in another order,
+ * no workspace beyond the integral-mode one).
  * Limits: 3 <= m <= 191, 1 <= r <= 511, each image below 2^30 pixels
  * (SFOC_E_UNSUPPORTED beyond).
  * n == 0 is valid and enqueues nothing.
@@ -361,7 +365,9 @@ int sfoc_plan_get_info(const sfoc_plan* plan, sfoc_plan_info* info, int32_t* fft
  * sfoc_match_candidates: the transform sides (64 / 128 / 160 / 192) usable
  * for template m and radius r with at most 8 offset blocks per axis, the
  * default first and the others by increasing side, and the offset blocks per
- * axis of each; returns the count (0: none; at most 4).
+ * axis of each; returns the count (0: none; at most 4).  With 16-bit
+ * descriptors a plan's autotuner also times the direct form where it
+ * applies, and takes it as the default there.
  * sfoc_sensed_tiles: 32 x 32 sensed-image tiles that cover the m x m
  * templates of the in-bounds IPs (template and search window inside their
  * images; host arrays, no device work).  Tiles start on multiples of 32 in
