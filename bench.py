@@ -349,6 +349,8 @@ def run_precision(args, S, synth, torch, dev, scene):
                 "kernels": kernel_table(kt, args.large_steps, p, H, W, len(lips), lm, lr, dpx),
                 "parity": parity_vs_stored_oracle(S, "large", cps, kind, ref_kind="o64"),
                 "generate_s": gen_s}
+            if kind == "bf16":
+                out["large_streamed_bf16"] = run_streamed(args, S, torch, p, ref, sen, lips, lm, lr, cps, R.wsb)
             del R
             torch.cuda.empty_cache()
         del ref, sen, dips
@@ -674,6 +676,40 @@ def run_sweep(args, S, torch):
                        f"{res['ips_per_pair']} block-FAST IPs per pair, 80x80 templates, r {res['radius']}, "
                        f"paper preset (N 6); SFOC and F-SFOC (first-order channels only)")
     return res
+
+
+def run_streamed(args, S, torch, p, ref, sen, ips, m, r, whole_cps, whole_ws, band_rows=1024):
+    """The 10000 x 10000 precision workload streamed over bands of 1024 IP
+    rows (sfoc_register_cps_streamed, IPs sorted by row): one band's
+    descriptors, integral images and scratch resident at a time.  Step time
+    (the call synchronises twice to plan its bands on the host), workspace
+    against the whole-image call's, integer CPs and flags equal to the
+    whole-image records, and parity against the stored oracle."""
+    import numpy as np
+    order = np.argsort(ips[:, 0], kind="stable")
+    sips = torch.from_numpy(np.ascontiguousarray(ips[order])).to(ref.device)
+    H, W = ref.shape
+    R = S.StreamedRegistrar(H, W, H, W, len(ips), m, r, p, band_rows=band_rows, device=ref.device)
+    R(ref, sen, sips)
+    torch.cuda.synchronize()
+    dts, _, kt, cps = timed_and_traced(S, torch, lambda: R(ref, sen, sips), args.large_steps)
+    g = np.empty((len(ips), 8), np.int32)
+    g[order] = cps.cpu().numpy()
+    w = S.cps_to_numpy(whole_cps)
+    gg = S.cps_to_numpy(g)
+    bands, y0 = 0, None
+    for y in ips[order, 0]:   # the library's band rule: a band starts at the first IP row past the last band
+        if y0 is None or y >= y0 + band_rows:
+            bands, y0 = bands + 1, int(y)
+    out = {"band_rows": band_rows, "bands": bands,
+           "value": len(ips) / dts, "unit": "CPs/s", "ms_per_step": 1e3 * dts, "steps": args.large_steps,
+           "workspace_gb": R.wsb / 1e9, "whole_image_workspace_gb": whole_ws / 1e9,
+           "integer_cps_equal_to_whole": int(np.sum((gg["dy"] == w["dy"]) & (gg["dx"] == w["dx"]))),
+           "flags_equal_to_whole": int(np.sum(gg["flags"] == w["flags"])), "ips": int(len(ips)),
+           "max_score_diff_to_whole": float(np.abs(gg["score"] - w["score"]).max()),
+           "parity": parity_vs_stored_oracle(S, "large", g, "bf16", ref_kind="o64")}
+    del R
+    return out
 
 
 def run_small_windows(args, S, synth, torch, dev):

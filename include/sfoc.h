@@ -240,7 +240,7 @@ int sfoc_fastncc_match(const void* desc_sen, int64_t Hs, int64_t Ws,
  * reference image and of the sensed image's tiles that the templates read
  * (an m x m template at each IP, Section 2.2), integral images of the
  * reference, then sfoc_fastncc_match.  Arguments as above; the descriptors,
- * integral images and the sensed tile mask live inside ws (see
+ * integral images and the sensed tile table live inside ws (see
  * sfoc_register_workspace).  The CPs equal those of sfoc_describe of both
  * whole images followed by sfoc_fastncc_match.
  */
@@ -253,6 +253,39 @@ int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr,
                       int32_t m, int32_t r, const sfoc_params* p,
                       float* ncc, sfoc_cp* cps,
                       void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * The pair call streamed over bands of rows, for scenes whose descriptors
+ * and integral images should not be resident whole (Section 2.2 as in
+ * sfoc_register_cps; the same kernels).  IPs must be sorted by row
+ * (non-decreasing; SFOC_E_INVALID_ARG otherwise) and every row prior must
+ * satisfy |dy| <= max_prior.  A band holds the IPs whose rows lie in
+ * [y0, y0 + band_rows), y0 the first remaining IP's row; for each band the
+ * pair call runs on the reference and sensed rows its search windows and
+ * templates read, widened by the descriptor's filter reach (so every row
+ * read has the whole image's descriptors) and clipped to the images, with
+ * the band's IP rows and priors taken relative to those rows.  The records
+ * are then put back in whole-image rows, and one median-displacement check
+ * runs over all n CPs.  The workspace (sfoc_register_streamed_workspace)
+ * holds one band: band_rows + m + 2r + 2 max_prior rows of the reference
+ * (plus the reach) instead of all Hr.  Integer CPs, flags and records equal
+ * the pair call's on the whole images up to the float64 rounding of box
+ * sums taken from band-relative integral images.
+ * The call reads the IPs (and priors) to the host and synchronises `stream`
+ * twice before its launches (the band plan is made on the host); the rest
+ * is asynchronous on `stream`.
+ * Errors: those of sfoc_register_cps; SFOC_E_INVALID_ARG for band_rows < 1,
+ * max_prior < 0, unsorted IPs or a prior beyond max_prior.
+ */
+int sfoc_register_streamed_workspace(int64_t Hr, int64_t Wr, int64_t Hs, int64_t Ws,
+                                     int32_t n, int32_t m, int32_t r, int32_t band_rows,
+                                     int32_t max_prior, const sfoc_params* p, size_t* bytes);
+int sfoc_register_cps_streamed(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr,
+                               const float* sen, int64_t Hs, int64_t Ws, int64_t lds,
+                               const int32_t* ips, const int32_t* prior, int32_t n,
+                               int32_t m, int32_t r, int32_t band_rows, int32_t max_prior,
+                               const sfoc_params* p, float* ncc, sfoc_cp* cps,
+                               void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Batched registration of many image pairs (uneven sizes, templates and

@@ -2,6 +2,8 @@
 // the caller's stream.  Nothing here allocates device memory.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -85,6 +87,116 @@ static RegisterLayout register_layout(int64_t Hr, int64_t Wr, int64_t Hs, int64_
     off = align_up(off + match_ws, 256);
     L.total = off;
     return L;
+}
+
+// The pair call's launches for sizes already checked and a workspace laid
+// out by register_layout (consistency = false leaves out the median check).
+static hipError_t register_core(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr, const float* sen, int64_t Hs,
+                                int64_t Ws, int64_t lds, const int32_t* ips, const int32_t* prior, int32_t n,
+                                int32_t m, int32_t r, const DescribeConsts& c, int32_t z, int32_t dtype, float* ncc,
+                                sfoc_cp* cps, const RegisterLayout& L, void* ws, hipStream_t st, bool consistency) {
+    const int ntiles = n * template_tile_slots(m, kDescribeTile);
+    char* base = (char*)ws;
+    void* dref = base + L.desc_ref;
+    void* dsen = base + L.desc_sen;
+    double* i1 = (double*)(base + L.integ1);
+    double* i2 = (double*)(base + L.integ2);
+    // Of the sensed image only the tiles under the templates of in-bounds
+    // IPs are described, one table entry per template tile; the table is
+    // written on a second stream while the reference image is described.
+    // The reference's integral scans (memory-bound) then run on that stream
+    // while the sensed image is described; the match waits for both.
+    SideStream* side = nullptr;
+    hipError_t e = side_stream(&side);
+    double* agg = (double*)(base + L.scan);
+    int4* tiles = (int4*)(base + L.tiles);
+    if (e == hipSuccess) e = hipEventRecord(side->start, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->start, 0);
+    if (e == hipSuccess)
+        e = launch_template_tiles(ips, prior, n, m, r, (int)Hs, (int)Ws, (int)Hr, (int)Wr, tiles, side->s);
+    if (e == hipSuccess) e = hipEventRecord(side->tiles, side->s);
+    if (e == hipSuccess) e = launch_describe(ref, (int)Hr, (int)Wr, ldr, dref, i1, i2, agg, c, st);
+    if (e == hipSuccess) e = hipEventRecord(side->fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->fork, 0);
+    if (e == hipSuccess) e = launch_integral(i1, i2, (int)Hr, (int)Wr, agg, side->s);
+    if (e == hipSuccess) e = hipEventRecord(side->join, side->s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, side->tiles, 0);
+    if (e == hipSuccess) e = launch_describe_tiles(sen, (int)Hs, (int)Ws, lds, dsen, tiles, ntiles, c, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, side->join, 0);
+    if (e != hipSuccess || n == 0) return e;
+    return launch_match(dsen, Hs, Ws, dref, Hr, Wr, i1, i2, z, dtype, ips, prior, n, m, r, ncc, cps, base + L.match,
+                        st, consistency);
+}
+
+// ---- band-streamed registration ---------------------------------------------
+// IPs sorted by row are taken in bands: a band starts at the next IP's row y0
+// and holds the IPs with row < y0 + band_rows.  Its sub-images are the rows
+// its templates and search windows read, widened by the filter reach Q + R
+// (so every row read has the descriptors of the whole image) and clipped to
+// the images; IP rows and priors are taken relative to them.
+struct Band {
+    int i0, i1;       // IPs [i0, i1)
+    int64_t s0, s1;   // sensed rows [s0, s1)
+    int64_t r0, r1;   // reference rows [r0, r1)
+};
+
+static void clip_rows(int64_t lo, int64_t hi, int64_t H, int64_t* a, int64_t* b) {
+    *a = std::min(std::max(lo, (int64_t)0), H);
+    *b = std::min(std::max(hi, (int64_t)0), H);
+    if (*b <= *a) {   // nothing of the image is read (every IP of the band is out of bounds): any one row
+        *a = std::min(*a, H - 1);
+        *b = *a + 1;
+    }
+}
+
+static void plan_bands(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m, int32_t r, int64_t Hs,
+                       int64_t Hr, int32_t band_rows, int halo, std::vector<Band>& out) {
+    out.clear();
+    const int64_t M = (int64_t)m + 2 * r;
+    for (int i0 = 0; i0 < n;) {
+        const int64_t y0 = ips[2 * i0];
+        int64_t smin = INT64_MAX, smax = INT64_MIN, rmin = INT64_MAX, rmax = INT64_MIN;
+        int i1 = i0;
+        for (; i1 < n && (int64_t)ips[2 * i1] < y0 + band_rows; ++i1) {
+            const int64_t ty = (int64_t)ips[2 * i1] - m / 2;
+            const int64_t sy = ty - r + (prior ? prior[2 * i1] : 0);
+            smin = std::min(smin, ty);
+            smax = std::max(smax, ty + m);
+            rmin = std::min(rmin, sy);
+            rmax = std::max(rmax, sy + M);
+        }
+        Band b;
+        b.i0 = i0;
+        b.i1 = i1;
+        clip_rows(smin - halo, smax + halo, Hs, &b.s0, &b.s1);
+        clip_rows(rmin - halo, rmax + halo, Hr, &b.r0, &b.r1);
+        out.push_back(b);
+        i0 = i1;
+    }
+}
+
+// Largest band sub-images for band_rows and priors with |dy| <= max_prior.
+static void band_bounds(int64_t Hr, int64_t Hs, int32_t m, int32_t r, int32_t band_rows, int32_t max_prior, int halo,
+                        int64_t* hs, int64_t* hr) {
+    *hs = std::min<int64_t>(Hs, (int64_t)band_rows - 1 + m + 2 * halo);
+    *hr = std::min<int64_t>(Hr, (int64_t)band_rows - 1 + 2 * (int64_t)max_prior + m + 2 * r + 2 * halo);
+}
+
+struct StreamLayout {
+    RegisterLayout band;   // one band's register workspace
+    size_t ips, prior, total;
+};
+
+static StreamLayout stream_layout(int64_t Hr, int64_t Wr, int64_t Hs, int64_t Ws, int32_t n, int32_t m, int32_t r,
+                                  int32_t band_rows, int32_t max_prior, int32_t z, size_t es, int halo) {
+    StreamLayout S;
+    int64_t hs = 0, hr = 0;
+    band_bounds(Hr, Hs, m, r, band_rows, max_prior, halo, &hs, &hr);
+    S.band = register_layout(hr, Wr, hs, Ws, n, m, z, es, match_plan(n, m, r).ws_bytes);
+    S.ips = S.band.total;
+    S.prior = align_up(S.ips + (size_t)n * 2 * sizeof(int32_t), 256);
+    S.total = align_up(S.prior + (size_t)n * 2 * sizeof(int32_t), 256);
+    return S;
 }
 
 }  // namespace sfoc
@@ -236,40 +348,96 @@ int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr, con
     const RegisterLayout L =
         register_layout(Hr, Wr, Hs, Ws, n, m, z, dtype_size(p->desc_dtype), match_plan(n, m, r).ws_bytes);
     if (!ws || ws_bytes < L.total) return SFOC_E_WORKSPACE;
-    char* base = (char*)ws;
-    void* dref = base + L.desc_ref;
-    void* dsen = base + L.desc_sen;
-    double* i1 = (double*)(base + L.integ1);
-    double* i2 = (double*)(base + L.integ2);
-    hipStream_t st = (hipStream_t)stream;
     DescribeConsts c;
     build_describe_consts(p, &c);
-    // Of the sensed image only the tiles under the templates of in-bounds
-    // IPs are described, one table entry per template tile; the table is
-    // written on a second stream while the reference image is described.
-    // The reference's integral scans (memory-bound) then run on that stream
-    // while the sensed image is described; the match waits for both.
-    SideStream* side = nullptr;
-    hipError_t e = side_stream(&side);
-    double* agg = (double*)(base + L.scan);
-    int4* tiles = (int4*)(base + L.tiles);
-    if (e == hipSuccess) e = hipEventRecord(side->start, st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->start, 0);
-    if (e == hipSuccess)
-        e = launch_template_tiles(ips, prior, n, m, r, (int)Hs, (int)Ws, (int)Hr, (int)Wr, tiles, side->s);
-    if (e == hipSuccess) e = hipEventRecord(side->tiles, side->s);
-    if (e == hipSuccess) e = launch_describe(ref, (int)Hr, (int)Wr, ldr, dref, i1, i2, agg, c, st);
-    if (e == hipSuccess) e = hipEventRecord(side->fork, st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->fork, 0);
-    if (e == hipSuccess) e = launch_integral(i1, i2, (int)Hr, (int)Wr, agg, side->s);
-    if (e == hipSuccess) e = hipEventRecord(side->join, side->s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, side->tiles, 0);
-    if (e == hipSuccess) e = launch_describe_tiles(sen, (int)Hs, (int)Ws, lds, dsen, tiles, (int)ntiles, c, st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, side->join, 0);
-    if (e != hipSuccess) return hip_status(e);
+    return hip_status(register_core(ref, Hr, Wr, ldr, sen, Hs, Ws, lds, ips, prior, n, m, r, c, z, p->desc_dtype, ncc,
+                                    cps, L, ws, (hipStream_t)stream, true));
+}
+
+int sfoc_register_streamed_workspace(int64_t Hr, int64_t Wr, int64_t Hs, int64_t Ws, int32_t n, int32_t m,
+                                     int32_t r, int32_t band_rows, int32_t max_prior, const sfoc_params* p,
+                                     size_t* bytes) {
+    if (!bytes || Hr < 1 || Wr < 1 || Hs < 1 || Ws < 1 || band_rows < 1 || max_prior < 0) return SFOC_E_INVALID_ARG;
+    int32_t z = 0;
+    int rc = check_params(p, &z);
+    if (rc) return rc;
+    rc = check_match_shape(n, m, r);
+    if (rc) return rc;
+    DescribeConsts c;
+    build_describe_consts(p, &c);
+    *bytes = stream_layout(Hr, Wr, Hs, Ws, n, m, r, band_rows, max_prior, z, dtype_size(p->desc_dtype), c.Q + c.R)
+                 .total;
+    return SFOC_OK;
+}
+
+int sfoc_register_cps_streamed(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr, const float* sen, int64_t Hs,
+                               int64_t Ws, int64_t lds, const int32_t* ips, const int32_t* prior, int32_t n,
+                               int32_t m, int32_t r, int32_t band_rows, int32_t max_prior, const sfoc_params* p,
+                               float* ncc, sfoc_cp* cps, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_image(ref, Hr, Wr, ldr);
+    if (rc) return rc;
+    rc = check_image(sen, Hs, Ws, lds);
+    if (rc) return rc;
+    int32_t z = 0;
+    rc = check_params(p, &z);
+    if (rc) return rc;
+    rc = check_match_shape(n, m, r);
+    if (rc) return rc;
+    if (band_rows < 1 || max_prior < 0) return SFOC_E_INVALID_ARG;
+    if (Hs * Ws >= kMaxPlane || Hr * Wr >= kMaxPlane) return SFOC_E_UNSUPPORTED;
+    if (n > 0 && (!ips || !cps)) return SFOC_E_INVALID_ARG;
+    if ((int64_t)n * template_tile_slots(m, kDescribeTile) > INT32_MAX) return SFOC_E_UNSUPPORTED;
+    DescribeConsts c;
+    build_describe_consts(p, &c);
+    const int halo = c.Q + c.R;
+    const StreamLayout S =
+        stream_layout(Hr, Wr, Hs, Ws, n, m, r, band_rows, max_prior, z, dtype_size(p->desc_dtype), halo);
+    if (!ws || ws_bytes < S.total) return SFOC_E_WORKSPACE;
     if (n == 0) return SFOC_OK;
-    e = launch_match(dsen, Hs, Ws, dref, Hr, Wr, i1, i2, z, p->desc_dtype, ips, prior, n, m, r, ncc, cps,
-                     base + L.match, st);
+    hipStream_t st = (hipStream_t)stream;
+    // the IPs (and priors) on the host: bands, sorted-order and prior checks
+    std::vector<int32_t> h_ips((size_t)n * 2), h_prior(prior ? (size_t)n * 2 : 0);
+    hipError_t e = hipMemcpyAsync(h_ips.data(), ips, (size_t)n * 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && prior)
+        e = hipMemcpyAsync(h_prior.data(), prior, (size_t)n * 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_status(e);
+    for (int32_t i = 0; i < n; ++i) {
+        if (i > 0 && h_ips[2 * i] < h_ips[2 * i - 2]) return SFOC_E_INVALID_ARG;   // not sorted by row
+        if (prior && std::abs((int64_t)h_prior[2 * i]) > max_prior) return SFOC_E_INVALID_ARG;
+    }
+    std::vector<Band> bands;
+    plan_bands(h_ips.data(), prior ? h_prior.data() : nullptr, n, m, r, Hs, Hr, band_rows, halo, bands);
+    // band-relative IP rows and row priors; far-outside values are clamped
+    // (such IPs are out of bounds either way)
+    const int64_t kFar = (int64_t)1 << 30;
+    std::vector<int32_t> b_ips((size_t)n * 2), b_prior((size_t)n * 2);
+    for (const Band& b : bands)
+        for (int i = b.i0; i < b.i1; ++i) {
+            const int64_t y = (int64_t)h_ips[2 * i] - b.s0;
+            const int64_t py = (prior ? (int64_t)h_prior[2 * i] : 0) + b.s0 - b.r0;
+            b_ips[2 * i] = (int32_t)std::min(std::max(y, -kFar), kFar);
+            b_ips[2 * i + 1] = h_ips[2 * i + 1];
+            b_prior[2 * i] = (int32_t)std::min(std::max(py, -kFar), kFar);
+            b_prior[2 * i + 1] = prior ? h_prior[2 * i + 1] : 0;
+        }
+    char* base = (char*)ws;
+    int32_t* d_ips = (int32_t*)(base + S.ips);
+    int32_t* d_prior = (int32_t*)(base + S.prior);
+    e = hipMemcpyAsync(d_ips, b_ips.data(), b_ips.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_prior, b_prior.data(), b_prior.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host arrays go out of scope before the bands finish
+    const int64_t V = 2 * (int64_t)r + 1;
+    for (size_t k = 0; k < bands.size() && e == hipSuccess; ++k) {
+        const Band& b = bands[k];
+        const int nb = b.i1 - b.i0;
+        e = register_core(ref + b.r0 * ldr, b.r1 - b.r0, Wr, ldr, sen + b.s0 * lds, b.s1 - b.s0, Ws, lds,
+                          d_ips + 2 * b.i0, d_prior + 2 * b.i0, nb, m, r, c, z, p->desc_dtype,
+                          ncc ? ncc + b.i0 * V * V : nullptr, cps + b.i0, S.band, ws, st, false);
+        if (e == hipSuccess) e = launch_cp_row_shift(cps + b.i0, nb, (int)b.s0, st);
+    }
+    if (e == hipSuccess) e = launch_consistency(cps, prior, n, st);
     return hip_status(e);
 }
 

@@ -80,10 +80,16 @@ hipError_t launch_template_tiles(const int32_t* ips, const int32_t* prior, int n
 hipError_t launch_integral(double* i1, double* i2, int H, int W, double* agg, hipStream_t st);
 // i1 == i2 == null: per-window integral images, built into ws after the
 // split-offset scratch (match_window_ws_bytes).
+// consistency = false leaves out the median-displacement check (see
+// launch_consistency).
 hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void* desc_ref, int64_t Hr, int64_t Wr,
                         const double* i1, const double* i2, int z, int dtype, const int32_t* ips,
                         const int32_t* prior, int n, int m, int r, float* ncc, sfoc_cp* cps, void* ws,
-                        hipStream_t st);
+                        hipStream_t st, bool consistency = true);
+// The median-displacement consistency check over n records (one workgroup).
+hipError_t launch_consistency(sfoc_cp* cps, const int32_t* prior, int n, hipStream_t st);
+// cps[i].sen_row += dy for i < n.
+hipError_t launch_cp_row_shift(sfoc_cp* cps, int n, int dy, hipStream_t st);
 // Fills the offset-block fields and scratch pointers of `a` for transform
 // side L (a.surf / a.blk point into ws, whose size is match_plan_L().ws_bytes).
 void match_args_layout(MatchArgs& a, const MatchPlan& mp, void* ws);

@@ -1611,7 +1611,7 @@ static hipError_t launch_match_side(const MatchArgs& a, int dtype, hipStream_t s
 hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void* desc_ref, int64_t Hr, int64_t Wr,
                         const double* i1, const double* i2, int z, int dtype, const int32_t* ips,
                         const int32_t* prior, int n, int m, int r, float* ncc, sfoc_cp* cps, void* ws,
-                        hipStream_t st) {
+                        hipStream_t st, bool consistency) {
     MatchArgs a;
     a.desc_sen = desc_sen;
     a.desc_ref = desc_ref;
@@ -1663,9 +1663,28 @@ hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void
                            (const int4*)nullptr);
         trace_end(st, SFOC_K_PEAK);
     }
+    if (!consistency) return hipGetLastError();
+    return launch_consistency(cps, prior, n, st);
+}
+
+hipError_t launch_consistency(sfoc_cp* cps, const int32_t* prior, int n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
     trace_begin(st, SFOC_K_CONSISTENCY);
     hipLaunchKernelGGL(consistency_kernel, dim3(1), dim3(kConsNT), 0, st, cps, prior, n, (const MatchArgs*)nullptr);
     trace_end(st, SFOC_K_CONSISTENCY);
+    return hipGetLastError();
+}
+
+// Adds dy to the sensed row of n CP records (records of IPs matched in a
+// band of rows, whose coordinates were taken relative to the band).
+__global__ __launch_bounds__(256) void cp_row_shift_kernel(sfoc_cp* cps, int n, int dy) {
+    const int i = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (i < n) cps[i].sen_row += dy;
+}
+
+hipError_t launch_cp_row_shift(sfoc_cp* cps, int n, int dy, hipStream_t st) {
+    if (n == 0 || dy == 0) return hipSuccess;
+    hipLaunchKernelGGL(cp_row_shift_kernel, dim3((n + 255) / 256), dim3(256), 0, st, cps, n, dy);
     return hipGetLastError();
 }
 

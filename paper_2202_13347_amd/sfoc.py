@@ -117,6 +117,10 @@ def lib() -> ctypes.CDLL:
         L.sfoc_register_workspace.argtypes = [i64, i64, i64, i64, i32, i32, i32, P, ctypes.POINTER(sz)]
         L.sfoc_register_cps.argtypes = [vp, i64, i64, i64, vp, i64, i64, i64, vp, vp, i32, i32, i32, P,
                                         vp, vp, vp, sz, vp]
+        L.sfoc_register_streamed_workspace.argtypes = [i64, i64, i64, i64, i32, i32, i32, i32, i32, P,
+                                                       ctypes.POINTER(sz)]
+        L.sfoc_register_cps_streamed.argtypes = [vp, i64, i64, i64, vp, i64, i64, i64, vp, vp, i32, i32, i32, i32,
+                                                 i32, P, vp, vp, vp, sz, vp]
         L.sfoc_plan_create.argtypes = [ctypes.POINTER(Pair), i32, P, i32, ctypes.c_char_p, vp,
                                        ctypes.POINTER(vp)]
         L.sfoc_register_cps_batched.argtypes = [vp, vp]
@@ -145,7 +149,7 @@ def lib() -> ctypes.CDLL:
                                          ctypes.c_int]
         for name in ("sfoc_trace_enable", "sfoc_trace_collect", "sfoc_params_preset", "sfoc_params_check", "sfoc_describe_workspace", "sfoc_describe",
                      "sfoc_match_workspace", "sfoc_fastncc_match", "sfoc_register_workspace",
-                     "sfoc_register_cps", "sfoc_plan_create", "sfoc_register_cps_batched", "sfoc_plan_destroy",
+                     "sfoc_register_cps", "sfoc_register_streamed_workspace", "sfoc_register_cps_streamed", "sfoc_plan_create", "sfoc_register_cps_batched", "sfoc_plan_destroy",
                      "sfoc_plan_get_info", "sfoc_match_candidates", "sfoc_head_features", "sfoc_head_workspace",
                      "sfoc_head_forward", "sfoc_head_train_step", "sfoc_head_infer", "sfoc_ransac_workspace",
                      "sfoc_ransac_cps", "sfoc_rectify", "sfoc_fast_workspace", "sfoc_detect_ips"):
@@ -338,6 +342,37 @@ def register_cps(ref, sen, ips, m: int, r: int, p: Params, prior=None, want_ncc=
                   device=ref.device, want_ncc=want_ncc)
     cps = R(ref, sen, ips, prior, stream)
     return (cps, R.ncc) if want_ncc else cps
+
+
+class StreamedRegistrar:
+    """Holds the one-band workspace of sfoc_register_cps_streamed: IPs sorted
+    by row, taken band_rows rows at a time, row priors within max_prior."""
+
+    def __init__(self, Hr, Wr, Hs, Ws, n, m, r, p: Params, band_rows: int, max_prior: int = 0, device="cuda",
+                 want_ncc=False):
+        torch = _torch()
+        self.p = p.copy()
+        self.shape = (Hr, Wr, Hs, Ws, n, m, r)
+        self.band_rows, self.max_prior = int(band_rows), int(max_prior)
+        b = ctypes.c_size_t(0)
+        _check(lib().sfoc_register_streamed_workspace(Hr, Wr, Hs, Ws, n, m, r, self.band_rows, self.max_prior,
+                                                      ctypes.byref(self.p), ctypes.byref(b)),
+               "sfoc_register_streamed_workspace")
+        self.wsb = b.value
+        self.ws = torch.empty(self.wsb, dtype=torch.uint8, device=device)
+        self.cps = torch.empty((n, 8), dtype=torch.int32, device=device)
+        V = 2 * r + 1
+        self.ncc = torch.empty((n, V, V), dtype=torch.float32, device=device) if want_ncc else None
+
+    def __call__(self, ref, sen, ips, prior=None, stream=None):
+        Hr, Wr, Hs, Ws, n, m, r = self.shape
+        assert ref.shape == (Hr, Wr) and sen.shape == (Hs, Ws) and ips.shape[0] == n
+        rc = lib().sfoc_register_cps_streamed(_ptr(ref), Hr, Wr, ref.stride(0), _ptr(sen), Hs, Ws, sen.stride(0),
+                                              _ptr(ips), _ptr(prior), n, m, r, self.band_rows, self.max_prior,
+                                              ctypes.byref(self.p), _ptr(self.ncc), _ptr(self.cps), _ptr(self.ws),
+                                              self.wsb, _stream(stream))
+        _check(rc, "sfoc_register_cps_streamed")
+        return self.cps
 
 
 class Plan:

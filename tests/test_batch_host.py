@@ -250,3 +250,23 @@ def test_plan_create_rejects_empty_and_null():
         S.SFOC_E_INVALID_ARG
     assert S.lib().sfoc_register_cps_batched(None, None) == S.SFOC_E_INVALID_ARG
     assert S.lib().sfoc_plan_destroy(None) == S.SFOC_E_INVALID_ARG
+
+
+def test_streamed_workspace_query():
+    p = S.preset("baseline")
+    b = ctypes.c_size_t(0)
+    q = S.lib().sfoc_register_streamed_workspace
+    assert q(10000, 10000, 10000, 10000, 5000, 64, 48, 0, 0, ctypes.byref(p), ctypes.byref(b)) == S.SFOC_E_INVALID_ARG
+    assert q(10000, 10000, 10000, 10000, 5000, 64, 48, 512, -1, ctypes.byref(p), ctypes.byref(b)) == \
+        S.SFOC_E_INVALID_ARG
+    assert q(10000, 10000, 10000, 10000, 5000, 2, 48, 512, 0, ctypes.byref(p), ctypes.byref(b)) == \
+        S.SFOC_E_INVALID_ARG
+    assert q(10000, 10000, 10000, 10000, 5000, 64, 48, 1024, 8, ctypes.byref(p), ctypes.byref(b)) == S.SFOC_OK
+    band = b.value
+    whole = S.register_workspace(10000, 10000, 10000, 10000, 5000, 64, 48, p)
+    assert band < whole / 4
+    # a band taller than the images needs what the whole-image call needs, plus the IP copies
+    assert q(10000, 10000, 10000, 10000, 5000, 64, 48, 1 << 20, 8, ctypes.byref(p), ctypes.byref(b)) == S.SFOC_OK
+    assert whole <= b.value <= whole + 2 * 5000 * 8 + 512
+    assert S.lib().sfoc_register_cps_streamed(None, 10, 10, 10, None, 10, 10, 10, None, None, 0, 16, 4, 8, 0,
+                                              ctypes.byref(p), None, None, None, 0, None) == S.SFOC_E_INVALID_ARG
