@@ -292,11 +292,39 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
     std::vector<DescribeJob> djobs(2 * (size_t)n_pairs);
     std::vector<int4> dtiles;
     std::vector<std::pair<int, int>> sens;
-    for (int k = 0; k < n_pairs; ++k) {   // reference tiles first
+    // Reference tiles first.  Sparse: the tiles the search windows read are
+    // described; the others only get zero aggregates (entries with w = 1,
+    // after the rest), so that the integral images stay exact wherever a
+    // window reads them, and only the read tiles get integral-image passes.
+    std::vector<std::vector<uint8_t>> rmask(n_pairs);
+    std::vector<int4> rzero, rread;
+    for (int k = 0; k < n_pairs; ++k) {
         const sfoc_pair& q = pairs[k];
         const int ntyr = (int)((q.Hr + T - 1) / T), ntxr = (int)((q.Wr + T - 1) / T);
+        if (sparse) {
+            rmask[k].assign((size_t)ntyr * ntxr, 0);
+            if (q.n > 0)
+                window_tile_mask(hips[k].data(), q.prior ? hprior[k].data() : nullptr, q.n, q.m, q.r, q.Hs, q.Ws,
+                                 q.Hr, q.Wr, T, rmask[k].data());
+        }
         for (int a = 0; a < ntyr; ++a)
-            for (int b = 0; b < ntxr; ++b) dtiles.push_back(make_int4(2 * k, a * T, b * T, 0));
+            for (int b = 0; b < ntxr; ++b) {
+                const bool read = !sparse || rmask[k][(size_t)a * ntxr + b];
+                (read ? rread : rzero).push_back(make_int4(2 * k, a * T, b * T, read ? 0 : 1));
+            }
+    }
+    // The describe kernel deals its entries to the eight XCDs as eight
+    // contiguous runs; each run gets an eighth of the described tiles.
+    {
+        const size_t N = rread.size() + rzero.size(), R = N / 8, nc = rread.size();
+        size_t ic = 0, iz = 0;
+        for (size_t x = 0; x < 8; ++x) {
+            const size_t want = (x + 1) * nc / 8 - x * nc / 8;
+            for (size_t j = 0; j < R; ++j)
+                dtiles.push_back(((j < want && ic < nc) || iz == rzero.size()) ? rread[ic++] : rzero[iz++]);
+        }
+        while (ic < nc) dtiles.push_back(rread[ic++]);
+        while (iz < rzero.size()) dtiles.push_back(rzero[iz++]);
     }
     const int nref_tiles = (int)dtiles.size();
     for (int k = 0; k < n_pairs; ++k) {
@@ -340,7 +368,8 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
         pm[k].scan = cur.take(describe_ws_bytes(q.Hr, q.Wr));
         pm[k].ws = cur.take(ws);
     }
-    // integral-image work lists: prefix items, then every tile of each reference
+    // integral-image work lists: prefix items, then the reference tiles the
+    // windows read (every tile when dense)
     std::vector<IntegJob> ijobs(n_pairs);
     std::vector<int4> ipre, itiles;
     size_t max_items[kNumForms] = {}, max_peak = 0;
@@ -350,7 +379,8 @@ int sfoc_plan_create(const sfoc_pair* pairs, int32_t n_pairs, const sfoc_params*
         integral_prefix_items(k, (int)q.Hr, (int)q.Wr, ipre);
         const IntegAgg ag = integ_agg(q.Hr, q.Wr);
         for (int a = 0; a < ag.nty; ++a)
-            for (int b = 0; b < ag.ntx; ++b) itiles.push_back(make_int4(k, a, b, 0));
+            for (int b = 0; b < ag.ntx; ++b)
+                if (!sparse || rmask[k][(size_t)a * ag.ntx + b]) itiles.push_back(make_int4(k, a, b, 0));
         for (int L : cands[k]) {
             const MatchPlan m = match_plan_L(q.n, q.m, q.r, L);
             max_items[bucket_of(L)] += (size_t)q.n * m.nb * m.nb;

@@ -222,6 +222,19 @@ constexpr int describe_wpc() { return VAR ? 4 : (Z >= 32 ? 2 : 3); }
 template <int Z, bool FAST, int VAR>
 constexpr int describe_cg() { return VAR ? 1 : (FAST ? 2 : (Z >= 4 ? 4 : Z)); }
 
+// The row sums, column sums and total of a tile that is not described, set
+// to zero (the layout of the describe kernel's aggregate output).
+SFOC_DEV void zero_tile_aggregates(const DescribeJob& J, int ty0, int tx0) {
+    const IntegAgg ag = integ_agg(J.H, J.W);
+    const int t = threadIdx.x, ta = ty0 / kTS, tb = tx0 / kTS;
+    if (t < 2 * kTS) {
+        const int q = t / kTS, i = t % kTS;
+        if (ty0 + i < J.H) J.agg[(q ? ag.rs2 : ag.rs1) + tb * (int64_t)J.H + ty0 + i] = 0.0;
+        if (tx0 + i < J.W) J.agg[(q ? ag.cs2 : ag.cs1) + ta * (int64_t)J.W + tx0 + i] = 0.0;
+        if (i == 0) J.agg[(q ? ag.tt2 : ag.tt1) + ta * ag.ntx + tb] = 0.0;
+    }
+}
+
 template <int Z, int CG, bool FAST, int VAR>
 __global__ __launch_bounds__(kNT, (describe_wpc<Z, FAST, VAR>())) void describe_kernel(const DescribeJob single,
                                                           const DescribeJob* __restrict__ jobs,
@@ -238,14 +251,20 @@ __global__ __launch_bounds__(kNT, (describe_wpc<Z, FAST, VAR>())) void describe_
     const int id = (int)(blockIdx.y * gridDim.x + blockIdx.x);
     const int k = id < q8 ? (id % 8) * (q8 / 8) + id / 8 : id;
     if (tiles) {
-        // entries: {job, tile row origin, tile column origin}; without a job
-        // table every entry is of `single`, and a negative job is an empty
-        // slot that the whole workgroup skips
+        // entries: {job, tile row origin, tile column origin, what}; without
+        // a job table every entry is of `single`, and a negative job is an
+        // empty slot that the whole workgroup skips.  what = 1: a grid tile
+        // that nothing reads, whose integral-image aggregates are set to
+        // zero (the box sums over the tiles that are described stay exact)
         const int4 e = tiles[k];
         if (e.x < 0) return;
         J = jobs ? load_table(jobs, e.x) : single;
         ty0 = e.y;
         tx0 = e.z;
+        if (e.w == 1) {
+            if (J.agg) zero_tile_aggregates(J, ty0, tx0);
+            return;
+        }
     } else {
         J = single;
         ty0 = (k / gridDim.x) * kTS;

@@ -7,6 +7,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <set>
 
 namespace sfoc {
@@ -319,6 +320,21 @@ void sensed_tiles(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m
             }
     }
     if (cover == kCoverGrid) out.assign(seen.begin(), seen.end());   // row-major
+}
+
+void window_tile_mask(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m, int32_t r, int64_t Hs,
+                      int64_t Ws, int64_t Hr, int64_t Wr, int T, uint8_t* mask) {
+    const int64_t ntx = (Wr + T - 1) / T, nty = (Hr + T - 1) / T, M = (int64_t)m + 2 * r;
+    memset(mask, 0, (size_t)(ntx * nty));
+    for (int32_t i = 0; i < n; ++i) {
+        int64_t ty, c0, c1;
+        const int pry = prior ? prior[2 * i] : 0, prx = prior ? prior[2 * i + 1] : 0;
+        if (!template_tile_range(ips[2 * i], ips[2 * i + 1], pry, prx, m, r, Hs, Ws, Hr, Wr, T, &ty, &c0, &c1))
+            continue;
+        const int64_t sy = (int64_t)ips[2 * i] - m / 2 - r + pry, sx = (int64_t)ips[2 * i + 1] - m / 2 - r + prx;
+        for (int64_t a = std::max<int64_t>(sy - 1, 0) / T; a <= (sy + M - 1) / T; ++a)
+            for (int64_t b = std::max<int64_t>(sx - 1, 0) / T; b <= (sx + M - 1) / T; ++b) mask[a * ntx + b] = 1;
+    }
 }
 
 }  // namespace sfoc

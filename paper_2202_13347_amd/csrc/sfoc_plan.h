@@ -202,6 +202,14 @@ constexpr int kCoverTemplate = SFOC_COVER_TEMPLATE, kCoverGrid = SFOC_COVER_GRID
 void sensed_tiles(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m, int32_t r, int64_t Hs,
                   int64_t Ws, int64_t Hr, int64_t Wr, int T, int cover, std::vector<std::pair<int, int>>& out);
 
+// Reference-image tiles (side T) that the match of in-bounds IPs reads:
+// every tile holding a pixel of [sy - 1, sy + M) x [sx - 1, sx + M), the
+// search window and the row and column before it (whose integral-image
+// entries are the box sums' upper-left corners).  mask has one byte per
+// tile of the Hr x Wr grid, row-major; host arrays (prior may be null).
+void window_tile_mask(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m, int32_t r, int64_t Hs,
+                      int64_t Ws, int64_t Hr, int64_t Wr, int T, uint8_t* mask);
+
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Image sides are limited so that every per-image index fits in int32 and
