@@ -64,7 +64,7 @@ static hipError_t side_stream(SideStream** out) {
 }
 
 struct RegisterLayout {
-    size_t desc_ref, desc_sen, integ1, integ2, scan, tiles, match, total;
+    size_t desc_ref, desc_sen, integ1, integ2, scan, tiles, rmask, match, total;
 };
 
 static RegisterLayout register_layout(int64_t Hr, int64_t Wr, int64_t Hs, int64_t Ws, int32_t n, int32_t m,
@@ -83,6 +83,8 @@ static RegisterLayout register_layout(int64_t Hr, int64_t Wr, int64_t Hs, int64_
     off = align_up(off + describe_ws_bytes(Hr, Wr), 256);
     L.tiles = off;
     off = align_up(off + (size_t)n * template_tile_slots(m, kDescribeTile) * 16, 256);
+    L.rmask = off;
+    off = align_up(off + tile_mask_bytes(Hr, Wr), 256);
     L.match = off;
     off = align_up(off + match_ws, 256);
     L.total = off;
@@ -101,24 +103,28 @@ static hipError_t register_core(const float* ref, int64_t Hr, int64_t Wr, int64_
     void* dsen = base + L.desc_sen;
     double* i1 = (double*)(base + L.integ1);
     double* i2 = (double*)(base + L.integ2);
-    // Of the sensed image only the tiles under the templates of in-bounds
-    // IPs are described, one table entry per template tile; the table is
-    // written on a second stream while the reference image is described.
-    // The reference's integral scans (memory-bound) then run on that stream
-    // while the sensed image is described; the match waits for both.
+    // Of the reference image only the tiles the search windows read are
+    // described (the others get zero integral-image aggregates; their mask
+    // is marked just before), and of the sensed image only the tiles under
+    // the templates of in-bounds IPs, one table entry per template tile,
+    // written on a second stream.  The reference's integral scans
+    // (memory-bound) then run on that stream while the sensed image is
+    // described; the match waits for both.
     SideStream* side = nullptr;
     hipError_t e = side_stream(&side);
     double* agg = (double*)(base + L.scan);
     int4* tiles = (int4*)(base + L.tiles);
+    uint8_t* rmask = (uint8_t*)(base + L.rmask);
     if (e == hipSuccess) e = hipEventRecord(side->start, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->start, 0);
     if (e == hipSuccess)
         e = launch_template_tiles(ips, prior, n, m, r, (int)Hs, (int)Ws, (int)Hr, (int)Wr, tiles, side->s);
     if (e == hipSuccess) e = hipEventRecord(side->tiles, side->s);
-    if (e == hipSuccess) e = launch_describe(ref, (int)Hr, (int)Wr, ldr, dref, i1, i2, agg, c, st);
+    if (e == hipSuccess) e = launch_window_mask(ips, prior, n, m, r, (int)Hs, (int)Ws, (int)Hr, (int)Wr, rmask, st);
+    if (e == hipSuccess) e = launch_describe(ref, (int)Hr, (int)Wr, ldr, dref, i1, i2, agg, c, st, rmask);
     if (e == hipSuccess) e = hipEventRecord(side->fork, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->fork, 0);
-    if (e == hipSuccess) e = launch_integral(i1, i2, (int)Hr, (int)Wr, agg, side->s);
+    if (e == hipSuccess) e = launch_integral(i1, i2, (int)Hr, (int)Wr, agg, side->s, rmask);
     if (e == hipSuccess) e = hipEventRecord(side->join, side->s);
     if (e == hipSuccess) e = hipStreamWaitEvent(st, side->tiles, 0);
     if (e == hipSuccess) e = launch_describe_tiles(sen, (int)Hs, (int)Ws, lds, dsen, tiles, ntiles, c, st);

@@ -238,7 +238,8 @@ SFOC_DEV void zero_tile_aggregates(const DescribeJob& J, int ty0, int tx0) {
 template <int Z, int CG, bool FAST, int VAR>
 __global__ __launch_bounds__(kNT, (describe_wpc<Z, FAST, VAR>())) void describe_kernel(const DescribeJob single,
                                                           const DescribeJob* __restrict__ jobs,
-                                                          const int4* __restrict__ tiles, const DescribeConsts C,
+                                                          const int4* __restrict__ tiles,
+                                                          const uint8_t* __restrict__ tmask, const DescribeConsts C,
                                                           int BSP_, int ISX, int BPP_, int IPP) {
     extern __shared__ float lds[];
     const int t = threadIdx.x;
@@ -269,6 +270,12 @@ __global__ __launch_bounds__(kNT, (describe_wpc<Z, FAST, VAR>())) void describe_
         J = single;
         ty0 = (k / gridDim.x) * kTS;
         tx0 = (k % gridDim.x) * kTS;
+        // a grid tile outside the mask is not described; with integral
+        // inputs its aggregates are set to zero
+        if (tmask && !tmask[(ty0 / kTS) * gridDim.x + tx0 / kTS]) {
+            if (J.agg) zero_tile_aggregates(J, ty0, tx0);
+            return;
+        }
     }
     const float* __restrict__ img = J.img;
     void* __restrict__ desc = J.desc;
@@ -811,7 +818,8 @@ __global__ __launch_bounds__(kScanNT) void integral_prefix(const IntegJob single
 // tiles that border them.
 template <bool BATCH>
 __global__ __launch_bounds__(kScanNT) void integral_tiles(const IntegJob single, const IntegJob* __restrict__ jobs,
-                                                          const int4* __restrict__ tiles) {
+                                                          const int4* __restrict__ tiles,
+                                                          uint8_t* __restrict__ tmask) {
     static_assert(kScanNT == kTS * kTS / kRun, "one run of 4 pixels per thread");
     IntegJob J;
     int ta, tb;
@@ -832,6 +840,12 @@ __global__ __launch_bounds__(kScanNT) void integral_tiles(const IntegJob single,
         J = single;
         ta = k / gridDim.x;
         tb = k - ta * gridDim.x;
+        if (tmask) {   // the mask's last reader: the byte is cleared for the next call
+            const bool read = tmask[k] != 0;
+            __syncthreads();
+            if (threadIdx.x == 0) tmask[k] = 0;
+            if (!read) return;   // a tile that nothing reads
+        }
     }
     __shared__ double above[2][kTS];
     __shared__ double wtot[2][kScanNT / 64][kTS];
@@ -906,7 +920,7 @@ __global__ __launch_bounds__(kScanNT) void integral_tiles(const IntegJob single,
 // ---- launch -------------------------------------------------------------
 template <int Z, bool FAST, int VAR>
 static hipError_t launch_describe_zf(const DescribeJob& job, const DescribeJob* jobs, const int4* tiles, int ntiles,
-                                     const DescribeConsts& c, hipStream_t st) {
+                                     const uint8_t* tmask, const DescribeConsts& c, hipStream_t st) {
     constexpr int CG = describe_cg<Z, FAST, VAR>();
     const DescribeGeom g = describe_geom(c, CG, VAR == 1);
     dim3 grid = tiles ? dim3(ntiles) : dim3((job.W + kTS - 1) / kTS, (job.H + kTS - 1) / kTS);
@@ -915,7 +929,7 @@ static hipError_t launch_describe_zf(const DescribeJob& job, const DescribeJob* 
     hipError_t e = ensure_dynamic_lds((const void*)kern, (int)g.bytes);
     if (e != hipSuccess) return e;
     trace_begin(st, SFOC_K_DESCRIBE);
-    hipLaunchKernelGGL(kern, grid, dim3(kNT), g.bytes, st, job, jobs, tiles, c, g.BSP, g.ISX, g.BPP, g.IPP);
+    hipLaunchKernelGGL(kern, grid, dim3(kNT), g.bytes, st, job, jobs, tiles, tmask, c, g.BSP, g.ISX, g.BPP, g.IPP);
     trace_end(st, SFOC_K_DESCRIBE);
     return hipGetLastError();
 }
@@ -930,25 +944,25 @@ int describe_configs(const DescribeConsts& c) { return describe_fast(c) && c.z <
 
 template <int Z>
 static hipError_t launch_describe_z(const DescribeJob& job, const DescribeJob* jobs, const int4* tiles, int ntiles,
-                                    const DescribeConsts& c, hipStream_t st, int var) {
-    if (!describe_fast(c)) return launch_describe_zf<Z, false, 0>(job, jobs, tiles, ntiles, c, st);
+                                    const uint8_t* tmask, const DescribeConsts& c, hipStream_t st, int var) {
+    if (!describe_fast(c)) return launch_describe_zf<Z, false, 0>(job, jobs, tiles, ntiles, tmask, c, st);
     if constexpr (Z <= 16 && Z % 2 == 0)
-        if (var == 1) return launch_describe_zf<Z, true, 1>(job, jobs, tiles, ntiles, c, st);
-    return launch_describe_zf<Z, true, 0>(job, jobs, tiles, ntiles, c, st);
+        if (var == 1) return launch_describe_zf<Z, true, 1>(job, jobs, tiles, ntiles, tmask, c, st);
+    return launch_describe_zf<Z, true, 0>(job, jobs, tiles, ntiles, tmask, c, st);
 }
 
 static hipError_t launch_describe_any(const DescribeJob& job, const DescribeJob* jobs, const int4* tiles, int ntiles,
-                                      const DescribeConsts& c, hipStream_t st, int var) {
+                                      const uint8_t* tmask, const DescribeConsts& c, hipStream_t st, int var) {
     switch (c.z) {
-        case 2: return launch_describe_z<2>(job, jobs, tiles, ntiles, c, st, var);
-        case 3: return launch_describe_z<3>(job, jobs, tiles, ntiles, c, st, var);
-        case 4: return launch_describe_z<4>(job, jobs, tiles, ntiles, c, st, var);
-        case 6: return launch_describe_z<6>(job, jobs, tiles, ntiles, c, st, var);
-        case 8: return launch_describe_z<8>(job, jobs, tiles, ntiles, c, st, var);
-        case 12: return launch_describe_z<12>(job, jobs, tiles, ntiles, c, st, var);
-        case 16: return launch_describe_z<16>(job, jobs, tiles, ntiles, c, st, var);
-        case 24: return launch_describe_z<24>(job, jobs, tiles, ntiles, c, st, var);
-        case 32: return launch_describe_z<32>(job, jobs, tiles, ntiles, c, st, var);
+        case 2: return launch_describe_z<2>(job, jobs, tiles, ntiles, tmask, c, st, var);
+        case 3: return launch_describe_z<3>(job, jobs, tiles, ntiles, tmask, c, st, var);
+        case 4: return launch_describe_z<4>(job, jobs, tiles, ntiles, tmask, c, st, var);
+        case 6: return launch_describe_z<6>(job, jobs, tiles, ntiles, tmask, c, st, var);
+        case 8: return launch_describe_z<8>(job, jobs, tiles, ntiles, tmask, c, st, var);
+        case 12: return launch_describe_z<12>(job, jobs, tiles, ntiles, tmask, c, st, var);
+        case 16: return launch_describe_z<16>(job, jobs, tiles, ntiles, tmask, c, st, var);
+        case 24: return launch_describe_z<24>(job, jobs, tiles, ntiles, tmask, c, st, var);
+        case 32: return launch_describe_z<32>(job, jobs, tiles, ntiles, tmask, c, st, var);
         default: return hipErrorInvalidValue;
     }
 }
@@ -957,20 +971,20 @@ static hipError_t launch_describe_any(const DescribeJob& job, const DescribeJob*
 hipError_t launch_describe_batched(const DescribeJob* jobs, const int4* tiles, int ntiles, const DescribeConsts& c,
                                    hipStream_t st, int var) {
     DescribeJob none{};
-    return launch_describe_any(none, jobs, tiles, ntiles, c, st, var);
+    return launch_describe_any(none, jobs, tiles, ntiles, nullptr, c, st, var);
 }
 
 hipError_t launch_describe(const float* img, int H, int W, int64_t ld, void* desc, double* i1, double* i2,
-                           double* agg, const DescribeConsts& c, hipStream_t st) {
+                           double* agg, const DescribeConsts& c, hipStream_t st, const uint8_t* tmask) {
     DescribeJob job{img, desc, i1, i2, agg, ld, H, W};
-    return launch_describe_any(job, nullptr, nullptr, 0, c, st, 0);
+    return launch_describe_any(job, nullptr, nullptr, 0, tmask, c, st, 0);
 }
 
 hipError_t launch_describe_tiles(const float* img, int H, int W, int64_t ld, void* desc, const int4* tiles,
                                  int ntiles, const DescribeConsts& c, hipStream_t st) {
     if (ntiles == 0) return hipSuccess;
     DescribeJob job{img, desc, nullptr, nullptr, nullptr, ld, H, W};
-    return launch_describe_any(job, nullptr, tiles, ntiles, c, st, 0);
+    return launch_describe_any(job, nullptr, tiles, ntiles, nullptr, c, st, 0);
 }
 
 // ---- template-aligned sensed tiles ------------------------------------------
@@ -993,6 +1007,34 @@ __global__ __launch_bounds__(256) void template_tiles_kernel(const int32_t* __re
                                   : make_int4(-1, 0, 0, 0);
 }
 
+// ---- reference tiles the search windows read ------------------------------
+// One thread per IP marks the tiles of its window_tile_range (the same rule
+// batched plans apply on the host); byte stores of 1, in any order.  The
+// mask is not cleared first: the integral pass, its last reader, clears
+// every byte it reads, and a byte left set by memory that never held a mask
+// only makes a tile be described that nothing reads.
+__global__ __launch_bounds__(256) void window_mask_mark(const int32_t* __restrict__ ips,
+                                                        const int32_t* __restrict__ prior, int n, int m, int r,
+                                                        int Hs, int Ws, int Hr, int Wr, uint8_t* __restrict__ mask) {
+    const int i = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (i >= n) return;
+    int64_t a0, a1, b0, b1;
+    if (!window_tile_range(ips[2 * i], ips[2 * i + 1], prior ? prior[2 * i] : 0, prior ? prior[2 * i + 1] : 0, m, r,
+                           Hs, Ws, Hr, Wr, kTS, &a0, &a1, &b0, &b1))
+        return;
+    const int64_t ntx = (Wr + kTS - 1) / kTS;
+    for (int64_t a = a0; a <= a1; ++a)
+        for (int64_t b = b0; b <= b1; ++b) mask[a * ntx + b] = 1;
+}
+
+hipError_t launch_window_mask(const int32_t* ips, const int32_t* prior, int n, int m, int r, int Hs, int Ws, int Hr,
+                              int Wr, uint8_t* mask, hipStream_t st) {
+    if (n > 0)
+        hipLaunchKernelGGL(window_mask_mark, dim3((n + 255) / 256), dim3(256), 0, st, ips, prior, n, m, r, Hs, Ws, Hr,
+                           Wr, mask);
+    return hipGetLastError();
+}
+
 hipError_t launch_template_tiles(const int32_t* ips, const int32_t* prior, int n, int m, int r, int Hs, int Ws,
                                  int Hr, int Wr, int4* tiles, hipStream_t st) {
     const int64_t cnt = (int64_t)n * template_tile_slots(m, kTS);
@@ -1002,7 +1044,7 @@ hipError_t launch_template_tiles(const int32_t* ips, const int32_t* prior, int n
     return hipGetLastError();
 }
 
-hipError_t launch_integral(double* i1, double* i2, int H, int W, double* agg, hipStream_t st) {
+hipError_t launch_integral(double* i1, double* i2, int H, int W, double* agg, hipStream_t st, uint8_t* tmask) {
     const IntegJob J{i1, i2, agg, H, W};
     const IntegJob* none = nullptr;
     const int4* nit = nullptr;
@@ -1010,7 +1052,7 @@ hipError_t launch_integral(double* i1, double* i2, int H, int W, double* agg, hi
     trace_begin(st, SFOC_K_INTEGRAL);
     hipLaunchKernelGGL(integral_prefix<false>, dim3(npre), dim3(kScanNT), 0, st, J, none, nit);
     hipLaunchKernelGGL(integral_tiles<false>, dim3((W + kTS - 1) / kTS, (H + kTS - 1) / kTS), dim3(kScanNT), 0, st,
-                       J, none, nit);
+                       J, none, nit, tmask);
     trace_end(st, SFOC_K_INTEGRAL);
     return hipGetLastError();
 }
@@ -1021,7 +1063,8 @@ hipError_t launch_integral_batched(const IntegJob* jobs, const int4* pre, int np
     const IntegJob none{};
     trace_begin(st, SFOC_K_INTEGRAL);
     hipLaunchKernelGGL(integral_prefix<true>, dim3(npre), dim3(kScanNT), 0, st, none, jobs, pre);
-    hipLaunchKernelGGL(integral_tiles<true>, dim3(ntiles), dim3(kScanNT), 0, st, none, jobs, tiles);
+    hipLaunchKernelGGL(integral_tiles<true>, dim3(ntiles), dim3(kScanNT), 0, st, none, jobs, tiles,
+                       (uint8_t*)nullptr);
     trace_end(st, SFOC_K_INTEGRAL);
     return hipGetLastError();
 }

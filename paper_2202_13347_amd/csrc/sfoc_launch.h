@@ -64,8 +64,10 @@ hipError_t ensure_dynamic_lds(const void* kern, int bytes);
 
 // ---- one image / one pair ------------------------------------------------
 // i1, i2 and agg (the aggregates, describe_ws_bytes) all null, or all set.
+// tmask (one byte per tile, row-major, or null): tiles outside it are not
+// described (their aggregates, when asked for, are set to zero).
 hipError_t launch_describe(const float* img, int H, int W, int64_t ld, void* desc, double* i1, double* i2,
-                           double* agg, const DescribeConsts& c, hipStream_t st);
+                           double* agg, const DescribeConsts& c, hipStream_t st, const uint8_t* tmask = nullptr);
 // The tiles of one image that a device table lists ({0, row origin, column
 // origin, 0}; entries with a negative first field are skipped), without
 // integral-image inputs.
@@ -77,7 +79,13 @@ hipError_t launch_template_tiles(const int32_t* ips, const int32_t* prior, int n
                                  int Hr, int Wr, int4* tiles, hipStream_t st);
 // Completes the integral images from what launch_describe left in i1, i2
 // and agg (the same buffers).
-hipError_t launch_integral(double* i1, double* i2, int H, int W, double* agg, hipStream_t st);
+hipError_t launch_integral(double* i1, double* i2, int H, int W, double* agg, hipStream_t st,
+                           uint8_t* tmask = nullptr);
+// Marks in mask (one byte per reference tile) the tiles each in-bounds IP's
+// search window reads (window_tile_range).  Bytes are not cleared here:
+// launch_integral, the last reader, clears every byte of its image's grid.
+hipError_t launch_window_mask(const int32_t* ips, const int32_t* prior, int n, int m, int r, int Hs, int Ws, int Hr,
+                              int Wr, uint8_t* mask, hipStream_t st);
 // i1 == i2 == null: per-window integral images, built into ws after the
 // split-offset scratch (match_window_ws_bytes).
 // consistency = false leaves out the median-displacement check (see

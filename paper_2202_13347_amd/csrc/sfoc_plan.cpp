@@ -152,6 +152,11 @@ size_t describe_ws_bytes(int64_t H, int64_t W) {
     return align_up((size_t)integ_agg(H, W).total * sizeof(double), 256);
 }
 
+size_t tile_mask_bytes(int64_t H, int64_t W) {
+    const IntegAgg g = integ_agg(H, W);
+    return align_up((size_t)(g.ntx * g.nty), 256);
+}
+
 MatchPlan match_plan_L(int32_t n, int32_t m, int32_t r, int L) {
     MatchPlan p{0, 1, 0, 0};
     if (L == kDirectSide) {
@@ -324,16 +329,15 @@ void sensed_tiles(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m
 
 void window_tile_mask(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m, int32_t r, int64_t Hs,
                       int64_t Ws, int64_t Hr, int64_t Wr, int T, uint8_t* mask) {
-    const int64_t ntx = (Wr + T - 1) / T, nty = (Hr + T - 1) / T, M = (int64_t)m + 2 * r;
+    const int64_t ntx = (Wr + T - 1) / T, nty = (Hr + T - 1) / T;
     memset(mask, 0, (size_t)(ntx * nty));
     for (int32_t i = 0; i < n; ++i) {
-        int64_t ty, c0, c1;
-        const int pry = prior ? prior[2 * i] : 0, prx = prior ? prior[2 * i + 1] : 0;
-        if (!template_tile_range(ips[2 * i], ips[2 * i + 1], pry, prx, m, r, Hs, Ws, Hr, Wr, T, &ty, &c0, &c1))
+        int64_t a0, a1, b0, b1;
+        if (!window_tile_range(ips[2 * i], ips[2 * i + 1], prior ? prior[2 * i] : 0, prior ? prior[2 * i + 1] : 0, m,
+                               r, Hs, Ws, Hr, Wr, T, &a0, &a1, &b0, &b1))
             continue;
-        const int64_t sy = (int64_t)ips[2 * i] - m / 2 - r + pry, sx = (int64_t)ips[2 * i + 1] - m / 2 - r + prx;
-        for (int64_t a = std::max<int64_t>(sy - 1, 0) / T; a <= (sy + M - 1) / T; ++a)
-            for (int64_t b = std::max<int64_t>(sx - 1, 0) / T; b <= (sx + M - 1) / T; ++b) mask[a * ntx + b] = 1;
+        for (int64_t a = a0; a <= a1; ++a)
+            for (int64_t b = b0; b <= b1; ++b) mask[a * ntx + b] = 1;
     }
 }
 

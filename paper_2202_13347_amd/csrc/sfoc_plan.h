@@ -83,6 +83,8 @@ inline SFOC_HOST_DEVICE IntegAgg integ_agg(int64_t H, int64_t W) {
 // Bytes of the aggregates (the describe workspace when integral images are
 // asked for): 2 (ntx H + nty W + nty ntx) doubles, about 1 byte per pixel.
 size_t describe_ws_bytes(int64_t H, int64_t W);
+// Bytes of a one-byte-per-tile mask of an H x W image.
+size_t tile_mask_bytes(int64_t H, int64_t W);
 // Size of the library-owned aggregate array of sfoc_describe_noalloc.
 constexpr size_t kNoAllocScratchBytes = SFOC_NOALLOC_SCRATCH_BYTES;
 
@@ -205,8 +207,23 @@ void sensed_tiles(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m
 // Reference-image tiles (side T) that the match of in-bounds IPs reads:
 // every tile holding a pixel of [sy - 1, sy + M) x [sx - 1, sx + M), the
 // search window and the row and column before it (whose integral-image
-// entries are the box sums' upper-left corners).  mask has one byte per
-// tile of the Hr x Wr grid, row-major; host arrays (prior may be null).
+// entries are the box sums' upper-left corners).  window_tile_range gives
+// one IP's tile rows [a0, a1] and columns [b0, b1] (false: the IP reads
+// nothing); window_tile_mask marks those of all IPs, one byte per tile of
+// the Hr x Wr grid, row-major (host arrays; prior may be null).
+inline SFOC_HOST_DEVICE bool window_tile_range(int py, int px, int pry, int prx, int m, int r, int64_t Hs,
+                                               int64_t Ws, int64_t Hr, int64_t Wr, int T, int64_t* a0, int64_t* a1,
+                                               int64_t* b0, int64_t* b1) {
+    int64_t ty, c0, c1;
+    if (!template_tile_range(py, px, pry, prx, m, r, Hs, Ws, Hr, Wr, T, &ty, &c0, &c1)) return false;
+    const int64_t M = (int64_t)m + 2 * r;
+    const int64_t sy = (int64_t)py - m / 2 - r + pry, sx = (int64_t)px - m / 2 - r + prx;
+    *a0 = (sy > 0 ? sy - 1 : 0) / T;
+    *a1 = (sy + M - 1) / T;
+    *b0 = (sx > 0 ? sx - 1 : 0) / T;
+    *b1 = (sx + M - 1) / T;
+    return true;
+}
 void window_tile_mask(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m, int32_t r, int64_t Hs,
                       int64_t Ws, int64_t Hr, int64_t Wr, int T, uint8_t* mask);
 
