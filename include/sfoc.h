@@ -237,12 +237,17 @@ int sfoc_fastncc_match(const void* desc_sen, int64_t Hs, int64_t Ws,
 
 /*
  * Whole fine-registration hot path for one pair: sfoc_describe of the
- * reference image and of the sensed image's tiles that the templates read
- * (an m x m template at each IP, Section 2.2), integral images of the
- * reference, then sfoc_fastncc_match.  Arguments as above; the descriptors,
- * integral images and the sensed tile table live inside ws (see
- * sfoc_register_workspace).  The CPs equal those of sfoc_describe of both
- * whole images followed by sfoc_fastncc_match.
+ * reference image's 32 x 32 tiles that the search windows read (and the row
+ * and column before each window, which hold the box sums' upper-left
+ * corners) and of the sensed image's tiles that the templates read (an
+ * m x m template at each IP, Section 2.2), integral images of the
+ * reference, then sfoc_fastncc_match.  Reference tiles no window reads are
+ * not described and count as zero in the integral images, so every box sum
+ * a window takes is that of the described values.  Arguments as above; the
+ * descriptors, integral images, the sensed tile table and the reference
+ * tile mask live inside ws (see sfoc_register_workspace).  The CPs equal
+ * those of sfoc_describe of both whole images followed by sfoc_fastncc_match
+ * up to the float64 rounding of those box sums (bit for bit in every test).
  */
 int sfoc_register_workspace(int64_t Hr, int64_t Wr, int64_t Hs, int64_t Ws,
                             int32_t n, int32_t m, int32_t r,
@@ -299,10 +304,13 @@ int sfoc_register_cps_streamed(const float* ref, int64_t Hr, int64_t Wr, int64_t
  * (descriptors, integral images, scratch and the launch tables; it is the
  * only call of this library that allocates) and builds the work lists:
  *  - describe: one launch over (image, 32 x 32 tile) entries of all images;
+ *    a reference image gets the tiles its search windows read, as in
+ *    sfoc_register_cps (the others only zero integral-image aggregates);
  *    a sensed image gets only the tiles over its templates, the shorter of
- *    the two lists of sfoc_sensed_tiles (SFOC_COVER_SMALLER), unless
- *    SFOC_PLAN_DENSE_SEN is set (then it is described whole);
- *  - integral images: three launches over all reference images;
+ *    the two lists of sfoc_sensed_tiles (SFOC_COVER_SMALLER); with
+ *    SFOC_PLAN_DENSE_SEN both images are described whole;
+ *  - integral images: three launches over the read tiles of all reference
+ *    images;
  *  - match: one launch per transform side over (pair, IP, offset block)
  *    items, side 64 on a second graph branch beside the larger sides; a
  *    peak launch over pairs
@@ -332,7 +340,7 @@ int sfoc_register_cps_streamed(const float* ref, int64_t Hr, int64_t Wr, int64_t
  * pointers) and keeps them allocated for the plan's lifetime; the plan
  * reads the image contents at each execution.  The IP and prior values are
  * read once at creation (host copies) when the sensed images are described
- * sparsely or the plan is autotuned; they must not change afterwards unless
+ * sparsely (both images) or the plan is autotuned; they must not change afterwards unless
  * SFOC_PLAN_DENSE_SEN is set and autotuning is off.  create synchronises
  * `stream`; execute is asynchronous on `stream`.  A plan is used by one
  * host thread at a time and on the device that was current at creation.
