@@ -437,3 +437,43 @@ def test_scene_all_cps_match_oracle(scene):
     assert np.abs(go["score"] - o["score"]).max() <= 1e-12
     st2, _, _ = compare_to_golden(gs, go, ties, r)
     assert st2["ambiguous"] == st["ambiguous"] and st2["ambiguous_taken"] == st["ambiguous_taken"]
+
+
+@pytest.mark.parametrize("dtype", [S.DTYPE_F32, S.DTYPE_BF16])
+def test_register_skips_unread_reference_tiles(dtype):
+    """A few IPs on a large pair: most reference tiles are read by no search
+    window, are not described and count as zero in the integral images.  The
+    pair call's CPs and surfaces against describing both images whole and
+    matching, over three calls on one workspace whose IP sets (and so the
+    reference tile masks) differ, the last with a prior that moves the
+    windows."""
+    pr = synth.make_pair(91, (600, 820), 6.0)
+    m, r = 36, 10
+    p = S.preset("baseline", dtype)
+    dr, ds = dev(pr.ref), dev(pr.sen)
+    Fr, i1, i2 = S.describe(dr, p)
+    Fs, _, _ = S.describe(ds, p, integrals=False)
+    sets = [np.array([[100, 120], [450, 700], [300, 400]], np.int32),
+            np.array([[60, 60], [550, 770], [300, 100], [200, 650], [480, 300]], np.int32),
+            np.array([[100, 120], [450, 700], [300, 400]], np.int32)]
+    priors = [None, None, np.array([[7, -9], [-8, 6], [9, 9]], np.int32)]
+    R = S.Registrar(600, 820, 600, 820, 5, m, r, p, want_ncc=True)
+    for k, (ips, pri) in enumerate(zip(sets, priors)):
+        say("unread reference tiles", dtype, "call", k)
+        n = len(ips)
+        dips = dev(ips)
+        dpri = None if pri is None else dev(pri)
+        cw, nw = S.fastncc_match(Fs, Fr, i1, i2, dips, m, r, prior=dpri, want_ncc=True)
+        cs = torch.empty((n, 8), dtype=torch.int32, device="cuda")
+        ns = torch.empty((n, 2 * r + 1, 2 * r + 1), dtype=torch.float32, device="cuda")
+        rc = S.lib().sfoc_register_cps(S._ptr(dr), 600, 820, 820, S._ptr(ds), 600, 820, 820, S._ptr(dips),
+                                       S._ptr(dpri), n, m, r, ctypes.byref(R.p), S._ptr(ns), S._ptr(cs),
+                                       S._ptr(R.ws), R.wsb, None)
+        assert rc == 0
+        torch.cuda.synchronize()
+        gw, gs = S.cps_to_numpy(cw), S.cps_to_numpy(cs)
+        np.testing.assert_array_equal(gw["dy"], gs["dy"])
+        np.testing.assert_array_equal(gw["dx"], gs["dx"])
+        np.testing.assert_array_equal(gw["flags"], gs["flags"])
+        assert np.abs(nw.cpu().numpy() - ns.cpu().numpy()).max() <= 1e-6
+        assert np.abs(gw["score"] - gs["score"]).max() <= 1e-6
