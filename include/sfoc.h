@@ -411,11 +411,11 @@ int sfoc_plan_get_info(const sfoc_plan* plan, sfoc_plan_info* info, int32_t* fft
  * applies, and takes it as the default there.
  * sfoc_sensed_tiles: 32 x 32 sensed-image tiles that cover the m x m
  * templates of the in-bounds IPs (template and search window inside their
- * images; host arrays, no device work).  Tiles start on multiples of 32 in
- * the column and may run past a template; they are clipped to the image.
- *   SFOC_COVER_TEMPLATE: per IP, ceil(m/32) tile rows from the template's
- *     first row by the tile columns it spans, in IP order (what
- *     sfoc_register_cps describes, which also repeats a tile two IPs share);
+ * images; host arrays, no device work).  Tiles may run past a template;
+ * they are clipped to the image.
+ *   SFOC_COVER_TEMPLATE: per IP, ceil(m/32) x ceil(m/32) tiles from the
+ *     template's top-left corner, in IP order (what sfoc_register_cps
+ *     describes, which also describes twice what tiles of two IPs share);
  *   SFOC_COVER_GRID: the tiles of the image's 32-grid that templates touch,
  *     row-major;
  *   SFOC_COVER_SMALLER: the shorter of the two (the template list on a

@@ -525,13 +525,15 @@ __global__ __launch_bounds__(kNT, (describe_wpc<Z, FAST, VAR>())) void describe_
     // 4. (per order block) normalisation, rounding, store, channel sums.
     //    Each thread stores its run of kRun pixels of a channel as one
     //    vector (8 threads cover a 128-byte row segment), so every store
-    //    instruction writes whole cache lines; unaligned widths and the
-    //    right edge fall back to scalar stores.  The channel sums for the
+    //    instruction writes whole cache lines; unaligned widths, tiles whose
+    //    column origin is not a multiple of kRun and the right edge fall back
+    //    to scalar stores.  The channel sums for the
     //    integral images accumulate in channel order.
     const int64_t plane = (int64_t)H * W;
     const int gy = ty0 + oy, gx0 = tx0 + ox0;
     const size_t align = C.dtype == SFOC_DTYPE_F32 ? 15 : 7;
-    const bool full = (W & (kRun - 1)) == 0 && ((uintptr_t)desc & align) == 0 && gx0 + kRun <= W;
+    const bool full =
+        (W & (kRun - 1)) == 0 && (gx0 & (kRun - 1)) == 0 && ((uintptr_t)desc & align) == 0 && gx0 + kRun <= W;
     const int64_t off0 = (int64_t)gy * W + gx0;
     double d1[kRun], d2[kRun];
 #pragma unroll
@@ -988,23 +990,24 @@ hipError_t launch_describe_tiles(const float* img, int H, int W, int64_t ld, voi
 }
 
 // ---- template-aligned sensed tiles ------------------------------------------
-// Slot (i, a, c) of the table, i < n, a < ceil(m / T), c < ceil(m / T) + 1:
-// the tile of IP i's template with rows from the template's row a * T and
-// columns of grid tile c0 + c, or an empty slot (job -1) where the IP reads
-// nothing or its template spans fewer tile columns (template_tile_range).
-// Two IPs may name the same tile: both describe it, with equal results.
+// Slot (i, a, c) of the table, i < n, a, c < ceil(m / T): the tile of IP i's
+// template with rows from the template's row a * T and columns from its
+// column c * T, or an empty slot (job -1) where the IP reads nothing
+// (template_tile_range).  Tiles of two IPs may overlap: both describe the
+// shared pixels, with equal results (a pixel's descriptor does not depend on
+// the tile that computes it).
 __global__ __launch_bounds__(256) void template_tiles_kernel(const int32_t* __restrict__ ips,
                                                              const int32_t* __restrict__ prior, int n, int m, int r,
                                                              int Hs, int Ws, int Hr, int Wr, int4* __restrict__ tiles) {
-    const int S = template_tile_slots(m, kTS), CT = template_tile_rows(m, kTS) + 1;
+    const int S = template_tile_slots(m, kTS), CT = template_tile_rows(m, kTS);
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= (int64_t)n * S) return;
     const int i = (int)(e / S), s = (int)(e - (int64_t)i * S), a = s / CT, c = s - a * CT;
-    int64_t ty, c0, c1;
+    int64_t ty, tx;
     const bool in = template_tile_range(ips[2 * i], ips[2 * i + 1], prior ? prior[2 * i] : 0,
-                                        prior ? prior[2 * i + 1] : 0, m, r, Hs, Ws, Hr, Wr, kTS, &ty, &c0, &c1);
-    tiles[e] = in && c0 + c <= c1 ? make_int4(0, (int)(ty + (int64_t)a * kTS), (int)((c0 + c) * kTS), 0)
-                                  : make_int4(-1, 0, 0, 0);
+                                        prior ? prior[2 * i + 1] : 0, m, r, Hs, Ws, Hr, Wr, &ty, &tx);
+    tiles[e] = in ? make_int4(0, (int)(ty + (int64_t)a * kTS), (int)(tx + (int64_t)c * kTS), 0)
+                  : make_int4(-1, 0, 0, 0);
 }
 
 // ---- reference tiles the search windows read ------------------------------

@@ -309,18 +309,19 @@ void sensed_tiles(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m
     }
     std::set<std::pair<int, int>> seen;
     for (int32_t i = 0; i < n; ++i) {
-        int64_t ty, c0, c1;
+        int64_t ty, tx;
         if (!template_tile_range(ips[2 * i], ips[2 * i + 1], prior ? prior[2 * i] : 0, prior ? prior[2 * i + 1] : 0,
-                                 m, r, Hs, Ws, Hr, Wr, T, &ty, &c0, &c1))
+                                 m, r, Hs, Ws, Hr, Wr, &ty, &tx))
             continue;
         if (cover == kCoverGrid) {
             for (int64_t a = ty / T; a <= (ty + m - 1) / T; ++a)
-                for (int64_t c = c0; c <= c1; ++c) seen.insert(std::pair<int, int>((int)(a * T), (int)(c * T)));
+                for (int64_t b = tx / T; b <= (tx + m - 1) / T; ++b)
+                    seen.insert(std::pair<int, int>((int)(a * T), (int)(b * T)));
             continue;
         }
         for (int a = 0; a < template_tile_rows(m, T); ++a)
-            for (int64_t c = c0; c <= c1; ++c) {
-                const std::pair<int, int> o((int)(ty + (int64_t)a * T), (int)(c * T));
+            for (int c = 0; c < template_tile_rows(m, T); ++c) {
+                const std::pair<int, int> o((int)(ty + (int64_t)a * T), (int)(tx + (int64_t)c * T));
                 if (seen.insert(o).second) out.push_back(o);
             }
     }

@@ -172,26 +172,22 @@ bool tune_cache_write(const char* path, const TuneCache& cache);
 int tune_cache_lookup(const TuneCache& cache, const std::string& dev, int z, int dtype, int m, int r);
 
 // Template-aligned sensed tiles: the describe tiles that cover one IP's
-// m x m template, with tile rows starting at the template's first row and
-// tile columns on the image's tile grid (so every descriptor row segment a
-// tile stores stays aligned).  ceil(m / T) rows of tiles by at most
-// ceil(m / T) + 1 columns.  An IP whose template or search window leaves its
-// image reads nothing (it is flagged out of bounds) and gets no tiles.
-// Returns false then; else the template's first row ty and the first and
-// last tile columns c0, c1 (in tiles).
+// m x m template exactly, ceil(m / T) rows by ceil(m / T) columns of tiles
+// from the template's top-left corner (tiles may run past the template).
+// An IP whose template or search window leaves its image reads nothing (it
+// is flagged out of bounds) and gets no tiles: template_tile_range returns
+// false then, else the template's top-left corner (ty, tx).
 inline SFOC_HOST_DEVICE int template_tile_rows(int m, int T) { return (m + T - 1) / T; }
-inline SFOC_HOST_DEVICE int template_tile_slots(int m, int T) { return ((m + T - 1) / T) * ((m + T - 1) / T + 1); }
+inline SFOC_HOST_DEVICE int template_tile_slots(int m, int T) { return ((m + T - 1) / T) * ((m + T - 1) / T); }
 inline SFOC_HOST_DEVICE bool template_tile_range(int py, int px, int pry, int prx, int m, int r, int64_t Hs,
-                                                 int64_t Ws, int64_t Hr, int64_t Wr, int T, int64_t* ty, int64_t* c0,
-                                                 int64_t* c1) {
+                                                 int64_t Ws, int64_t Hr, int64_t Wr, int64_t* ty, int64_t* tx) {
     const int64_t M = (int64_t)m + 2 * r;
     const int64_t y = (int64_t)py - m / 2, x = (int64_t)px - m / 2;
     const int64_t sy = y - r + pry, sx = x - r + prx;
     if (y < 0 || x < 0 || y + m > Hs || x + m > Ws) return false;
     if (sy < 0 || sx < 0 || sy + M > Hr || sx + M > Wr) return false;
     *ty = y;
-    *c0 = x / T;
-    *c1 = (x + m - 1) / T;
+    *tx = x;
     return true;
 }
 // Sensed tiles of all in-bounds IPs (host arrays; prior may be null) as
@@ -214,8 +210,8 @@ void sensed_tiles(const int32_t* ips, const int32_t* prior, int32_t n, int32_t m
 inline SFOC_HOST_DEVICE bool window_tile_range(int py, int px, int pry, int prx, int m, int r, int64_t Hs,
                                                int64_t Ws, int64_t Hr, int64_t Wr, int T, int64_t* a0, int64_t* a1,
                                                int64_t* b0, int64_t* b1) {
-    int64_t ty, c0, c1;
-    if (!template_tile_range(py, px, pry, prx, m, r, Hs, Ws, Hr, Wr, T, &ty, &c0, &c1)) return false;
+    int64_t ty, tx;
+    if (!template_tile_range(py, px, pry, prx, m, r, Hs, Ws, Hr, Wr, &ty, &tx)) return false;
     const int64_t M = (int64_t)m + 2 * r;
     const int64_t sy = (int64_t)py - m / 2 - r + pry, sx = (int64_t)px - m / 2 - r + prx;
     *a0 = (sy > 0 ? sy - 1 : 0) / T;

@@ -126,8 +126,8 @@ def test_sensed_tiles_cover_the_templates(seed):
     got = S.sensed_tiles(ips, m, r, Hs, Ws, Hr, Wr, prior)
     tl = [tuple(map(int, t)) for t in got]
     assert len(set(tl)) == len(tl)                                     # distinct
-    for (y, x) in tl:                                                   # inside, on the column grid
-        assert 0 <= y < Hs and 0 <= x < Ws and x % 32 == 0
+    for (y, x) in tl:                                                   # inside the image
+        assert 0 <= y < Hs and 0 <= x < Ws
     # every template pixel of an in-bounds IP is described by some tile ...
     cov = np.zeros((Hs, Ws), dtype=bool)
     for (y, x) in tl:
@@ -137,14 +137,14 @@ def test_sensed_tiles_cover_the_templates(seed):
     for (ty, tx) in tops:
         need[ty:ty + m, tx:tx + m] = True
     assert not (need & ~cov).any()
-    # ... and every tile starts on a row of some template's tile rows, over
-    # a tile column that template reads
+    # ... and every tile is one of some template's tiles: rows and columns
+    # from its top-left corner in steps of 32
     for (y, x) in tl:
-        assert any((y - ty) % 32 == 0 and 0 <= y - ty < m and tx // 32 <= x // 32 <= (tx + m - 1) // 32
+        assert any((y - ty) % 32 == 0 and 0 <= y - ty < m and (x - tx) % 32 == 0 and 0 <= x - tx < m
                    for (ty, tx) in tops), (y, x)
-    # at most ceil(m/32) x (ceil(m/32) + 1) tiles per in-bounds IP
+    # at most ceil(m/32)^2 tiles per in-bounds IP
     k = -(-m // 32)
-    assert len(tl) <= len(tops) * k * (k + 1)
+    assert len(tl) <= len(tops) * k * k
     if not tops:
         assert len(tl) == 0
 
@@ -176,7 +176,7 @@ def test_sensed_tiles_cover_choice():
     # sparse IPs: each template's own tiles are fewer than the grid tiles it
     # touches; dense IPs: neighbours share grid tiles
     sparse = np.array([[100, 100], [300, 300]], np.int32)
-    assert len(S.sensed_tiles(sparse, 64, 8, 512, 512, 512, 512)) == 2 * 2 * 3
+    assert len(S.sensed_tiles(sparse, 64, 8, 512, 512, 512, 512)) == 2 * 2 * 2
     assert len(S.sensed_tiles(sparse, 64, 8, 512, 512, 512, 512, cover=S.COVER_GRID)) == 2 * 3 * 3
     dense = np.array([[y, x] for y in range(100, 200, 4) for x in range(100, 200, 4)], np.int32)
     g = S.sensed_tiles(dense, 64, 8, 512, 512, 512, 512, cover=S.COVER_GRID)

@@ -94,10 +94,15 @@ int main(int argc, char** argv) {
             pri[i] = (int32_t)(rng() % 200) - 100;
         }
         std::vector<std::pair<int, int>> tiles;
-        sensed_tiles(ips, (t & 1) ? pri : nullptr, n, m, r, Hs, Ws, Hr, Wr, 32, t % 3, tiles);
-        if ((int64_t)tiles.size() > (int64_t)n * template_tile_slots(m, 32)) printf("too many tiles\n");
+        const int cover = t % 3, k = template_tile_rows(m, 32);
+        sensed_tiles(ips, (t & 1) ? pri : nullptr, n, m, r, Hs, Ws, Hr, Wr, 32, cover, tiles);
+        if ((int64_t)tiles.size() > (int64_t)n * (k + 1) * (k + 1)) printf("too many tiles\n");
         for (const auto& o : tiles)
-            if (o.first < 0 || o.first >= Hs || o.second < 0 || o.second >= Ws || o.second % 32) printf("bad tile\n");
+            if (o.first < 0 || o.first >= Hs || o.second < 0 || o.second >= Ws ||
+                (cover == kCoverGrid && (o.first % 32 || o.second % 32)))
+                printf("bad tile\n");
+        std::vector<uint8_t> wm((size_t)(((Hr + 31) / 32) * ((Wr + 31) / 32)));
+        window_tile_mask(ips, (t & 1) ? pri : nullptr, n, m, r, Hs, Ws, Hr, Wr, 32, wm.data());
         free(ips);
         free(pri);
     }
