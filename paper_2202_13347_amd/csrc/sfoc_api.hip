@@ -40,7 +40,7 @@ hipError_t ensure_dynamic_lds(const void* kern, int bytes) {
 // for the life of the process; default priority, non-blocking.
 struct SideStream {
     hipStream_t s = nullptr;
-    hipEvent_t start = nullptr, tiles = nullptr, fork = nullptr, join = nullptr;
+    hipEvent_t start = nullptr, join = nullptr;
 };
 
 static hipError_t side_stream(SideStream** out) {
@@ -53,8 +53,6 @@ static hipError_t side_stream(SideStream** out) {
         SideStream t;
         e = hipStreamCreateWithFlags(&t.s, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&t.start, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&t.tiles, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&t.fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&t.join, hipEventDisableTiming);
         if (e != hipSuccess) return e;
         ss = t;
@@ -106,10 +104,11 @@ static hipError_t register_core(const float* ref, int64_t Hr, int64_t Wr, int64_
     // Of the reference image only the tiles the search windows read are
     // described (the others get zero integral-image aggregates; their mask
     // is marked just before), and of the sensed image only the tiles under
-    // the templates of in-bounds IPs, one table entry per template tile,
-    // written on a second stream.  The reference's integral scans
-    // (memory-bound) then run on that stream while the sensed image is
-    // described; the match waits for both.
+    // the templates of in-bounds IPs, one table entry per template tile.
+    // The sensed tiles (table, then describe) run on a second stream beside
+    // the reference describe and its integral scans, so that each launch's
+    // last round of workgroups shares the GPU with the other's; the match
+    // waits for both.
     SideStream* side = nullptr;
     hipError_t e = side_stream(&side);
     double* agg = (double*)(base + L.scan);
@@ -119,15 +118,11 @@ static hipError_t register_core(const float* ref, int64_t Hr, int64_t Wr, int64_
     if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->start, 0);
     if (e == hipSuccess)
         e = launch_template_tiles(ips, prior, n, m, r, (int)Hs, (int)Ws, (int)Hr, (int)Wr, tiles, side->s);
-    if (e == hipSuccess) e = hipEventRecord(side->tiles, side->s);
+    if (e == hipSuccess) e = launch_describe_tiles(sen, (int)Hs, (int)Ws, lds, dsen, tiles, ntiles, c, side->s);
+    if (e == hipSuccess) e = hipEventRecord(side->join, side->s);
     if (e == hipSuccess) e = launch_window_mask(ips, prior, n, m, r, (int)Hs, (int)Ws, (int)Hr, (int)Wr, rmask, st);
     if (e == hipSuccess) e = launch_describe(ref, (int)Hr, (int)Wr, ldr, dref, i1, i2, agg, c, st, rmask);
-    if (e == hipSuccess) e = hipEventRecord(side->fork, st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->fork, 0);
-    if (e == hipSuccess) e = launch_integral(i1, i2, (int)Hr, (int)Wr, agg, side->s, rmask);
-    if (e == hipSuccess) e = hipEventRecord(side->join, side->s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, side->tiles, 0);
-    if (e == hipSuccess) e = launch_describe_tiles(sen, (int)Hs, (int)Ws, lds, dsen, tiles, ntiles, c, st);
+    if (e == hipSuccess) e = launch_integral(i1, i2, (int)Hr, (int)Wr, agg, st, rmask);
     if (e == hipSuccess) e = hipStreamWaitEvent(st, side->join, 0);
     if (e != hipSuccess || n == 0) return e;
     return launch_match(dsen, Hs, Ws, dref, Hr, Wr, i1, i2, z, dtype, ips, prior, n, m, r, ncc, cps, base + L.match,
