@@ -815,14 +815,24 @@ __global__ __launch_bounds__(kScanNT) void integral_prefix(const IntegJob single
     }
 }
 
-// One 32 x 32 tile per workgroup: thread t holds a run of 4 pixels of row
-// t / 8.  Row 0 and column 0 of the integral images are set to zero by the
-// tiles that border them.
+// One 32 x 32 tile per workgroup, in three phases over an LDS copy of the
+// tile.  Thread t first holds column t % 32 of rows 4 (t / 32) .. + 3, so a
+// wave's loads and stores cover two rows of 32 consecutive pixels: it loads
+// s, sums down its four rows, then adds the totals of the row groups above
+// (the column prefix C).  Then thread t holds a run of 4 pixels of row t / 8
+// and sums C along the row: I = Corner + prefix(Above) + prefix(Left) +
+// prefix over the row of C, the decomposition above in another order.  The
+// results go back through LDS to the column layout for the stores.  Row 0
+// and column 0 of the integral images are set to zero by the tiles that
+// border them.
 template <bool BATCH>
 __global__ __launch_bounds__(kScanNT) void integral_tiles(const IntegJob single, const IntegJob* __restrict__ jobs,
                                                           const int4* __restrict__ tiles,
                                                           uint8_t* __restrict__ tmask) {
-    static_assert(kScanNT == kTS * kTS / kRun, "one run of 4 pixels per thread");
+    constexpr int kRows = kTS * kTS / kScanNT;   // rows per thread in the column layout
+    constexpr int kGroups = kTS / kRows;         // row groups in a tile
+    constexpr int kRuns = kTS / kRun;            // runs in a tile row
+    static_assert(kRows == 4 && kGroups * kTS == kScanNT && kRuns * kTS == kScanNT, "tile layouts");
     IntegJob J;
     int ta, tb;
     // Workgroups are dealt to the eight XCDs in turn; renumbered so that each
@@ -849,73 +859,98 @@ __global__ __launch_bounds__(kScanNT) void integral_tiles(const IntegJob single,
             if (!read) return;   // a tile that nothing reads
         }
     }
-    __shared__ double above[2][kTS];
-    __shared__ double wtot[2][kScanNT / 64][kTS];
+    __shared__ double T[2][kTS][kTS + 1];   // the tile of both maps
+    __shared__ double tot[2][kScanNT];      // row-group totals, then run totals
+    __shared__ double pre_left[2][kTS];     // inclusive prefix of Left over the tile rows
+    __shared__ double pre_above[2][kTS];    // Corner + inclusive prefix of Above over the tile columns
     const int H = J.H, W = J.W, t = threadIdx.x;
     const IntegAgg ag = integ_agg(H, W);
     const double* __restrict__ agg = J.agg;
     const int64_t P = W + 1;
     const int y0 = ta * kTS, x0 = tb * kTS;
-    const int i = t / (kTS / kRun), j0 = (t % (kTS / kRun)) * kRun, rl = t % (kTS / kRun);
-    const int lane = t & 63, wv = t >> 6;
-    const int y = y0 + i;
-    // Corner + prefix over the tile's columns of Above (wave 0: map 1 in
-    // lanes 0..31, map 2 in lanes 32..63)
-    if (t < 2 * kTS) {
-        const int q = t / kTS, jj = t % kTS;
-        double v = x0 + jj < W ? agg[(q ? ag.cs2 : ag.cs1) + ta * (int64_t)W + x0 + jj] : 0.0;
+    const int c = t % kTS, gr = t / kTS;    // column layout: column c, rows kRows * gr + k
+    // Left (map 1 in lanes 0..31, map 2 in lanes 32..63 of waves 0 and 2)
+    // and Above with Corner (waves 1 and 3), loaded before the tile and
+    // without branches (waves 2 and 3 repeat 0 and 1; only those store).
+    const bool is_above = (t / (2 * kTS)) & 1;
+    const int qa = (t / kTS) & 1, ea = t % kTS;
+    const int64_t ia = is_above ? (qa ? ag.cs2 : ag.cs1) + ta * (int64_t)W + min(x0 + ea, W - 1)
+                                : (qa ? ag.rs2 : ag.rs1) + tb * (int64_t)H + min(y0 + ea, H - 1);
+    const double va_in = agg[ia];
+    const bool va_ok = is_above ? x0 + ea < W : y0 + ea < H;
+    const double corner = agg[(qa ? ag.tt2 : ag.tt1) + ta * ag.ntx + tb];
+    // The tile, at clamped addresses (every load in bounds and all of them in
+    // flight at once); pixels outside the image count as zero.
+    double s[2][kRows];
+    bool ok[kRows];
 #pragma unroll
-        for (int d = 1; d < kTS; d <<= 1) {
-            const double u = __shfl_up(v, d, kTS);
-            if (jj >= d) v += u;
-        }
-        above[q][jj] = agg[(q ? ag.tt2 : ag.tt1) + ta * ag.ntx + tb] + v;
+    for (int k = 0; k < kRows; ++k) {
+        const int y = y0 + kRows * gr + k, x = x0 + c;
+        ok[k] = y < H && x < W;
+        const int64_t off = (int64_t)(min(y, H - 1) + 1) * P + min(x, W - 1) + 1;
+        s[0][k] = J.g1[off];
+        s[1][k] = J.g2[off];
     }
-    double r[2][kRun];
+    // the prefixes of Left, and of Above with Corner
+    double va = va_ok ? va_in : 0.0;
+#pragma unroll
+    for (int d = 1; d < kTS; d <<= 1) {
+        const double u = __shfl_up(va, d, kTS);
+        if (ea >= d) va += u;
+    }
+    if (t < 4 * kTS) {
+        if (!is_above) pre_left[qa][ea] = va;
+        else pre_above[qa][ea] = corner + va;
+    }
+    // column prefix: down the thread's rows, then the row groups above
+#pragma unroll
     for (int q = 0; q < 2; ++q) {
-        double* __restrict__ g = q ? J.g2 : J.g1;
-        double v[kRun];
 #pragma unroll
-        for (int k = 0; k < kRun; ++k) v[k] = (y < H && x0 + j0 + k < W) ? g[(int64_t)(y + 1) * P + x0 + j0 + 1 + k] : 0.0;
+        for (int k = 0; k < kRows; ++k) s[q][k] = ok[k] ? s[q][k] : 0.0;
 #pragma unroll
-        for (int k = 1; k < kRun; ++k) v[k] += v[k - 1];
-        // exclusive prefix of the run totals over the 8 lanes of the row
-        double inc = v[kRun - 1];
-#pragma unroll
-        for (int d = 1; d < kTS / kRun; d <<= 1) {
-            const double u = __shfl_up(inc, d, kTS / kRun);
-            if (rl >= d) inc += u;
-        }
-        double ex = __shfl_up(inc, 1, kTS / kRun);
-        if (rl == 0) ex = 0.0;
-        const double left = y < H ? agg[(q ? ag.rs2 : ag.rs1) + tb * (int64_t)H + y] : 0.0;
-        const double base = left + ex;
-#pragma unroll
-        for (int k = 0; k < kRun; ++k) r[q][k] = base + v[k];
-        // prefix over the 8 rows of the wave, column by column
-#pragma unroll
-        for (int d = kTS / kRun; d < 64; d <<= 1)
-#pragma unroll
-            for (int k = 0; k < kRun; ++k) {
-                const double u = __shfl_up(r[q][k], d, 64);
-                if (lane >= d) r[q][k] += u;
-            }
-        if (lane >= 64 - kTS / kRun)
-#pragma unroll
-            for (int k = 0; k < kRun; ++k) wtot[q][wv][j0 + k] = r[q][k];
+        for (int k = 1; k < kRows; ++k) s[q][k] += s[q][k - 1];
+        tot[q][gr * kTS + c] = s[q][kRows - 1];
     }
     __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        double e = 0.0;
+        for (int g2 = 0; g2 < gr; ++g2) e += tot[q][g2 * kTS + c];
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) T[q][kRows * gr + k][c] = s[q][k] + e;
+    }
+    __syncthreads();
+    // row prefix of C: thread t holds the run of row i from column j0
+    const int i = t / kRuns, rl = t % kRuns, j0 = rl * kRun;
+    double v[2][kRun];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) v[q][k] = T[q][i][j0 + k];
+#pragma unroll
+        for (int k = 1; k < kRun; ++k) v[q][k] += v[q][k - 1];
+        tot[q][i * kRuns + rl] = v[q][kRun - 1];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        double e = pre_left[q][i];
+        for (int r2 = 0; r2 < rl; ++r2) e += tot[q][i * kRuns + r2];
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) T[q][i][j0 + k] = pre_above[q][j0 + k] + (e + v[q][k]);
+    }
+    __syncthreads();
+#pragma unroll
     for (int q = 0; q < 2; ++q) {
         double* __restrict__ g = q ? J.g2 : J.g1;
 #pragma unroll
-        for (int k = 0; k < kRun; ++k) {
-            double acc = above[q][j0 + k];
-            for (int w = 0; w < wv; ++w) acc += wtot[q][w][j0 + k];
-            if (y < H && x0 + j0 + k < W) g[(int64_t)(y + 1) * P + x0 + j0 + 1 + k] = acc + r[q][k];
+        for (int k = 0; k < kRows; ++k) {
+            const int y = y0 + kRows * gr + k, x = x0 + c;
+            if (ok[k]) g[(int64_t)(y + 1) * P + x + 1] = T[q][kRows * gr + k][c];
         }
         if (ta == 0 && t < kTS && x0 + t < W) g[x0 + t + 1] = 0.0;
         if (ta == 0 && tb == 0 && t == 0) g[0] = 0.0;
-        if (tb == 0 && rl == 0 && y < H) g[(int64_t)(y + 1) * P] = 0.0;
+        if (tb == 0 && t < kTS && y0 + t < H) g[(int64_t)(y0 + t + 1) * P] = 0.0;
     }
 }
 
