@@ -235,23 +235,23 @@ def parity_vs_stored_oracle(S, name, cps, kind="o64", ref_kind=None):
 
 
 def described_px(S, ips, m, r, H, W):
-    """Pixels the two describe launches of a register step cover, on
-    average: the whole reference image, and the sensed image's tiles under
-    the templates.  The pair call describes each IP's own template tiles
-    (a tile two IPs share is described twice), so the tiles are counted per
-    IP, each clipped to the image."""
+    """Pixels the describe launch of a register step covers: the whole
+    reference image and the sensed image's tiles under the templates, both
+    in one launch.  The pair call describes each IP's own template tiles (a
+    tile two IPs share is described twice), so the tiles are counted per IP,
+    each clipped to the image."""
     import numpy as np
     sen_px = 0.0
     for k in range(len(ips)):
         t = S.sensed_tiles(ips[k:k + 1], m, r, H, W, H, W)
         sen_px += float((np.minimum(32, H - t[:, 0]) * np.minimum(32, W - t[:, 1])).sum())
-    return (H * W + sen_px) / 2.0, sen_px
+    return H * W + sen_px, sen_px
 
 
 def kernel_table(kt, steps, p, H, W, n, m, r, desc_px=None):
     """Roof entries of the describe, integral and match launches of one
     register step (HIP-event durations from the library's trace); desc_px is
-    the mean pixel count of a describe launch (H W when both are whole)."""
+    the pixel count of a describe launch (H W if not given)."""
     z = p.z
     es = 4 if p.desc_dtype == 0 else 2
     avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kt.items()}
@@ -862,7 +862,7 @@ def main():
                                f"descriptors, float64 integral images",
                    "image": [H, W], "ips": n, "template": m, "radius": r, "z": z, "fft_side": 128},
         "sfoc_mpixel_per_s": sfoc_mpix,
-        "sfoc_mpixel_per_s_step": 2 * px * args.steps / elapsed / 1e6,
+        "sfoc_mpixel_per_s_step": px * args.steps / elapsed / 1e6,
         "described_px": {"reference": H * W, "sensed_tiles": sen_px},
         "kernel_ms_per_launch": avg,
         "kernel_ms_per_step": per_step,
@@ -880,16 +880,16 @@ def main():
         "parity": parity_vs_stored_oracle(S, "scene", R.cps),
     }
     out["integral_standalone"] = run_integral_alone(args, S, torch, p, ref)
-    # The step's two describe launches run concurrently (the sensed tiles on
-    # a second stream), so each launch's event time includes the other's share
-    # of the GPU; the same kernel on the reference image with nothing beside
-    # it gives the kernel's own rate.
+    # The step's describe launch covers both images (the reference image's
+    # grid tiles and the sensed template tiles); the same kernel on the
+    # reference image alone, with the counters of that launch, is reported
+    # as the kernel's roofline, and the step's launch beside it.
     d_alone = out["integral_standalone"]["describe_ms_per_call"]
     if dom == "describe" and d_alone > 0:
         fl = sfoc_flops_per_px(p) * H * W
         rf = out["roofline"]
-        rf["in_step"] = {"note": "the step's two describe launches overlap on two streams; each launch's "
-                                 "duration includes the other's share of the GPU",
+        rf["in_step"] = {"note": "the step's one describe launch: the reference image's grid tiles and the "
+                                 "sensed image's template tiles",
                          "ms_per_launch": d_ms, "achieved": rf["achieved"], "frac": rf["frac"]}
         rf.update({"launch": f"the {H}x{W} reference image's describe, timed with HIP events on its stream "
                              f"with nothing beside it (the same kernel and tiles as in the step)",

@@ -35,34 +35,8 @@ hipError_t ensure_dynamic_lds(const void* kern, int bytes) {
     return e;
 }
 
-// A second stream (and a fork / join event pair) per device and host
-// thread, for work that overlaps the caller's stream inside one call.  Kept
-// for the life of the process; default priority, non-blocking.
-struct SideStream {
-    hipStream_t s = nullptr;
-    hipEvent_t start = nullptr, join = nullptr;
-};
-
-static hipError_t side_stream(SideStream** out) {
-    thread_local std::map<int, SideStream> per_device;
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    SideStream& ss = per_device[dev];
-    if (!ss.s) {
-        SideStream t;
-        e = hipStreamCreateWithFlags(&t.s, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&t.start, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&t.join, hipEventDisableTiming);
-        if (e != hipSuccess) return e;
-        ss = t;
-    }
-    *out = &ss;
-    return hipSuccess;
-}
-
 struct RegisterLayout {
-    size_t desc_ref, desc_sen, integ1, integ2, scan, tiles, rmask, match, total;
+    size_t desc_ref, desc_sen, integ1, integ2, scan, jobs, tiles, rmask, match, total;
 };
 
 static RegisterLayout register_layout(int64_t Hr, int64_t Wr, int64_t Hs, int64_t Ws, int32_t n, int32_t m,
@@ -79,8 +53,10 @@ static RegisterLayout register_layout(int64_t Hr, int64_t Wr, int64_t Hs, int64_
     off = align_up(off + (size_t)(Hr + 1) * (Wr + 1) * sizeof(double), 256);
     L.scan = off;
     off = align_up(off + describe_ws_bytes(Hr, Wr), 256);
+    L.jobs = off;
+    off = align_up(off + 2 * sizeof(DescribeJob), 256);
     L.tiles = off;
-    off = align_up(off + (size_t)n * template_tile_slots(m, kDescribeTile) * 16, 256);
+    off = align_up(off + (size_t)pair_table_entries((int)Hr, (int)Wr, n, m) * 16, 256);
     L.rmask = off;
     off = align_up(off + tile_mask_bytes(Hr, Wr), 256);
     L.match = off;
@@ -95,35 +71,24 @@ static hipError_t register_core(const float* ref, int64_t Hr, int64_t Wr, int64_
                                 int64_t Ws, int64_t lds, const int32_t* ips, const int32_t* prior, int32_t n,
                                 int32_t m, int32_t r, const DescribeConsts& c, int32_t z, int32_t dtype, float* ncc,
                                 sfoc_cp* cps, const RegisterLayout& L, void* ws, hipStream_t st, bool consistency) {
-    const int ntiles = n * template_tile_slots(m, kDescribeTile);
     char* base = (char*)ws;
     void* dref = base + L.desc_ref;
     void* dsen = base + L.desc_sen;
     double* i1 = (double*)(base + L.integ1);
     double* i2 = (double*)(base + L.integ2);
     // Of the reference image only the tiles the search windows read are
-    // described (the others get zero integral-image aggregates; their mask
-    // is marked just before), and of the sensed image only the tiles under
-    // the templates of in-bounds IPs, one table entry per template tile.
-    // The sensed tiles (table, then describe) run on a second stream beside
-    // the reference describe and its integral scans, so that each launch's
-    // last round of workgroups shares the GPU with the other's; the match
-    // waits for both.
-    SideStream* side = nullptr;
-    hipError_t e = side_stream(&side);
+    // described (the others get zero integral-image aggregates), and of the
+    // sensed image only the tiles under the templates of in-bounds IPs, one
+    // table entry per template tile.  Both images go into one describe
+    // launch, so that they share the GPU to the end of the launch; the
+    // integral scans and the match follow on the same stream.
     double* agg = (double*)(base + L.scan);
+    DescribeJob* jobs = (DescribeJob*)(base + L.jobs);
     int4* tiles = (int4*)(base + L.tiles);
     uint8_t* rmask = (uint8_t*)(base + L.rmask);
-    if (e == hipSuccess) e = hipEventRecord(side->start, st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->start, 0);
-    if (e == hipSuccess)
-        e = launch_template_tiles(ips, prior, n, m, r, (int)Hs, (int)Ws, (int)Hr, (int)Wr, tiles, side->s);
-    if (e == hipSuccess) e = launch_describe_tiles(sen, (int)Hs, (int)Ws, lds, dsen, tiles, ntiles, c, side->s);
-    if (e == hipSuccess) e = hipEventRecord(side->join, side->s);
-    if (e == hipSuccess) e = launch_window_mask(ips, prior, n, m, r, (int)Hs, (int)Ws, (int)Hr, (int)Wr, rmask, st);
-    if (e == hipSuccess) e = launch_describe(ref, (int)Hr, (int)Wr, ldr, dref, i1, i2, agg, c, st, rmask);
+    hipError_t e = launch_describe_pair(ref, (int)Hr, (int)Wr, ldr, dref, i1, i2, agg, sen, (int)Hs, (int)Ws, lds, dsen,
+                                        ips, prior, n, m, r, jobs, tiles, rmask, c, st);
     if (e == hipSuccess) e = launch_integral(i1, i2, (int)Hr, (int)Wr, agg, st, rmask);
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, side->join, 0);
     if (e != hipSuccess || n == 0) return e;
     return launch_match(dsen, Hs, Ws, dref, Hr, Wr, i1, i2, z, dtype, ips, prior, n, m, r, ncc, cps, base + L.match,
                         st, consistency);

@@ -256,13 +256,14 @@ __global__ __launch_bounds__(kNT, (describe_wpc<Z, FAST, VAR>())) void describe_
         // a job table every entry is of `single`, and a negative job is an
         // empty slot that the whole workgroup skips.  what = 1: a grid tile
         // that nothing reads, whose integral-image aggregates are set to
-        // zero (the box sums over the tiles that are described stay exact)
+        // zero (the box sums over the tiles that are described stay exact);
+        // what = 2: a grid tile that is described if the mask marks it
         const int4 e = tiles[k];
         if (e.x < 0) return;
         J = jobs ? load_table(jobs, e.x) : single;
         ty0 = e.y;
         tx0 = e.z;
-        if (e.w == 1) {
+        if (e.w == 1 || (e.w == 2 && !tmask[(ty0 / kTS) * ((J.W + kTS - 1) / kTS) + tx0 / kTS])) {
             if (J.agg) zero_tile_aggregates(J, ty0, tx0);
             return;
         }
@@ -1024,62 +1025,75 @@ hipError_t launch_describe_tiles(const float* img, int H, int W, int64_t ld, voi
     return launch_describe_any(job, nullptr, tiles, ntiles, nullptr, c, st, 0);
 }
 
-// ---- template-aligned sensed tiles ------------------------------------------
-// Slot (i, a, c) of the table, i < n, a, c < ceil(m / T): the tile of IP i's
+// ---- the pair call's describe table ---------------------------------------
+// One launch describes both images of a pair.  Entries 0 .. NR - 1 of the
+// table are the reference image's grid tiles in row-major order, {0, row
+// origin, column origin, 2}: described where the window mask marks the
+// tile, else given zero integral-image aggregates.  Slot (i, a, c) after
+// them, i < n, a, c < ceil(m / T), is the sensed image's tile of IP i's
 // template with rows from the template's row a * T and columns from its
-// column c * T, or an empty slot (job -1) where the IP reads nothing
-// (template_tile_range).  Tiles of two IPs may overlap: both describe the
-// shared pixels, with equal results (a pixel's descriptor does not depend on
-// the tile that computes it).
-__global__ __launch_bounds__(256) void template_tiles_kernel(const int32_t* __restrict__ ips,
-                                                             const int32_t* __restrict__ prior, int n, int m, int r,
-                                                             int Hs, int Ws, int Hr, int Wr, int4* __restrict__ tiles) {
+// column c * T ({1, ...}), or an empty slot (job -1) where the IP reads
+// nothing (template_tile_range).  Tiles of two IPs may overlap: both
+// describe the shared pixels, with equal results (a pixel's descriptor does
+// not depend on the tile that computes it).  Thread 0 writes the two jobs;
+// thread i < n also marks the reference tiles of IP i's search window
+// (window_tile_range, the rule batched plans apply on the host), byte
+// stores of 1 in any order.  The mask is not cleared first: the integral
+// pass, its last reader, clears every byte it reads, and a byte left set by
+// memory that never held a mask only makes a tile be described that
+// nothing reads.
+__global__ __launch_bounds__(256) void pair_table_kernel(const int32_t* __restrict__ ips,
+                                                         const int32_t* __restrict__ prior, int n, int m, int r,
+                                                         int Hs, int Ws, int Hr, int Wr, const DescribeJob jref,
+                                                         const DescribeJob jsen, DescribeJob* __restrict__ jobs,
+                                                         int4* __restrict__ tiles, uint8_t* __restrict__ mask) {
     const int S = template_tile_slots(m, kTS), CT = template_tile_rows(m, kTS);
+    const int ntx = (Wr + kTS - 1) / kTS, NR = ntx * ((Hr + kTS - 1) / kTS);
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= (int64_t)n * S) return;
-    const int i = (int)(e / S), s = (int)(e - (int64_t)i * S), a = s / CT, c = s - a * CT;
-    int64_t ty, tx;
-    const bool in = template_tile_range(ips[2 * i], ips[2 * i + 1], prior ? prior[2 * i] : 0,
-                                        prior ? prior[2 * i + 1] : 0, m, r, Hs, Ws, Hr, Wr, &ty, &tx);
-    tiles[e] = in ? make_int4(0, (int)(ty + (int64_t)a * kTS), (int)(tx + (int64_t)c * kTS), 0)
-                  : make_int4(-1, 0, 0, 0);
+    if (e == 0) {
+        jobs[0] = jref;
+        jobs[1] = jsen;
+    }
+    if (e < n) {
+        const int i = (int)e;
+        int64_t a0, a1, b0, b1;
+        if (window_tile_range(ips[2 * i], ips[2 * i + 1], prior ? prior[2 * i] : 0, prior ? prior[2 * i + 1] : 0, m,
+                              r, Hs, Ws, Hr, Wr, kTS, &a0, &a1, &b0, &b1))
+            for (int64_t a = a0; a <= a1; ++a)
+                for (int64_t b = b0; b <= b1; ++b) mask[a * ntx + b] = 1;
+    }
+    if (e < NR) {
+        const int a = (int)(e / ntx), b = (int)(e - (int64_t)a * ntx);
+        tiles[e] = make_int4(0, a * kTS, b * kTS, 2);
+    } else if (e < NR + (int64_t)n * S) {
+        const int64_t f = e - NR;
+        const int i = (int)(f / S), s = (int)(f - (int64_t)i * S), a = s / CT, c = s - a * CT;
+        int64_t ty, tx;
+        const bool in = template_tile_range(ips[2 * i], ips[2 * i + 1], prior ? prior[2 * i] : 0,
+                                            prior ? prior[2 * i + 1] : 0, m, r, Hs, Ws, Hr, Wr, &ty, &tx);
+        tiles[e] = in ? make_int4(1, (int)(ty + (int64_t)a * kTS), (int)(tx + (int64_t)c * kTS), 0)
+                      : make_int4(-1, 0, 0, 0);
+    }
 }
 
-// ---- reference tiles the search windows read ------------------------------
-// One thread per IP marks the tiles of its window_tile_range (the same rule
-// batched plans apply on the host); byte stores of 1, in any order.  The
-// mask is not cleared first: the integral pass, its last reader, clears
-// every byte it reads, and a byte left set by memory that never held a mask
-// only makes a tile be described that nothing reads.
-__global__ __launch_bounds__(256) void window_mask_mark(const int32_t* __restrict__ ips,
-                                                        const int32_t* __restrict__ prior, int n, int m, int r,
-                                                        int Hs, int Ws, int Hr, int Wr, uint8_t* __restrict__ mask) {
-    const int i = (int)(blockIdx.x * 256 + threadIdx.x);
-    if (i >= n) return;
-    int64_t a0, a1, b0, b1;
-    if (!window_tile_range(ips[2 * i], ips[2 * i + 1], prior ? prior[2 * i] : 0, prior ? prior[2 * i + 1] : 0, m, r,
-                           Hs, Ws, Hr, Wr, kTS, &a0, &a1, &b0, &b1))
-        return;
-    const int64_t ntx = (Wr + kTS - 1) / kTS;
-    for (int64_t a = a0; a <= a1; ++a)
-        for (int64_t b = b0; b <= b1; ++b) mask[a * ntx + b] = 1;
+int64_t pair_table_entries(int Hr, int Wr, int n, int m) {
+    return (int64_t)((Wr + kTS - 1) / kTS) * ((Hr + kTS - 1) / kTS) + (int64_t)n * template_tile_slots(m, kTS);
 }
 
-hipError_t launch_window_mask(const int32_t* ips, const int32_t* prior, int n, int m, int r, int Hs, int Ws, int Hr,
-                              int Wr, uint8_t* mask, hipStream_t st) {
-    if (n > 0)
-        hipLaunchKernelGGL(window_mask_mark, dim3((n + 255) / 256), dim3(256), 0, st, ips, prior, n, m, r, Hs, Ws, Hr,
-                           Wr, mask);
-    return hipGetLastError();
-}
-
-hipError_t launch_template_tiles(const int32_t* ips, const int32_t* prior, int n, int m, int r, int Hs, int Ws,
-                                 int Hr, int Wr, int4* tiles, hipStream_t st) {
-    const int64_t cnt = (int64_t)n * template_tile_slots(m, kTS);
-    if (cnt == 0) return hipSuccess;
-    hipLaunchKernelGGL(template_tiles_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, ips, prior, n, m,
-                       r, Hs, Ws, Hr, Wr, tiles);
-    return hipGetLastError();
+hipError_t launch_describe_pair(const float* ref, int Hr, int Wr, int64_t ldr, void* dref, double* i1, double* i2,
+                                double* agg, const float* sen, int Hs, int Ws, int64_t lds, void* dsen,
+                                const int32_t* ips, const int32_t* prior, int n, int m, int r, DescribeJob* jobs,
+                                int4* tiles, uint8_t* mask, const DescribeConsts& c, hipStream_t st) {
+    const DescribeJob jref{ref, dref, i1, i2, agg, ldr, Hr, Wr};
+    const DescribeJob jsen{sen, dsen, nullptr, nullptr, nullptr, lds, Hs, Ws};
+    const int64_t cnt = pair_table_entries(Hr, Wr, n, m);
+    const int64_t nthr = cnt > n ? cnt : n;
+    hipLaunchKernelGGL(pair_table_kernel, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, st, ips, prior, n, m, r,
+                       Hs, Ws, Hr, Wr, jref, jsen, jobs, tiles, mask);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    DescribeJob none{};
+    return launch_describe_any(none, jobs, tiles, (int)cnt, mask, c, st, 0);
 }
 
 hipError_t launch_integral(double* i1, double* i2, int H, int W, double* agg, hipStream_t st, uint8_t* tmask) {

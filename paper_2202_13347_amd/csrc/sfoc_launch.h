@@ -73,19 +73,24 @@ hipError_t launch_describe(const float* img, int H, int W, int64_t ld, void* des
 // integral-image inputs.
 hipError_t launch_describe_tiles(const float* img, int H, int W, int64_t ld, void* desc, const int4* tiles,
                                  int ntiles, const DescribeConsts& c, hipStream_t st);
-// Writes the template-aligned sensed tiles of n IPs (device arrays) into
-// tiles: n * template_tile_slots(m, kDescribeTile) entries.
-hipError_t launch_template_tiles(const int32_t* ips, const int32_t* prior, int n, int m, int r, int Hs, int Ws,
-                                 int Hr, int Wr, int4* tiles, hipStream_t st);
+// Entries of the pair call's describe table: the reference image's grid
+// tiles, then n * template_tile_slots(m, kDescribeTile) sensed slots.
+int64_t pair_table_entries(int Hr, int Wr, int n, int m);
+// Both images of a pair in one describe launch (n IPs, device arrays): a
+// small kernel marks in mask (one byte per reference tile) the tiles each
+// in-bounds IP's search window reads (window_tile_range) and writes the two
+// jobs and the table (pair_table_entries entries); the describe launch then
+// takes the reference tiles the mask marks (the others get zero aggregates)
+// and the template-aligned sensed tiles.  Mask bytes are not cleared here:
+// launch_integral, the last reader, clears every byte of the grid.
+hipError_t launch_describe_pair(const float* ref, int Hr, int Wr, int64_t ldr, void* dref, double* i1, double* i2,
+                                double* agg, const float* sen, int Hs, int Ws, int64_t lds, void* dsen,
+                                const int32_t* ips, const int32_t* prior, int n, int m, int r, DescribeJob* jobs,
+                                int4* tiles, uint8_t* mask, const DescribeConsts& c, hipStream_t st);
 // Completes the integral images from what launch_describe left in i1, i2
 // and agg (the same buffers).
 hipError_t launch_integral(double* i1, double* i2, int H, int W, double* agg, hipStream_t st,
                            uint8_t* tmask = nullptr);
-// Marks in mask (one byte per reference tile) the tiles each in-bounds IP's
-// search window reads (window_tile_range).  Bytes are not cleared here:
-// launch_integral, the last reader, clears every byte of its image's grid.
-hipError_t launch_window_mask(const int32_t* ips, const int32_t* prior, int n, int m, int r, int Hs, int Ws, int Hr,
-                              int Wr, uint8_t* mask, hipStream_t st);
 // i1 == i2 == null: per-window integral images, built into ws after the
 // split-offset scratch (match_window_ws_bytes).
 // consistency = false leaves out the median-displacement check (see
