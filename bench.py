@@ -770,7 +770,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds for the oracle baseline (0: skip)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--batched-steps", type=int, default=5, help="timed steps of the batching workload (0: skip)")
