@@ -243,9 +243,10 @@ int sfoc_fastncc_match(const void* desc_sen, int64_t Hs, int64_t Ws,
  * m x m template at each IP, Section 2.2), integral images of the
  * reference, then sfoc_fastncc_match.  Reference tiles no window reads are
  * not described and count as zero in the integral images, so every box sum
- * a window takes is that of the described values.  Arguments as above; the
- * descriptors, integral images, the sensed tile table and the reference
- * tile mask live inside ws (see sfoc_register_workspace).  The CPs equal
+ * a window takes is that of the described values.  Both images' tiles go
+ * into one describe launch.  Arguments as above; the descriptors, integral
+ * images, the describe table of both images' tiles and the reference tile
+ * mask live inside ws (see sfoc_register_workspace).  The CPs equal
  * those of sfoc_describe of both whole images followed by sfoc_fastncc_match
  * up to the float64 rounding of those box sums (bit for bit in every test).
  */
