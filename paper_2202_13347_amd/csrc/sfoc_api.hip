@@ -35,12 +35,38 @@ hipError_t ensure_dynamic_lds(const void* kern, int bytes) {
     return e;
 }
 
+// A second stream (and a fork / join event pair) per device and host
+// thread, for work that overlaps the caller's stream inside one call.  Kept
+// for the life of the process; default priority, non-blocking.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t start = nullptr, join = nullptr;
+};
+
+static hipError_t side_stream(SideStream** out) {
+    thread_local std::map<int, SideStream> per_device;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    SideStream& ss = per_device[dev];
+    if (!ss.s) {
+        SideStream t;
+        e = hipStreamCreateWithFlags(&t.s, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&t.start, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&t.join, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+        ss = t;
+    }
+    *out = &ss;
+    return hipSuccess;
+}
+
 struct RegisterLayout {
-    size_t desc_ref, desc_sen, integ1, integ2, scan, jobs, tiles, rmask, match, total;
+    size_t desc_ref, desc_sen, integ1, integ2, scan, jobs, tiles, rmask, split, match, total;
 };
 
 static RegisterLayout register_layout(int64_t Hr, int64_t Wr, int64_t Hs, int64_t Ws, int32_t n, int32_t m,
-                                      int32_t z, size_t es, size_t match_ws) {
+                                      int32_t r, int32_t z, size_t es, size_t match_ws) {
     RegisterLayout L;
     size_t off = 0;
     L.desc_ref = off;
@@ -59,6 +85,8 @@ static RegisterLayout register_layout(int64_t Hr, int64_t Wr, int64_t Hs, int64_
     off = align_up(off + (size_t)pair_table_entries((int)Hr, (int)Wr, n, m) * 16, 256);
     L.rmask = off;
     off = align_up(off + tile_mask_bytes(Hr, Wr), 256);
+    L.split = off;
+    off = align_up(off + match_split_bytes(n, r), 256);
     L.match = off;
     off = align_up(off + match_ws, 256);
     L.total = off;
@@ -80,18 +108,38 @@ static hipError_t register_core(const float* ref, int64_t Hr, int64_t Wr, int64_
     // described (the others get zero integral-image aggregates), and of the
     // sensed image only the tiles under the templates of in-bounds IPs, one
     // table entry per template tile.  Both images go into one describe
-    // launch, so that they share the GPU to the end of the launch; the
-    // integral scans and the match follow on the same stream.
+    // launch, so that they share the GPU to the end of the launch.  The
+    // match's transforms do not read the integral images: where the match
+    // splits (an FFT side without offset blocks), the integral scans run on
+    // a second stream beside the transforms, and the NCC and peaks follow
+    // once both are done.  Otherwise the scans precede the match.
     double* agg = (double*)(base + L.scan);
     DescribeJob* jobs = (DescribeJob*)(base + L.jobs);
     int4* tiles = (int4*)(base + L.tiles);
     uint8_t* rmask = (uint8_t*)(base + L.rmask);
     hipError_t e = launch_describe_pair(ref, (int)Hr, (int)Wr, ldr, dref, i1, i2, agg, sen, (int)Hs, (int)Ws, lds, dsen,
                                         ips, prior, n, m, r, jobs, tiles, rmask, c, st);
-    if (e == hipSuccess) e = launch_integral(i1, i2, (int)Hr, (int)Wr, agg, st, rmask);
-    if (e != hipSuccess || n == 0) return e;
-    return launch_match(dsen, Hs, Ws, dref, Hr, Wr, i1, i2, z, dtype, ips, prior, n, m, r, ncc, cps, base + L.match,
-                        st, consistency);
+    if (e != hipSuccess) return e;
+    if (!match_split_ok(n, m, r, dtype)) {
+        e = launch_integral(i1, i2, (int)Hr, (int)Wr, agg, st, rmask);
+        if (e != hipSuccess || n == 0) return e;
+        return launch_match(dsen, Hs, Ws, dref, Hr, Wr, i1, i2, z, dtype, ips, prior, n, m, r, ncc, cps,
+                            base + L.match, st, consistency);
+    }
+    SideStream* side = nullptr;
+    void* split = base + L.split;
+    e = side_stream(&side);
+    if (e == hipSuccess) e = hipEventRecord(side->start, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->start, 0);
+    if (e == hipSuccess) e = launch_integral(i1, i2, (int)Hr, (int)Wr, agg, side->s, rmask);
+    if (e == hipSuccess) e = hipEventRecord(side->join, side->s);
+    if (e == hipSuccess)
+        e = launch_match_fft(dsen, Hs, Ws, dref, Hr, Wr, z, dtype, ips, prior, n, m, r, ncc, cps, base + L.match,
+                             split, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, side->join, 0);
+    if (e != hipSuccess) return e;
+    return launch_match_finish(dsen, Hs, Ws, dref, Hr, Wr, i1, i2, z, dtype, ips, prior, n, m, r, ncc, cps,
+                               base + L.match, split, st, consistency);
 }
 
 // ---- band-streamed registration ---------------------------------------------
@@ -158,7 +206,7 @@ static StreamLayout stream_layout(int64_t Hr, int64_t Wr, int64_t Hs, int64_t Ws
     StreamLayout S;
     int64_t hs = 0, hr = 0;
     band_bounds(Hr, Hs, m, r, band_rows, max_prior, halo, &hs, &hr);
-    S.band = register_layout(hr, Wr, hs, Ws, n, m, z, es, match_plan(n, m, r).ws_bytes);
+    S.band = register_layout(hr, Wr, hs, Ws, n, m, r, z, es, match_plan(n, m, r).ws_bytes);
     S.ips = S.band.total;
     S.prior = align_up(S.ips + (size_t)n * 2 * sizeof(int32_t), 256);
     S.total = align_up(S.prior + (size_t)n * 2 * sizeof(int32_t), 256);
@@ -290,7 +338,7 @@ int sfoc_register_workspace(int64_t Hr, int64_t Wr, int64_t Hs, int64_t Ws, int3
     if (rc) return rc;
     rc = check_match_shape(n, m, r);
     if (rc) return rc;
-    *bytes = register_layout(Hr, Wr, Hs, Ws, n, m, z, dtype_size(p->desc_dtype), match_plan(n, m, r).ws_bytes).total;
+    *bytes = register_layout(Hr, Wr, Hs, Ws, n, m, r, z, dtype_size(p->desc_dtype), match_plan(n, m, r).ws_bytes).total;
     return SFOC_OK;
 }
 
@@ -312,7 +360,7 @@ int sfoc_register_cps(const float* ref, int64_t Hr, int64_t Wr, int64_t ldr, con
     const int64_t ntiles = (int64_t)n * template_tile_slots(m, kDescribeTile);
     if (ntiles > INT32_MAX) return SFOC_E_UNSUPPORTED;
     const RegisterLayout L =
-        register_layout(Hr, Wr, Hs, Ws, n, m, z, dtype_size(p->desc_dtype), match_plan(n, m, r).ws_bytes);
+        register_layout(Hr, Wr, Hs, Ws, n, m, r, z, dtype_size(p->desc_dtype), match_plan(n, m, r).ws_bytes);
     if (!ws || ws_bytes < L.total) return SFOC_E_WORKSPACE;
     DescribeConsts c;
     build_describe_consts(p, &c);

@@ -51,6 +51,12 @@ struct MatchArgs {
     // 0: integ1 / integ2 are the reference image's integral images; 1: they
     // hold one (M+1) x (M+1) pair per IP, built over its own search window
     int32_t integ_win;
+    // Split form (rst set, one offset block): the transforms leave R_ST
+    // (n x V x V, row-major) in rst and the template sums R_T, R_TT (2 per
+    // IP) in tsum instead of the NCC; ncc_finish_kernel assembles the NCC
+    // and the peaks from them and the integral images.
+    float* rst = nullptr;
+    double* tsum = nullptr;
 };
 
 // SFOC_OK for hipSuccess, else SFOC_E_HIP (the HIP error is kept for
@@ -99,6 +105,22 @@ hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void
                         const double* i1, const double* i2, int z, int dtype, const int32_t* ips,
                         const int32_t* prior, int n, int m, int r, float* ncc, sfoc_cp* cps, void* ws,
                         hipStream_t st, bool consistency = true);
+// The same match in two launches, so that the integral images need not
+// exist before the second: launch_match_fft runs the transforms and leaves
+// R_ST and the template sums in `split` (match_split_bytes(n, r) bytes);
+// launch_match_finish assembles the NCC surfaces (ncc, if set) and the
+// peaks into cps from them and the integral images, then (consistency) the
+// median check.  Only where match_split_ok: an FFT side without offset
+// blocks.  ws is launch_match's workspace.
+bool match_split_ok(int n, int m, int r, int dtype);
+size_t match_split_bytes(int n, int r);
+hipError_t launch_match_fft(const void* desc_sen, int64_t Hs, int64_t Ws, const void* desc_ref, int64_t Hr,
+                            int64_t Wr, int z, int dtype, const int32_t* ips, const int32_t* prior, int n, int m,
+                            int r, float* ncc, sfoc_cp* cps, void* ws, void* split, hipStream_t st);
+hipError_t launch_match_finish(const void* desc_sen, int64_t Hs, int64_t Ws, const void* desc_ref, int64_t Hr,
+                               int64_t Wr, const double* i1, const double* i2, int z, int dtype, const int32_t* ips,
+                               const int32_t* prior, int n, int m, int r, float* ncc, sfoc_cp* cps, void* ws,
+                               void* split, hipStream_t st, bool consistency);
 // The median-displacement consistency check over n records (one workgroup).
 hipError_t launch_consistency(sfoc_cp* cps, const int32_t* prior, int n, hipStream_t st);
 // cps[i].sen_row += dy for i < n.

@@ -985,10 +985,43 @@ SFOC_DEV void match_item(const MatchArgs& A, int i, int bq, int slot, const floa
         __syncthreads();
     }
 
+    if (A.rst) {   // split form: R_ST and the template sums for ncc_finish_kernel
+        float* __restrict__ o = A.rst + (int64_t)i * V * V;
+        for (int e = t; e < Vu * Vv; e += C::NT) {
+            const int u = e / Vv, v = e - u * Vv;
+            const float* rr = reinterpret_cast<const float*>(buf + C::row((u >> 1) * 2));
+            o[(u0 + u) * V + v0 + v] = rr[(u & 1) * L + v];
+        }
+        if (t == 0) {
+            A.tsum[2 * i] = red[64];
+            A.tsum[2 * i + 1] = red[65];
+        }
+        return;
+    }
     ncc_peak<C::NT>(A, i, slot, u0, v0, Vu, Vv, red[64], red[65], red, [&](int u, int v) {
         const float* rr = reinterpret_cast<const float*>(buf + C::row((u >> 1) * 2));
         return rr[(u & 1) * L + v];
     });
+}
+
+// Split form, second launch: one workgroup per IP assembles the NCC surface
+// (Eq. 9 with the box sums of Eq. 16) from the R_ST and template sums the
+// transforms left, and takes its peak, as the fused form does.  IPs whose
+// template or search window leaves its image got their record from the
+// transforms' launch.
+constexpr int kFinishNT = 256;
+__global__ __launch_bounds__(kFinishNT) void ncc_finish_kernel(const MatchArgs A) {
+    __shared__ double red[66];
+    const int i = (int)blockIdx.x;
+    const int m = A.m, r = A.r, M = m + 2 * r, V = 2 * r + 1;
+    const int py = A.ips[2 * i], px = A.ips[2 * i + 1];
+    const int pry = A.prior ? A.prior[2 * i] : 0, prx = A.prior ? A.prior[2 * i + 1] : 0;
+    const int64_t ty = (int64_t)py - m / 2, tx = (int64_t)px - m / 2;
+    const int64_t sy = ty - r + pry, sx = tx - r + prx;
+    if (!in_image(ty, tx, m, m, A.Hs, A.Ws) || !in_image(sy, sx, M, M, A.Hr, A.Wr)) return;
+    const float* __restrict__ R = A.rst + (int64_t)i * V * V;
+    ncc_peak<kFinishNT>(A, i, i, 0, 0, V, V, A.tsum[2 * i], A.tsum[2 * i + 1], red,
+                        [&](int u, int v) { return R[u * V + v]; });
 }
 
 template <int L, int DT, bool BATCH>
@@ -1606,6 +1639,78 @@ template <int L>
 static hipError_t launch_match_side(const MatchArgs& a, int dtype, hipStream_t st) {
     return dtype == 0 ? launch_match_L<L, 0>(a, st) : dtype == 1 ? launch_match_L<L, 1>(a, st)
                                                                  : launch_match_L<L, 2>(a, st);
+}
+
+// ---- split form: transforms, then NCC and peaks ----------------------------
+bool match_split_ok(int n, int m, int r, int dtype) {
+    const MatchPlan mp = match_plan_dt(n, m, r, dtype);
+    return n > 0 && mp.L != kDirectSide && mp.L != 0 && mp.nb == 1;
+}
+
+static size_t split_rst_bytes(int n, int r) {
+    const size_t V = 2 * (size_t)r + 1;
+    return ((size_t)n * V * V * sizeof(float) + 255) / 256 * 256;
+}
+
+size_t match_split_bytes(int n, int r) { return split_rst_bytes(n, r) + (size_t)n * 2 * sizeof(double); }
+
+static MatchArgs split_args(const void* desc_sen, int64_t Hs, int64_t Ws, const void* desc_ref, int64_t Hr,
+                            int64_t Wr, const double* i1, const double* i2, int z, int dtype, const int32_t* ips,
+                            const int32_t* prior, int n, int m, int r, float* ncc, sfoc_cp* cps, void* ws,
+                            void* split) {
+    MatchArgs a;
+    a.desc_sen = desc_sen;
+    a.desc_ref = desc_ref;
+    a.integ1 = i1;
+    a.integ2 = i2;
+    a.ips = ips;
+    a.prior = prior;
+    a.ncc = ncc;
+    a.cps = cps;
+    a.Hs = Hs;
+    a.Ws = Ws;
+    a.Hr = Hr;
+    a.Wr = Wr;
+    a.z = z;
+    a.dtype = dtype;
+    a.n = n;
+    a.m = m;
+    a.r = r;
+    match_args_layout(a, match_plan_dt(n, m, r, dtype), ws);
+    a.integ_win = 0;
+    a.rst = (float*)split;
+    a.tsum = (double*)((char*)split + split_rst_bytes(n, r));
+    return a;
+}
+
+hipError_t launch_match_fft(const void* desc_sen, int64_t Hs, int64_t Ws, const void* desc_ref, int64_t Hr,
+                            int64_t Wr, int z, int dtype, const int32_t* ips, const int32_t* prior, int n, int m,
+                            int r, float* ncc, sfoc_cp* cps, void* ws, void* split, hipStream_t st) {
+    if (!match_split_ok(n, m, r, dtype)) return hipErrorInvalidValue;
+    const MatchArgs a = split_args(desc_sen, Hs, Ws, desc_ref, Hr, Wr, nullptr, nullptr, z, dtype, ips, prior, n, m,
+                                   r, ncc, cps, ws, split);
+    switch (match_plan_dt(n, m, r, dtype).L) {
+        case 64: return launch_match_side<64>(a, dtype, st);
+        case 128: return launch_match_side<128>(a, dtype, st);
+        case 160: return launch_match_side<160>(a, dtype, st);
+        case 192: return launch_match_side<192>(a, dtype, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_match_finish(const void* desc_sen, int64_t Hs, int64_t Ws, const void* desc_ref, int64_t Hr,
+                               int64_t Wr, const double* i1, const double* i2, int z, int dtype, const int32_t* ips,
+                               const int32_t* prior, int n, int m, int r, float* ncc, sfoc_cp* cps, void* ws,
+                               void* split, hipStream_t st, bool consistency) {
+    if (!match_split_ok(n, m, r, dtype) || !i1 || !i2) return hipErrorInvalidValue;
+    const MatchArgs a = split_args(desc_sen, Hs, Ws, desc_ref, Hr, Wr, i1, i2, z, dtype, ips, prior, n, m, r, ncc,
+                                   cps, ws, split);
+    trace_begin(st, SFOC_K_PEAK);
+    hipLaunchKernelGGL(ncc_finish_kernel, dim3(n), dim3(kFinishNT), 0, st, a);
+    trace_end(st, SFOC_K_PEAK);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !consistency) return e;
+    return launch_consistency(cps, prior, n, st);
 }
 
 hipError_t launch_match(const void* desc_sen, int64_t Hs, int64_t Ws, const void* desc_ref, int64_t Hr, int64_t Wr,
