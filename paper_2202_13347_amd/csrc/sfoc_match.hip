@@ -774,7 +774,7 @@ SFOC_DEV void ncc_peak(const MatchArgs& A, int i, int slot, int u0, int v0, int 
 // the surface and its best score, and peak_kernel combines the blocks.
 // Every thread of the workgroup calls it with the same item; it returns
 // with the workgroup synchronised.
-template <int L, int DT>
+template <int L, int DT, bool SPLIT = false>
 SFOC_DEV void match_item(const MatchArgs& A, int i, int bq, int slot, const float2* tw, float2* buf, double* red) {
     using C = MatchCfg<L>;
     const int nblk = A.nbu * A.nbv;
@@ -985,7 +985,7 @@ SFOC_DEV void match_item(const MatchArgs& A, int i, int bq, int slot, const floa
         __syncthreads();
     }
 
-    if (A.rst) {   // split form: R_ST and the template sums for ncc_finish_kernel
+    if constexpr (SPLIT) {   // split form: R_ST and the template sums for ncc_finish_kernel
         float* __restrict__ o = A.rst + (int64_t)i * V * V;
         for (int e = t; e < Vu * Vv; e += C::NT) {
             const int u = e / Vv, v = e - u * Vv;
@@ -996,12 +996,12 @@ SFOC_DEV void match_item(const MatchArgs& A, int i, int bq, int slot, const floa
             A.tsum[2 * i] = red[64];
             A.tsum[2 * i + 1] = red[65];
         }
-        return;
+    } else {
+        ncc_peak<C::NT>(A, i, slot, u0, v0, Vu, Vv, red[64], red[65], red, [&](int u, int v) {
+            const float* rr = reinterpret_cast<const float*>(buf + C::row((u >> 1) * 2));
+            return rr[(u & 1) * L + v];
+        });
     }
-    ncc_peak<C::NT>(A, i, slot, u0, v0, Vu, Vv, red[64], red[65], red, [&](int u, int v) {
-        const float* rr = reinterpret_cast<const float*>(buf + C::row((u >> 1) * 2));
-        return rr[(u & 1) * L + v];
-    });
 }
 
 // Split form, second launch: one workgroup per IP assembles the NCC surface
@@ -1024,7 +1024,7 @@ __global__ __launch_bounds__(kFinishNT) void ncc_finish_kernel(const MatchArgs A
                         [&](int u, int v) { return R[u * V + v]; });
 }
 
-template <int L, int DT, bool BATCH>
+template <int L, int DT, bool BATCH, bool SPLIT = false>
 __global__ __launch_bounds__(MatchCfg<L>::NT, MatchCfg<L>::WAVES_PER_SIMD) void match_kernel(const MatchArgs single,
                                                                    const MatchArgs* __restrict__ pairs,
                                                                    const int4* __restrict__ items) {
@@ -1049,7 +1049,7 @@ __global__ __launch_bounds__(MatchCfg<L>::NT, MatchCfg<L>::WAVES_PER_SIMD) void 
         const int k = id < q8 ? (id % 8) * (q8 / 8) + id / 8 : id;
         const int nblk = single.nbu * single.nbv;
         const int i = k / nblk;
-        match_item<L, DT>(single, i, k - i * nblk, k, tw, buf, red);
+        match_item<L, DT, SPLIT>(single, i, k - i * nblk, k, tw, buf, red);
     }
 }
 
@@ -1580,10 +1580,10 @@ void match_args_layout(MatchArgs& a, const MatchPlan& mp, void* ws) {
     }
 }
 
-template <int L, int DT>
+template <int L, int DT, bool SPLIT = false>
 static hipError_t launch_match_L(const MatchArgs& a, hipStream_t st) {
     using C = MatchCfg<L>;
-    auto kern = match_kernel<L, DT, false>;
+    auto kern = match_kernel<L, DT, false, SPLIT>;
     hipError_t e = ensure_dynamic_lds((const void*)kern, (int)C::lds_bytes);
     if (e != hipSuccess) return e;
     trace_begin(st, SFOC_K_MATCH);
@@ -1635,10 +1635,10 @@ static hipError_t launch_direct(const MatchArgs& a, const MatchArgs* pairs, cons
 
 DirLaunch direct_launch_of(int m, int r) { return DirLaunch{m, dir_nkb(m, r)}; }
 
-template <int L>
+template <int L, bool SPLIT = false>
 static hipError_t launch_match_side(const MatchArgs& a, int dtype, hipStream_t st) {
-    return dtype == 0 ? launch_match_L<L, 0>(a, st) : dtype == 1 ? launch_match_L<L, 1>(a, st)
-                                                                 : launch_match_L<L, 2>(a, st);
+    return dtype == 0 ? launch_match_L<L, 0, SPLIT>(a, st)
+                      : dtype == 1 ? launch_match_L<L, 1, SPLIT>(a, st) : launch_match_L<L, 2, SPLIT>(a, st);
 }
 
 // ---- split form: transforms, then NCC and peaks ----------------------------
@@ -1690,10 +1690,10 @@ hipError_t launch_match_fft(const void* desc_sen, int64_t Hs, int64_t Ws, const 
     const MatchArgs a = split_args(desc_sen, Hs, Ws, desc_ref, Hr, Wr, nullptr, nullptr, z, dtype, ips, prior, n, m,
                                    r, ncc, cps, ws, split);
     switch (match_plan_dt(n, m, r, dtype).L) {
-        case 64: return launch_match_side<64>(a, dtype, st);
-        case 128: return launch_match_side<128>(a, dtype, st);
-        case 160: return launch_match_side<160>(a, dtype, st);
-        case 192: return launch_match_side<192>(a, dtype, st);
+        case 64: return launch_match_side<64, true>(a, dtype, st);
+        case 128: return launch_match_side<128, true>(a, dtype, st);
+        case 160: return launch_match_side<160, true>(a, dtype, st);
+        case 192: return launch_match_side<192, true>(a, dtype, st);
         default: return hipErrorInvalidValue;
     }
 }
