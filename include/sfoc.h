@@ -244,9 +244,15 @@ int sfoc_fastncc_match(const void* desc_sen, int64_t Hs, int64_t Ws,
  * reference, then sfoc_fastncc_match.  Reference tiles no window reads are
  * not described and count as zero in the integral images, so every box sum
  * a window takes is that of the described values.  Both images' tiles go
- * into one describe launch.  Arguments as above; the descriptors, integral
- * images, the describe table of both images' tiles and the reference tile
- * mask live inside ws (see sfoc_register_workspace).  The CPs equal
+ * into one describe launch.  Where the match runs on an FFT side without
+ * offset blocks, the integral scans run on a second stream beside the
+ * match's transforms (one library-owned, non-blocking, default-priority
+ * stream per device and host thread, created on first use with its two
+ * events); `stream` waits for it before the NCC assembly, so all later work
+ * on `stream` is ordered after the call.  Arguments as above; the
+ * descriptors, integral images, the describe table of both images' tiles,
+ * the match's R_ST surfaces and the reference tile mask live inside ws (see
+ * sfoc_register_workspace).  The CPs equal
  * those of sfoc_describe of both whole images followed by sfoc_fastncc_match
  * up to the float64 rounding of those box sums (bit for bit in every test).
  */
