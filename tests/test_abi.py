@@ -87,8 +87,15 @@ def test_workspace_queries():
     p = S.preset("baseline")
     assert S.describe_workspace(2048, 2048, p) > 0
     w = S.register_workspace(2048, 2048, 2048, 2048, 400, 64, 32, p)
-    # two float32 descriptors + two float64 integral images at least
-    assert w >= 2 * 16 * 2048 * 2048 * 4 + 2 * 2049 * 2049 * 8
+    # two float32 descriptors + two float64 integral images, the describe
+    # table of both images (4096 reference tiles + 4 sensed slots per IP,
+    # 16 B each) and the split match's R_ST surfaces and template sums
+    assert w >= (2 * 16 * 2048 * 2048 * 4 + 2 * 2049 * 2049 * 8 + (4096 + 400 * 4) * 16
+                 + 400 * 65 * 65 * 4 + 400 * 2 * 8)
+    # the split buffer grows with the IPs: 100 more IPs add at least their
+    # surfaces, sums and table slots
+    w2 = S.register_workspace(2048, 2048, 2048, 2048, 500, 64, 32, p)
+    assert w2 - w >= 100 * (65 * 65 * 4 + 2 * 8 + 4 * 16) - 3 * 256
     b = ctypes.c_size_t()
     assert S.lib().sfoc_match_workspace(10, 64, 32, 16, ctypes.byref(b)) == 0 and b.value == 0
     # windows up to 192 x 192 are one transform: no workspace
