@@ -1092,8 +1092,9 @@ hipError_t launch_describe_pair(const float* ref, int Hr, int Wr, int64_t ldr, v
                        Hs, Ws, Hr, Wr, jref, jsen, jobs, tiles, mask);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    // configuration 1 (four workgroups per CU) where the parameters have it
     DescribeJob none{};
-    return launch_describe_any(none, jobs, tiles, (int)cnt, mask, c, st, 0);
+    return launch_describe_any(none, jobs, tiles, (int)cnt, mask, c, st, 1);
 }
 
 hipError_t launch_integral(double* i1, double* i2, int H, int W, double* agg, hipStream_t st, uint8_t* tmask) {
